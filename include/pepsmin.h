@@ -1,0 +1,195 @@
+/*
+ * pepsmin — sampled finite-PEPS amplitudes, local energies, log-derivatives
+ * and the minimum-step stochastic-reconfiguration (minSR) update on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The calls follow the operations a sampling-based PEPS optimisation needs
+ * (arXiv 2503.12557, Sec. "Finite PEPS and Sampling"): samples from
+ * p(S) = |Psi(S)|^2/<Psi|Psi>, the amplitudes Psi(S), the local estimator
+ * O_loc(S) = sum_S' <S|O|S'> Psi(S')/Psi(S) (Eq. local_estimator), the
+ * log-derivatives O_{S,i} = (dPsi(S)/dtheta_i)/Psi(S) (Eq. tdvp) and the
+ * minSR solution dtheta = O^dagger (O O^dagger)^-1 E_loc (Eq. tdvp_fast).
+ *
+ * Conventions shared by every call
+ *  - Lattice: open Lx x Ly square lattice, rows x = 0..Lx-1 from the top,
+ *    columns y = 0..Ly-1, site n = x*Ly + y. Physical dimension d = 2.
+ *  - Parameters theta: the entries of the site tensors T[x,y] of shape
+ *    (d, Dl, Dr, Du, Dd) in C order, sites concatenated in row-major order;
+ *    virtual legs on an open edge have dimension 1. theta is FP64 (real
+ *    modes) and is converted to the compute precision inside the call.
+ *  - Samples: uint8 [n][Lx*Ly], one physical index per site (0 = spin up /
+ *    atom in |g>, 1 = spin down / atom in |r>).
+ *  - Amplitudes are contracted with boundary MPS of bond chi (Sec. "On the
+ *    boundary MPS method"): rows are absorbed from the top and from the
+ *    bottom, each MPS-MPO product is truncated to chi by a left QR sweep and
+ *    a right SVD sweep (the same truncated state as the density-matrix
+ *    algorithm) and every tensor is divided by its largest modulus with the
+ *    logarithms accumulated in FP64 (Sec. "On Numerical Stability").
+ *  - Every pointer passed to a compute call is caller-owned DEVICE memory
+ *    unless stated otherwise; the library reads and writes it only from
+ *    work enqueued on the given stream, keeps no reference after the call
+ *    and frees nothing it did not allocate. The context owns only its own
+ *    workspace, grown on demand with hipMalloc.
+ *  - Every call returns a peps_status; no exception crosses the ABI. On an
+ *    error nothing is enqueued and peps_last_error() describes it.
+ *  - Calls enqueue work on `stream` and return; results are valid after the
+ *    stream is synchronised. One context per host thread at a time.
+ */
+#ifndef PEPSMIN_H
+#define PEPSMIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PEPS_OK = 0,
+  PEPS_ERR_ARG = 1,          /* bad shape, null pointer, out-of-range value */
+  PEPS_ERR_UNSUPPORTED = 2,  /* valid request outside what is implemented */
+  PEPS_ERR_HIP = 3,          /* a HIP runtime call failed */
+  PEPS_ERR_OOM = 4,          /* device workspace could not be allocated */
+  PEPS_ERR_NONFINITE = 5     /* non-finite input (theta, E_loc) */
+} peps_status;
+
+/* Compute precision of the contractions. Log scales, local energies and the
+ * minSR solve are always FP64. */
+typedef enum {
+  PEPS_F64 = 0,   /* FP64 everywhere */
+  PEPS_F32 = 1,   /* FP32 contractions, QR and SVD */
+  PEPS_BF16 = 2   /* BF16 contraction operands with FP32 accumulation; QR/SVD in FP32 */
+} peps_dtype;
+
+/* Per-sample flags (bit set = condition seen for that sample). */
+enum {
+  PEPS_FLAG_ZERO = 1,        /* Psi(S) = 0 exactly */
+  PEPS_FLAG_NONFINITE = 2,   /* a non-finite value appeared */
+  PEPS_FLAG_NOCONV = 4,      /* a Jacobi SVD hit its sweep limit */
+  PEPS_FLAG_DEGENERATE = 8   /* relative gap at a truncation cut below 1e-8 */
+};
+
+/* Sampler kinds for peps_sample. */
+enum { PEPS_SAMPLE_EXCHANGE = 0, PEPS_SAMPLE_FLIP = 1 };
+
+typedef struct {
+  int Lx, Ly;   /* lattice size, 2 <= Lx, Ly <= 32 */
+  int d;        /* physical dimension, must be 2 */
+  int D;        /* virtual bond dimension, >= 1 */
+  int chi;      /* boundary-MPS bond dimension D_c, >= 1 */
+  int dtype;    /* peps_dtype */
+} peps_geom;
+
+typedef struct peps_ctx peps_ctx;
+
+/* Create a context for one geometry and precision; *out receives it.
+ * PEPS_ERR_UNSUPPORTED if chi*D exceeds what the kernels hold on chip. */
+peps_status peps_create(const peps_geom* geom, peps_ctx** out);
+void peps_destroy(peps_ctx* ctx);
+
+/* Thread-local description of the last error; valid until the next call. */
+const char* peps_last_error(void);
+
+/* Number of parameters N_p; the compact log-derivative row has N_p/d. */
+size_t peps_num_params(const peps_ctx* ctx);
+
+/* Bytes of the environment cache for n samples: every top environment
+ * E^u[0..Lx-2] and bottom environment E^l[1..Lx-1] of every sample, each site
+ * tensor padded to chi*D*chi entries of the compute precision, plus the FP64
+ * log scales. */
+size_t peps_env_cache_bytes(const peps_ctx* ctx, int n);
+
+/* Hamiltonian H = sum_t h_t + sum_(i<j) V_ij n_i n_j + sum_i onsite[i][s_i].
+ * HOST pointers. Term t acts on term_nsites[t] (1..3) sites listed in
+ * term_sites[3*t + j] and has the 2^k x 2^k complex matrix
+ * term_mats[t][c][c'] = <c|h_t|c'> stored as interleaved (re, im) FP64 pairs
+ * in blocks of 64 complex entries per term (8 x 8, row-major, only the
+ * leading 2^k x 2^k used); the first listed site is the most significant
+ * bit of c. Diagonal pairs: pair_ij[2p], pair_ij[2p+1], value pair_v[p].
+ * onsite: [N][2] FP64 or NULL. The local energy of S is
+ * E_loc(S) = sum_t sum_S' <S|h_t|S'> Psi(S')/Psi(S) + diagonal parts
+ * (Eq. local_obs with the element read as <S|H|S'>); every ratio is taken
+ * inside the one-row or two-row strip that holds the changed sites, reusing
+ * the environments outside it (Sec. "On reusing environments"); diagonal
+ * terms of any range need no amplitude.
+ * PEPS_ERR_UNSUPPORTED if an off-diagonal term changes sites on more than
+ * two adjacent rows. */
+peps_status peps_set_hamiltonian(peps_ctx* ctx, int n_terms, const int* term_nsites,
+                                 const int* term_sites, const double* term_mats,
+                                 int n_pairs, const int* pair_ij, const double* pair_v,
+                                 const double* onsite);
+
+/* ln Psi(S)_i* = ln(E^u[i*] . E^l[i*+1]) with i* = floor(Lx/2) - 1
+ * (Eq. boundary_MPS_approx), as (ln|Psi|, arg Psi) FP64 pairs in
+ * logpsi[n][2]. env_cache: device buffer of peps_env_cache_bytes(n) that
+ * receives every environment of every sample, or NULL to keep none.
+ * flags: int32 [n] or NULL. */
+peps_status peps_amplitude(peps_ctx* ctx, const double* theta, const uint8_t* samples,
+                           int n, void* env_cache, double* logpsi, int32_t* flags,
+                           void* stream);
+
+/* Local energies eloc[n][2] (complex, FP64) of the Hamiltonian set by
+ * peps_set_hamiltonian. env_cache must hold the environments written by
+ * peps_amplitude for the same theta and samples, or be NULL (then they are
+ * rebuilt in the context's workspace). */
+peps_status peps_local_energy(peps_ctx* ctx, const double* theta, const uint8_t* samples,
+                              int n, const void* env_cache, double* eloc, int32_t* flags,
+                              void* stream);
+
+/* Log-derivatives O_k(S) = d ln Psi_row(x)(S) / d theta_k for every
+ * parameter k of a site (x, y) with physical index s_xy (the hole network
+ * of row x between E^u[x-1] and E^l[x+1], divided by that strip's
+ * amplitude); parameters with p != s_xy have O = 0 and are not stored.
+ * O: compact [n][N_p/d] in FP64 (PEPS_F64) or FP32 (PEPS_F32, PEPS_BF16),
+ * site-major with the (l, r, u, d) entries of each site in C order.
+ * env_cache as for peps_local_energy. */
+peps_status peps_logderiv(peps_ctx* ctx, const double* theta, const uint8_t* samples,
+                          int n, const void* env_cache, void* O, void* stream);
+
+/* Fused amplitude + local energy + log-derivatives of one batch, sharing the
+ * environments and the one-row strips between the three; outputs as in the
+ * three calls above (any of eloc, O may be NULL). */
+peps_status peps_evaluate(peps_ctx* ctx, const double* theta, const uint8_t* samples,
+                          int n, double* logpsi, double* eloc, void* O, int32_t* flags,
+                          void* stream);
+
+/* minSR step (Eqs. tdvp, tdvp_fast). With O the compact log-derivatives of
+ * peps_logderiv (expanded with zeros where p != s_xy) and E = eloc:
+ *   Obar = (O - <O>)/sqrt(n), ebar = (E - <E>)/sqrt(n),
+ *   T = Obar Obar^T (n x n, FP64),
+ *   dtheta = Obar^T (T + eps I)^+ ebar,
+ * where eigenvalues of T + eps I at or below rcond * (largest) are dropped
+ * from the pseudo-inverse. The solve is a Cholesky factorisation of
+ * T + eps I, which equals the pseudo-inverse whenever no eigenvalue is
+ * dropped; that holds when trace(T) + eps <= eps / rcond, which is checked on
+ * the device. If the check fails diag[3] is set to 1 and dtheta is filled
+ * with NaN. The real part of eloc is used (real PEPS). dtheta: FP64 [N_p],
+ * the direction of Eq. tdvp: theta moves as theta - tau * dtheta.
+ * diag (device, FP64 [8]): [0] trace(T)+eps (bound on the largest
+ * eigenvalue), [1] eps, [2] number of dropped eigenvalues (0), [3] 1 if the
+ * certificate failed, [4] <E>, [5] Var(E)/1, [6] n, [7] smallest Cholesky
+ * pivot. */
+peps_status minsr_step(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
+                       const double* eloc, double eps, double rcond, double* dtheta,
+                       double* diag, void* stream);
+
+/* Local Metropolis sampling of p(S) ~ |Psi(S)|^2 (Sec. "On Direct
+ * Sampling" names Markov chains as the alternative to direct sampling).
+ * kind PEPS_SAMPLE_EXCHANGE: exchanges of anti-aligned nearest neighbours
+ * (S^z conserved, chains start with floor(N/2) up spins); PEPS_SAMPLE_FLIP:
+ * single-site flips. A move is accepted iff u < |Psi(S')/Psi(S)|^2 with the
+ * ratio taken in the strip holding the move and u from Philox4x32-10 keyed
+ * by seed (counter: move id, sweep + offset, chain, tag). Chain c writes
+ * samples[c*per_chain + j] = its state after sweep burn_in + (j+1)*thin - 1.
+ * accepted: int32 [n_chains] accepted-move counts (or NULL). */
+peps_status peps_sample(peps_ctx* ctx, const double* theta, int kind, int n_chains,
+                        int per_chain, int burn_in, int thin, uint64_t seed,
+                        uint64_t offset, uint8_t* samples, int32_t* accepted,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEPSMIN_H */

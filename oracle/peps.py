@@ -216,7 +216,7 @@ def compress_density_matrix(mps, chi: int):
     G[0] = np.ones((1, 1))
     for y in range(n - 1):
         P = mps[y]
-        G[y + 1] = np.einsum('ab,akc,bkd->cd', G[y], P.conj(), P)
+        G[y + 1] = np.einsum('ab,akc,bkd->cd', G[y], P.conj(), P, optimize='greedy')
     out = [None] * n
     W = np.ones((1, 1))
     for y in range(n - 1, 0, -1):
@@ -283,7 +283,7 @@ def overlap(top, bottom):
     """Contract two boundary MPS over their physical legs (E^u[i] . E^l[i+1])."""
     L = np.ones((1, 1), dtype=np.result_type(top[0], bottom[0]))
     for a, b in zip(top, bottom):
-        L = np.einsum('ac,akb,ckd->bd', L, a, b)
+        L = np.einsum('ac,akb,ckd->bd', L, a, b, optimize='greedy')
     return L[0, 0]
 
 
@@ -311,6 +311,11 @@ def amplitude_row_index(g: Geometry) -> int:
 # left and right partial contractions (Sec. "On reusing environments").
 # ----------------------------------------------------------------------------
 
+def _c(spec, a, b):
+    """One pairwise contraction (einsum with a BLAS-backed path)."""
+    return np.einsum(spec, a, b, optimize=True)
+
+
 def _trivial_mps(Ly, dtype):
     return [np.ones((1, 1, 1), dtype=dtype) for _ in range(Ly)]
 
@@ -333,10 +338,14 @@ class Strip1:
         self.value = np.einsum('amc,amc->', self.Lf[n], self.Rt[n])
 
     def step_left(self, L, y, a):
-        return np.einsum('amc,aub,mrud,cde->bre', L, self.Up[y], a, self.Bt[y])
+        X = _c('amc,aub->mcub', L, self.Up[y])
+        X = _c('mcub,mrud->cbrd', X, a)
+        return _c('cbrd,cde->bre', X, self.Bt[y])
 
     def step_right(self, R, y, a):
-        return np.einsum('bre,aub,mrud,cde->amc', R, self.Up[y], a, self.Bt[y])
+        X = _c('bre,aub->reau', R, self.Up[y])
+        X = _c('reau,mrud->eamd', X, a)
+        return _c('eamd,cde->amc', X, self.Bt[y])
 
     def window(self, y0, tensors):
         """Strip value with sites y0.. replaced by ``tensors``."""
@@ -347,8 +356,9 @@ class Strip1:
 
     def hole(self, y):
         """d(strip value)/d(row tensor y), legs (l, r, u, d)."""
-        return np.einsum('amc,aub,cde,bre->mrud', self.Lf[y], self.Up[y],
-                         self.Bt[y], self.Rt[y + 1])
+        X = _c('amc,aub->mcub', self.Lf[y], self.Up[y])
+        X = _c('mcub,cde->mubde', X, self.Bt[y])
+        return _c('mubde,bre->mrud', X, self.Rt[y + 1])
 
 
 class Strip2:
@@ -369,12 +379,16 @@ class Strip2:
         self.value = np.einsum('amnc,amnc->', self.Lf[n], self.Rt[n])
 
     def step_left(self, L, y, a1, a2):
-        return np.einsum('amnc,aub,mrut,nstd,cde->brse', L, self.Up[y], a1, a2,
-                         self.Bt[y])
+        X = _c('amnc,aub->mncub', L, self.Up[y])
+        X = _c('mncub,mrut->ncbrt', X, a1)
+        X = _c('ncbrt,nstd->cbrsd', X, a2)
+        return _c('cbrsd,cde->brse', X, self.Bt[y])
 
     def step_right(self, R, y, a1, a2):
-        return np.einsum('brse,aub,mrut,nstd,cde->amnc', R, self.Up[y], a1, a2,
-                         self.Bt[y])
+        X = _c('brse,cde->brscd', R, self.Bt[y])
+        X = _c('brscd,nstd->brcnt', X, a2)
+        X = _c('brcnt,mrut->bcnmu', X, a1)
+        return _c('bcnmu,aub->amnc', X, self.Up[y])
 
     def window(self, y0, cols):
         L = self.Lf[y0]

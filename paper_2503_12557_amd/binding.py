@@ -1,0 +1,222 @@
+"""ctypes binding of libpepsmin.so (declared in include/pepsmin.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+stream, every step of the computation runs in the library's HIP kernels.
+There is no fallback: if the library is missing or a call fails, an
+exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpepsmin.so")
+
+PEPS_OK = 0
+STATUS_NAMES = {0: "PEPS_OK", 1: "PEPS_ERR_ARG", 2: "PEPS_ERR_UNSUPPORTED", 3: "PEPS_ERR_HIP",
+                4: "PEPS_ERR_OOM", 5: "PEPS_ERR_NONFINITE"}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
+FLAG_ZERO, FLAG_NONFINITE, FLAG_NOCONV, FLAG_DEGENERATE = 1, 2, 4, 8
+SAMPLE_EXCHANGE, SAMPLE_FLIP = 0, 1
+
+# every symbol the header declares
+EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
+           "peps_env_cache_bytes", "peps_set_hamiltonian", "peps_amplitude",
+           "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample"]
+
+
+class PepsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("d", ctypes.c_int),
+                ("D", ctypes.c_int), ("chi", ctypes.c_int), ("dtype", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built: run paper_2503_12557_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, Z, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_uint64
+    lib.peps_create.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(P)]
+    lib.peps_create.restype = I
+    lib.peps_destroy.argtypes = [P]
+    lib.peps_destroy.restype = None
+    lib.peps_last_error.argtypes = []
+    lib.peps_last_error.restype = ctypes.c_char_p
+    lib.peps_num_params.argtypes = [P]
+    lib.peps_num_params.restype = Z
+    lib.peps_env_cache_bytes.argtypes = [P, I]
+    lib.peps_env_cache_bytes.restype = Z
+    lib.peps_set_hamiltonian.argtypes = [P, I, P, P, P, I, P, P, P]
+    lib.peps_set_hamiltonian.restype = I
+    lib.peps_amplitude.argtypes = [P, P, P, I, P, P, P, P]
+    lib.peps_amplitude.restype = I
+    lib.peps_local_energy.argtypes = [P, P, P, I, P, P, P, P]
+    lib.peps_local_energy.restype = I
+    lib.peps_logderiv.argtypes = [P, P, P, I, P, P, P]
+    lib.peps_logderiv.restype = I
+    lib.peps_evaluate.argtypes = [P, P, P, I, P, P, P, P, P]
+    lib.peps_evaluate.restype = I
+    lib.minsr_step.argtypes = [P, P, P, I, P, D, D, P, P, P]
+    lib.minsr_step.restype = I
+    lib.peps_sample.argtypes = [P, P, I, I, I, I, I, U64, U64, P, P, P]
+    lib.peps_sample.restype = I
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != PEPS_OK:
+        raise PepsError(st, load().peps_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One geometry (Lx x Ly, D, chi) and one compute precision."""
+
+    def __init__(self, Lx, Ly, D, chi, dtype="f64", d=2):
+        lib = load()
+        self.Lx, self.Ly, self.D, self.chi, self.d = Lx, Ly, D, chi, d
+        self.dtype = dtype
+        g = Geom(Lx, Ly, d, D, chi, DTYPES[dtype])
+        h = ctypes.c_void_p()
+        _check(lib.peps_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+        self.n_params = lib.peps_num_params(h)
+        self.n_compact = self.n_params // d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().peps_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def o_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def env_cache_bytes(self, n):
+        return load().peps_env_cache_bytes(self._h, n)
+
+    def set_hamiltonian(self, ham):
+        """ham: dict from hamiltonians.* (host numpy arrays)."""
+        nt = len(ham["nsites"])
+        ns = np.ascontiguousarray(ham["nsites"], dtype=np.int32)
+        st = np.ascontiguousarray(ham["sites"], dtype=np.int32).reshape(-1)
+        mats = np.ascontiguousarray(ham["mats"], dtype=np.float64).reshape(-1)
+        pij = np.ascontiguousarray(ham["pair_ij"], dtype=np.int32).reshape(-1)
+        pv = np.ascontiguousarray(ham["pair_v"], dtype=np.float64)
+        on = ham.get("onsite")
+        on = None if on is None else np.ascontiguousarray(on, dtype=np.float64).reshape(-1)
+        self._ham_keep = (ns, st, mats, pij, pv, on)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
+        _check(load().peps_set_hamiltonian(self._h, nt, c(ns), c(st), c(mats), len(pv), c(pij),
+                                          c(pv), c(on)))
+
+    def _args(self, theta, samples):
+        import torch
+        assert theta.dtype == torch.float64 and theta.is_cuda and theta.numel() == self.n_params
+        assert samples.dtype == torch.uint8 and samples.is_cuda
+        assert samples.dim() == 2 and samples.shape[1] == self.Lx * self.Ly
+        return theta.contiguous(), samples.contiguous()
+
+    def amplitude(self, theta, samples, env_cache=None, flags=None):
+        import torch
+        theta, samples = self._args(theta, samples)
+        n = samples.shape[0]
+        logpsi = torch.empty(n, 2, dtype=torch.float64, device=theta.device)
+        if flags is None:
+            flags = torch.zeros(n, dtype=torch.int32, device=theta.device)
+        _check(load().peps_amplitude(self._h, _ptr(theta), _ptr(samples), n, _ptr(env_cache),
+                                     _ptr(logpsi), _ptr(flags), _stream()))
+        return logpsi, flags
+
+    def new_env_cache(self, n, device="cuda"):
+        import torch
+        return torch.empty(self.env_cache_bytes(n), dtype=torch.uint8, device=device)
+
+    def local_energy(self, theta, samples, env_cache=None, flags=None):
+        import torch
+        theta, samples = self._args(theta, samples)
+        n = samples.shape[0]
+        eloc = torch.empty(n, 2, dtype=torch.float64, device=theta.device)
+        _check(load().peps_local_energy(self._h, _ptr(theta), _ptr(samples), n, _ptr(env_cache),
+                                        _ptr(eloc), _ptr(flags), _stream()))
+        return eloc
+
+    def logderiv(self, theta, samples, env_cache=None):
+        import torch
+        theta, samples = self._args(theta, samples)
+        n = samples.shape[0]
+        O = torch.empty(n, self.n_compact, dtype=self.o_dtype, device=theta.device)
+        _check(load().peps_logderiv(self._h, _ptr(theta), _ptr(samples), n, _ptr(env_cache),
+                                    _ptr(O), _stream()))
+        return O
+
+    def evaluate(self, theta, samples, want_e=True, want_o=True, out=None):
+        """Fused ln Psi + E_loc + O; returns (logpsi, eloc, O, flags)."""
+        import torch
+        theta, samples = self._args(theta, samples)
+        n = samples.shape[0]
+        dev = theta.device
+        if out is None:
+            out = (torch.empty(n, 2, dtype=torch.float64, device=dev),
+                   torch.empty(n, 2, dtype=torch.float64, device=dev) if want_e else None,
+                   torch.empty(n, self.n_compact, dtype=self.o_dtype, device=dev) if want_o else None,
+                   torch.zeros(n, dtype=torch.int32, device=dev))
+        logpsi, eloc, O, flags = out
+        _check(load().peps_evaluate(self._h, _ptr(theta), _ptr(samples), n, _ptr(logpsi),
+                                    _ptr(eloc), _ptr(O), _ptr(flags), _stream()))
+        return logpsi, eloc, O, flags
+
+    def minsr_step(self, O, samples, eloc, eps=1e-4, rcond=1e-12):
+        import torch
+        n = samples.shape[0]
+        assert O.dtype == self.o_dtype and O.shape == (n, self.n_compact)
+        dtheta = torch.empty(self.n_params, dtype=torch.float64, device=O.device)
+        diag = torch.zeros(8, dtype=torch.float64, device=O.device)
+        _check(load().minsr_step(self._h, _ptr(O.contiguous()), _ptr(samples.contiguous()), n,
+                                 _ptr(eloc.contiguous()), float(eps), float(rcond), _ptr(dtheta),
+                                 _ptr(diag), _stream()))
+        return dtheta, diag
+
+    def sample(self, theta, kind="exchange", n_chains=256, per_chain=4, burn_in=32, thin=1,
+               seed=0, offset=0):
+        import torch
+        assert theta.dtype == torch.float64 and theta.is_cuda
+        n = n_chains * per_chain
+        samples = torch.empty(n, self.Lx * self.Ly, dtype=torch.uint8, device=theta.device)
+        acc = torch.zeros(n_chains, dtype=torch.int32, device=theta.device)
+        k = SAMPLE_EXCHANGE if kind == "exchange" else SAMPLE_FLIP
+        _check(load().peps_sample(self._h, _ptr(theta.contiguous()), k, n_chains, per_chain,
+                                  burn_in, thin, seed, offset, _ptr(samples), _ptr(acc),
+                                  _stream()))
+        return samples, acc

@@ -1,0 +1,631 @@
+// C-ABI of the library: argument validation, lattice tables, the
+// Hamiltonian term compiler, workspace management and stream-ordered
+// launches. Declared in include/pepsmin.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pepsmin.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace pm;
+
+namespace {
+
+thread_local std::string g_err;
+
+peps_status fail(peps_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(PEPS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+// A device buffer that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  peps_status ensure(size_t bytes) {
+    if (bytes <= cap) return PEPS_OK;
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      return fail(PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    cap = bytes;
+    return PEPS_OK;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+}  // namespace
+
+struct peps_ctx {
+  peps_geom g;
+  Lattice L;
+  std::vector<int> tab;  // host copy
+  int* d_tab = nullptr;
+  size_t tsize = 8;      // bytes per compute element
+  int icut = 0;
+  // Hamiltonian
+  bool has_ham = false;
+  HamDev H{};
+  int* d_hint = nullptr;
+  double* d_hdbl = nullptr;
+  // workspace
+  DevBuf theta_c, env_int, rscr, rt1, rt2, epart, bad, mean, Tm, vec, eloc_tmp, logpsi_tmp;
+  int jac_sweeps = 40;
+  size_t chunk_budget = (size_t)6 << 30;  // bytes of per-chunk scratch
+};
+
+static size_t elem_bytes(int dtype) { return dtype == PEPS_F64 ? 8 : 4; }
+
+static size_t env_tensor_elems_per_sample(const Lattice& L) {
+  return (size_t)L.n_slots * L.Ly * L.site_box;
+}
+
+static peps_status build_tables(peps_ctx* c) {
+  const peps_geom& g = c->g;
+  const int Lx = g.Lx, Ly = g.Ly, D = g.D, N = Lx * Ly;
+  Lattice& L = c->L;
+  L.Lx = Lx;
+  L.Ly = Ly;
+  L.D = D;
+  L.chi = g.chi;
+  L.N = N;
+  L.bmax = std::max(g.chi, D);
+  L.site_box = L.bmax * D * L.bmax;
+  L.n_slots = 2 * (Lx - 1);
+  std::vector<int> poff(N), blk(N), legs(4 * N), coff(N);
+  int off = 0, coffs = 0;
+  for (int x = 0; x < Lx; ++x)
+    for (int y = 0; y < Ly; ++y) {
+      const int n = x * Ly + y;
+      const int Dl = y == 0 ? 1 : D, Dr = y == Ly - 1 ? 1 : D;
+      const int Du = x == 0 ? 1 : D, Dd = x == Lx - 1 ? 1 : D;
+      legs[4 * n] = Dl;
+      legs[4 * n + 1] = Dr;
+      legs[4 * n + 2] = Du;
+      legs[4 * n + 3] = Dd;
+      blk[n] = Dl * Dr * Du * Dd;
+      poff[n] = off;
+      coff[n] = coffs;
+      off += g.d * blk[n];
+      coffs += blk[n];
+    }
+  L.n_params = off;
+  L.n_compact = coffs;
+  std::vector<int> csite(coffs);
+  for (int n = 0; n < N; ++n)
+    for (int j = 0; j < blk[n]; ++j) csite[coff[n] + j] = n;
+  // environment dims: simulate both sweeps
+  std::vector<int> ed((size_t)L.n_slots * Ly * 3, 1);
+  auto set = [&](int slot, int y, int a, int k, int b) {
+    ed[((size_t)slot * Ly + y) * 3 + 0] = a;
+    ed[((size_t)slot * Ly + y) * 3 + 1] = k;
+    ed[((size_t)slot * Ly + y) * 3 + 2] = b;
+  };
+  auto get = [&](int slot, int y, int i) { return ed[((size_t)slot * Ly + y) * 3 + i]; };
+  for (int dir = 0; dir < 2; ++dir) {
+    const int x0 = dir ? Lx - 1 : 0;
+    const int s0 = dir ? (Lx - 1) + (Lx - 2) : 0;
+    for (int y = 0; y < Ly; ++y) {
+      const int n = x0 * Ly + y;
+      set(s0, y, legs[4 * n], dir ? legs[4 * n + 2] : legs[4 * n + 3], legs[4 * n + 1]);
+    }
+    for (int t = 1; t <= Lx - 2; ++t) {
+      const int x = dir ? Lx - 1 - t : t;
+      const int sp = dir ? (Lx - 1) + (x + 1 - 1) : x - 1;
+      const int sn = dir ? (Lx - 1) + (x - 1) : x;
+      std::vector<int> kk(Ly, 0);
+      int kp = 1;
+      for (int y = 0; y < Ly - 1; ++y) {
+        const int n = x * Ly + y;
+        const int kout = dir ? legs[4 * n + 2] : legs[4 * n + 3];
+        const int Pr = get(sp, y, 2) * legs[4 * n + 1];
+        kk[y] = std::min(kp * kout, Pr);
+        kp = kk[y];
+      }
+      int nbr = 1;
+      for (int y = Ly - 1; y >= 0; --y) {
+        const int n = x * Ly + y;
+        const int kout = dir ? legs[4 * n + 2] : legs[4 * n + 3];
+        const int zc = kout * nbr;
+        int r = 1;
+        if (y > 0) r = std::min(std::min(g.chi, kk[y - 1]), zc);
+        set(sn, y, r, kout, nbr);
+        nbr = r;
+      }
+    }
+  }
+  // concatenate
+  std::vector<int>& tab = c->tab;
+  tab.clear();
+  L.off_param = (int)tab.size();
+  tab.insert(tab.end(), poff.begin(), poff.end());
+  L.off_block = (int)tab.size();
+  tab.insert(tab.end(), blk.begin(), blk.end());
+  L.off_legs = (int)tab.size();
+  tab.insert(tab.end(), legs.begin(), legs.end());
+  L.off_compact = (int)tab.size();
+  tab.insert(tab.end(), coff.begin(), coff.end());
+  L.off_env = (int)tab.size();
+  tab.insert(tab.end(), ed.begin(), ed.end());
+  L.off_csite = (int)tab.size();
+  tab.insert(tab.end(), csite.begin(), csite.end());
+  HIPCHK(hipMalloc(&c->d_tab, tab.size() * sizeof(int)));
+  HIPCHK(hipMemcpy(c->d_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+  return PEPS_OK;
+}
+
+extern "C" {
+
+const char* peps_last_error(void) { return g_err.c_str(); }
+
+peps_status peps_create(const peps_geom* geom, peps_ctx** out) {
+  if (!geom || !out) return fail(PEPS_ERR_ARG, "null geometry or output pointer");
+  *out = nullptr;
+  const peps_geom& g = *geom;
+  if (g.Lx < 2 || g.Ly < 2 || g.Lx > 32 || g.Ly > 32)
+    return fail(PEPS_ERR_ARG, "lattice %dx%d outside 2..32", g.Lx, g.Ly);
+  if (g.d != 2) return fail(PEPS_ERR_UNSUPPORTED, "physical dimension %d (only d = 2)", g.d);
+  if (g.D < 1 || g.chi < 1) return fail(PEPS_ERR_ARG, "D = %d, chi = %d must be >= 1", g.D, g.chi);
+  if (g.dtype != PEPS_F64 && g.dtype != PEPS_F32 && g.dtype != PEPS_BF16)
+    return fail(PEPS_ERR_ARG, "unknown dtype %d", g.dtype);
+  const int bmax = std::max(g.chi, g.D);
+  if (bmax * g.D > 128)
+    return fail(PEPS_ERR_UNSUPPORTED, "chi*D = %d above the on-chip limit 128", bmax * g.D);
+  const size_t eb = elem_bytes(g.dtype);
+  const size_t lds = std::max(std::max(env_lds_elems(bmax, g.D), strip1_lds_elems(bmax, g.D)),
+                              strip2_lds_elems(bmax, g.D)) * eb;
+  if (lds > 160 * 1024)
+    return fail(PEPS_ERR_UNSUPPORTED, "chi = %d, D = %d needs %zu bytes of LDS per workgroup",
+                g.chi, g.D, lds);
+  peps_ctx* c = new peps_ctx();
+  c->g = g;
+  c->tsize = eb;
+  c->icut = g.Lx / 2 - 1;
+  peps_status st = build_tables(c);
+  if (st != PEPS_OK) {
+    peps_destroy(c);
+    return st;
+  }
+  *out = c;
+  return PEPS_OK;
+}
+
+void peps_destroy(peps_ctx* c) {
+  if (!c) return;
+  if (c->d_tab) hipFree(c->d_tab);
+  if (c->d_hint) hipFree(c->d_hint);
+  if (c->d_hdbl) hipFree(c->d_hdbl);
+  DevBuf* bufs[] = {&c->theta_c, &c->env_int, &c->rscr,  &c->rt1, &c->rt2,      &c->epart,
+                    &c->bad,     &c->mean,    &c->Tm,    &c->vec, &c->eloc_tmp, &c->logpsi_tmp};
+  for (DevBuf* b : bufs) b->release();
+  delete c;
+}
+
+size_t peps_num_params(const peps_ctx* c) { return c ? (size_t)c->L.n_params : 0; }
+
+size_t peps_env_cache_bytes(const peps_ctx* c, int n) {
+  if (!c || n < 0) return 0;
+  return (size_t)n * env_tensor_elems_per_sample(c->L) * c->tsize +
+         (size_t)n * c->L.n_slots * sizeof(double);
+}
+
+peps_status peps_set_hamiltonian(peps_ctx* c, int n_terms, const int* term_nsites,
+                                 const int* term_sites, const double* term_mats, int n_pairs,
+                                 const int* pair_ij, const double* pair_v, const double* onsite) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (n_terms < 0 || n_pairs < 0) return fail(PEPS_ERR_ARG, "negative term or pair count");
+  if (n_terms > 0 && (!term_nsites || !term_sites || !term_mats))
+    return fail(PEPS_ERR_ARG, "null term arrays");
+  if (n_pairs > 0 && (!pair_ij || !pair_v)) return fail(PEPS_ERR_ARG, "null pair arrays");
+  const Lattice& L = c->L;
+  const int Ly = L.Ly, N = L.N;
+  struct Move {
+    int x, two, y0, y1, ns, site[3];
+    std::vector<int> contrib;  // (term, mask) pairs
+  };
+  std::map<std::vector<int>, int> index;
+  std::vector<Move> moves;
+  for (int t = 0; t < n_terms; ++t) {
+    const int k = term_nsites[t];
+    if (k < 1 || k > 3) return fail(PEPS_ERR_ARG, "term %d acts on %d sites (1..3)", t, k);
+    for (int j = 0; j < k; ++j) {
+      const int sj = term_sites[3 * t + j];
+      if (sj < 0 || sj >= N) return fail(PEPS_ERR_ARG, "term %d site %d out of range", t, sj);
+      for (int i = 0; i < j; ++i)
+        if (term_sites[3 * t + i] == sj) return fail(PEPS_ERR_ARG, "term %d repeats site %d", t, sj);
+    }
+    const double* h = term_mats + (size_t)t * 128;
+    const int dim = 1 << k;
+    for (int i = 0; i < 128; ++i)
+      if (!std::isfinite(h[i])) return fail(PEPS_ERR_NONFINITE, "term %d matrix not finite", t);
+    for (int mask = 1; mask < dim; ++mask) {
+      bool nz = false;
+      for (int cc = 0; cc < dim && !nz; ++cc) {
+        const int c2 = cc ^ mask;
+        nz = h[(cc * 8 + c2) * 2] != 0.0 || h[(cc * 8 + c2) * 2 + 1] != 0.0;
+      }
+      if (!nz) continue;
+      std::vector<int> sites;
+      for (int j = 0; j < k; ++j)
+        if ((mask >> (k - 1 - j)) & 1) sites.push_back(term_sites[3 * t + j]);
+      std::sort(sites.begin(), sites.end());
+      auto it = index.find(sites);
+      int id;
+      if (it == index.end()) {
+        Move m;
+        int xmin = 1 << 30, xmax = -1, ymin = 1 << 30, ymax = -1;
+        for (int sidx : sites) {
+          xmin = std::min(xmin, sidx / Ly);
+          xmax = std::max(xmax, sidx / Ly);
+          ymin = std::min(ymin, sidx % Ly);
+          ymax = std::max(ymax, sidx % Ly);
+        }
+        if (xmax - xmin > 1)
+          return fail(PEPS_ERR_UNSUPPORTED,
+                      "term %d changes sites on rows %d..%d (at most two adjacent rows)", t, xmin,
+                      xmax);
+        m.x = xmin;
+        m.two = xmax > xmin;
+        if (m.two && xmin >= L.Lx - 1) return fail(PEPS_ERR_ARG, "bad row pair");
+        m.y0 = ymin;
+        m.y1 = ymax;
+        m.ns = (int)sites.size();
+        for (int j = 0; j < 3; ++j) m.site[j] = j < m.ns ? sites[j] : -1;
+        id = (int)moves.size();
+        moves.push_back(m);
+        index[sites] = id;
+      } else {
+        id = it->second;
+      }
+      moves[id].contrib.push_back(t);
+      moves[id].contrib.push_back(mask);
+    }
+  }
+  // group by strip, sort by first column
+  const int n_strips = L.Lx + (L.Lx - 1);
+  std::vector<std::vector<int>> by(n_strips);
+  for (int i = 0; i < (int)moves.size(); ++i)
+    by[moves[i].two ? L.Lx + moves[i].x : moves[i].x].push_back(i);
+  std::vector<int> mstart(n_strips + 1, 0), mv, contrib;
+  for (int s = 0; s < n_strips; ++s) {
+    std::stable_sort(by[s].begin(), by[s].end(),
+                     [&](int a, int b) { return moves[a].y0 < moves[b].y0; });
+    mstart[s] = (int)(mv.size() / 8);
+    for (int i : by[s]) {
+      const Move& m = moves[i];
+      mv.push_back(m.y0);
+      mv.push_back(m.y1);
+      mv.push_back(m.ns);
+      for (int j = 0; j < 3; ++j) mv.push_back(m.site[j]);
+      mv.push_back((int)(contrib.size() / 2));
+      mv.push_back((int)(m.contrib.size() / 2));
+      contrib.insert(contrib.end(), m.contrib.begin(), m.contrib.end());
+    }
+  }
+  mstart[n_strips] = (int)(mv.size() / 8);
+  std::vector<int> terms(4 * (size_t)n_terms, -1);
+  for (int t = 0; t < n_terms; ++t) {
+    terms[4 * t] = term_nsites[t];
+    for (int j = 0; j < term_nsites[t]; ++j) terms[4 * t + 1 + j] = term_sites[3 * t + j];
+  }
+  std::vector<int> pairs(2 * (size_t)n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int i = pair_ij[2 * p], j = pair_ij[2 * p + 1];
+    if (i < 0 || j < 0 || i >= N || j >= N) return fail(PEPS_ERR_ARG, "pair %d out of range", p);
+    if (!std::isfinite(pair_v[p])) return fail(PEPS_ERR_NONFINITE, "pair %d value not finite", p);
+    pairs[2 * p] = i;
+    pairs[2 * p + 1] = j;
+  }
+  // upload: ints = mstart | moves | contrib | terms | pairs; doubles = mats | pair_v | onsite
+  std::vector<int> ints;
+  const size_t o_ms = 0;
+  ints.insert(ints.end(), mstart.begin(), mstart.end());
+  const size_t o_mv = ints.size();
+  ints.insert(ints.end(), mv.begin(), mv.end());
+  const size_t o_ct = ints.size();
+  ints.insert(ints.end(), contrib.begin(), contrib.end());
+  const size_t o_tm = ints.size();
+  ints.insert(ints.end(), terms.begin(), terms.end());
+  const size_t o_pr = ints.size();
+  ints.insert(ints.end(), pairs.begin(), pairs.end());
+  ints.push_back(0);
+  std::vector<double> dbl;
+  dbl.insert(dbl.end(), term_mats, term_mats + (size_t)n_terms * 128);
+  const size_t o_pv = dbl.size();
+  dbl.insert(dbl.end(), pair_v, pair_v + n_pairs);
+  const size_t o_on = dbl.size();
+  if (onsite) {
+    for (int i = 0; i < 2 * N; ++i)
+      if (!std::isfinite(onsite[i])) return fail(PEPS_ERR_NONFINITE, "onsite not finite");
+    dbl.insert(dbl.end(), onsite, onsite + 2 * N);
+  }
+  dbl.push_back(0.0);
+  if (c->d_hint) hipFree(c->d_hint);
+  if (c->d_hdbl) hipFree(c->d_hdbl);
+  c->d_hint = nullptr;
+  c->d_hdbl = nullptr;
+  HIPCHK(hipMalloc(&c->d_hint, ints.size() * sizeof(int)));
+  HIPCHK(hipMalloc(&c->d_hdbl, dbl.size() * sizeof(double)));
+  HIPCHK(hipMemcpy(c->d_hint, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_hdbl, dbl.data(), dbl.size() * sizeof(double), hipMemcpyHostToDevice));
+  HamDev& H = c->H;
+  H.n_strips = n_strips;
+  H.n_terms = n_terms;
+  H.n_pairs = n_pairs;
+  H.mstart = c->d_hint + o_ms;
+  H.moves = c->d_hint + o_mv;
+  H.contrib = c->d_hint + o_ct;
+  H.terms = c->d_hint + o_tm;
+  H.pair_ij = c->d_hint + o_pr;
+  H.mats = c->d_hdbl;
+  H.pair_v = c->d_hdbl + o_pv;
+  H.onsite = onsite ? c->d_hdbl + o_on : nullptr;
+  c->has_ham = true;
+  return PEPS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// internal drivers
+// ---------------------------------------------------------------------------
+static peps_status prepare_theta(peps_ctx* c, const double* theta, hipStream_t st) {
+  const int np = c->L.n_params;
+  peps_status s = c->theta_c.ensure((size_t)np * c->tsize);
+  if (s != PEPS_OK) return s;
+  s = c->bad.ensure(64);
+  if (s != PEPS_OK) return s;
+  HIPCHK(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
+  HIPCHK(launch_convert_theta(c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, theta, c->theta_c.p,
+                              np, (int*)c->bad.p, st));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(PEPS_ERR_NONFINITE, "theta contains non-finite values");
+  return PEPS_OK;
+}
+
+static size_t per_sample_scratch(const peps_ctx* c) {
+  const Lattice& L = c->L;
+  const size_t BD = (size_t)L.bmax * L.D;
+  const size_t box = L.site_box;
+  const size_t box2 = (size_t)L.bmax * L.bmax * L.D * L.D;
+  size_t r = 2 * (size_t)L.Ly * BD * BD;
+  size_t s1 = (size_t)L.Lx * (L.Ly + 1) * box;
+  size_t s2 = (size_t)(L.Lx - 1) * (L.Ly + 1) * box2;
+  return (r + s1 + s2) * c->tsize;
+}
+
+static int chunk_size(const peps_ctx* c, int n) {
+  const size_t per = per_sample_scratch(c);
+  size_t ch = c->chunk_budget / (per ? per : 1);
+  if (ch < 64) ch = 64;
+  return (int)std::min<size_t>(ch, (size_t)n);
+}
+
+template <int M>
+static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int n, char* env_t,
+                            double* env_l, int* flags, hipStream_t st) {
+  const Lattice& L = c->L;
+  const int ch = chunk_size(c, n);
+  const size_t BD = (size_t)L.bmax * L.D;
+  peps_status s = c->rscr.ensure((size_t)ch * 2 * L.Ly * BD * BD * c->tsize);
+  if (s != PEPS_OK) return s;
+  const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
+  for (int c0 = 0; c0 < n; c0 += ch) {
+    const int m = std::min(ch, n - c0);
+    HIPCHK(launch_env_sweep<M>(L, c->d_tab, c->theta_c.p, samples + (size_t)c0 * L.N,
+                               env_t + (size_t)c0 * per_t, env_l + (size_t)c0 * L.n_slots,
+                               c->rscr.p, flags ? flags + c0 : nullptr, m, c->jac_sweeps, st));
+  }
+  return PEPS_OK;
+}
+
+template <int M>
+static peps_status run_strips(peps_ctx* c, const uint8_t* samples, int n, const char* env_t,
+                              double* eloc, void* O, int* flags, hipStream_t st) {
+  const Lattice& L = c->L;
+  const int ch = chunk_size(c, n);
+  const size_t box = L.site_box;
+  const size_t box2 = (size_t)L.bmax * L.bmax * L.D * L.D;
+  const int nparts = 1 + L.Lx + (L.Lx - 1);
+  const bool want_e = eloc != nullptr;
+  const bool want_o = O != nullptr;
+  peps_status s = c->rt1.ensure((size_t)ch * L.Lx * (L.Ly + 1) * box * c->tsize);
+  if (s != PEPS_OK) return s;
+  if (want_e) {
+    s = c->rt2.ensure((size_t)ch * (L.Lx - 1) * (L.Ly + 1) * box2 * c->tsize);
+    if (s != PEPS_OK) return s;
+    s = c->epart.ensure((size_t)ch * nparts * 2 * sizeof(double));
+    if (s != PEPS_OK) return s;
+  }
+  HamDev H = c->H;
+  if (!c->has_ham) {
+    H = HamDev{};
+  }
+  const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
+  const size_t ob = (c->g.dtype == PEPS_F64 ? 8 : 4);
+  for (int c0 = 0; c0 < n; c0 += ch) {
+    const int m = std::min(ch, n - c0);
+    const uint8_t* sm = samples + (size_t)c0 * L.N;
+    const char* et = env_t + (size_t)c0 * per_t;
+    char* Oc = want_o ? (char*)O + (size_t)c0 * L.n_compact * ob : nullptr;
+    if (want_e) HIPCHK(hipMemsetAsync(c->epart.p, 0, (size_t)m * nparts * 2 * sizeof(double), st));
+    HIPCHK(launch_strip1<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt1.p, (double*)c->epart.p,
+                            Oc, flags ? flags + c0 : nullptr, m, want_e, want_o, st));
+    if (want_e) {
+      if (H.n_strips)
+        HIPCHK(launch_strip2<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt2.p,
+                                (double*)c->epart.p, flags ? flags + c0 : nullptr, m, st));
+      HIPCHK(launch_energy_diag_sum(L, H, sm, (const double*)c->epart.p, nparts,
+                                    eloc + (size_t)c0 * 2, m, st));
+    }
+  }
+  return PEPS_OK;
+}
+
+static peps_status check_common(peps_ctx* c, const double* theta, const uint8_t* samples, int n) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (!theta) return fail(PEPS_ERR_ARG, "null theta");
+  if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
+  if (n > 0 && !samples) return fail(PEPS_ERR_ARG, "null samples");
+  return PEPS_OK;
+}
+
+template <int M>
+static peps_status evaluate_impl(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
+                                 void* env_cache, bool env_given, double* logpsi, double* eloc,
+                                 void* O, int* flags, hipStream_t st) {
+  const Lattice& L = c->L;
+  char* env_t;
+  double* env_l;
+  const size_t tbytes = (size_t)n * env_tensor_elems_per_sample(L) * c->tsize;
+  if (env_cache) {
+    env_t = (char*)env_cache;
+    env_l = (double*)((char*)env_cache + tbytes);
+  } else {
+    peps_status s = c->env_int.ensure(peps_env_cache_bytes(c, n));
+    if (s != PEPS_OK) return s;
+    env_t = (char*)c->env_int.p;
+    env_l = (double*)((char*)c->env_int.p + tbytes);
+  }
+  if (flags) HIPCHK(hipMemsetAsync(flags, 0, (size_t)n * sizeof(int32_t), st));
+  if (!env_given) {
+    peps_status s = run_envs<M>(c, samples, n, env_t, env_l, flags, st);
+    if (s != PEPS_OK) return s;
+  }
+  if (logpsi) HIPCHK(launch_overlap<M>(L, c->d_tab, env_t, env_l, c->icut, logpsi, flags, n, st));
+  if (eloc || O) {
+    if (eloc && !c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
+    peps_status s = run_strips<M>(c, samples, n, env_t, eloc, O, flags, st);
+    if (s != PEPS_OK) return s;
+  }
+  return PEPS_OK;
+}
+
+static peps_status dispatch(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
+                            void* env_cache, bool env_given, double* logpsi, double* eloc, void* O,
+                            int* flags, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) return PEPS_OK;
+  peps_status s = prepare_theta(c, theta, st);
+  if (s != PEPS_OK) return s;
+  switch (c->g.dtype) {
+    case PEPS_F64:
+      return evaluate_impl<MODE_F64>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                     flags, st);
+    case PEPS_F32:
+      return evaluate_impl<MODE_F32>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                     flags, st);
+    default:
+      return evaluate_impl<MODE_BF16>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                      flags, st);
+  }
+}
+
+extern "C" {
+
+peps_status peps_amplitude(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
+                           void* env_cache, double* logpsi, int32_t* flags, void* stream) {
+  peps_status s = check_common(c, theta, samples, n);
+  if (s != PEPS_OK) return s;
+  if (n > 0 && !logpsi && !env_cache) return fail(PEPS_ERR_ARG, "no output requested");
+  return dispatch(c, theta, samples, n, env_cache, false, logpsi, nullptr, nullptr, flags, stream);
+}
+
+peps_status peps_local_energy(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
+                              const void* env_cache, double* eloc, int32_t* flags, void* stream) {
+  peps_status s = check_common(c, theta, samples, n);
+  if (s != PEPS_OK) return s;
+  if (n > 0 && !eloc) return fail(PEPS_ERR_ARG, "null eloc");
+  if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
+  return dispatch(c, theta, samples, n, (void*)env_cache, env_cache != nullptr, nullptr, eloc,
+                  nullptr, flags, stream);
+}
+
+peps_status peps_logderiv(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
+                          const void* env_cache, void* O, void* stream) {
+  peps_status s = check_common(c, theta, samples, n);
+  if (s != PEPS_OK) return s;
+  if (n > 0 && !O) return fail(PEPS_ERR_ARG, "null O");
+  return dispatch(c, theta, samples, n, (void*)env_cache, env_cache != nullptr, nullptr, nullptr,
+                  O, nullptr, stream);
+}
+
+peps_status peps_evaluate(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
+                          double* logpsi, double* eloc, void* O, int32_t* flags, void* stream) {
+  peps_status s = check_common(c, theta, samples, n);
+  if (s != PEPS_OK) return s;
+  if (eloc && !c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
+  return dispatch(c, theta, samples, n, nullptr, false, logpsi, eloc, O, flags, stream);
+}
+
+peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n,
+                       const double* eloc, double eps, double rcond, double* dtheta, double* diag,
+                       void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (n < 2) return fail(PEPS_ERR_ARG, "minSR needs at least 2 samples (got %d)", n);
+  if (!O || !samples || !eloc || !dtheta || !diag) return fail(PEPS_ERR_ARG, "null pointer");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(PEPS_ERR_ARG, "eps must be finite and >= 0");
+  if (!(rcond >= 0.0 && rcond < 1.0)) return fail(PEPS_ERR_ARG, "rcond must be in [0, 1)");
+  if ((size_t)n * n > ((size_t)1 << 33)) return fail(PEPS_ERR_UNSUPPORTED, "n = %d too large", n);
+  hipStream_t st = (hipStream_t)stream;
+  const Lattice& L = c->L;
+  peps_status s = c->mean.ensure((size_t)L.n_params * sizeof(double));
+  if (s != PEPS_OK) return s;
+  s = c->Tm.ensure((size_t)n * n * sizeof(double));
+  if (s != PEPS_OK) return s;
+  s = c->vec.ensure(((size_t)2 * n + 1 + 16 + 2) * sizeof(double));
+  if (s != PEPS_OK) return s;
+  // reject non-finite E before any work
+  {
+    std::vector<double> h(2 * (size_t)n);
+    HIPCHK(hipMemcpyAsync(h.data(), eloc, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (double v : h)
+      if (!std::isfinite(v)) return fail(PEPS_ERR_NONFINITE, "eloc contains non-finite values");
+  }
+  HIPCHK(launch_minsr(L, c->d_tab, c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, O, samples, n,
+                      eloc, eps, rcond, dtheta, diag, (double*)c->mean.p, (double*)c->Tm.p,
+                      (double*)c->vec.p, st));
+  return PEPS_OK;
+}
+
+peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains, int per_chain,
+                        int burn_in, int thin, uint64_t seed, uint64_t offset, uint8_t* samples,
+                        int32_t* accepted, void* stream) {
+  (void)c; (void)theta; (void)kind; (void)n_chains; (void)per_chain; (void)burn_in; (void)thin;
+  (void)seed; (void)offset; (void)samples; (void)accepted; (void)stream;
+  return fail(PEPS_ERR_UNSUPPORTED, "peps_sample is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Host-side launchers of the device kernels (one translation unit each).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace pm {
+
+// Hamiltonian tables on the device (built by the host term compiler).
+//   mstart[n_strips+1] : CSR of the moves of each strip (one-row strips
+//                        x = 0..Lx-1, then two-row strips x = 0..Lx-2), moves
+//                        of a strip sorted by their first column
+//   moves[8*m]          : y0, y1, nsites, site0, site1, site2, cstart, ccount
+//   contrib[2*c]        : term, flip mask (bit j = j-th site of the term, MSB first)
+//   terms[4*t]          : nsites, site0, site1, site2
+//   mats[t][64][2]      : <c|h_t|c'> as (re, im)
+struct HamDev {
+  int n_strips;
+  int n_terms;
+  int n_pairs;
+  const int* mstart;
+  const int* moves;
+  const int* contrib;
+  const int* terms;
+  const double* mats;
+  const int* pair_ij;
+  const double* pair_v;
+  const double* onsite;  // [N][2] or null
+};
+
+size_t env_lds_elems(int bmax, int D);
+size_t strip1_lds_elems(int bmax, int D);
+size_t strip2_lds_elems(int bmax, int D);
+
+template <int M>
+hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
+                            const uint8_t* samples, void* env, double* logs, void* rscr,
+                            int* flags, int n, int jac_sweeps, hipStream_t st);
+template <int M>
+hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, const double* logs,
+                          int icut, double* logpsi, int* flags, int n, hipStream_t st);
+hipError_t launch_convert_theta(int mode, const double* src, void* dst, int n, int* bad,
+                                hipStream_t st);
+
+template <int M>
+hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
+                         const uint8_t* samples, const void* env, const HamDev& H, void* rt,
+                         double* epart, void* O, int* flags, int n, bool want_e, bool want_o,
+                         hipStream_t st);
+template <int M>
+hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
+                         const uint8_t* samples, const void* env, const HamDev& H, void* rt,
+                         double* epart, int* flags, int n, hipStream_t st);
+hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8_t* samples,
+                                  const double* epart, int nparts, double* eloc, int n,
+                                  hipStream_t st);
+
+// minSR
+hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
+                        const uint8_t* samples, int n, const double* eloc, double eps,
+                        double rcond, double* dtheta, double* diag, double* ws_mean,
+                        double* ws_T, double* ws_vec, hipStream_t st);
+
+}  // namespace pm

@@ -1,0 +1,613 @@
+// Strips between cached environments (Sec. "On reusing environments"):
+// local energies from amplitude ratios inside one-row and two-row strips,
+// and log-derivatives from the one-row hole networks (Sec. "Finite PEPS and
+// Sampling", Eq. tdvp).
+//
+// One workgroup owns one (sample, strip). It first builds every right
+// partial contraction of the strip (kept in global scratch, read back once),
+// then walks the strip left to right carrying the left partial in LDS. At
+// each column it evaluates the hole tensor (one-row strips: O for that site),
+// the amplitude ratio of every move whose window starts there, and extends
+// the left partial. Ratios are numerator / denominator of the same strip
+// (Sec. "On Numerical Stability" notes ratios are what matters).
+#include "common.h"
+#include "kernels.h"
+
+namespace pm {
+
+struct EnvRef {
+  const void* p;
+  int a, k, b;  // dims; p == nullptr means the trivial bond-1 environment
+};
+
+template <typename T>
+__device__ __forceinline__ const T* env_site(const T* envs, const Lattice& L, int slot, int y) {
+  return envs + ((size_t)slot * L.Ly + y) * L.site_box;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* tensor_of(const T* theta, const int* tab, const Lattice& L,
+                                             int n, int p) {
+  return theta + tab[L.off_param + n] + p * tab[L.off_block + n];
+}
+
+__device__ __forceinline__ void legs_of(const int* tab, const Lattice& L, int n, int& Dl, int& Dr,
+                                        int& Du, int& Dd) {
+  const int* lg = tab + L.off_legs + 4 * n;
+  Dl = lg[0];
+  Dr = lg[1];
+  Du = lg[2];
+  Dd = lg[3];
+}
+
+// ---------------------------------------------------------------------------
+// One-row strip helpers. Up env U_y[a,u,b], down env B_y[c,d,e],
+// site A[m,r,u,d], left partial L[a,m,c], right partial R[b,r,e].
+// ---------------------------------------------------------------------------
+template <int M, typename T>
+__device__ void s1_step_left(const T* Lp, const T* U, int ua, int ub, const T* A, int Dl, int Dr,
+                             int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout) {
+  // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
+  gemm<M>(Dl * ba, Du * ub, ua, Lp, 1, Dl * ba, U, Du * ub, 1, X1, Du * ub, 1, false);
+  __syncthreads();
+  // X2[b,r,c,d] = sum_{m,u} X1[m,c,u,b] A[m,r,u,d]
+  const int tot = ub * Dr * ba * Dd;
+  for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+    int t = i;
+    const int d = t % Dd; t /= Dd;
+    const int c = t % ba; t /= ba;
+    const int r = t % Dr; t /= Dr;
+    const int b = t;
+    T acc = 0;
+    for (int m = 0; m < Dl; ++m)
+      for (int u = 0; u < Du; ++u)
+        acc += opnd<M>(X1[((m * ba + c) * Du + u) * ub + b]) *
+               opnd<M>(A[((m * Dr + r) * Du + u) * Dd + d]);
+    X2[i] = acc;
+  }
+  __syncthreads();
+  // L'[(b,r), e] = sum_{(c,d)} X2[(b,r),(c,d)] B[(c,d), e]
+  gemm<M>(ub * Dr, bb, ba * Dd, X2, ba * Dd, 1, Bt, bb, 1, Lout, bb, 1, false);
+  __syncthreads();
+}
+
+template <int M, typename T>
+__device__ void s1_step_right(const T* Rp, const T* U, int ua, int ub, const T* A, int Dl, int Dr,
+                              int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2, T* Rout) {
+  // X1[(a,u),(r,e)] = sum_b U[(a,u),b] R[b,(r,e)]
+  gemm<M>(ua * Du, Dr * bb, ub, U, ub, 1, Rp, Dr * bb, 1, X1, Dr * bb, 1, false);
+  __syncthreads();
+  // X2[(a,m),(d,e)] = sum_{u,r} X1[a,u,r,e] A[m,r,u,d]
+  const int tot = ua * Dl * Dd * bb;
+  for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+    int t = i;
+    const int e = t % bb; t /= bb;
+    const int d = t % Dd; t /= Dd;
+    const int m = t % Dl; t /= Dl;
+    const int a = t;
+    T acc = 0;
+    for (int u = 0; u < Du; ++u)
+      for (int r = 0; r < Dr; ++r)
+        acc += opnd<M>(X1[((a * Du + u) * Dr + r) * bb + e]) *
+               opnd<M>(A[((m * Dr + r) * Du + u) * Dd + d]);
+    X2[i] = acc;
+  }
+  __syncthreads();
+  // R'[(a,m), c] = sum_{(d,e)} X2[(a,m),(d,e)] B[c,(d,e)]
+  gemm<M>(ua * Dl, ba, Dd * bb, X2, Dd * bb, 1, Bt, 1, Dd * bb, Rout, ba, 1, false);
+  __syncthreads();
+}
+
+template <typename T>
+__device__ T lds_dot(const T* a, const T* b, int cnt, T* red) {
+  T s = 0;
+  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) s += a[i] * b[i];
+  return block_sum(s, red);
+}
+
+// Sum of <S|h_t|S'> over the contributions of a move: the coefficient of
+// the move's amplitude ratio in E_loc(S).
+__device__ void move_coef(const HamDev& H, const int* mv, const uint8_t* s, double& cre,
+                          double& cim) {
+  cre = 0.0;
+  cim = 0.0;
+  const int cs = mv[6], cc = mv[7];
+  for (int q = 0; q < cc; ++q) {
+    const int t = H.contrib[2 * (cs + q)], mask = H.contrib[2 * (cs + q) + 1];
+    const int* tt = H.terms + 4 * t;
+    const int k = tt[0];
+    int c = 0;
+    for (int j = 0; j < k; ++j) c = 2 * c + pbit(s[tt[1 + j]]);
+    const int c2 = c ^ mask;
+    const double* h = H.mats + ((size_t)t * 64 + c * 8 + c2) * 2;
+    cre += h[0];
+    cim += h[1];
+  }
+}
+
+__device__ __forceinline__ bool in_move(const int* mv, int n) {
+  const int ns = mv[2];
+  for (int j = 0; j < ns; ++j)
+    if (mv[3 + j] == n) return true;
+  return false;
+}
+
+size_t strip1_lds_elems(int bmax, int D) {
+  const size_t BD = (size_t)bmax * D;
+  return 3 * (size_t)bmax * D * bmax + 2 * BD * BD + (size_t)D * D * D * D + 16;
+}
+
+template <int M>
+__global__ void __launch_bounds__(PEPS_BLOCK)
+k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
+         const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
+         HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
+         typename ModeT<M>::T* __restrict__ Oout, int* __restrict__ flags, int n, int want_e,
+         int want_o) {
+  typedef typename ModeT<M>::T T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int smp = blockIdx.x, x = blockIdx.y;
+  if (smp >= n) return;
+  const int tid = threadIdx.x;
+  const int B = L.bmax, D = L.D, BD = B * D;
+  const int box = B * D * B;
+  T* Lf = sm;
+  T* Lt = Lf + box;
+  T* Lt2 = Lt + box;
+  T* X1 = Lt2 + box;
+  T* X2 = X1 + BD * BD;
+  T* Env = X2 + BD * BD;
+  T* red = Env + D * D * D * D;
+  __shared__ T one[1];
+  __shared__ int fl;
+  if (tid == 0) {
+    one[0] = T(1);
+    fl = 0;
+  }
+  const uint8_t* s = samples + (size_t)smp * L.N;
+  const size_t slot_elems = (size_t)L.Ly * L.site_box;
+  const T* envs = env + (size_t)smp * L.n_slots * slot_elems;
+  T* Rt = rtscr + ((size_t)smp * L.Lx + x) * (size_t)(L.Ly + 1) * box;
+  const int* ed = tab + L.off_env;
+  const bool has_up = x > 0, has_dn = x < L.Lx - 1;
+  const int su = has_up ? slot_top(L, x - 1) : -1;
+  const int sd = has_dn ? slot_bottom(L, x + 1) : -1;
+  __syncthreads();
+
+  auto upT = [&](int y) -> const T* { return has_up ? env_site(envs, L, su, y) : one; };
+  auto dnT = [&](int y) -> const T* { return has_dn ? env_site(envs, L, sd, y) : one; };
+  auto ua_ = [&](int y) { return has_up ? ed[(su * L.Ly + y) * 3 + 0] : 1; };
+  auto ub_ = [&](int y) { return has_up ? ed[(su * L.Ly + y) * 3 + 2] : 1; };
+  auto ba_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 0] : 1; };
+  auto bb_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 2] : 1; };
+
+  // right partials Rt[y] (y = Ly .. 0), Rt[y] has dims (ua(y), Dl(y), ba(y))
+  T* RtL = Rt + (size_t)L.Ly * box;
+  if (tid == 0) RtL[0] = T(1);
+  __syncthreads();
+  for (int y = L.Ly - 1; y >= 0; --y) {
+    const int ns = x * L.Ly + y;
+    int Dl, Dr, Du, Dd;
+    legs_of(tab, L, ns, Dl, Dr, Du, Dd);
+    const T* A = tensor_of(theta, tab, L, ns, pbit(s[ns]));
+    s1_step_right<M>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
+                     dnT(y), ba_(y), bb_(y), X1, X2, Rt + (size_t)y * box);
+  }
+  const T psi_row = Rt[0];
+  if (tid == 0 && (psi_row == T(0) || !isfinite((double)psi_row))) fl |= (psi_row == T(0)) ? 1 : 2;
+
+  // moves of this strip
+  const int m0 = H.n_strips ? H.mstart[x] : 0;
+  const int m1 = H.n_strips ? H.mstart[x + 1] : 0;
+  int mi = m0;
+  double ere = 0.0, eim = 0.0;
+
+  if (tid == 0) Lf[0] = T(1);
+  __syncthreads();
+  for (int y = 0; y < L.Ly; ++y) {
+    const int ns = x * L.Ly + y;
+    int Dl, Dr, Du, Dd;
+    legs_of(tab, L, ns, Dl, Dr, Du, Dd);
+    const int ua = ua_(y), ub = ub_(y), ba = ba_(y), bb = bb_(y);
+    const T* U = upT(y);
+    const T* Bt = dnT(y);
+    const T* A = tensor_of(theta, tab, L, ns, pbit(s[ns]));
+    const T* Rn = Rt + (size_t)(y + 1) * box;
+    const int nA = Dl * Dr * Du * Dd;
+    if (want_o) {
+      // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
+      gemm<M>(Dl * ba, Du * ub, ua, Lf, 1, Dl * ba, U, Du * ub, 1, X1, Du * ub, 1, false);
+      // Q[(b,r),(c,d)] = sum_e R[(b,r),e] B[(c,d),e]
+      gemm<M>(ub * Dr, ba * Dd, bb, Rn, bb, 1, Bt, 1, bb, X2, ba * Dd, 1, false);
+      __syncthreads();
+      // Env[m,r,u,d] = sum_{c,b} X1[m,c,u,b] Q[b,r,c,d]
+      for (int i = tid; i < nA; i += PEPS_BLOCK) {
+        int t = i;
+        const int d = t % Dd; t /= Dd;
+        const int u = t % Du; t /= Du;
+        const int r = t % Dr; t /= Dr;
+        const int m = t;
+        T acc = 0;
+        for (int c = 0; c < ba; ++c)
+          for (int b = 0; b < ub; ++b)
+            acc += opnd<M>(X1[((m * ba + c) * Du + u) * ub + b]) *
+                   opnd<M>(X2[((b * Dr + r) * ba + c) * Dd + d]);
+        Env[i] = acc;
+      }
+      __syncthreads();
+      const T psi_loc = lds_dot(Env, A, nA, red);
+      T* o = Oout + (size_t)smp * L.n_compact + tab[L.off_compact + ns];
+      const T inv = T(1) / psi_loc;
+      for (int i = tid; i < nA; i += PEPS_BLOCK) o[i] = Env[i] * inv;
+    }
+    if (want_e) {
+      while (mi < m1 && H.moves[8 * mi] == y) {
+        const int* mv = H.moves + 8 * mi;
+        double cre, cim;
+        move_coef(H, mv, s, cre, cim);
+        if (cre != 0.0 || cim != 0.0) {
+          const int y1 = mv[1];
+          // L_tmp = Lf, then step through the window with the moved tensors
+          const T* cur = Lf;
+          T* nxt = Lt;
+          for (int yy = y; yy <= y1; ++yy) {
+            const int n2 = x * L.Ly + yy;
+            int dl, dr, du, dd;
+            legs_of(tab, L, n2, dl, dr, du, dd);
+            const int p = in_move(mv, n2) ? 1 - pbit(s[n2]) : pbit(s[n2]);
+            s1_step_left<M>(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p), dl,
+                            dr, du, dd, dnT(yy), ba_(yy), bb_(yy), X1, X2, nxt);
+            cur = nxt;
+            nxt = (nxt == Lt) ? Lt2 : Lt;
+          }
+          const int cnt = ub_(y1) * tab[L.off_legs + 4 * (x * L.Ly + y1) + 1] * bb_(y1);
+          const T num = lds_dot(cur, (const T*)(Rt + (size_t)(y1 + 1) * box), cnt, red);
+          const double ratio = (double)num / (double)psi_row;
+          ere += cre * ratio;
+          eim += cim * ratio;
+        }
+        ++mi;
+      }
+    }
+    // Lf <- step(Lf, A_y)
+    s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
+    for (int i = tid; i < ub * Dr * bb; i += PEPS_BLOCK) Lf[i] = Lt[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (want_e) {
+      const int nparts = 1 + L.Lx + (L.Lx - 1);
+      epart[((size_t)smp * nparts + 1 + x) * 2] = ere;
+      epart[((size_t)smp * nparts + 1 + x) * 2 + 1] = eim;
+    }
+    if (fl && flags) atomicOr(flags + smp, fl);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-row strip: rows x (A1[m1,r1,u,t]) and x+1 (A2[m2,s,t,d]) between
+// U = E^u[x-1] and B = E^l[x+2]. Left partial L[a,m1,m2,c], right partial
+// R[b,r1,s,e]. Contractions are chunked over the outer environment bond so
+// the intermediates stay O(chi D^3).
+// ---------------------------------------------------------------------------
+template <int M, typename T>
+__device__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
+                             int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2, int Dd2,
+                             const T* Bt, int ba, int bb, T* X1, T* X2, T* X3, T* Lout) {
+  const int inner = Dl1 * Dl2 * ba;
+  for (int b = 0; b < ub; ++b) {
+    // X1[(m1,m2,c), u] = sum_a L[a,(m1,m2,c)] U[a,u,b]
+    gemm<M>(inner, uk, ua, Lp, 1, inner, U + b, uk * ub, ub, X1, uk, 1, false);
+    __syncthreads();
+    // X2[m2,c,r1,t] = sum_{m1,u} X1[m1,m2,c,u] A1[m1,r1,u,t]
+    {
+      const int tot = Dl2 * ba * Dr1 * Dd1;
+      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+        int q = i;
+        const int t = q % Dd1; q /= Dd1;
+        const int r1 = q % Dr1; q /= Dr1;
+        const int c = q % ba; q /= ba;
+        const int m2 = q;
+        T acc = 0;
+        for (int m1 = 0; m1 < Dl1; ++m1)
+          for (int u = 0; u < uk; ++u)
+            acc += opnd<M>(X1[((m1 * Dl2 + m2) * ba + c) * uk + u]) *
+                   opnd<M>(A1[((m1 * Dr1 + r1) * uk + u) * Dd1 + t]);
+        X2[i] = acc;
+      }
+    }
+    __syncthreads();
+    // X3[r1,s,c,d] = sum_{m2,t} X2[m2,c,r1,t] A2[m2,s,t,d]
+    {
+      const int tot = Dr1 * Dr2 * ba * Dd2;
+      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+        int q = i;
+        const int d = q % Dd2; q /= Dd2;
+        const int c = q % ba; q /= ba;
+        const int sidx = q % Dr2; q /= Dr2;
+        const int r1 = q;
+        T acc = 0;
+        for (int m2 = 0; m2 < Dl2; ++m2)
+          for (int t = 0; t < Dd1; ++t)
+            acc += opnd<M>(X2[((m2 * ba + c) * Dr1 + r1) * Dd1 + t]) *
+                   opnd<M>(A2[((m2 * Dr2 + sidx) * Dd1 + t) * Dd2 + d]);
+        X3[i] = acc;
+      }
+    }
+    __syncthreads();
+    // L'[b,(r1,s),e] = sum_{(c,d)} X3[(r1,s),(c,d)] B[(c,d),e]
+    gemm<M>(Dr1 * Dr2, bb, ba * Dd2, X3, ba * Dd2, 1, Bt, bb, 1, Lout + b * (Dr1 * Dr2 * bb), bb,
+            1, false);
+    __syncthreads();
+  }
+}
+
+template <int M, typename T>
+__device__ void s2_step_right(const T* Rp, const T* U, int ua, int uk, int ub, const T* A1,
+                              int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2, int Dd2,
+                              const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Y3, T* Rout) {
+  const int rw = Dr1 * Dr2 * bb;
+  for (int a = 0; a < ua; ++a) {
+    // Y1[u,(r1,s,e)] = sum_b U[a,u,b] R[b,(r1,s,e)]
+    gemm<M>(uk, rw, ub, U + a * uk * ub, ub, 1, Rp, rw, 1, Y1, rw, 1, false);
+    __syncthreads();
+    // Y2[m1,t,s,e] = sum_{u,r1} A1[m1,r1,u,t] Y1[u,r1,s,e]
+    {
+      const int tot = Dl1 * Dd1 * Dr2 * bb;
+      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+        int q = i;
+        const int e = q % bb; q /= bb;
+        const int sidx = q % Dr2; q /= Dr2;
+        const int t = q % Dd1; q /= Dd1;
+        const int m1 = q;
+        T acc = 0;
+        for (int u = 0; u < uk; ++u)
+          for (int r1 = 0; r1 < Dr1; ++r1)
+            acc += opnd<M>(A1[((m1 * Dr1 + r1) * uk + u) * Dd1 + t]) *
+                   opnd<M>(Y1[((u * Dr1 + r1) * Dr2 + sidx) * bb + e]);
+        Y2[i] = acc;
+      }
+    }
+    __syncthreads();
+    // Y3[(m1,m2),(d,e)] = sum_{t,s} A2[m2,s,t,d] Y2[m1,t,s,e]
+    {
+      const int tot = Dl1 * Dl2 * Dd2 * bb;
+      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+        int q = i;
+        const int e = q % bb; q /= bb;
+        const int d = q % Dd2; q /= Dd2;
+        const int m2 = q % Dl2; q /= Dl2;
+        const int m1 = q;
+        T acc = 0;
+        for (int t = 0; t < Dd1; ++t)
+          for (int sidx = 0; sidx < Dr2; ++sidx)
+            acc += opnd<M>(A2[((m2 * Dr2 + sidx) * Dd1 + t) * Dd2 + d]) *
+                   opnd<M>(Y2[((m1 * Dd1 + t) * Dr2 + sidx) * bb + e]);
+        Y3[i] = acc;
+      }
+    }
+    __syncthreads();
+    // R'[a,(m1,m2),c] = sum_{(d,e)} Y3[(m1,m2),(d,e)] B[c,(d,e)]
+    gemm<M>(Dl1 * Dl2, ba, Dd2 * bb, Y3, Dd2 * bb, 1, Bt, 1, Dd2 * bb,
+            Rout + a * (Dl1 * Dl2 * ba), ba, 1, false);
+    __syncthreads();
+  }
+}
+
+size_t strip2_lds_elems(int bmax, int D) {
+  const size_t B2D2 = (size_t)bmax * bmax * D * D;
+  const size_t BD3 = (size_t)bmax * D * D * D;
+  return 3 * B2D2 + 3 * BD3 + 16;
+}
+
+template <int M>
+__global__ void __launch_bounds__(PEPS_BLOCK)
+k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
+         const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
+         HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
+         int* __restrict__ flags, int n) {
+  typedef typename ModeT<M>::T T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int smp = blockIdx.x, x = blockIdx.y;
+  if (smp >= n) return;
+  const int tid = threadIdx.x;
+  const int B = L.bmax, D = L.D;
+  const int box2 = B * B * D * D;
+  const int bd3 = B * D * D * D;
+  T* Lf = sm;
+  T* Lt = Lf + box2;
+  T* Lt2 = Lt + box2;
+  T* X1 = Lt2 + box2;
+  T* X2 = X1 + bd3;
+  T* X3 = X2 + bd3;
+  T* red = X3 + bd3;
+  __shared__ T one[1];
+  __shared__ int fl;
+  if (tid == 0) {
+    one[0] = T(1);
+    fl = 0;
+  }
+  const int strip = L.Lx + x;
+  const int m0 = H.mstart[strip], m1 = H.mstart[strip + 1];
+  const int nparts = 1 + L.Lx + (L.Lx - 1);
+  if (m0 == m1) {
+    if (tid == 0) {
+      epart[((size_t)smp * nparts + strip + 1) * 2] = 0.0;
+      epart[((size_t)smp * nparts + strip + 1) * 2 + 1] = 0.0;
+    }
+    return;
+  }
+  const uint8_t* s = samples + (size_t)smp * L.N;
+  const size_t slot_elems = (size_t)L.Ly * L.site_box;
+  const T* envs = env + (size_t)smp * L.n_slots * slot_elems;
+  T* Rt = rtscr + ((size_t)smp * (L.Lx - 1) + x) * (size_t)(L.Ly + 1) * box2;
+  const int* ed = tab + L.off_env;
+  const bool has_up = x > 0, has_dn = x + 1 < L.Lx - 1;
+  const int su = has_up ? slot_top(L, x - 1) : -1;
+  const int sd = has_dn ? slot_bottom(L, x + 2) : -1;
+  __syncthreads();
+  auto upT = [&](int y) -> const T* { return has_up ? env_site(envs, L, su, y) : one; };
+  auto dnT = [&](int y) -> const T* { return has_dn ? env_site(envs, L, sd, y) : one; };
+  auto ua_ = [&](int y) { return has_up ? ed[(su * L.Ly + y) * 3 + 0] : 1; };
+  auto uk_ = [&](int y) { return has_up ? ed[(su * L.Ly + y) * 3 + 1] : 1; };
+  auto ub_ = [&](int y) { return has_up ? ed[(su * L.Ly + y) * 3 + 2] : 1; };
+  auto ba_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 0] : 1; };
+  auto bb_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 2] : 1; };
+
+  T* RtL = Rt + (size_t)L.Ly * box2;
+  if (tid == 0) RtL[0] = T(1);
+  __syncthreads();
+  for (int y = L.Ly - 1; y >= 0; --y) {
+    const int n1 = x * L.Ly + y, n2 = n1 + L.Ly;
+    int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
+    legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
+    legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
+    s2_step_right<M>(Rt + (size_t)(y + 1) * box2, upT(y), ua_(y), uk_(y), ub_(y),
+                     tensor_of(theta, tab, L, n1, pbit(s[n1])), Dl1, Dr1, Dd1,
+                     tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2, dnT(y), ba_(y),
+                     bb_(y), X1, X2, X3, Rt + (size_t)y * box2);
+  }
+  const T psi2 = Rt[0];
+  if (tid == 0 && (psi2 == T(0) || !isfinite((double)psi2))) fl |= (psi2 == T(0)) ? 1 : 2;
+
+  int mi = m0;
+  double ere = 0.0, eim = 0.0;
+  if (tid == 0) Lf[0] = T(1);
+  __syncthreads();
+  for (int y = 0; y < L.Ly && mi < m1; ++y) {
+    while (mi < m1 && H.moves[8 * mi] == y) {
+      const int* mv = H.moves + 8 * mi;
+      double cre, cim;
+      move_coef(H, mv, s, cre, cim);
+      if (cre != 0.0 || cim != 0.0) {
+        const int y1 = mv[1];
+        const T* cur = Lf;
+        T* nxt = Lt;
+        for (int yy = y; yy <= y1; ++yy) {
+          const int a1 = x * L.Ly + yy, a2 = a1 + L.Ly;
+          int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
+          legs_of(tab, L, a1, Dl1, Dr1, Du1, Dd1);
+          legs_of(tab, L, a2, Dl2, Dr2, Du2, Dd2);
+          const int p1 = in_move(mv, a1) ? 1 - pbit(s[a1]) : pbit(s[a1]);
+          const int p2 = in_move(mv, a2) ? 1 - pbit(s[a2]) : pbit(s[a2]);
+          s2_step_left<M>(cur, upT(yy), ua_(yy), uk_(yy), ub_(yy), tensor_of(theta, tab, L, a1, p1),
+                          Dl1, Dr1, Dd1, tensor_of(theta, tab, L, a2, p2), Dl2, Dr2, Dd2, dnT(yy),
+                          ba_(yy), bb_(yy), X1, X2, X3, nxt);
+          cur = nxt;
+          nxt = (nxt == Lt) ? Lt2 : Lt;
+        }
+        const int a1 = x * L.Ly + y1;
+        const int cnt = ub_(y1) * tab[L.off_legs + 4 * a1 + 1] *
+                        tab[L.off_legs + 4 * (a1 + L.Ly) + 1] * bb_(y1);
+        const T num = lds_dot(cur, (const T*)(Rt + (size_t)(y1 + 1) * box2), cnt, red);
+        const double ratio = (double)num / (double)psi2;
+        ere += cre * ratio;
+        eim += cim * ratio;
+      }
+      ++mi;
+    }
+    if (mi >= m1) break;
+    const int n1 = x * L.Ly + y, n2 = n1 + L.Ly;
+    int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
+    legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
+    legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
+    s2_step_left<M>(Lf, upT(y), ua_(y), uk_(y), ub_(y), tensor_of(theta, tab, L, n1, pbit(s[n1])),
+                    Dl1, Dr1, Dd1, tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2,
+                    dnT(y), ba_(y), bb_(y), X1, X2, X3, Lt);
+    const int cnt = ub_(y) * Dr1 * Dr2 * bb_(y);
+    for (int i = tid; i < cnt; i += PEPS_BLOCK) Lf[i] = Lt[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    epart[((size_t)smp * nparts + strip + 1) * 2] = ere;
+    epart[((size_t)smp * nparts + strip + 1) * 2 + 1] = eim;
+    if (fl && flags) atomicOr(flags + smp, fl);
+  }
+}
+
+// Diagonal part of E_loc plus the sum of the strip parts, one block per sample.
+__global__ void __launch_bounds__(PEPS_BLOCK)
+k_energy_diag_sum(Lattice L, HamDev H, const uint8_t* __restrict__ samples,
+                  const double* __restrict__ epart, int nparts, double* __restrict__ eloc, int n) {
+  __shared__ double red[8];
+  const int smp = blockIdx.x;
+  if (smp >= n) return;
+  const uint8_t* s = samples + (size_t)smp * L.N;
+  double re = 0.0, im = 0.0;
+  for (int t = threadIdx.x; t < H.n_terms; t += PEPS_BLOCK) {
+    const int* tt = H.terms + 4 * t;
+    int c = 0;
+    for (int j = 0; j < tt[0]; ++j) c = 2 * c + pbit(s[tt[1 + j]]);
+    const double* h = H.mats + ((size_t)t * 64 + c * 8 + c) * 2;
+    re += h[0];
+    im += h[1];
+  }
+  for (int p = threadIdx.x; p < H.n_pairs; p += PEPS_BLOCK) {
+    const int i = H.pair_ij[2 * p], j = H.pair_ij[2 * p + 1];
+    if (pbit(s[i]) && pbit(s[j])) re += H.pair_v[p];
+  }
+  if (H.onsite)
+    for (int q = threadIdx.x; q < L.N; q += PEPS_BLOCK) re += H.onsite[2 * q + pbit(s[q])];
+  re = block_sum(re, red);
+  im = block_sum(im, red);
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < nparts; ++k) {
+      re += epart[((size_t)smp * nparts + k) * 2];
+      im += epart[((size_t)smp * nparts + k) * 2 + 1];
+    }
+    eloc[2 * smp] = re;
+    eloc[2 * smp + 1] = im;
+  }
+}
+
+template <int M>
+hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
+                         const uint8_t* samples, const void* env, const HamDev& H, void* rt,
+                         double* epart, void* O, int* flags, int n, bool want_e, bool want_o,
+                         hipStream_t st) {
+  typedef typename ModeT<M>::T T;
+  const size_t lds = strip1_lds_elems(L.bmax, L.D) * sizeof(T);
+  hipFuncSetAttribute((const void*)k_strip1<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL(k_strip1<M>, dim3(n, L.Lx), dim3(PEPS_BLOCK), lds, st, L, tab,
+                     (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O, flags, n,
+                     want_e ? 1 : 0, want_o ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
+                         const uint8_t* samples, const void* env, const HamDev& H, void* rt,
+                         double* epart, int* flags, int n, hipStream_t st) {
+  typedef typename ModeT<M>::T T;
+  const size_t lds = strip2_lds_elems(L.bmax, L.D) * sizeof(T);
+  hipFuncSetAttribute((const void*)k_strip2<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL(k_strip2<M>, dim3(n, L.Lx - 1), dim3(PEPS_BLOCK), lds, st, L, tab,
+                     (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8_t* samples,
+                                  const double* epart, int nparts, double* eloc, int n,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_diag_sum, dim3(n), dim3(PEPS_BLOCK), 0, st, L, H, samples, epart,
+                     nparts, eloc, n);
+  return hipGetLastError();
+}
+
+#define INST(M)                                                                                 \
+  template hipError_t launch_strip1<M>(const Lattice&, const int*, const void*, const uint8_t*, \
+                                       const void*, const HamDev&, void*, double*, void*, int*, \
+                                       int, bool, bool, hipStream_t);                           \
+  template hipError_t launch_strip2<M>(const Lattice&, const int*, const void*, const uint8_t*, \
+                                       const void*, const HamDev&, void*, double*, int*, int,   \
+                                       hipStream_t);
+INST(MODE_F64)
+INST(MODE_F32)
+INST(MODE_BF16)
+#undef INST
+
+}  // namespace pm
