@@ -1,0 +1,276 @@
+"""Throughput of the sampled finite-PEPS hot path on one MI355X.
+
+Workload (8x8 open lattice, d=2, D=4, chi=16, 4096 configurations, J1-J2
+Heisenberg with J2/J1 = 0.5, tensors i.i.d. N(0,1) from a fixed seed): one
+step evaluates ln Psi, the local energies E_loc and the log-derivatives O of
+every configuration of the batch (the samples are drawn once, before the
+timed region, by the library's Metropolis sampler when it is available).
+The timed precision defaults to FP32; the same batch is also evaluated in
+FP64 outside the timed region and the relative error of the batch-mean
+energy is reported.
+
+Prints one JSON line. Extra fields: the FP64 throughput, the minSR step time,
+the per-kernel split from HIP events, the roofline of the dominant kernel
+and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "fp32_vector_tflops": 157.3,
+    "fp64_vector_tflops": 78.6,
+    "hbm_gbs": 8000.0,
+}
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic flop model of the environment build (the canonical two-sweep
+# truncation: left QR sweep, right SVD sweep), per sample and both sweeps.
+#   GEMM m x k x n: 2mnk;  Householder R of m x n (m >= n): 2mn^2 - 2n^3/3;
+#   SVD of an m x n block (m <= n) with its m right singular vectors:
+#   4 m^2 n + 8 m^3 (Golub and Van Loan's count for the R-SVD).
+# ---------------------------------------------------------------------------
+def _legs(Lx, Ly, D, x, y):
+    return (1 if y == 0 else D, 1 if y == Ly - 1 else D, 1 if x == 0 else D,
+            1 if x == Lx - 1 else D)
+
+
+def env_flops_per_sample(Lx, Ly, D, chi):
+    total = 0.0
+    for direction in (0, 1):
+        # bonds of the first row MPS
+        bonds = [_legs(Lx, Ly, D, 0 if direction == 0 else Lx - 1, y)[1] for y in range(Ly)]
+        right = [1] + bonds[:-1]  # left bond of site y
+        left_b = right
+        right_b = bonds
+        for t in range(1, Lx - 1):
+            x = t if direction == 0 else Lx - 1 - t
+            kk = []
+            kp = 1
+            for y in range(Ly - 1):
+                Dl, Dr, Du, Dd = _legs(Lx, Ly, D, x, y)
+                Din, Dout = (Du, Dd) if direction == 0 else (Dd, Du)
+                Pl, Pr = left_b[y] * Dl, right_b[y] * Dr
+                total += Dout * 2.0 * Pl * Pr * Din            # P_k
+                if y > 0:
+                    total += Dout * 2.0 * kp * Pl * Pr          # R P_k
+                m, n = kp * Dout, Pr
+                if m >= n:
+                    total += 2.0 * m * n * n - 2.0 * n ** 3 / 3
+                else:
+                    total += 2.0 * n * m * m - 2.0 * m ** 3 / 3
+                kp = min(m, n)
+                kk.append(kp)
+            nbr = 1
+            new_left = [1] * Ly
+            new_right = [1] * Ly
+            for y in range(Ly - 1, -1, -1):
+                Dl, Dr, Du, Dd = _legs(Lx, Ly, D, x, y)
+                Din, Dout = (Du, Dd) if direction == 0 else (Dd, Du)
+                bl, br = left_b[y], right_b[y]
+                Pl = bl * Dl
+                zc = Dout * nbr
+                total += 2.0 * bl * Din * nbr * br * Dr        # T1
+                total += 2.0 * Pl * zc * Din * Dr              # Z
+                if y > 0:
+                    kpr = kk[y - 1]
+                    total += 2.0 * kpr * Pl * zc               # C = R Z
+                    m = kpr
+                    if m > zc:
+                        total += 2.0 * m * zc * zc - 2.0 * zc ** 3 / 3
+                        m = zc
+                    total += 4.0 * m * m * zc + 8.0 * m ** 3   # SVD
+                    r = min(chi, kpr, zc)
+                    total += 2.0 * Pl * zc * r                 # W
+                else:
+                    r = 1
+                new_left[y] = r
+                new_right[y] = nbr
+                nbr = r
+            left_b, right_b = new_left, new_right
+    return total
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def cpu_baseline(theta, Lx, Ly, D, chi, configs, seconds=12.0):
+    """The FP64 oracle on the host, one process and one BLAS thread, on the
+    first configurations of the batch until about `seconds` have passed."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hamiltonian as OH
+    from oracle import peps
+    g = peps.Geometry(Lx, Ly, 2, D)
+    ham = OH.j1j2(Lx, Ly, 1.0, 0.5)
+    T = peps.site_tensors(theta, g)
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while done < len(configs):
+            sc = peps.SampleContraction(T, g, configs[done], chi)
+            sc.local_energy(ham)
+            sc.logderiv_compact()
+            done += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} configurations of the same batch (psi + E_loc + O, FP64 numpy, "
+                      f"1 BLAS thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sampler", default="auto", choices=["auto", "uniform", "metropolis"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2503_12557_amd import Context, hamiltonians
+    from paper_2503_12557_amd.binding import PepsError
+
+    Lx, Ly, D, chi, n = 8, 8, 4, 16, args.n
+    dev = torch.device("cuda:0")
+    theta_np = synth.theta(Lx, Ly, 2, D, seed=2, mu=0.0)
+    theta = torch.from_numpy(theta_np).to(dev)
+    ham = hamiltonians.j1j2(Lx, Ly, 1.0, 0.5)
+
+    ctx64 = Context(Lx, Ly, D, chi, "f64")
+    ctx64.set_hamiltonian(ham)
+    sampler_used = "uniform S_z=0 permutations (seed 1)"
+    samples = None
+    t_sample = None
+    if args.sampler in ("auto", "metropolis"):
+        try:
+            ctx_s = Context(Lx, Ly, D, chi, "f32")
+            chains = min(n, 1024)
+            per = (n + chains - 1) // chains
+            t0 = time.perf_counter()
+            samples, acc = ctx_s.sample(theta, "exchange", n_chains=chains, per_chain=per,
+                                        burn_in=8, thin=1, seed=1)
+            _sync()
+            t_sample = time.perf_counter() - t0
+            sampler_used = (f"local exchange Metropolis (library sampler, FP32, {chains} chains x "
+                            f"{per}, burn-in 8 sweeps, seed 1)")
+        except PepsError:
+            if args.sampler == "metropolis":
+                raise
+            samples = None
+    if samples is None:
+        samples = torch.from_numpy(synth.sz0_configs(Lx * Ly, n, seed=1)).to(dev)
+    samples = samples[:n].contiguous()
+
+    # FP64 reference pass (untimed) on the same batch
+    lp64, e64, O64, f64 = ctx64.evaluate(theta, samples)
+    _sync()
+    t0 = time.perf_counter()
+    ctx64.evaluate(theta, samples)
+    _sync()
+    t64 = time.perf_counter() - t0
+
+    ctx = ctx64 if args.dtype == "f64" else Context(Lx, Ly, D, chi, args.dtype)
+    if ctx is not ctx64:
+        ctx.set_hamiltonian(ham)
+    out = ctx.evaluate(theta, samples)
+    for _ in range(args.warmup):
+        ctx.evaluate(theta, samples, out=out)
+    _sync()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.evaluate(theta, samples, out=out)
+    _sync()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    lp, el, O, fl = out
+    e_lo = el[:, 0].double().mean().item()
+    e_hi = e64[:, 0].mean().item()
+    rel_e = abs(e_lo - e_hi) / abs(e_hi)
+    flags = int(torch.bitwise_or(fl, f64).max().item())
+
+    # minSR step on the batch (FP64 solve), timed separately
+    ctx.minsr_step(O, samples, el, eps=1e-4, rcond=1e-12)
+    _sync()
+    t0 = time.perf_counter()
+    dth, diag = ctx.minsr_step(O, samples, el, eps=1e-4, rcond=1e-12)
+    _sync()
+    t_minsr = time.perf_counter() - t0
+
+    ms_per_step = dt / args.steps * 1e3
+    value = n / (dt / args.steps)
+    per_kernel = {k: {"ms_total": round(v[0], 3), "launches": v[1],
+                      "ms_avg": round(v[0] / v[1], 4) if v[1] else None}
+                  for k, v in prof.items() if v[1]}
+    # dominant kernel and its roofline
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
+    env_avg_ms = per_kernel["env"]["ms_avg"]
+    env_flops = env_flops_per_sample(Lx, Ly, D, chi) * n
+    peak = PEAK["fp64_vector_tflops"] if args.dtype == "f64" else PEAK["fp32_vector_tflops"]
+    achieved = env_flops / (env_avg_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_env_sweep", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                "traffic": None,
+                "algorithmic_flops_per_launch": env_flops,
+                "avg_launch_ms": env_avg_ms, "dominant_kernel_by_time": dom}
+
+    res = {
+        "metric": "samples/s (psi+E_loc+O)",
+        "value": round(value, 2),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "8x8 open lattice d=2 D=4 chi=16, J1-J2 J2/J1=0.5, "
+                               f"{n} configurations, tensors N(0,1) seed 2",
+                   "samples": sampler_used, "global_batch": n},
+        "energy_rel_err_vs_f64": rel_e,
+        "energy_mean_f64": e_hi,
+        "value_f64": round(n / t64, 2),
+        "minsr_step_ms": round(t_minsr * 1e3, 2),
+        "sampling_s": round(t_sample, 2) if t_sample is not None else None,
+        "minsr_diag": [float(v) for v in diag.cpu().numpy()],
+        "flags_or": flags,
+        "per_kernel": per_kernel,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        k = min(n, 64)
+        res["cpu_baseline"] = cpu_baseline(theta_np, Lx, Ly, D, chi, samples[:k].cpu().numpy())
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

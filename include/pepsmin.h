@@ -188,6 +188,24 @@ peps_status peps_sample(peps_ctx* ctx, const double* theta, int kind, int n_chai
                         uint64_t offset, uint8_t* samples, int32_t* accepted,
                         void* stream);
 
+/* Kernel timing. With profiling enabled every kernel launch of the context
+ * is bracketed by two HIP events on its launch stream. peps_profile_read
+ * waits for the recorded events and returns, per kernel kind, the summed
+ * milliseconds (ms[PEPS_PROF_KINDS], host FP64) and launch counts
+ * (counts[PEPS_PROF_KINDS], host); reset != 0 clears the totals. */
+enum {
+  PEPS_PROF_ENV = 0,      /* boundary-MPS environments (both directions) */
+  PEPS_PROF_OVERLAP = 1,  /* amplitude at the middle cut */
+  PEPS_PROF_STRIP1 = 2,   /* one-row strips: ratios and log-derivatives */
+  PEPS_PROF_STRIP2 = 3,   /* two-row strips: ratios */
+  PEPS_PROF_ESUM = 4,     /* diagonal energy and the per-sample sum */
+  PEPS_PROF_MINSR = 5,    /* the whole minSR step */
+  PEPS_PROF_SAMPLE = 6,   /* Metropolis sweeps */
+  PEPS_PROF_KINDS = 8
+};
+peps_status peps_profile(peps_ctx* ctx, int enable);
+peps_status peps_profile_read(peps_ctx* ctx, double* ms, long* counts, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ SAMPLE_EXCHANGE, SAMPLE_FLIP = 0, 1
 # every symbol the header declares
 EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_env_cache_bytes", "peps_set_hamiltonian", "peps_amplitude",
-           "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample"]
+           "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample",
+           "peps_profile", "peps_profile_read"]
+PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
 class PepsError(RuntimeError):
@@ -75,6 +77,10 @@ def load():
     lib.minsr_step.restype = I
     lib.peps_sample.argtypes = [P, P, I, I, I, I, I, U64, U64, P, P, P]
     lib.peps_sample.restype = I
+    lib.peps_profile.argtypes = [P, I]
+    lib.peps_profile.restype = I
+    lib.peps_profile_read.argtypes = [P, P, P, I]
+    lib.peps_profile_read.restype = I
     _lib = lib
     return lib
 
@@ -207,6 +213,17 @@ class Context:
                                  _ptr(eloc.contiguous()), float(eps), float(rcond), _ptr(dtheta),
                                  _ptr(diag), _stream()))
         return dtheta, diag
+
+    def profile(self, enable=True):
+        _check(load().peps_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset=True):
+        """{kind: (total ms, launches)} from the library's HIP events."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_long * 8)()
+        _check(load().peps_profile_read(self._h, ctypes.cast(ms, ctypes.c_void_p),
+                                        ctypes.cast(cnt, ctypes.c_void_p), 1 if reset else 0))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(PROF_KINDS)}
 
     def sample(self, theta, kind="exchange", n_chains=256, per_chain=4, burn_in=32, thin=1,
                seed=0, offset=0):

@@ -79,7 +79,34 @@ struct peps_ctx {
   // workspace
   DevBuf theta_c, env_int, rscr, rt1, rt2, epart, bad, mean, Tm, vec, eloc_tmp, logpsi_tmp;
   int jac_sweeps = 40;
+  // optional per-kernel timing with HIP events on the launch stream
+  bool prof = false;
+  struct Ev { hipEvent_t a, b; int kind; };
+  std::vector<Ev> pending;
+  double prof_ms[PEPS_PROF_KINDS] = {};
+  long prof_n[PEPS_PROF_KINDS] = {};
   size_t chunk_budget = (size_t)6 << 30;  // bytes of per-chunk scratch
+};
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+  peps_ctx* c;
+  hipStream_t st;
+  int kind;
+  hipEvent_t a{}, b{};
+  ProfScope(peps_ctx* c_, hipStream_t st_, int kind_) : c(c_), st(st_), kind(kind_) {
+    if (c->prof) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof) {
+      hipEventRecord(b, st);
+      c->pending.push_back({a, b, kind});
+    }
+  }
 };
 
 static size_t elem_bytes(int dtype) { return dtype == PEPS_F64 ? 8 : 4; }
@@ -442,6 +469,7 @@ static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int n, char* en
   const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
   for (int c0 = 0; c0 < n; c0 += ch) {
     const int m = std::min(ch, n - c0);
+    ProfScope ps(c, st, PEPS_PROF_ENV);
     HIPCHK(launch_env_sweep<M>(L, c->d_tab, c->theta_c.p, samples + (size_t)c0 * L.N,
                                env_t + (size_t)c0 * per_t, env_l + (size_t)c0 * L.n_slots,
                                c->rscr.p, flags ? flags + c0 : nullptr, m, c->jac_sweeps, st));
@@ -479,12 +507,18 @@ static peps_status run_strips(peps_ctx* c, const uint8_t* samples, int n, const 
     const char* et = env_t + (size_t)c0 * per_t;
     char* Oc = want_o ? (char*)O + (size_t)c0 * L.n_compact * ob : nullptr;
     if (want_e) HIPCHK(hipMemsetAsync(c->epart.p, 0, (size_t)m * nparts * 2 * sizeof(double), st));
-    HIPCHK(launch_strip1<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt1.p, (double*)c->epart.p,
+    {
+      ProfScope ps(c, st, PEPS_PROF_STRIP1);
+      HIPCHK(launch_strip1<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt1.p, (double*)c->epart.p,
                             Oc, flags ? flags + c0 : nullptr, m, want_e, want_o, st));
+    }
     if (want_e) {
-      if (H.n_strips)
+      if (H.n_strips) {
+        ProfScope ps(c, st, PEPS_PROF_STRIP2);
         HIPCHK(launch_strip2<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt2.p,
                                 (double*)c->epart.p, flags ? flags + c0 : nullptr, m, st));
+      }
+      ProfScope ps(c, st, PEPS_PROF_ESUM);
       HIPCHK(launch_energy_diag_sum(L, H, sm, (const double*)c->epart.p, nparts,
                                     eloc + (size_t)c0 * 2, m, st));
     }
@@ -522,7 +556,10 @@ static peps_status evaluate_impl(peps_ctx* c, const double* theta, const uint8_t
     peps_status s = run_envs<M>(c, samples, n, env_t, env_l, flags, st);
     if (s != PEPS_OK) return s;
   }
-  if (logpsi) HIPCHK(launch_overlap<M>(L, c->d_tab, env_t, env_l, c->icut, logpsi, flags, n, st));
+  if (logpsi) {
+    ProfScope ps(c, st, PEPS_PROF_OVERLAP);
+    HIPCHK(launch_overlap<M>(L, c->d_tab, env_t, env_l, c->icut, logpsi, flags, n, st));
+  }
   if (eloc || O) {
     if (eloc && !c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
     peps_status s = run_strips<M>(c, samples, n, env_t, eloc, O, flags, st);
@@ -614,18 +651,90 @@ peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n
     for (double v : h)
       if (!std::isfinite(v)) return fail(PEPS_ERR_NONFINITE, "eloc contains non-finite values");
   }
+  ProfScope ps(c, st, PEPS_PROF_MINSR);
   HIPCHK(launch_minsr(L, c->d_tab, c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, O, samples, n,
                       eloc, eps, rcond, dtheta, diag, (double*)c->mean.p, (double*)c->Tm.p,
                       (double*)c->vec.p, st));
   return PEPS_OK;
 }
 
+peps_status peps_profile(peps_ctx* c, int enable) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  c->prof = enable != 0;
+  return PEPS_OK;
+}
+
+peps_status peps_profile_read(peps_ctx* c, double* ms, long* counts, int reset) {
+  if (!c || !ms || !counts) return fail(PEPS_ERR_ARG, "null pointer");
+  for (auto& e : c->pending) {
+    HIPCHK(hipEventSynchronize(e.b));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+    c->prof_ms[e.kind] += t;
+    c->prof_n[e.kind] += 1;
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  c->pending.clear();
+  for (int k = 0; k < PEPS_PROF_KINDS; ++k) {
+    ms[k] = c->prof_ms[k];
+    counts[k] = c->prof_n[k];
+    if (reset) {
+      c->prof_ms[k] = 0.0;
+      c->prof_n[k] = 0;
+    }
+  }
+  return PEPS_OK;
+}
+
 peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains, int per_chain,
                         int burn_in, int thin, uint64_t seed, uint64_t offset, uint8_t* samples,
                         int32_t* accepted, void* stream) {
-  (void)c; (void)theta; (void)kind; (void)n_chains; (void)per_chain; (void)burn_in; (void)thin;
-  (void)seed; (void)offset; (void)samples; (void)accepted; (void)stream;
-  return fail(PEPS_ERR_UNSUPPORTED, "peps_sample is not built yet");
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (!theta || !samples) return fail(PEPS_ERR_ARG, "null theta or samples");
+  if (kind != PEPS_SAMPLE_EXCHANGE && kind != PEPS_SAMPLE_FLIP)
+    return fail(PEPS_ERR_ARG, "unknown sampler kind %d", kind);
+  if (n_chains < 1 || per_chain < 1 || burn_in < 0 || thin < 1)
+    return fail(PEPS_ERR_ARG, "need n_chains >= 1, per_chain >= 1, burn_in >= 0, thin >= 1");
+  if ((long long)burn_in + (long long)per_chain * thin > (1LL << 30))
+    return fail(PEPS_ERR_ARG, "too many sweeps");
+  const Lattice& L = c->L;
+  const size_t lds = sample_lds_elems(L.bmax, L.D) * c->tsize;
+  if (lds + 8 * 1024 > 160 * 1024)
+    return fail(PEPS_ERR_UNSUPPORTED, "sampler needs %zu bytes of LDS per workgroup", lds);
+  hipStream_t st = (hipStream_t)stream;
+  peps_status s = prepare_theta(c, theta, st);
+  if (s != PEPS_OK) return s;
+  const size_t BD = (size_t)L.bmax * L.D;
+  const size_t box = L.site_box;
+  const size_t box2 = (size_t)L.bmax * L.bmax * L.D * L.D;
+  const size_t nc = (size_t)n_chains;
+  if ((s = c->env_int.ensure(nc * env_tensor_elems_per_sample(L) * c->tsize)) != PEPS_OK) return s;
+  if ((s = c->eloc_tmp.ensure(nc * L.n_slots * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->rscr.ensure(nc * L.Ly * BD * BD * c->tsize)) != PEPS_OK) return s;
+  if ((s = c->rt1.ensure(nc * (L.Ly + 1) * box * c->tsize)) != PEPS_OK) return s;
+  if ((s = c->rt2.ensure(nc * (L.Ly + 1) * box2 * c->tsize)) != PEPS_OK) return s;
+  ProfScope ps(c, st, PEPS_PROF_SAMPLE);
+  switch (c->g.dtype) {
+    case PEPS_F64:
+      HIPCHK(launch_metropolis<MODE_F64>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain,
+                                         burn_in, thin, seed, offset, samples, accepted,
+                                         c->env_int.p, (double*)c->eloc_tmp.p, c->rscr.p,
+                                         c->rt1.p, c->rt2.p, c->jac_sweeps, st));
+      break;
+    case PEPS_F32:
+      HIPCHK(launch_metropolis<MODE_F32>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain,
+                                         burn_in, thin, seed, offset, samples, accepted,
+                                         c->env_int.p, (double*)c->eloc_tmp.p, c->rscr.p,
+                                         c->rt1.p, c->rt2.p, c->jac_sweeps, st));
+      break;
+    default:
+      HIPCHK(launch_metropolis<MODE_BF16>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain,
+                                          burn_in, thin, seed, offset, samples, accepted,
+                                          c->env_int.p, (double*)c->eloc_tmp.p, c->rscr.p,
+                                          c->rt1.p, c->rt2.p, c->jac_sweeps, st));
+  }
+  return PEPS_OK;
 }
 
 }  // extern "C"

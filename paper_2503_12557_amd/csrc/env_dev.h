@@ -1,0 +1,319 @@
+// Device-side boundary-MPS building blocks shared by the environment
+// kernel and the sampler: the first row read as an MPS and the absorption
+// of one further row with its truncation back to chi (see env.hip).
+#pragma once
+
+#include "common.h"
+
+namespace pm {
+
+// A tensor of site (x, y) seen from a sweep direction: legs (l, r, in, out)
+// where "in" faces the environment being absorbed and "out" is the new
+// physical leg (top sweep: in = up, out = down; bottom sweep: swapped).
+struct SiteView {
+  int Dl, Dr, Din, Dout;
+  int s_l, s_r, s_in, s_out;  // element strides in the (l, r, u, d) tensor
+};
+
+__device__ __forceinline__ SiteView site_view(const int* tab, const Lattice& L, int n, bool bottom) {
+  const int* lg = tab + L.off_legs + 4 * n;
+  SiteView v;
+  v.Dl = lg[0];
+  v.Dr = lg[1];
+  const int Du = lg[2], Dd = lg[3];
+  const int s_d = 1, s_u = Dd, s_r = Du * Dd, s_l = lg[1] * Du * Dd;
+  v.s_l = s_l;
+  v.s_r = s_r;
+  if (!bottom) {
+    v.Din = Du; v.Dout = Dd; v.s_in = s_u; v.s_out = s_d;
+  } else {
+    v.Din = Dd; v.Dout = Du; v.s_in = s_d; v.s_out = s_u;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* site_tensor(const T* theta, const int* tab, const Lattice& L,
+                                               const uint8_t* s, int n) {
+  return theta + tab[L.off_param + n] + pbit(s[n]) * tab[L.off_block + n];
+}
+
+template <typename T>
+__device__ void load_lds(T* dst, const T* src, int cnt) {
+  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) dst[i] = src[i];
+}
+
+// Divide the LDS tensor by its largest modulus; returns ln(divisor).
+template <typename T>
+__device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
+  T mx = 0;
+  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) {
+    const T a = fabs(t[i]);
+    mx = a > mx ? a : mx;
+  }
+  mx = block_max(mx, red);
+  if (!(mx > T(0)) || !isfinite((double)mx)) {
+    if (threadIdx.x == 0) *flag |= (mx == T(0)) ? 1 : 2;
+    __syncthreads();
+    return 0.0;
+  }
+  const T inv = T(1) / mx;
+  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) t[i] *= inv;
+  __syncthreads();
+  return log((double)mx);
+}
+
+inline size_t env_lds_elems_(int bmax, int D) {
+  const size_t BD = (size_t)bmax * D;
+  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + 3 * BD * BD + 2 * BD * bmax +
+         4 * BD + 16;
+}
+
+
+// LDS carve-up of one workgroup for the environment code.
+template <typename T>
+struct EnvSmem {
+  T *Ebuf, *Abuf, *P, *S, *Z, *W, *Bn, *vv, *ww, *sig, *red;
+  __device__ EnvSmem(T* sm, const Lattice& L) {
+    const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
+    Ebuf = sm;
+    Abuf = Ebuf + B * D * B;
+    P = Abuf + D * D * D * D;   // P_k (left) / T1 (right)
+    S = P + BD * BD;            // stacked QR buffer (left) / C and Z (right)
+    Z = S + BD * BD;
+    W = S + 2 * BD * BD;
+    Bn = W + BD * B;
+    vv = Bn + B * BD;
+    ww = vv + 2 * BD;
+    sig = ww + BD;
+    red = sig + BD;
+  }
+};
+
+// The first row of a sweep read as an MPS, normalised, into its slot.
+template <int M>
+__device__ void env_first_row(const Lattice& L, const int* tab, const typename ModeT<M>::T* theta,
+                              const uint8_t* s, bool bottom, typename ModeT<M>::T* envs,
+                              double* lg, const EnvSmem<typename ModeT<M>::T>& sh, int* flp) {
+  typedef typename ModeT<M>::T T;
+  const int tid = threadIdx.x;
+  T* Ebuf = sh.Ebuf;
+  T* red = sh.red;
+  int& fl = *flp;
+  const size_t slot_elems = (size_t)L.Ly * L.site_box;
+  // ---- first row read as an MPS ----
+  const int x0 = bottom ? L.Lx - 1 : 0;
+  const int slot0 = bottom ? slot_bottom(L, L.Lx - 1) : slot_top(L, 0);
+  double logacc = 0.0;
+  for (int y = 0; y < L.Ly; ++y) {
+    const int nsite = x0 * L.Ly + y;
+    const SiteView v = site_view(tab, L, nsite, bottom);
+    const T* a = site_tensor(theta, tab, L, s, nsite);
+    const int cnt = v.Dl * v.Dout * v.Dr;
+    for (int i = tid; i < cnt; i += PEPS_BLOCK) {
+      const int l = i / (v.Dout * v.Dr), rem = i - l * (v.Dout * v.Dr);
+      const int k = rem / v.Dr, r = rem - k * v.Dr;
+      Ebuf[i] = a[l * v.s_l + r * v.s_r + k * v.s_out];
+    }
+    __syncthreads();
+    logacc += normalize_lds(Ebuf, cnt, red, flp);
+    T* dst = envs + (size_t)slot0 * slot_elems + (size_t)y * L.site_box;
+    for (int i = tid; i < cnt; i += PEPS_BLOCK) dst[i] = Ebuf[i];
+    __syncthreads();
+  }
+  if (tid == 0) lg[slot0] = logacc;
+
+}
+
+// Absorb row t of the sweep (x = t from the top, Lx-1-t from the bottom) into
+// the previous environment and truncate to chi; R is this sweep's scratch
+// for the Ly R factors.
+template <int M>
+__device__ void env_absorb_row(const Lattice& L, const int* tab, const typename ModeT<M>::T* theta,
+                               const uint8_t* s, bool bottom, int t, typename ModeT<M>::T* envs,
+                               double* lg, typename ModeT<M>::T* R,
+                               const EnvSmem<typename ModeT<M>::T>& sh, int* sel, int* sflag,
+                               int* flp, int jac_sweeps) {
+  typedef typename ModeT<M>::T T;
+  const int tid = threadIdx.x;
+  const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
+  T *Ebuf = sh.Ebuf, *Abuf = sh.Abuf, *P = sh.P, *S = sh.S, *Z = sh.Z, *W = sh.W, *Bn = sh.Bn;
+  T *vv = sh.vv, *ww = sh.ww, *sig = sh.sig, *red = sh.red;
+  int& fl = *flp;
+  (void)B;
+  (void)D;
+  const size_t slot_elems = (size_t)L.Ly * L.site_box;
+  const int* edims = tab + L.off_env;
+  const T tol = Eps<T>::v * T(4);
+    const int x = bottom ? L.Lx - 1 - t : t;
+    const int sp = bottom ? slot_bottom(L, x + 1) : slot_top(L, x - 1);
+    const int sn = bottom ? slot_bottom(L, x) : slot_top(L, x);
+    const T* Eprev = envs + (size_t)sp * slot_elems;
+    T* Enew = envs + (size_t)sn * slot_elems;
+
+    // left-to-right QR sweep: R_y of R_{y-1} P_y
+    int kprev = 1;  // rows of R_{y-1}
+    for (int y = 0; y < L.Ly - 1; ++y) {
+      const int nsite = x * L.Ly + y;
+      const SiteView v = site_view(tab, L, nsite, bottom);
+      const int bl = edims[(sp * L.Ly + y) * 3 + 0];
+      const int br = edims[(sp * L.Ly + y) * 3 + 2];
+      const int Pl = bl * v.Dl, Pr = br * v.Dr;
+      load_lds(Ebuf, Eprev + (size_t)y * L.site_box, bl * v.Din * br);
+      const T* a = site_tensor(theta, tab, L, s, nsite);
+      load_lds(Abuf, a, v.Dl * v.Dr * v.Din * v.Dout);
+      __syncthreads();
+      const T* Rp = (y > 0) ? R + (size_t)(y - 1) * BD * BD : nullptr;
+      int kr = 0;
+      for (int k = 0; k < v.Dout; ++k) {
+        // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k]
+        const int tot = Pl * Pr;
+        for (int i = tid; i < tot; i += PEPS_BLOCK) {
+          const int row = i / Pr, col = i - row * Pr;
+          const int aa = row / v.Dl, l = row - aa * v.Dl;
+          const int b = col / v.Dr, r = col - b * v.Dr;
+          T acc = 0;
+          for (int in = 0; in < v.Din; ++in)
+            acc += opnd<M>(Ebuf[(aa * v.Din + in) * br + b]) *
+                   opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]);
+          P[i] = acc;
+        }
+        __syncthreads();
+        // M_k = R_{y-1} P_k into rows kr.. of the stack
+        if (y == 0) {
+          for (int i = tid; i < Pr; i += PEPS_BLOCK) S[kr * Pr + i] = P[i];
+        } else {
+          gemm<M>(kprev, Pr, Pl, Rp, Pl, 1, P, Pr, 1, S + kr * Pr, Pr, 1, false);
+        }
+        __syncthreads();
+        const int m = kr + kprev;
+        house_qr_r(S, m, Pr, Pr, vv, ww, red);
+        kr = m < Pr ? m : Pr;
+      }
+      // store R_y (kr x Pr, row stride Pr)
+      T* Ry = R + (size_t)y * BD * BD;
+      for (int i = tid; i < kr * Pr; i += PEPS_BLOCK) Ry[i] = S[i];
+      __syncthreads();
+      kprev = kr;
+    }
+
+    // right-to-left SVD sweep
+    int nbr = 1;       // new bond to the right of site y
+    double logrow = 0.0;
+    for (int y = L.Ly - 1; y >= 0; --y) {
+      const int nsite = x * L.Ly + y;
+      const SiteView v = site_view(tab, L, nsite, bottom);
+      const int bl = edims[(sp * L.Ly + y) * 3 + 0];
+      const int br = edims[(sp * L.Ly + y) * 3 + 2];
+      const int Pl = bl * v.Dl;
+      load_lds(Ebuf, Eprev + (size_t)y * L.site_box, bl * v.Din * br);
+      const T* a = site_tensor(theta, tab, L, s, nsite);
+      load_lds(Abuf, a, v.Dl * v.Dr * v.Din * v.Dout);
+      if (y == L.Ly - 1) {
+        if (tid == 0) W[0] = T(1);
+      }
+      __syncthreads();
+      // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]
+      for (int r = 0; r < v.Dr; ++r)
+        gemm<M>(bl * v.Din, nbr, br, Ebuf, br, 1, W + r * nbr, v.Dr * nbr, 1, P + r * nbr,
+                v.Dr * nbr, 1, false);
+      __syncthreads();
+      // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]
+      const int zc = v.Dout * nbr;
+      {
+        const int tot = Pl * zc;
+        for (int i = tid; i < tot; i += PEPS_BLOCK) {
+          const int row = i / zc, col = i - row * zc;
+          const int aa = row / v.Dl, l = row - aa * v.Dl;
+          const int k = col / nbr, c = col - k * nbr;
+          T acc = 0;
+          for (int in = 0; in < v.Din; ++in)
+            for (int r = 0; r < v.Dr; ++r)
+              acc += opnd<M>(P[(aa * v.Din + in) * (v.Dr * nbr) + r * nbr + c]) *
+                     opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]);
+          Z[i] = acc;
+        }
+      }
+      __syncthreads();
+      int rnew;
+      T* newt;
+      if (y > 0) {
+        // recompute kprev = rows of R_{y-1}
+        int kp = 1;
+        for (int yy = 0; yy < y; ++yy) {
+          const int ns2 = x * L.Ly + yy;
+          const SiteView v2 = site_view(tab, L, ns2, bottom);
+          const int br2 = edims[(sp * L.Ly + yy) * 3 + 2];
+          const int rows = kp * v2.Dout, cols = br2 * v2.Dr;
+          kp = rows < cols ? rows : cols;
+        }
+        const T* Rp = R + (size_t)(y - 1) * BD * BD;
+        // C = R_{y-1} Z  (kp x zc)
+        gemm<M>(kp, zc, Pl, Rp, Pl, 1, Z, zc, 1, S, zc, 1, false);
+        __syncthreads();
+        int m = kp;
+        if (m > zc) {
+          house_qr_r(S, m, zc, zc, vv, ww, red);
+          m = zc;
+        }
+        const int used = jacobi_rows(S, m, zc, zc, tol, jac_sweeps, sflag);
+        if (used < 0 && tid == 0) fl |= 4;
+        // row norms
+        for (int i = tid; i < m; i += PEPS_BLOCK) {
+          T q = 0;
+          for (int e = 0; e < zc; ++e) q += S[i * zc + e] * S[i * zc + e];
+          sig[i] = sqrt(q);
+        }
+        __syncthreads();
+        rnew = edims[(sn * L.Ly + y) * 3 + 0];
+        // rank rows by descending norm (ties by index)
+        for (int i = tid; i < m; i += PEPS_BLOCK) {
+          int rk = 0;
+          const T si = sig[i];
+          for (int j = 0; j < m; ++j) {
+            const T sj = sig[j];
+            rk += (sj > si) || (sj == si && j < i);
+          }
+          if (rk < rnew) sel[rk] = i;
+        }
+        __syncthreads();
+        T smax = 0;
+        for (int i = 0; i < m; ++i) smax = sig[i] > smax ? sig[i] : smax;
+        if (tid == 0 && rnew < m) {
+          const T sa = sig[sel[rnew - 1]];
+          // the largest discarded value
+          T sb = 0;
+          for (int i = 0; i < m; ++i) {
+            bool kept = false;
+            for (int j = 0; j < rnew; ++j) kept |= (sel[j] == i);
+            if (!kept && sig[i] > sb) sb = sig[i];
+          }
+          if (sa > T(0) && (sa - sb) < T(1e-8) * sa) fl |= 8;
+        }
+        const T thresh = smax * Eps<T>::v * T(4);
+        for (int i = tid; i < rnew * zc; i += PEPS_BLOCK) {
+          const int j = i / zc, e = i - j * zc;
+          const T sj = sig[sel[j]];
+          Bn[i] = (sj > thresh) ? S[sel[j] * zc + e] / sj : T(0);
+        }
+        __syncthreads();
+        // W_y[(a,l), j] = sum_e Z[(a,l), e] Bn[j, e]
+        gemm<M>(Pl, rnew, zc, Z, zc, 1, Bn, 1, zc, W, rnew, 1, false);
+        newt = Bn;
+      } else {
+        rnew = 1;
+        newt = Z;
+      }
+      __syncthreads();
+      const int cnt = rnew * zc;
+      logrow += normalize_lds(newt, cnt, red, flp);
+      T* dst = Enew + (size_t)y * L.site_box;
+      for (int i = tid; i < cnt; i += PEPS_BLOCK) dst[i] = newt[i];
+      nbr = rnew;
+      __syncthreads();
+    }
+    if (tid == 0) lg[sn] = lg[sp] + logrow;
+    __syncthreads();
+  }
+
+}  // namespace pm

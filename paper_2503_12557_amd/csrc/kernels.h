@@ -57,6 +57,15 @@ hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8
                                   const double* epart, int nparts, double* eloc, int n,
                                   hipStream_t st);
 
+// Metropolis sampler
+size_t sample_lds_elems(int bmax, int D);
+template <int M>
+hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta, int kind,
+                             int n_chains, int per_chain, int burn_in, int thin, uint64_t seed,
+                             uint64_t offset, uint8_t* samples, int* accepted, void* envscr,
+                             double* logscr, void* rscr, void* rt1, void* rt2, int jac_sweeps,
+                             hipStream_t st);
+
 // minSR
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,

@@ -12,125 +12,9 @@
 // (Sec. "On Numerical Stability" notes ratios are what matters).
 #include "common.h"
 #include "kernels.h"
+#include "strip_dev.h"
 
 namespace pm {
-
-struct EnvRef {
-  const void* p;
-  int a, k, b;  // dims; p == nullptr means the trivial bond-1 environment
-};
-
-template <typename T>
-__device__ __forceinline__ const T* env_site(const T* envs, const Lattice& L, int slot, int y) {
-  return envs + ((size_t)slot * L.Ly + y) * L.site_box;
-}
-
-template <typename T>
-__device__ __forceinline__ const T* tensor_of(const T* theta, const int* tab, const Lattice& L,
-                                             int n, int p) {
-  return theta + tab[L.off_param + n] + p * tab[L.off_block + n];
-}
-
-__device__ __forceinline__ void legs_of(const int* tab, const Lattice& L, int n, int& Dl, int& Dr,
-                                        int& Du, int& Dd) {
-  const int* lg = tab + L.off_legs + 4 * n;
-  Dl = lg[0];
-  Dr = lg[1];
-  Du = lg[2];
-  Dd = lg[3];
-}
-
-// ---------------------------------------------------------------------------
-// One-row strip helpers. Up env U_y[a,u,b], down env B_y[c,d,e],
-// site A[m,r,u,d], left partial L[a,m,c], right partial R[b,r,e].
-// ---------------------------------------------------------------------------
-template <int M, typename T>
-__device__ void s1_step_left(const T* Lp, const T* U, int ua, int ub, const T* A, int Dl, int Dr,
-                             int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout) {
-  // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
-  gemm<M>(Dl * ba, Du * ub, ua, Lp, 1, Dl * ba, U, Du * ub, 1, X1, Du * ub, 1, false);
-  __syncthreads();
-  // X2[b,r,c,d] = sum_{m,u} X1[m,c,u,b] A[m,r,u,d]
-  const int tot = ub * Dr * ba * Dd;
-  for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
-    int t = i;
-    const int d = t % Dd; t /= Dd;
-    const int c = t % ba; t /= ba;
-    const int r = t % Dr; t /= Dr;
-    const int b = t;
-    T acc = 0;
-    for (int m = 0; m < Dl; ++m)
-      for (int u = 0; u < Du; ++u)
-        acc += opnd<M>(X1[((m * ba + c) * Du + u) * ub + b]) *
-               opnd<M>(A[((m * Dr + r) * Du + u) * Dd + d]);
-    X2[i] = acc;
-  }
-  __syncthreads();
-  // L'[(b,r), e] = sum_{(c,d)} X2[(b,r),(c,d)] B[(c,d), e]
-  gemm<M>(ub * Dr, bb, ba * Dd, X2, ba * Dd, 1, Bt, bb, 1, Lout, bb, 1, false);
-  __syncthreads();
-}
-
-template <int M, typename T>
-__device__ void s1_step_right(const T* Rp, const T* U, int ua, int ub, const T* A, int Dl, int Dr,
-                              int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2, T* Rout) {
-  // X1[(a,u),(r,e)] = sum_b U[(a,u),b] R[b,(r,e)]
-  gemm<M>(ua * Du, Dr * bb, ub, U, ub, 1, Rp, Dr * bb, 1, X1, Dr * bb, 1, false);
-  __syncthreads();
-  // X2[(a,m),(d,e)] = sum_{u,r} X1[a,u,r,e] A[m,r,u,d]
-  const int tot = ua * Dl * Dd * bb;
-  for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
-    int t = i;
-    const int e = t % bb; t /= bb;
-    const int d = t % Dd; t /= Dd;
-    const int m = t % Dl; t /= Dl;
-    const int a = t;
-    T acc = 0;
-    for (int u = 0; u < Du; ++u)
-      for (int r = 0; r < Dr; ++r)
-        acc += opnd<M>(X1[((a * Du + u) * Dr + r) * bb + e]) *
-               opnd<M>(A[((m * Dr + r) * Du + u) * Dd + d]);
-    X2[i] = acc;
-  }
-  __syncthreads();
-  // R'[(a,m), c] = sum_{(d,e)} X2[(a,m),(d,e)] B[c,(d,e)]
-  gemm<M>(ua * Dl, ba, Dd * bb, X2, Dd * bb, 1, Bt, 1, Dd * bb, Rout, ba, 1, false);
-  __syncthreads();
-}
-
-template <typename T>
-__device__ T lds_dot(const T* a, const T* b, int cnt, T* red) {
-  T s = 0;
-  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) s += a[i] * b[i];
-  return block_sum(s, red);
-}
-
-// Sum of <S|h_t|S'> over the contributions of a move: the coefficient of
-// the move's amplitude ratio in E_loc(S).
-__device__ void move_coef(const HamDev& H, const int* mv, const uint8_t* s, double& cre,
-                          double& cim) {
-  cre = 0.0;
-  cim = 0.0;
-  const int cs = mv[6], cc = mv[7];
-  for (int q = 0; q < cc; ++q) {
-    const int t = H.contrib[2 * (cs + q)], mask = H.contrib[2 * (cs + q) + 1];
-    const int* tt = H.terms + 4 * t;
-    const int k = tt[0];
-    int c = 0;
-    for (int j = 0; j < k; ++j) c = 2 * c + pbit(s[tt[1 + j]]);
-    const int c2 = c ^ mask;
-    const double* h = H.mats + ((size_t)t * 64 + c * 8 + c2) * 2;
-    cre += h[0];
-    cim += h[1];
-  }
-}
-
-__device__ __forceinline__ bool in_move(const int* mv, int n) {
-  const int ns = mv[2];
-  for (int j = 0; j < ns; ++j)
-    if (mv[3 + j] == n) return true;
-  return false;
-}
 
 size_t strip1_lds_elems(int bmax, int D) {
   const size_t BD = (size_t)bmax * D;
@@ -202,7 +86,15 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   const int m1 = H.n_strips ? H.mstart[x + 1] : 0;
   int mi = m0;
   double ere = 0.0, eim = 0.0;
-
+  // numerators summed per window end y1; each is divided by the strip value
+  // taken along the same left-partial path, <L_y1, R_y1+1>, so the two
+  // carry the same rounding
+  __shared__ double nre[32], nim[32], zv[32];
+  if (tid < 32) {
+    nre[tid] = 0.0;
+    nim[tid] = 0.0;
+    zv[tid] = 1.0;
+  }
   if (tid == 0) Lf[0] = T(1);
   __syncthreads();
   for (int y = 0; y < L.Ly; ++y) {
@@ -263,9 +155,10 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           }
           const int cnt = ub_(y1) * tab[L.off_legs + 4 * (x * L.Ly + y1) + 1] * bb_(y1);
           const T num = lds_dot(cur, (const T*)(Rt + (size_t)(y1 + 1) * box), cnt, red);
-          const double ratio = (double)num / (double)psi_row;
-          ere += cre * ratio;
-          eim += cim * ratio;
+          if (tid == 0) {
+            nre[y1] += cre * (double)num;
+            nim[y1] += cim * (double)num;
+          }
         }
         ++mi;
       }
@@ -274,124 +167,23 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
     for (int i = tid; i < ub * Dr * bb; i += PEPS_BLOCK) Lf[i] = Lt[i];
     __syncthreads();
+    if (want_e) {
+      const T z = lds_dot(Lf, (const T*)Rn, ub * Dr * bb, red);
+      if (tid == 0) zv[y] = (double)z;
+    }
   }
   if (tid == 0) {
     if (want_e) {
+      for (int y = 0; y < L.Ly; ++y)
+        if (nre[y] != 0.0 || nim[y] != 0.0) {
+          ere += nre[y] / zv[y];
+          eim += nim[y] / zv[y];
+        }
       const int nparts = 1 + L.Lx + (L.Lx - 1);
       epart[((size_t)smp * nparts + 1 + x) * 2] = ere;
       epart[((size_t)smp * nparts + 1 + x) * 2 + 1] = eim;
     }
     if (fl && flags) atomicOr(flags + smp, fl);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Two-row strip: rows x (A1[m1,r1,u,t]) and x+1 (A2[m2,s,t,d]) between
-// U = E^u[x-1] and B = E^l[x+2]. Left partial L[a,m1,m2,c], right partial
-// R[b,r1,s,e]. Contractions are chunked over the outer environment bond so
-// the intermediates stay O(chi D^3).
-// ---------------------------------------------------------------------------
-template <int M, typename T>
-__device__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
-                             int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2, int Dd2,
-                             const T* Bt, int ba, int bb, T* X1, T* X2, T* X3, T* Lout) {
-  const int inner = Dl1 * Dl2 * ba;
-  for (int b = 0; b < ub; ++b) {
-    // X1[(m1,m2,c), u] = sum_a L[a,(m1,m2,c)] U[a,u,b]
-    gemm<M>(inner, uk, ua, Lp, 1, inner, U + b, uk * ub, ub, X1, uk, 1, false);
-    __syncthreads();
-    // X2[m2,c,r1,t] = sum_{m1,u} X1[m1,m2,c,u] A1[m1,r1,u,t]
-    {
-      const int tot = Dl2 * ba * Dr1 * Dd1;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
-        int q = i;
-        const int t = q % Dd1; q /= Dd1;
-        const int r1 = q % Dr1; q /= Dr1;
-        const int c = q % ba; q /= ba;
-        const int m2 = q;
-        T acc = 0;
-        for (int m1 = 0; m1 < Dl1; ++m1)
-          for (int u = 0; u < uk; ++u)
-            acc += opnd<M>(X1[((m1 * Dl2 + m2) * ba + c) * uk + u]) *
-                   opnd<M>(A1[((m1 * Dr1 + r1) * uk + u) * Dd1 + t]);
-        X2[i] = acc;
-      }
-    }
-    __syncthreads();
-    // X3[r1,s,c,d] = sum_{m2,t} X2[m2,c,r1,t] A2[m2,s,t,d]
-    {
-      const int tot = Dr1 * Dr2 * ba * Dd2;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
-        int q = i;
-        const int d = q % Dd2; q /= Dd2;
-        const int c = q % ba; q /= ba;
-        const int sidx = q % Dr2; q /= Dr2;
-        const int r1 = q;
-        T acc = 0;
-        for (int m2 = 0; m2 < Dl2; ++m2)
-          for (int t = 0; t < Dd1; ++t)
-            acc += opnd<M>(X2[((m2 * ba + c) * Dr1 + r1) * Dd1 + t]) *
-                   opnd<M>(A2[((m2 * Dr2 + sidx) * Dd1 + t) * Dd2 + d]);
-        X3[i] = acc;
-      }
-    }
-    __syncthreads();
-    // L'[b,(r1,s),e] = sum_{(c,d)} X3[(r1,s),(c,d)] B[(c,d),e]
-    gemm<M>(Dr1 * Dr2, bb, ba * Dd2, X3, ba * Dd2, 1, Bt, bb, 1, Lout + b * (Dr1 * Dr2 * bb), bb,
-            1, false);
-    __syncthreads();
-  }
-}
-
-template <int M, typename T>
-__device__ void s2_step_right(const T* Rp, const T* U, int ua, int uk, int ub, const T* A1,
-                              int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2, int Dd2,
-                              const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Y3, T* Rout) {
-  const int rw = Dr1 * Dr2 * bb;
-  for (int a = 0; a < ua; ++a) {
-    // Y1[u,(r1,s,e)] = sum_b U[a,u,b] R[b,(r1,s,e)]
-    gemm<M>(uk, rw, ub, U + a * uk * ub, ub, 1, Rp, rw, 1, Y1, rw, 1, false);
-    __syncthreads();
-    // Y2[m1,t,s,e] = sum_{u,r1} A1[m1,r1,u,t] Y1[u,r1,s,e]
-    {
-      const int tot = Dl1 * Dd1 * Dr2 * bb;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
-        int q = i;
-        const int e = q % bb; q /= bb;
-        const int sidx = q % Dr2; q /= Dr2;
-        const int t = q % Dd1; q /= Dd1;
-        const int m1 = q;
-        T acc = 0;
-        for (int u = 0; u < uk; ++u)
-          for (int r1 = 0; r1 < Dr1; ++r1)
-            acc += opnd<M>(A1[((m1 * Dr1 + r1) * uk + u) * Dd1 + t]) *
-                   opnd<M>(Y1[((u * Dr1 + r1) * Dr2 + sidx) * bb + e]);
-        Y2[i] = acc;
-      }
-    }
-    __syncthreads();
-    // Y3[(m1,m2),(d,e)] = sum_{t,s} A2[m2,s,t,d] Y2[m1,t,s,e]
-    {
-      const int tot = Dl1 * Dl2 * Dd2 * bb;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
-        int q = i;
-        const int e = q % bb; q /= bb;
-        const int d = q % Dd2; q /= Dd2;
-        const int m2 = q % Dl2; q /= Dl2;
-        const int m1 = q;
-        T acc = 0;
-        for (int t = 0; t < Dd1; ++t)
-          for (int sidx = 0; sidx < Dr2; ++sidx)
-            acc += opnd<M>(A2[((m2 * Dr2 + sidx) * Dd1 + t) * Dd2 + d]) *
-                   opnd<M>(Y2[((m1 * Dd1 + t) * Dr2 + sidx) * bb + e]);
-        Y3[i] = acc;
-      }
-    }
-    __syncthreads();
-    // R'[a,(m1,m2),c] = sum_{(d,e)} Y3[(m1,m2),(d,e)] B[c,(d,e)]
-    gemm<M>(Dl1 * Dl2, ba, Dd2 * bb, Y3, Dd2 * bb, 1, Bt, 1, Dd2 * bb,
-            Rout + a * (Dl1 * Dl2 * ba), ba, 1, false);
-    __syncthreads();
   }
 }
 
@@ -474,9 +266,17 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
 
   int mi = m0;
   double ere = 0.0, eim = 0.0;
+  __shared__ double nre[32], nim[32], zv[32];
+  if (tid < 32) {
+    nre[tid] = 0.0;
+    nim[tid] = 0.0;
+    zv[tid] = 1.0;
+  }
+  int yneed = -1;
   if (tid == 0) Lf[0] = T(1);
   __syncthreads();
-  for (int y = 0; y < L.Ly && mi < m1; ++y) {
+  for (int y = 0; y < L.Ly; ++y) {
+    if (mi >= m1 && y > yneed) break;
     while (mi < m1 && H.moves[8 * mi] == y) {
       const int* mv = H.moves + 8 * mi;
       double cre, cim;
@@ -502,13 +302,14 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
         const int cnt = ub_(y1) * tab[L.off_legs + 4 * a1 + 1] *
                         tab[L.off_legs + 4 * (a1 + L.Ly) + 1] * bb_(y1);
         const T num = lds_dot(cur, (const T*)(Rt + (size_t)(y1 + 1) * box2), cnt, red);
-        const double ratio = (double)num / (double)psi2;
-        ere += cre * ratio;
-        eim += cim * ratio;
+        if (tid == 0) {
+          nre[y1] += cre * (double)num;
+          nim[y1] += cim * (double)num;
+        }
+        yneed = y1 > yneed ? y1 : yneed;
       }
       ++mi;
     }
-    if (mi >= m1) break;
     const int n1 = x * L.Ly + y, n2 = n1 + L.Ly;
     int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
     legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
@@ -519,8 +320,15 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     const int cnt = ub_(y) * Dr1 * Dr2 * bb_(y);
     for (int i = tid; i < cnt; i += PEPS_BLOCK) Lf[i] = Lt[i];
     __syncthreads();
+    const T z = lds_dot(Lf, (const T*)(Rt + (size_t)(y + 1) * box2), cnt, red);
+    if (tid == 0) zv[y] = (double)z;
   }
   if (tid == 0) {
+    for (int y = 0; y < L.Ly; ++y)
+      if (nre[y] != 0.0 || nim[y] != 0.0) {
+        ere += nre[y] / zv[y];
+        eim += nim[y] / zv[y];
+      }
     epart[((size_t)smp * nparts + strip + 1) * 2] = ere;
     epart[((size_t)smp * nparts + strip + 1) * 2 + 1] = eim;
     if (fl && flags) atomicOr(flags + smp, fl);
