@@ -206,6 +206,51 @@ enum {
 peps_status peps_profile(peps_ctx* ctx, int enable);
 peps_status peps_profile_read(peps_ctx* ctx, double* ms, long* counts, int reset);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal for independence Metropolis-Hastings (an extension: the
+ * paper corrects approximate samples by importance weights, App. "direct
+ * sampling of PEPS"; here the PEPS judges every proposal through the
+ * acceptance |Psi(S')|^2 q(S) / (|Psi(S)|^2 q(S'))).
+ * q is a masked autoregressive network over the N sites in raster order with
+ * one hidden ReLU layer of width H (H <= 256): hidden degrees
+ * m(k) = (k mod (N-1)) + 1, input mask [m(k) >= n+1], output mask
+ * [n+1 > m(k)], p(s_n = 1 | s_<n) = sigmoid(logit_n). With n_up >= 0 every
+ * configuration has exactly n_up zeros: a site is forced once the zeros or
+ * the ones are used up and then contributes a factor 1 to q.
+ * Parameters: FP32 device vector W1 [H][N], b1 [H], W2 [N][H], b2 [N];
+ * with bf16 != 0 the weights are rounded to bfloat16 where they enter a
+ * product (FP32 accumulation). Configurations: uint8 [n][N] device.
+ * ---------------------------------------------------------------------- */
+typedef struct made_ctx made_ctx;
+peps_status made_create(int N, int H, int n_up, int bf16, made_ctx** out);
+void made_destroy(made_ctx* m);
+size_t made_num_params(const made_ctx* m);
+/* loss = -mean_b ln q(x_b) (device FP64 scalar) and its gradient (device
+ * FP32, parameter layout) for a batch of B configurations. */
+peps_status made_loss_grad(made_ctx* m, const float* params, const uint8_t* x, int B,
+                           float* grads, double* loss, void* stream);
+/* One Adam step (Kingma and Ba) on params with moments mom, var (device
+ * FP32, same layout), step counter t >= 1. */
+peps_status made_adam_step(made_ctx* m, float* params, const float* grads, float* mom,
+                           float* var, int t, double lr, double beta1, double beta2, double eps,
+                           void* stream);
+/* Draw n configurations from q site by site (uniforms from Philox4x32-10,
+ * counter (site, sample, offset, tag)) with their ln q (device FP64 [n]). */
+peps_status made_sample(made_ctx* m, const float* params, int n, uint64_t seed, uint64_t offset,
+                        uint8_t* out, double* logq, void* stream);
+/* ln q of given configurations (device FP64 [n]). */
+peps_status made_logq(made_ctx* m, const float* params, const uint8_t* x, int n, double* logq,
+                      void* stream);
+/* One independence Metropolis-Hastings step for n_chains chains: chain c
+ * moves to prop[c] iff ln u < 2 (ln|Psi(prop)| - ln|Psi(state)|)
+ * + ln q(state) - ln q(prop), u from Philox (counter: chain, step, 0, tag).
+ * state_logpsi / prop_logpsi are [n][2] (ln|Psi|, arg) as from
+ * peps_amplitude; accepted[c] is incremented on acceptance (or NULL). */
+peps_status imh_step(int n_chains, int N, uint8_t* state, double* state_logpsi,
+                     double* state_logq, const uint8_t* prop, const double* prop_logpsi,
+                     const double* prop_logq, uint64_t seed, uint64_t step, int32_t* accepted,
+                     void* stream);
+
 #ifdef __cplusplus
 }
 #endif

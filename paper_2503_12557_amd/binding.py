@@ -26,7 +26,9 @@ SAMPLE_EXCHANGE, SAMPLE_FLIP = 0, 1
 EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_env_cache_bytes", "peps_set_hamiltonian", "peps_amplitude",
            "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample",
-           "peps_profile", "peps_profile_read"]
+           "peps_profile", "peps_profile_read", "made_create", "made_destroy",
+           "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
+           "imh_step"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -81,6 +83,22 @@ def load():
     lib.peps_profile.restype = I
     lib.peps_profile_read.argtypes = [P, P, P, I]
     lib.peps_profile_read.restype = I
+    lib.made_create.argtypes = [I, I, I, I, ctypes.POINTER(P)]
+    lib.made_create.restype = I
+    lib.made_destroy.argtypes = [P]
+    lib.made_destroy.restype = None
+    lib.made_num_params.argtypes = [P]
+    lib.made_num_params.restype = Z
+    lib.made_loss_grad.argtypes = [P, P, P, I, P, P, P]
+    lib.made_loss_grad.restype = I
+    lib.made_adam_step.argtypes = [P, P, P, P, P, I, D, D, D, D, P]
+    lib.made_adam_step.restype = I
+    lib.made_sample.argtypes = [P, P, I, U64, U64, P, P, P]
+    lib.made_sample.restype = I
+    lib.made_logq.argtypes = [P, P, P, I, P, P]
+    lib.made_logq.restype = I
+    lib.imh_step.argtypes = [I, I, P, P, P, P, P, P, U64, U64, P, P]
+    lib.imh_step.restype = I
     _lib = lib
     return lib
 
@@ -237,3 +255,112 @@ class Context:
                                   burn_in, thin, seed, offset, _ptr(samples), _ptr(acc),
                                   _stream()))
         return samples, acc
+
+
+class Made:
+    """Masked autoregressive proposal q over N sites (hidden width H)."""
+
+    def __init__(self, N, H=256, n_up=None, bf16=False):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.made_create(N, H, -1 if n_up is None else n_up, 1 if bf16 else 0,
+                               ctypes.byref(h)))
+        self._h = h
+        self.N, self.H, self.n_up = N, H, n_up
+        self.n_params = lib.made_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().made_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def loss_grad(self, params, x, grads=None, loss=None):
+        import torch
+        B = x.shape[0]
+        if grads is None:
+            grads = torch.empty_like(params)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=params.device)
+        _check(load().made_loss_grad(self._h, _ptr(params), _ptr(x), B, _ptr(grads), _ptr(loss),
+                                     _stream()))
+        return loss, grads
+
+    def adam(self, params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(load().made_adam_step(self._h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), t,
+                                     lr, beta1, beta2, eps, _stream()))
+
+    def sample(self, params, n, seed=0, offset=0):
+        import torch
+        out = torch.empty(n, self.N, dtype=torch.uint8, device=params.device)
+        lq = torch.empty(n, dtype=torch.float64, device=params.device)
+        _check(load().made_sample(self._h, _ptr(params), n, seed, offset, _ptr(out), _ptr(lq),
+                                  _stream()))
+        return out, lq
+
+    def logq(self, params, x):
+        import torch
+        lq = torch.empty(x.shape[0], dtype=torch.float64, device=params.device)
+        _check(load().made_logq(self._h, _ptr(params), _ptr(x.contiguous()), x.shape[0], _ptr(lq),
+                                _stream()))
+        return lq
+
+    def train(self, params, data, steps, batch=1024, lr=1e-3, seed=0):
+        """Adam on mean -ln q over shuffled mini-batches of `data` (uint8
+        [M][N] on the device); returns the per-step losses (device tensor)."""
+        import torch
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        m = torch.zeros_like(params)
+        v = torch.zeros_like(params)
+        grads = torch.empty_like(params)
+        losses = torch.empty(steps, dtype=torch.float64, device=params.device)
+        M = data.shape[0]
+        perm = torch.randperm(M, generator=g).to(params.device)
+        pos = 0
+        for t in range(1, steps + 1):
+            if pos + batch > M:
+                perm = torch.randperm(M, generator=g).to(params.device)
+                pos = 0
+            xb = data.index_select(0, perm[pos:pos + batch]).contiguous()
+            pos += batch
+            self.loss_grad(params, xb, grads, losses[t - 1:t])
+            self.adam(params, grads, m, v, t, lr)
+        return losses
+
+
+def imh_step(state, state_lp, state_lq, prop, prop_lp, prop_lq, seed, step, accepted):
+    """One independence Metropolis-Hastings step on device tensors."""
+    n, N = state.shape
+    _check(load().imh_step(n, N, _ptr(state), _ptr(state_lp), _ptr(state_lq), _ptr(prop),
+                           _ptr(prop_lp), _ptr(prop_lq), seed, step, _ptr(accepted), _stream()))
+
+
+def run_imh(ctx, theta, made, params, n_chains, n_steps, seed=0, record=None, init=None):
+    """Independence MH chains driven by the learned proposal: every step draws
+    one proposal per chain from q, evaluates ln|Psi| of the proposals with
+    peps_amplitude and accepts with the PEPS as the judge. Chains start from
+    `init` (uint8 [n_chains][N] on the device, e.g. local-Metropolis samples)
+    or from a draw of q. Returns the final states, the visited states per
+    step ([n_steps][n_chains][N] if record) and the acceptance counts."""
+    import torch
+    dev = theta.device
+    if init is None:
+        state, st_lq = made.sample(params, n_chains, seed=seed, offset=0)
+    else:
+        state = init.clone().contiguous()
+        st_lq = made.logq(params, state)
+    st_lp, _ = ctx.amplitude(theta, state)
+    acc = torch.zeros(n_chains, dtype=torch.int32, device=dev)
+    hist = [] if record else None
+    for t in range(1, n_steps + 1):
+        prop, pr_lq = made.sample(params, n_chains, seed=seed, offset=t)
+        pr_lp, _ = ctx.amplitude(theta, prop)
+        imh_step(state, st_lp, st_lq, prop, pr_lp, pr_lq, seed, t, acc)
+        if record:
+            hist.append(state.clone())
+    return state, (torch.stack(hist) if record else None), acc

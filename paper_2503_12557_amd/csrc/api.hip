@@ -737,4 +737,118 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
   return PEPS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// learned proposal
+// ---------------------------------------------------------------------------
+struct made_ctx {
+  int N, H, n_up, bf16;
+  DevBuf a, lg, dlg, da, logq;
+};
+
+peps_status made_create(int N, int H, int n_up, int bf16, made_ctx** out) {
+  if (!out) return fail(PEPS_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (N < 2 || N > 4096) return fail(PEPS_ERR_ARG, "N = %d outside 2..4096", N);
+  if (H < 1 || H > 256) return fail(PEPS_ERR_UNSUPPORTED, "hidden width %d outside 1..256", H);
+  if (n_up < -1 || n_up > N) return fail(PEPS_ERR_ARG, "n_up = %d outside -1..N", n_up);
+  made_ctx* m = new made_ctx();
+  m->N = N;
+  m->H = H;
+  m->n_up = n_up;
+  m->bf16 = bf16 ? 1 : 0;
+  *out = m;
+  return PEPS_OK;
+}
+
+void made_destroy(made_ctx* m) {
+  if (!m) return;
+  m->a.release();
+  m->lg.release();
+  m->dlg.release();
+  m->da.release();
+  m->logq.release();
+  delete m;
+}
+
+size_t made_num_params(const made_ctx* m) {
+  return m ? (size_t)2 * m->N * m->H + m->N + m->H : 0;
+}
+
+static peps_status made_ws(made_ctx* m, int B, bool grad) {
+  peps_status s;
+  if ((s = m->a.ensure((size_t)B * m->H * sizeof(float))) != PEPS_OK) return s;
+  if ((s = m->lg.ensure((size_t)B * m->N * sizeof(float))) != PEPS_OK) return s;
+  if ((s = m->logq.ensure((size_t)B * sizeof(double))) != PEPS_OK) return s;
+  if (grad) {
+    if ((s = m->dlg.ensure((size_t)B * m->N * sizeof(float))) != PEPS_OK) return s;
+    if ((s = m->da.ensure((size_t)B * m->H * sizeof(float))) != PEPS_OK) return s;
+  }
+  return PEPS_OK;
+}
+
+peps_status made_loss_grad(made_ctx* m, const float* params, const uint8_t* x, int B,
+                           float* grads, double* loss, void* stream) {
+  if (!m || !params || !x || !grads || !loss) return fail(PEPS_ERR_ARG, "null pointer");
+  if (B < 1) return fail(PEPS_ERR_ARG, "batch %d < 1", B);
+  peps_status s = made_ws(m, B, true);
+  if (s != PEPS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_made_forward(m->N, m->H, m->n_up, m->bf16, params, x, B, (float*)m->a.p,
+                             (float*)m->lg.p, st));
+  HIPCHK(launch_made_head(m->N, m->H, m->n_up, x, B, (const float*)m->lg.p, (float*)m->dlg.p,
+                          (double*)m->logq.p, st));
+  HIPCHK(launch_made_backward(m->N, m->H, m->n_up, m->bf16, params, x, B, (const float*)m->a.p,
+                              (const float*)m->dlg.p, (float*)m->da.p, grads,
+                              (const double*)m->logq.p, loss, st));
+  return PEPS_OK;
+}
+
+peps_status made_adam_step(made_ctx* m, float* params, const float* grads, float* mom,
+                           float* var, int t, double lr, double beta1, double beta2, double eps,
+                           void* stream) {
+  if (!m || !params || !grads || !mom || !var) return fail(PEPS_ERR_ARG, "null pointer");
+  if (t < 1) return fail(PEPS_ERR_ARG, "Adam step counter starts at 1");
+  if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(PEPS_ERR_ARG, "bad Adam hyper-parameters");
+  HIPCHK(launch_made_adam((int)made_num_params(m), params, grads, mom, var, t, (float)lr,
+                          (float)beta1, (float)beta2, (float)eps, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
+peps_status made_sample(made_ctx* m, const float* params, int n, uint64_t seed, uint64_t offset,
+                        uint8_t* out, double* logq, void* stream) {
+  if (!m || !params || !out || !logq) return fail(PEPS_ERR_ARG, "null pointer");
+  if (n < 0) return fail(PEPS_ERR_ARG, "negative count");
+  if (n == 0) return PEPS_OK;
+  HIPCHK(launch_made_sample(m->N, m->H, m->n_up, m->bf16, params, n, seed, offset, out, logq,
+                            (hipStream_t)stream));
+  return PEPS_OK;
+}
+
+peps_status made_logq(made_ctx* m, const float* params, const uint8_t* x, int n, double* logq,
+                      void* stream) {
+  if (!m || !params || !x || !logq) return fail(PEPS_ERR_ARG, "null pointer");
+  if (n < 0) return fail(PEPS_ERR_ARG, "negative count");
+  if (n == 0) return PEPS_OK;
+  peps_status s = made_ws(m, n, false);
+  if (s != PEPS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_made_forward(m->N, m->H, m->n_up, m->bf16, params, x, n, (float*)m->a.p,
+                             (float*)m->lg.p, st));
+  HIPCHK(launch_made_head(m->N, m->H, m->n_up, x, n, (const float*)m->lg.p, nullptr, logq, st));
+  return PEPS_OK;
+}
+
+peps_status imh_step(int n_chains, int N, uint8_t* state, double* state_logpsi,
+                     double* state_logq, const uint8_t* prop, const double* prop_logpsi,
+                     const double* prop_logq, uint64_t seed, uint64_t step, int32_t* accepted,
+                     void* stream) {
+  if (n_chains < 1 || N < 1) return fail(PEPS_ERR_ARG, "bad sizes");
+  if (!state || !state_logpsi || !state_logq || !prop || !prop_logpsi || !prop_logq)
+    return fail(PEPS_ERR_ARG, "null pointer");
+  HIPCHK(launch_imh(n_chains, N, state, state_logpsi, state_logq, prop, prop_logpsi, prop_logq,
+                    seed, step, accepted, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
 }  // extern "C"

@@ -66,6 +66,24 @@ hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta
                              double* logscr, void* rscr, void* rt1, void* rt2, int jac_sweeps,
                              hipStream_t st);
 
+// learned proposal
+hipError_t launch_made_forward(int N, int H, int n_up, int bf16, const float* P,
+                               const uint8_t* x, int B, float* a, float* lg, hipStream_t st);
+hipError_t launch_made_head(int N, int H, int n_up, const uint8_t* x, int B, const float* lg,
+                            float* dlg, double* logq, hipStream_t st);
+hipError_t launch_made_backward(int N, int H, int n_up, int bf16, const float* P,
+                                const uint8_t* x, int B, const float* a, const float* dlg,
+                                float* da, float* G, const double* logq, double* loss,
+                                hipStream_t st);
+hipError_t launch_made_adam(int n, float* P, const float* G, float* m, float* v, int t, float lr,
+                            float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_made_sample(int N, int H, int n_up, int bf16, const float* P, int n,
+                              uint64_t seed, uint64_t offset, uint8_t* out, double* logq,
+                              hipStream_t st);
+hipError_t launch_imh(int n_chains, int N, uint8_t* state, double* st_lp, double* st_lq,
+                      const uint8_t* prop, const double* pr_lp, const double* pr_lq, uint64_t seed,
+                      uint64_t step, int* accepted, hipStream_t st);
+
 // minSR
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,

@@ -1,0 +1,164 @@
+"""The learned proposal on the GPU against the FP64 oracle: loss, gradient,
+ln q and the Adam step (FP32 kernels, 1e-5 relative), the sampler's
+distribution (chi-square against q enumerated over the S^z = 0 sector), the
+independence-MH chain's distribution (chi-square against |Psi|^2), and what
+training buys: the trained proposal's IMH acceptance rises above the
+untrained one's and agrees with the exact acceptance computed by
+enumeration."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth
+from oracle import made as OM
+from oracle import peps
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _made(N, H, n_up, bf16=False):
+    from paper_2503_12557_amd.binding import Made
+    return Made(N, H, n_up, bf16)
+
+
+@pytest.mark.parametrize("N,H,n_up,B", [(16, 32, 8, 64), (36, 100, 18, 200), (64, 256, -1, 130)])
+def test_loss_grad_logq_match_oracle(dev, N, H, n_up, B):
+    nu = None if n_up < 0 else n_up
+    p = OM.init_params(N, H, seed=N, scale=0.3)
+    if nu is None:
+        x = synth.bit_configs(N, B, seed=2)
+    else:
+        x = synth.sz0_configs(N, B, seed=2)
+    m = _made(N, H, nu)
+    pt = torch.tensor(p, dtype=torch.float32, device=dev)
+    xt = torch.from_numpy(x).to(dev)
+    loss, g = m.loss_grad(pt, xt)
+    lq = m.logq(pt, xt)
+    torch.cuda.synchronize()
+    p32 = pt.double().cpu().numpy()  # the oracle sees the FP32-rounded parameters
+    ref_loss, ref_g = OM.loss_and_grad(p32, x, N, H, nu)
+    ref_lq = OM.log_q(p32, x, N, H, nu)
+    assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert np.abs(g.double().cpu().numpy() - ref_g).max() <= 1e-5 * np.abs(ref_g).max()
+    assert np.abs(lq.cpu().numpy() - ref_lq).max() <= 1e-5 * np.abs(ref_lq).max()
+
+
+def test_adam_step_matches_oracle(dev):
+    N, H = 16, 32
+    m = _made(N, H, 8)
+    rng = np.random.default_rng(1)
+    n = m.n_params
+    p, g = rng.standard_normal(n), rng.standard_normal(n)
+    mo, v = rng.random(n) * 0.1, rng.random(n) * 0.01
+    t = lambda a: torch.tensor(a, dtype=torch.float32, device=dev)
+    pt, gt, mt, vt = t(p), t(g), t(mo), t(v)
+    m.adam(pt, gt, mt, vt, 7, lr=1e-3)
+    # the kernel holds the hyper-parameters in FP32; the oracle gets the same values
+    f = lambda z: float(np.float32(z))
+    ref, rm, rv = OM.adam(t(p).double().cpu().numpy(), t(g).double().cpu().numpy(),
+                          t(mo).double().cpu().numpy(), t(v).double().cpu().numpy(), 7,
+                          lr=f(1e-3), b1=f(0.9), b2=f(0.999), eps=f(1e-8))
+    assert np.abs(pt.double().cpu().numpy() - ref).max() < 1e-6
+    assert np.abs(mt.double().cpu().numpy() - rm).max() < 1e-6
+    assert np.abs(vt.double().cpu().numpy() - rv).max() < 1e-6 * np.abs(rv).max()
+
+
+def test_sampler_distribution_and_logq(dev):
+    N, H, n_up = 8, 16, 4
+    p = OM.init_params(N, H, seed=5, scale=1.0)
+    m = _made(N, H, n_up)
+    pt = torch.tensor(p, dtype=torch.float32, device=dev)
+    s, lq = m.sample(pt, 40000, seed=3)
+    lq2 = m.logq(pt, s)
+    torch.cuda.synchronize()
+    sn = s.cpu().numpy()
+    assert (np.sum(sn == 0, axis=1) == n_up).all()
+    assert np.abs(lq.cpu().numpy() - lq2.cpu().numpy()).max() < 1e-5
+    confs = OM.enumerate_sector(N, n_up)
+    q = np.exp(OM.log_q(pt.double().cpu().numpy(), confs, N, H, n_up))
+    idx = {tuple(c): i for i, c in enumerate(confs.tolist())}
+    counts = np.zeros(len(confs))
+    for row in sn.tolist():
+        counts[idx[tuple(row)]] += 1
+    exp = q * len(sn)
+    keep = exp > 5
+    c = np.append(counts[keep], counts[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    assert stats.chisquare(c, e).pvalue > 1e-3
+
+
+def test_imh_chain_distribution(dev):
+    from paper_2503_12557_amd import Context
+    from paper_2503_12557_amd.binding import run_imh
+    Lx, Ly, D, chi = 2, 3, 2, 4
+    N = Lx * Ly
+    theta = synth.theta(Lx, Ly, 2, D, seed=3)
+    ctx = Context(Lx, Ly, D, chi, "f64")
+    m = _made(N, 16, 3)
+    pt = torch.tensor(OM.init_params(N, 16, seed=1, scale=0.5), dtype=torch.float32, device=dev)
+    th = torch.from_numpy(theta).to(dev)
+    # chains start from local-Metropolis samples of |Psi|^2, so every step of
+    # an exact IMH chain is distributed as |Psi|^2
+    init, _ = ctx.sample(th, "exchange", n_chains=512, per_chain=1, burn_in=30, seed=2)
+    _, hist, acc = run_imh(ctx, th, m, pt, n_chains=512, n_steps=30, seed=11, record=True,
+                           init=init)
+    visited = hist[2::6].reshape(-1, N).cpu().numpy()
+    confs = OM.enumerate_sector(N, 3)
+    psi = peps.exact_amplitudes(theta, peps.Geometry(Lx, Ly, 2, D), confs)
+    pr = np.abs(psi) ** 2
+    pr /= pr.sum()
+    idx = {tuple(c): i for i, c in enumerate(confs.tolist())}
+    counts = np.zeros(len(confs))
+    for row in visited.tolist():
+        counts[idx[tuple(row)]] += 1
+    exp = pr * len(visited)
+    keep = exp > 5
+    c = np.append(counts[keep], counts[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    if e[-1] == 0:
+        c, e = c[:-1], e[:-1]
+    assert stats.chisquare(c, e).pvalue > 1e-3
+
+
+def test_training_raises_imh_acceptance(dev):
+    # 4x4 exact contraction: train q on the PEPS sampler's configurations and
+    # compare the IMH acceptance before and after with the exact acceptance
+    from paper_2503_12557_amd import Context
+    from paper_2503_12557_amd.binding import run_imh
+    Lx, Ly, D, chi, H = 4, 4, 2, 4, 64
+    N = Lx * Ly
+    theta = synth.theta(Lx, Ly, 2, D, seed=1, mu=0.3)
+    th = torch.from_numpy(theta).to(dev)
+    ctx = Context(Lx, Ly, D, chi, "f32")
+    data, _ = ctx.sample(th, "exchange", n_chains=1024, per_chain=8, burn_in=16, thin=2, seed=4)
+    m = _made(N, H, N // 2)
+    p0 = torch.tensor(OM.init_params(N, H, seed=2, scale=0.05), dtype=torch.float32, device=dev)
+    pt = p0.clone()
+    losses = m.train(pt, data, steps=400, batch=1024, lr=3e-3, seed=0)
+    torch.cuda.synchronize()
+    ls = losses.cpu().numpy()
+    assert ls[-20:].mean() < ls[:20].mean() - 0.5
+    confs = OM.enumerate_sector(N, N // 2)
+    psi = peps.exact_amplitudes(theta, peps.Geometry(Lx, Ly, 2, D), confs)
+    pr = np.abs(psi) ** 2
+    pr /= pr.sum()
+    ct = torch.from_numpy(confs).to(dev)
+    acc_exact = []
+    for p in (p0, pt):
+        q = np.exp(m.logq(p, ct).cpu().numpy())
+        acc_exact.append(OM.exact_imh_acceptance(pr, q / q.sum()))
+    _, _, acc = run_imh(ctx, th, m, pt, n_chains=1024, n_steps=20, seed=9,
+                        init=data[::8].contiguous())
+    emp = acc.sum().item() / (1024 * 20)
+    print(f"exact acceptance untrained {acc_exact[0]:.3f} trained {acc_exact[1]:.3f}, "
+          f"empirical trained {emp:.3f}")
+    assert acc_exact[1] > acc_exact[0] + 0.1
+    assert abs(emp - acc_exact[1]) < 0.03
