@@ -147,6 +147,13 @@ peps_status peps_local_energy(peps_ctx* ctx, const double* theta, const uint8_t*
 peps_status peps_logderiv(peps_ctx* ctx, const double* theta, const uint8_t* samples,
                           int n, const void* env_cache, void* O, void* stream);
 
+/* Vector-Jacobian product of ln Psi over a batch (the backward pass of the
+ * log-amplitude): grad_theta[k] = sum_s g[s] O_k(S_s) with O from
+ * peps_logderiv (compact, compute precision) expanded with zeros where
+ * p != s_xy. g: FP64 [n]; grad_theta: FP64 [N_p], overwritten. */
+peps_status peps_logderiv_vjp(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
+                              const double* g, double* grad_theta, void* stream);
+
 /* Fused amplitude + local energy + log-derivatives of one batch, sharing the
  * environments and the one-row strips between the three; outputs as in the
  * three calls above (any of eloc, O may be NULL). */

@@ -658,6 +658,21 @@ peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n
   return PEPS_OK;
 }
 
+peps_status peps_logderiv_vjp(peps_ctx* c, const void* O, const uint8_t* samples, int n,
+                              const double* g, double* grad_theta, void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
+  if (!grad_theta || (n > 0 && (!O || !samples || !g))) return fail(PEPS_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) {
+    HIPCHK(hipMemsetAsync(grad_theta, 0, (size_t)c->L.n_params * sizeof(double), st));
+    return PEPS_OK;
+  }
+  HIPCHK(launch_vjp(c->L, c->d_tab, c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, O, samples, n,
+                    g, grad_theta, st));
+  return PEPS_OK;
+}
+
 peps_status peps_profile(peps_ctx* c, int enable) {
   if (!c) return fail(PEPS_ERR_ARG, "null context");
   c->prof = enable != 0;

@@ -84,6 +84,10 @@ hipError_t launch_imh(int n_chains, int N, uint8_t* state, double* st_lp, double
                       const uint8_t* prop, const double* pr_lp, const double* pr_lq, uint64_t seed,
                       uint64_t step, int* accepted, hipStream_t st);
 
+hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
+                      const uint8_t* samples, int n, const double* g, double* out,
+                      hipStream_t st);
+
 // minSR
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,

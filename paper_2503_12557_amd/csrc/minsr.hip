@@ -410,6 +410,40 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
   return hipGetLastError();
 }
 
+// grad_k = sum_s g_s O_sk with O expanded from the compact rows (zero where
+// p != s_xy): the vector-Jacobian product of ln Psi over a batch.
+template <typename TO>
+__global__ void k_vjp(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
+                      const uint8_t* __restrict__ samples, int n, const double* __restrict__ g,
+                      double* __restrict__ out) {
+  const int jc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jc >= L.n_compact) return;
+  const int site = tab[L.off_csite + jc];
+  const int j = jc - tab[L.off_compact + site];
+  const int off = tab[L.off_param + site], blk = tab[L.off_block + site];
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int s = 0; s < n; ++s) {
+    const double v = (double)O[(size_t)s * L.n_compact + jc] * g[s];
+    if (pbit(samples[(size_t)s * L.N + site])) acc1 += v;
+    else acc0 += v;
+  }
+  out[off + j] = acc0;
+  out[off + blk + j] = acc1;
+}
+
+hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
+                      const uint8_t* samples, int n, const double* g, double* out,
+                      hipStream_t st) {
+  const int cb = (L.n_compact + 255) / 256;
+  if (mode == MODE_F64)
+    hipLaunchKernelGGL(k_vjp<double>, dim3(cb), dim3(256), 0, st, L, tab, (const double*)O,
+                       samples, n, g, out);
+  else
+    hipLaunchKernelGGL(k_vjp<float>, dim3(cb), dim3(256), 0, st, L, tab, (const float*)O,
+                       samples, n, g, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,
                         double rcond, double* dtheta, double* diag, double* ws_mean,
