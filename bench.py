@@ -101,6 +101,31 @@ def env_flops_per_sample(Lx, Ly, D, chi):
     return total
 
 
+def kernel_source_hash():
+    """Hash of the sources the environment kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "env_dev.h", "env.hip"):
+        with open(os.path.join(ROOT, "paper_2503_12557_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def env_traffic(dtype):
+    """HBM bytes per k_env_sweep launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE + WRITE_SIZE, calibrated by a copy of known size), or
+    None when they were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_env_sweep.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("dtype") != dtype:
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -132,6 +157,63 @@ def cpu_baseline(theta, Lx, Ly, D, chi, configs, seconds=12.0):
                       f"1 BLAS thread), {dt:.1f} s"}
 
 
+def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
+    """Effective samples per second of the energy series: local exchange
+    Metropolis against independence MH with the learned proposal (trained on
+    65536 configurations of the local sampler, 2000 Adam steps by default).
+    Sampling time only; E_loc of the recorded states is evaluated untimed."""
+    import torch
+
+    from paper_2503_12557_amd import analysis
+    from paper_2503_12557_amd.binding import Made, run_imh
+    N = Lx * Ly
+    ctx = Context(Lx, Ly, D, chi, "f32")
+    ctx.set_hamiltonian(ham)
+    chains, T = 256, 32
+    init, _ = ctx.sample(theta, "exchange", n_chains=chains, per_chain=1, burn_in=16, seed=21)
+    _sync()
+    t0 = time.perf_counter()
+    mh, acc_mh = ctx.sample(theta, "exchange", n_chains=chains, per_chain=T, burn_in=0,
+                            seed=22)
+    _sync()
+    t_mh = time.perf_counter() - t0
+    e_mh = ctx.evaluate(theta, mh, want_o=False)[1][:, 0].view(chains, T).cpu().numpy()
+    t0 = time.perf_counter()
+    data, _ = ctx.sample(theta, "exchange", n_chains=1024, per_chain=64, burn_in=16, seed=23)
+    _sync()
+    t_data = time.perf_counter() - t0
+    made = Made(N, 256, N // 2, bf16=True)
+    params = torch.tensor(0.01 * np.random.default_rng(7).standard_normal(made.n_params),
+                          dtype=torch.float32, device=theta.device)
+    t0 = time.perf_counter()
+    losses = made.train(params, data, steps=made_steps, batch=1024, lr=1e-3, seed=0)
+    _sync()
+    t_train = time.perf_counter() - t0
+    ls = losses.cpu().numpy()
+    t0 = time.perf_counter()
+    _, hist, acc = run_imh(ctx, theta, made, params, n_chains=chains, n_steps=T, seed=24,
+                           record=True, init=init)
+    _sync()
+    t_imh = time.perf_counter() - t0
+    states = hist.permute(1, 0, 2).reshape(chains * T, N).contiguous()
+    e_imh = ctx.evaluate(theta, states, want_o=False)[1][:, 0].view(chains, T).cpu().numpy()
+    tau_mh, tau_imh = analysis.tau_int(e_mh), analysis.tau_int(e_imh)
+    sweeps_moves = (2 * Ly - 1) * Lx
+    return {
+        "workload": f"{Lx}x{Ly} D={D} chi={chi} J1-J2 J2/J1=0.5, {chains} chains x {T} "
+                    "steps, energy series, stationary starts",
+        "local_mh": {"tau_int": tau_mh, "ess": chains * T / tau_mh, "seconds": t_mh,
+                     "ess_per_s": chains * T / tau_mh / t_mh,
+                     "acceptance_per_move": float(acc_mh.sum().item()) / (chains * T * sweeps_moves)},
+        "imh_learned": {"tau_int": tau_imh, "ess": chains * T / tau_imh, "seconds": t_imh,
+                        "ess_per_s": chains * T / tau_imh / t_imh,
+                        "acceptance": float(acc.sum().item()) / (chains * T)},
+        "made": {"N": N, "hidden": 256, "bf16_weights": True, "train_configs": int(data.shape[0]),
+                 "adam_steps": made_steps, "train_s": t_train, "data_s": t_data,
+                 "loss_first": float(ls[:20].mean()), "loss_last": float(ls[-20:].mean())},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +223,8 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sampler", default="auto", choices=["auto", "uniform", "metropolis"])
+    ap.add_argument("--no-ess", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--made-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -192,6 +276,12 @@ def main():
     _sync()
     t64 = time.perf_counter() - t0
 
+    # a plain elementwise kernel of known traffic (256 MiB read + 256 MiB
+    # written); its FETCH_SIZE / WRITE_SIZE under rocprofv3 --pmc calibrate
+    # the traffic counters
+    calib = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    torch.mul(calib, 2.0)
+    del calib
     ctx = ctx64 if args.dtype == "f64" else Context(Lx, Ly, D, chi, args.dtype)
     if ctx is not ctx64:
         ctx.set_hamiltonian(ham)
@@ -236,7 +326,7 @@ def main():
     achieved = env_flops / (env_avg_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_env_sweep", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-                "traffic": None,
+                "traffic": env_traffic(args.dtype),
                 "algorithmic_flops_per_launch": env_flops,
                 "avg_launch_ms": env_avg_ms, "dominant_kernel_by_time": dom}
 
@@ -266,6 +356,17 @@ def main():
         "per_kernel": per_kernel,
         "roofline": roofline,
     }
+    # energy error on the mu = 0.5 tensors (positive mean, less cancellation)
+    th5 = torch.from_numpy(synth.theta(Lx, Ly, 2, D, seed=3, mu=0.5)).to(dev)
+    ctx_s5 = Context(Lx, Ly, D, chi, "f32")
+    s5, _ = ctx_s5.sample(th5, "exchange", n_chains=1024, per_chain=1, burn_in=8, seed=5)
+    e5_hi = ctx64.evaluate(th5, s5, want_o=False)[1][:, 0].mean().item()
+    e5_lo = ctx.evaluate(th5, s5, want_o=False)[1][:, 0].double().mean().item()
+    res["energy_rel_err_vs_f64_mu0.5"] = abs(e5_lo - e5_hi) / abs(e5_hi)
+    res["energy_mean_f64_mu0.5"] = e5_hi
+    if not args.no_ess:
+        res["learned_proposal"] = ess_comparison(Context, theta, Lx, Ly, D, chi, ham,
+                                                 args.made_steps)
     if not args.no_cpu:
         k = min(n, 64)
         res["cpu_baseline"] = cpu_baseline(theta_np, Lx, Ly, D, chi, samples[:k].cpu().numpy())

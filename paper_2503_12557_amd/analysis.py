@@ -1,0 +1,34 @@
+"""Chain statistics for the sampler comparison (host side, numpy).
+
+tau_int of a scalar series observed on many chains, with Sokal's automatic
+window: the autocorrelation rho(t) is averaged over chains and the window W
+is the smallest with W >= c * tau(W), tau(W) = 1 + 2 sum_{t=1..W} rho(t).
+The effective sample size of chains x T observations is chains*T / tau_int.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def tau_int(series, c=5.0):
+    x = np.asarray(series, dtype=np.float64)
+    x = x - x.mean(axis=1, keepdims=True)
+    T = x.shape[1]
+    var = float((x * x).mean())
+    if var == 0.0 or T < 2:
+        return 1.0
+    f = np.fft.rfft(x, n=2 * T, axis=1)
+    ac = np.fft.irfft(f * np.conj(f), axis=1)[:, :T].mean(axis=0)
+    ac /= np.arange(T, 0, -1)
+    rho = ac / ac[0]
+    tau = 1.0
+    for W in range(1, T):
+        tau = 1.0 + 2.0 * rho[1:W + 1].sum()
+        if W >= c * tau:
+            break
+    return max(float(tau), 1.0)
+
+
+def ess(series, c=5.0):
+    x = np.asarray(series)
+    return x.size / tau_int(x, c)

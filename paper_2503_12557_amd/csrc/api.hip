@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pepsmin.h"
+#include "pepsmin.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -455,7 +455,10 @@ static int chunk_size(const peps_ctx* c, int n) {
   const size_t per = per_sample_scratch(c);
   size_t ch = c->chunk_budget / (per ? per : 1);
   if (ch < 64) ch = 64;
-  return (int)std::min<size_t>(ch, (size_t)n);
+  if (ch >= (size_t)n) return n;
+  // equal chunks: no small tail launch
+  const size_t nch = ((size_t)n + ch - 1) / ch;
+  return (int)(((size_t)n + nch - 1) / nch);
 }
 
 template <int M>

@@ -125,98 +125,140 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 // ---------------------------------------------------------------------------
 // Strided GEMM over the block: C[i,j] (+)= sum_k A[i*sai + k*sak] * B[k*sbk + j*sbj]
 // written to C[i*sci + j*scj]. Operands may live in LDS or global memory.
+// Lanes run over j (a power of two >= n, at most 64), the rest of the block
+// over i, two rows per thread so each B element is read once for both.
 // The caller synchronises before reading C.
 // ---------------------------------------------------------------------------
 template <int M, typename T>
 __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T* B, int sbk,
                      int sbj, T* C, int sci, int scj, bool acc) {
-  const int tot = m * n;
-  for (int idx = threadIdx.x; idx < tot; idx += PEPS_BLOCK) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    T s = 0;
-    const T* a = A + i * sai;
-    const T* b = B + j * sbj;
-    for (int kk = 0; kk < k; ++kk) s += opnd<M>(a[kk * sak]) * opnd<M>(b[kk * sbk]);
-    T* c = C + i * sci + j * scj;
-    *c = acc ? *c + s : s;
+  int lj = 0;
+  while ((1 << lj) < n && lj < 6) ++lj;
+  const int LJ = 1 << lj;
+  const int tx = threadIdx.x & (LJ - 1), ty = threadIdx.x >> lj;
+  const int rp = PEPS_BLOCK >> lj;
+  for (int i = ty; i < m; i += 2 * rp) {
+    const int i2 = i + rp;
+    const bool two = i2 < m;
+    const T* a1 = A + i * sai;
+    const T* a2 = A + (two ? i2 : i) * sai;
+    for (int j = tx; j < n; j += LJ) {
+      const T* bp = B + j * sbj;
+      T s1 = 0, s2 = 0;
+      for (int kk = 0; kk < k; ++kk) {
+        const T bv = opnd<M>(bp[kk * sbk]);
+        s1 += opnd<M>(a1[kk * sak]) * bv;
+        s2 += opnd<M>(a2[kk * sak]) * bv;
+      }
+      T* c1 = C + i * sci + j * scj;
+      *c1 = acc ? *c1 + s1 : s1;
+      if (two) {
+        T* c2 = C + i2 * sci + j * scj;
+        *c2 = acc ? *c2 + s2 : s2;
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR of the LDS matrix A (m x n, row stride lda), keeping only R:
-// on exit rows 0..min(m,n)-1 hold R (upper trapezoidal) and the rest of
-// column j below the diagonal is zero. v: LDS scratch of m, w: of n,
-// red: reduction scratch.
+// Householder QR keeping only R, for a stacked LDS matrix A (m x n, row
+// stride lda) whose first kr rows are already upper triangular (zero below
+// the diagonal) and whose remaining rows are dense. Reflector j only touches
+// row j and the dense rows, so the triangular block is never swept. On exit
+// rows 0..min(m,n)-1 hold R and every entry below the diagonal is zero.
+// part: LDS scratch of 4 * n elements, red: >= 16 elements. Three barriers
+// per column; lanes run over columns, the four waves over rows, no integer
+// division in the loops. n <= 128.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void house_qr_r(T* A, int m, int n, int lda, T* v, T* w, T* red) {
-  const int tid = threadIdx.x;
+__device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* part, T* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int kmax = m < n ? m : n;
+  int prev_j = -1, prev_r0 = 0;
+  T prev_alpha = 0;
   for (int j = 0; j < kmax; ++j) {
-    T s = 0;
-    for (int i = j + 1 + tid; i < m; i += PEPS_BLOCK) {
-      const T a = A[i * lda + j];
-      s += a * a;
+    const int r0 = kr > j + 1 ? kr : j + 1;
+    // finish the previous column (its entries were read until the last barrier)
+    if (prev_j >= 0) {
+      if (tid == 0) A[prev_j * lda + prev_j] = prev_alpha;
+      for (int i = prev_r0 + tid; i < m; i += PEPS_BLOCK) A[i * lda + prev_j] = T(0);
     }
-    s = block_sum(s, red);
-    if (s == T(0)) continue;  // block-uniform
+    T sq = 0;
+    for (int i = r0 + tid; i < m; i += PEPS_BLOCK) {
+      const T v = A[i * lda + j];
+      sq += v * v;
+    }
+    sq = wave_sum(sq);
+    T* rb = red + (j & 1) * 8;
+    if (lane == 0) rb[wv] = sq;
+    __syncthreads();
+    const T s = rb[0] + rb[1] + rb[2] + rb[3];
+    prev_j = -1;
+    if (s == T(0)) continue;  // block-uniform: nothing to eliminate
     const T ajj = A[j * lda + j];
     const T nrm = sqrt(ajj * ajj + s);
     const T alpha = ajj > T(0) ? -nrm : nrm;
     const T v0 = ajj - alpha;
     const T tau = T(2) / (v0 * v0 + s);
-    for (int i = j + tid; i < m; i += PEPS_BLOCK) v[i] = (i == j) ? v0 : A[i * lda + j];
-    __syncthreads();
-    const int nc = n - j - 1;
-    if (nc > 0) {
-      int G = 64;
-      while (G > 1 && G * nc > PEPS_BLOCK) G >>= 1;
-      const int ncol_par = PEPS_BLOCK / G;
-      const int g = tid / G, lane = tid - (tid / G) * G;
-      for (int c0 = 0; c0 < nc; c0 += ncol_par) {
-        const int c = j + 1 + c0 + g;
-        T p = 0;
-        if (c0 + g < nc)
-          for (int i = j + lane; i < m; i += G) p += v[i] * A[i * lda + c];
-        p = group_sum(p, G);
-        if (lane == 0 && c0 + g < nc) w[c] = tau * p;
-      }
-      __syncthreads();
-      const int nr = m - j;
-      const int tot = nr * nc;
-      for (int idx = tid; idx < tot; idx += PEPS_BLOCK) {
-        const int i = j + idx / nc, c = j + 1 + idx - (idx / nc) * nc;
-        A[i * lda + c] -= v[i] * w[c];
+    // partial w over this wave's rows, lanes over columns; row j is read into
+    // registers here because wave 0 rewrites it after the barrier
+    T rowj[2];
+    for (int c0 = j + 1, h = 0; c0 < n; c0 += 64, ++h) {
+      const int c = c0 + lane;
+      T pw = 0;
+      if (c < n) {
+        rowj[h] = A[j * lda + c];
+        for (int i = r0 + wv; i < m; i += 4) pw += A[i * lda + j] * A[i * lda + c];
+        part[wv * n + c] = pw;
       }
     }
     __syncthreads();
-    if (tid == 0) A[j * lda + j] = alpha;
-    for (int i = j + 1 + tid; i < m; i += PEPS_BLOCK) A[i * lda + j] = T(0);
+    for (int c0 = j + 1, h = 0; c0 < n; c0 += 64, ++h) {
+      const int c = c0 + lane;
+      if (c < n) {
+        const T w = tau * (v0 * rowj[h] + part[c] + part[n + c] + part[2 * n + c] +
+                           part[3 * n + c]);
+        if (wv == 0) A[j * lda + c] -= v0 * w;
+        for (int i = r0 + wv; i < m; i += 4) A[i * lda + c] -= A[i * lda + j] * w;
+      }
+    }
     __syncthreads();
+    prev_j = j;
+    prev_r0 = r0;
+    prev_alpha = alpha;
   }
+  if (prev_j >= 0) {
+    if (tid == 0) A[prev_j * lda + prev_j] = prev_alpha;
+    for (int i = prev_r0 + tid; i < m; i += PEPS_BLOCK) A[i * lda + prev_j] = T(0);
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi on the m rows of the LDS matrix X (m x n, row
-// stride ldx, m <= n, m <= 2*PEPS_BLOCK): rotates pairs of rows until every
-// pair is orthogonal to relative tolerance tol. Pairs follow the circle
-// (round-robin) schedule, m-1 rounds of m/2 disjoint pairs per sweep.
-// Returns the number of sweeps used, or -1 if max_sweeps was reached.
+// stride ldx, m <= n): rotates pairs of rows until every pair is orthogonal
+// to relative tolerance tol. Pairs follow the circle (round-robin) schedule,
+// m-1 rounds of m/2 disjoint pairs per sweep; each pair is held by G lanes,
+// each lane keeping its NC elements of both rows in registers between the
+// dot products and the rotation. Returns the number of sweeps used, or -1
+// if max_sweeps was reached.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag) {
+template <typename T, int NC>
+__device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag,
+                              int G) {
   const int tid = threadIdx.x;
   const int mp = m + (m & 1);
   const int npairs = mp >> 1;
-  if (m < 2) return 0;
-  int G = 64;
-  while (G > 1 && G * npairs > PEPS_BLOCK) G >>= 1;
   const int pr = tid / G, lane = tid - (tid / G) * G;
+  const int per_pass = PEPS_BLOCK / G;
+  // lane owns the contiguous elements [lane*NC, lane*NC + NC) of both rows
+  const int e0 = lane * NC;
+  const bool full = e0 + NC <= n;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) *sflag = 0;
     __syncthreads();
     for (int r = 0; r < mp - 1; ++r) {
-      for (int pb = 0; pb < npairs; pb += PEPS_BLOCK / G) {
+      for (int pb = 0; pb < npairs; pb += per_pass) {
         const int pi = pb + pr;
         int p = -1, q = -1;
         if (pi < npairs) {
@@ -224,19 +266,36 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, i
             p = mp - 1;
             q = r;
           } else {
-            p = (r + pi) % (mp - 1);
-            q = (r - pi + (mp - 1)) % (mp - 1);
+            p = r + pi;
+            if (p >= mp - 1) p -= mp - 1;
+            q = r - pi;
+            if (q < 0) q += mp - 1;
           }
         }
         const bool act = (pi < npairs) && p < m && q < m;
-        T a = 0, b = 0, c = 0;
-        if (act) {
-          for (int e = lane; e < n; e += G) {
-            const T xp = X[p * ldx + e], xq = X[q * ldx + e];
-            a += xp * xp;
-            b += xq * xq;
-            c += xp * xq;
+        T xp[NC], xq[NC];
+        T* rp = X + p * ldx + e0;
+        T* rq = X + q * ldx + e0;
+        if (act && full) {
+#pragma unroll
+          for (int t = 0; t < NC; ++t) {
+            xp[t] = rp[t];
+            xq[t] = rq[t];
           }
+        } else {
+#pragma unroll
+          for (int t = 0; t < NC; ++t) {
+            const bool ok = act && e0 + t < n;
+            xp[t] = ok ? rp[t] : T(0);
+            xq[t] = ok ? rq[t] : T(0);
+          }
+        }
+        T a = 0, b = 0, c = 0;
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          a += xp[t] * xp[t];
+          b += xq[t] * xq[t];
+          c += xp[t] * xq[t];
         }
         a = group_sum(a, G);
         b = group_sum(b, G);
@@ -249,10 +308,19 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, i
           else t = (zeta >= T(0) ? T(1) : T(-1)) / (az + sqrt(T(1) + zeta * zeta));
           const T cs = T(1) / sqrt(T(1) + t * t);
           const T sn = cs * t;
-          for (int e = lane; e < n; e += G) {
-            const T xp = X[p * ldx + e], xq = X[q * ldx + e];
-            X[p * ldx + e] = cs * xp - sn * xq;
-            X[q * ldx + e] = sn * xp + cs * xq;
+          if (full) {
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+              rp[u] = cs * xp[u] - sn * xq[u];
+              rq[u] = sn * xp[u] + cs * xq[u];
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < NC; ++u)
+              if (e0 + u < n) {
+                rp[u] = cs * xp[u] - sn * xq[u];
+                rq[u] = sn * xp[u] + cs * xq[u];
+              }
           }
           if (lane == 0) *sflag = 1;
         }
@@ -264,6 +332,21 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, i
     if (f == 0) return sweep + 1;
   }
   return -1;
+}
+
+template <typename T>
+__device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag) {
+  if (m < 2) return 0;
+  const int npairs = (m + (m & 1)) >> 1;
+  int G = 64;
+  while (G > 1 && G * npairs > PEPS_BLOCK) G >>= 1;
+  const int nc = (n + G - 1) / G;
+  if (nc <= 1) return jacobi_rows_nc<T, 1>(X, m, n, ldx, tol, max_sweeps, sflag, G);
+  if (nc <= 2) return jacobi_rows_nc<T, 2>(X, m, n, ldx, tol, max_sweeps, sflag, G);
+  if (nc <= 4) return jacobi_rows_nc<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G);
+  if (nc <= 8) return jacobi_rows_nc<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G);
+  if (nc <= 16) return jacobi_rows_nc<T, 16>(X, m, n, ldx, tol, max_sweeps, sflag, G);
+  return jacobi_rows_nc<T, 32>(X, m, n, ldx, tol, max_sweeps, sflag, G);
 }
 
 // ---------------------------------------------------------------------------

@@ -65,7 +65,7 @@ __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
 
 inline size_t env_lds_elems_(int bmax, int D) {
   const size_t BD = (size_t)bmax * D;
-  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + 3 * BD * BD + 2 * BD * bmax +
+  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + 3 * BD * BD + 2 * BD + 2 * BD * bmax +
          4 * BD + 16;
 }
 
@@ -79,9 +79,11 @@ struct EnvSmem {
     Ebuf = sm;
     Abuf = Ebuf + B * D * B;
     P = Abuf + D * D * D * D;   // P_k (left) / T1 (right)
-    S = P + BD * BD;            // stacked QR buffer (left) / C and Z (right)
-    Z = S + BD * BD;
-    W = S + 2 * BD * BD;
+    // stacked QR buffer (left) / C then Z (right); rows padded by one
+    // element so rows of the LDS matrices fall on different banks
+    S = P + BD * BD;
+    Z = S + BD * (BD + 1);
+    W = S + 2 * BD * (BD + 1);
     Bn = W + BD * B;
     vv = Bn + B * BD;
     ww = vv + 2 * BD;
@@ -181,18 +183,18 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         __syncthreads();
         // M_k = R_{y-1} P_k into rows kr.. of the stack
         if (y == 0) {
-          for (int i = tid; i < Pr; i += PEPS_BLOCK) S[kr * Pr + i] = P[i];
+          for (int i = tid; i < Pr; i += PEPS_BLOCK) S[kr * (Pr + 1) + i] = P[i];
         } else {
-          gemm<M>(kprev, Pr, Pl, Rp, Pl, 1, P, Pr, 1, S + kr * Pr, Pr, 1, false);
+          gemm<M>(kprev, Pr, Pl, Rp, Pl, 1, P, Pr, 1, S + kr * (Pr + 1), Pr + 1, 1, false);
         }
         __syncthreads();
         const int m = kr + kprev;
-        house_qr_r(S, m, Pr, Pr, vv, ww, red);
+        house_qr_stacked(S, kr, m, Pr, Pr + 1, vv, red);
         kr = m < Pr ? m : Pr;
       }
       // store R_y (kr x Pr, row stride Pr)
       T* Ry = R + (size_t)y * BD * BD;
-      for (int i = tid; i < kr * Pr; i += PEPS_BLOCK) Ry[i] = S[i];
+      for (int i = tid; i < kr * Pr; i += PEPS_BLOCK) Ry[i] = S[(i / Pr) * (Pr + 1) + i % Pr];
       __syncthreads();
       kprev = kr;
     }
@@ -249,19 +251,20 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         }
         const T* Rp = R + (size_t)(y - 1) * BD * BD;
         // C = R_{y-1} Z  (kp x zc)
-        gemm<M>(kp, zc, Pl, Rp, Pl, 1, Z, zc, 1, S, zc, 1, false);
+        const int ldc = zc + 1;
+        gemm<M>(kp, zc, Pl, Rp, Pl, 1, Z, zc, 1, S, ldc, 1, false);
         __syncthreads();
         int m = kp;
         if (m > zc) {
-          house_qr_r(S, m, zc, zc, vv, ww, red);
+          house_qr_stacked(S, 0, m, zc, ldc, vv, red);
           m = zc;
         }
-        const int used = jacobi_rows(S, m, zc, zc, tol, jac_sweeps, sflag);
+        const int used = jacobi_rows(S, m, zc, ldc, tol, jac_sweeps, sflag);
         if (used < 0 && tid == 0) fl |= 4;
         // row norms
         for (int i = tid; i < m; i += PEPS_BLOCK) {
           T q = 0;
-          for (int e = 0; e < zc; ++e) q += S[i * zc + e] * S[i * zc + e];
+          for (int e = 0; e < zc; ++e) q += S[i * ldc + e] * S[i * ldc + e];
           sig[i] = sqrt(q);
         }
         __syncthreads();
@@ -294,7 +297,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         for (int i = tid; i < rnew * zc; i += PEPS_BLOCK) {
           const int j = i / zc, e = i - j * zc;
           const T sj = sig[sel[j]];
-          Bn[i] = (sj > thresh) ? S[sel[j] * zc + e] / sj : T(0);
+          Bn[i] = (sj > thresh) ? S[sel[j] * ldc + e] / sj : T(0);
         }
         __syncthreads();
         // W_y[(a,l), j] = sum_e Z[(a,l), e] Bn[j, e]

@@ -105,3 +105,15 @@ def test_adam_first_step_is_sign_step():
     p2, m, v = made.adam(p, g, np.zeros(3), np.zeros(3), 1, lr=1e-3)
     assert np.allclose(p2[:2], p[:2] - 1e-3 * np.sign(g[:2]), atol=1e-9)
     assert p2[2] == p[2]
+
+
+def test_product_tau_int_matches_oracle_definition():
+    # the product's FFT-based tau_int against the oracle's direct sums
+    from paper_2503_12557_amd import analysis
+    rng = np.random.default_rng(9)
+    C, T, a = 16, 600, 0.6
+    x = np.zeros((C, T))
+    e = rng.standard_normal((C, T))
+    for t in range(1, T):
+        x[:, t] = a * x[:, t - 1] + e[:, t]
+    assert abs(analysis.tau_int(x) - made.integrated_autocorr(x)) < 1e-8
