@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define PEPS_BLOCK 256
+#define PEPS_BLOCK_MAX 512
+// threads of the running block (launches use 256 or 512)
+#define PEPS_NT ((int)blockDim.x)
 
 namespace pm {
 
@@ -16,6 +18,11 @@ namespace pm {
 // nearest even) and the products are accumulated in FP32.
 // ---------------------------------------------------------------------------
 enum Mode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
+
+// Threads per environment / sampler workgroup: FP64 holds more LDS per
+// workgroup (one per CU), so it runs eight waves; the FP32 modes fit two
+// workgroups per CU and run four waves each.
+__host__ __device__ constexpr int env_threads(int mode) { return mode == 0 ? 512 : 256; }
 
 template <int M> struct ModeT;
 template <> struct ModeT<MODE_F64> { typedef double T; };
@@ -96,7 +103,7 @@ __device__ T block_sum(T v, T* red) {
   __syncthreads();
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < PEPS_BLOCK / 64; ++i) s += red[i];
+  for (int i = 0; i < PEPS_NT / 64; ++i) s += red[i];
   __syncthreads();
   return s;
 }
@@ -110,7 +117,7 @@ __device__ T block_max(T v, T* red) {
   __syncthreads();
   T s = red[0];
 #pragma unroll
-  for (int i = 1; i < PEPS_BLOCK / 64; ++i) s = red[i] > s ? red[i] : s;
+  for (int i = 1; i < PEPS_NT / 64; ++i) s = red[i] > s ? red[i] : s;
   __syncthreads();
   return s;
 }
@@ -136,7 +143,7 @@ __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T*
   while ((1 << lj) < n && lj < 6) ++lj;
   const int LJ = 1 << lj;
   const int tx = threadIdx.x & (LJ - 1), ty = threadIdx.x >> lj;
-  const int rp = PEPS_BLOCK >> lj;
+  const int rp = PEPS_NT >> lj;
   for (int i = ty; i < m; i += 2 * rp) {
     const int i2 = i + rp;
     const bool two = i2 < m;
@@ -162,74 +169,85 @@ __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T*
 
 // ---------------------------------------------------------------------------
 // Householder QR keeping only R, for a stacked LDS matrix A (m x n, row
-// stride lda) whose first kr rows are already upper triangular (zero below
-// the diagonal) and whose remaining rows are dense. Reflector j only touches
-// row j and the dense rows, so the triangular block is never swept. On exit
-// rows 0..min(m,n)-1 hold R and every entry below the diagonal is zero.
-// part: LDS scratch of 4 * n elements, red: >= 16 elements. Three barriers
-// per column; lanes run over columns, the four waves over rows, no integer
-// division in the loops. n <= 128.
+// stride lda, n <= 256) whose first kr rows are already upper triangular
+// (zero below the diagonal) and whose remaining rows are dense. Reflector j
+// only touches row j and the dense rows, so the triangular block is never
+// swept. On exit rows 0..min(m,n)-1 hold R and every entry below the
+// diagonal is zero. Column c belongs to wave (c mod waves); inside the wave four
+// lanes share a column and split its rows, so the reflector's dot products
+// reduce over four lanes without touching LDS, and each column costs one
+// barrier: the wave that owns column j+1 also sums its squares for the next
+// reflector. nrm: LDS scratch of >= 2 elements.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* part, T* red) {
+__device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* nrm) {
+  const int NW = PEPS_NT / 64;  // waves in the block
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int sub = lane & 3, cl = lane >> 2;  // row subset, column slot in the wave
   const int kmax = m < n ? m : n;
-  int prev_j = -1, prev_r0 = 0;
-  T prev_alpha = 0;
+  if (kmax <= 0) return;
+  // squares of column 0 below its diagonal (rows >= max(kr, 1))
+  if (wv == 0) {
+    const int r0 = kr > 1 ? kr : 1;
+    T sq = 0;
+    for (int i = r0 + lane; i < m; i += 64) sq += A[i * lda] * A[i * lda];
+    sq = wave_sum(sq);
+    if (lane == 0) nrm[0] = sq;
+  }
+  __syncthreads();
   for (int j = 0; j < kmax; ++j) {
     const int r0 = kr > j + 1 ? kr : j + 1;
-    // finish the previous column (its entries were read until the last barrier)
-    if (prev_j >= 0) {
-      if (tid == 0) A[prev_j * lda + prev_j] = prev_alpha;
-      for (int i = prev_r0 + tid; i < m; i += PEPS_BLOCK) A[i * lda + prev_j] = T(0);
+    const T s = nrm[j & 1];
+    const int r0n = kr > j + 2 ? kr : j + 2;  // rows of the next reflector
+    if (s == T(0)) {
+      // nothing to eliminate in column j; the next column's squares are
+      // still needed
+      if (j + 1 < kmax && ((j + 1) % NW) == wv) {
+        T sq = 0;
+        for (int i = r0n + lane; i < m; i += 64) sq += A[i * lda + j + 1] * A[i * lda + j + 1];
+        sq = wave_sum(sq);
+        if (lane == 0) nrm[(j + 1) & 1] = sq;
+      }
+      __syncthreads();
+      continue;
     }
-    T sq = 0;
-    for (int i = r0 + tid; i < m; i += PEPS_BLOCK) {
-      const T v = A[i * lda + j];
-      sq += v * v;
-    }
-    sq = wave_sum(sq);
-    T* rb = red + (j & 1) * 8;
-    if (lane == 0) rb[wv] = sq;
-    __syncthreads();
-    const T s = rb[0] + rb[1] + rb[2] + rb[3];
-    prev_j = -1;
-    if (s == T(0)) continue;  // block-uniform: nothing to eliminate
     const T ajj = A[j * lda + j];
-    const T nrm = sqrt(ajj * ajj + s);
-    const T alpha = ajj > T(0) ? -nrm : nrm;
+    const T nr = sqrt(ajj * ajj + s);
+    const T alpha = ajj > T(0) ? -nr : nr;
     const T v0 = ajj - alpha;
     const T tau = T(2) / (v0 * v0 + s);
-    // partial w over this wave's rows, lanes over columns; row j is read into
-    // registers here because wave 0 rewrites it after the barrier
-    T rowj[2];
-    for (int c0 = j + 1, h = 0; c0 < n; c0 += 64, ++h) {
-      const int c = c0 + lane;
-      T pw = 0;
-      if (c < n) {
-        rowj[h] = A[j * lda + c];
-        for (int i = r0 + wv; i < m; i += 4) pw += A[i * lda + j] * A[i * lda + c];
-        part[wv * n + c] = pw;
+    // columns c > j owned by this lane: c = NW * (16 q + cl) + wv
+    for (int q = 0; q < 256 / (16 * NW); ++q) {
+      const int c = NW * (16 * q + cl) + wv;
+      const bool own = c > j && c < n;  // uniform across the four lanes of c
+      T d = 0;
+      T rowj = 0;
+      if (own) {
+        rowj = A[j * lda + c];
+        for (int i = r0 + sub; i < m; i += 4) d += A[i * lda + j] * A[i * lda + c];
+      }
+      d += __shfl_xor(d, 1, 64);
+      d += __shfl_xor(d, 2, 64);
+      T sqn = 0;
+      if (own) {
+        const T w = tau * (v0 * rowj + d);
+        if (sub == 0) A[j * lda + c] = rowj - v0 * w;
+        for (int i = r0 + sub; i < m; i += 4) {
+          const T nv = A[i * lda + c] - A[i * lda + j] * w;
+          A[i * lda + c] = nv;
+          if (i >= r0n) sqn += nv * nv;
+        }
+      }
+      if (c == j + 1 && j + 1 < kmax) {  // this column feeds the next reflector
+        sqn += __shfl_xor(sqn, 1, 64);
+        sqn += __shfl_xor(sqn, 2, 64);
+        if (sub == 0) nrm[(j + 1) & 1] = sqn;
       }
     }
     __syncthreads();
-    for (int c0 = j + 1, h = 0; c0 < n; c0 += 64, ++h) {
-      const int c = c0 + lane;
-      if (c < n) {
-        const T w = tau * (v0 * rowj[h] + part[c] + part[n + c] + part[2 * n + c] +
-                           part[3 * n + c]);
-        if (wv == 0) A[j * lda + c] -= v0 * w;
-        for (int i = r0 + wv; i < m; i += 4) A[i * lda + c] -= A[i * lda + j] * w;
-      }
-    }
-    __syncthreads();
-    prev_j = j;
-    prev_r0 = r0;
-    prev_alpha = alpha;
-  }
-  if (prev_j >= 0) {
-    if (tid == 0) A[prev_j * lda + prev_j] = prev_alpha;
-    for (int i = prev_r0 + tid; i < m; i += PEPS_BLOCK) A[i * lda + prev_j] = T(0);
+    // column j is final: R_jj = alpha, zeros below (nobody reads it again)
+    if (tid == 0) A[j * lda + j] = alpha;
+    for (int i = r0 + tid; i < m; i += PEPS_NT) A[i * lda + j] = T(0);
   }
   __syncthreads();
 }
@@ -243,18 +261,60 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* part, T
 // dot products and the rotation. Returns the number of sweeps used, or -1
 // if max_sweeps was reached.
 // ---------------------------------------------------------------------------
+// NC contiguous elements through 16-byte LDS accesses (caller checks alignment)
+template <typename T, int NC>
+__device__ __forceinline__ void load16(const T* src, T* dst) {
+  constexpr int W = 16 / sizeof(T);
+#pragma unroll
+  for (int t = 0; t < NC; t += W) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(src + t);
+      dst[t] = v.x;
+      dst[t + 1] = v.y;
+      dst[t + 2] = v.z;
+      dst[t + 3] = v.w;
+    } else {
+      const double2 v = *reinterpret_cast<const double2*>(src + t);
+      dst[t] = v.x;
+      dst[t + 1] = v.y;
+    }
+  }
+}
+template <typename T, int NC>
+__device__ __forceinline__ void store16(T* dst, const T* src) {
+  constexpr int W = 16 / sizeof(T);
+#pragma unroll
+  for (int t = 0; t < NC; t += W) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(dst + t) = make_float4(src[t], src[t + 1], src[t + 2], src[t + 3]);
+    } else {
+      *reinterpret_cast<double2*>(dst + t) = make_double2(src[t], src[t + 1]);
+    }
+  }
+}
+
 template <typename T, int NC>
 __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag,
-                              int G) {
+                              int G, T* nrm) {
   const int tid = threadIdx.x;
   const int mp = m + (m & 1);
   const int npairs = mp >> 1;
   const int pr = tid / G, lane = tid - (tid / G) * G;
-  const int per_pass = PEPS_BLOCK / G;
+  const int per_pass = PEPS_NT / G;
   // lane owns the contiguous elements [lane*NC, lane*NC + NC) of both rows
   const int e0 = lane * NC;
   const bool full = e0 + NC <= n;
+  // 16-byte LDS accesses when every owned run is 16-byte aligned
+  const bool vec = (NC * sizeof(T)) % 16 == 0 && (ldx * sizeof(T)) % 16 == 0 &&
+                   (reinterpret_cast<uintptr_t>(X) & 15) == 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // squared row norms, refreshed every sweep and then carried through the
+    // rotations: a' = a - t c, b' = b + t c
+    for (int i = tid; i < m; i += PEPS_NT) {
+      T q2 = 0;
+      for (int e = 0; e < n; ++e) q2 += X[i * ldx + e] * X[i * ldx + e];
+      nrm[i] = q2;
+    }
     if (tid == 0) *sflag = 0;
     __syncthreads();
     for (int r = 0; r < mp - 1; ++r) {
@@ -276,7 +336,10 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
         T xp[NC], xq[NC];
         T* rp = X + p * ldx + e0;
         T* rq = X + q * ldx + e0;
-        if (act && full) {
+        if (act && full && vec) {
+          load16<T, NC>(rp, xp);
+          load16<T, NC>(rq, xq);
+        } else if (act && full) {
 #pragma unroll
           for (int t = 0; t < NC; ++t) {
             xp[t] = rp[t];
@@ -290,16 +353,11 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
             xq[t] = ok ? rq[t] : T(0);
           }
         }
-        T a = 0, b = 0, c = 0;
+        T c = 0;
 #pragma unroll
-        for (int t = 0; t < NC; ++t) {
-          a += xp[t] * xp[t];
-          b += xq[t] * xq[t];
-          c += xp[t] * xq[t];
-        }
-        a = group_sum(a, G);
-        b = group_sum(b, G);
+        for (int t = 0; t < NC; ++t) c += xp[t] * xq[t];
         c = group_sum(c, G);
+        const T a = act ? nrm[p] : T(0), b = act ? nrm[q] : T(0);
         if (act && c != T(0) && fabs(c) > tol * sqrt(a * b)) {
           const T zeta = (b - a) / (T(2) * c);
           const T az = fabs(zeta);
@@ -309,10 +367,21 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
           const T cs = T(1) / sqrt(T(1) + t * t);
           const T sn = cs * t;
           if (full) {
+            T yp[NC], yq[NC];
 #pragma unroll
             for (int u = 0; u < NC; ++u) {
-              rp[u] = cs * xp[u] - sn * xq[u];
-              rq[u] = sn * xp[u] + cs * xq[u];
+              yp[u] = cs * xp[u] - sn * xq[u];
+              yq[u] = sn * xp[u] + cs * xq[u];
+            }
+            if (vec) {
+              store16<T, NC>(rp, yp);
+              store16<T, NC>(rq, yq);
+            } else {
+#pragma unroll
+              for (int u = 0; u < NC; ++u) {
+                rp[u] = yp[u];
+                rq[u] = yq[u];
+              }
             }
           } else {
 #pragma unroll
@@ -322,7 +391,11 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
                 rq[u] = sn * xp[u] + cs * xq[u];
               }
           }
-          if (lane == 0) *sflag = 1;
+          if (lane == 0) {
+            *sflag = 1;
+            nrm[p] = a - t * c;
+            nrm[q] = b + t * c;
+          }
         }
       }
       __syncthreads();
@@ -335,18 +408,19 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
 }
 
 template <typename T>
-__device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag) {
+__device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag,
+                           T* nrm) {
   if (m < 2) return 0;
   const int npairs = (m + (m & 1)) >> 1;
   int G = 64;
-  while (G > 1 && G * npairs > PEPS_BLOCK) G >>= 1;
+  while (G > 1 && G * npairs > PEPS_NT) G >>= 1;
   const int nc = (n + G - 1) / G;
-  if (nc <= 1) return jacobi_rows_nc<T, 1>(X, m, n, ldx, tol, max_sweeps, sflag, G);
-  if (nc <= 2) return jacobi_rows_nc<T, 2>(X, m, n, ldx, tol, max_sweeps, sflag, G);
-  if (nc <= 4) return jacobi_rows_nc<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G);
-  if (nc <= 8) return jacobi_rows_nc<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G);
-  if (nc <= 16) return jacobi_rows_nc<T, 16>(X, m, n, ldx, tol, max_sweeps, sflag, G);
-  return jacobi_rows_nc<T, 32>(X, m, n, ldx, tol, max_sweeps, sflag, G);
+  if (nc <= 1) return jacobi_rows_nc<T, 1>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  if (nc <= 2) return jacobi_rows_nc<T, 2>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  if (nc <= 4) return jacobi_rows_nc<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  if (nc <= 8) return jacobi_rows_nc<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  if (nc <= 16) return jacobi_rows_nc<T, 16>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  return jacobi_rows_nc<T, 32>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,7 +23,7 @@ namespace pm {
 size_t env_lds_elems(int bmax, int D) { return env_lds_elems_(bmax, D); }
 
 template <int M>
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
             const uint8_t* __restrict__ samples, typename ModeT<M>::T* __restrict__ env,
             double* __restrict__ logs, typename ModeT<M>::T* __restrict__ rscr,
@@ -52,7 +52,7 @@ k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* 
 
 // ln(E^u[i] . E^l[i+1]) + scales for one sample per workgroup.
 template <int M>
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_overlap(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ env,
           const double* __restrict__ logs, int icut, double* __restrict__ logpsi,
           int* __restrict__ flags, int n) {
@@ -120,7 +120,7 @@ hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
   hipFuncSetAttribute((const void*)k_env_sweep<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   dim3 grid(n, 2);
-  hipLaunchKernelGGL(k_env_sweep<M>, grid, dim3(PEPS_BLOCK), lds, st, L, tab, (const T*)theta,
+  hipLaunchKernelGGL(k_env_sweep<M>, grid, dim3(env_threads(M)), lds, st, L, tab, (const T*)theta,
                      samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps);
   return hipGetLastError();
 }
@@ -130,7 +130,7 @@ hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, con
                           int icut, double* logpsi, int* flags, int n, hipStream_t st) {
   typedef typename ModeT<M>::T T;
   const size_t lds = (size_t)(L.bmax * L.bmax + L.bmax * L.D * L.bmax) * sizeof(T);
-  hipLaunchKernelGGL(k_overlap<M>, dim3(n), dim3(PEPS_BLOCK), lds, st, L, tab, (const T*)env,
+  hipLaunchKernelGGL(k_overlap<M>, dim3(n), dim3(256), lds, st, L, tab, (const T*)env,
                      logs, icut, logpsi, flags, n);
   return hipGetLastError();
 }

@@ -40,14 +40,14 @@ __device__ __forceinline__ const T* site_tensor(const T* theta, const int* tab, 
 
 template <typename T>
 __device__ void load_lds(T* dst, const T* src, int cnt) {
-  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) dst[i] = src[i];
+  for (int i = threadIdx.x; i < cnt; i += PEPS_NT) dst[i] = src[i];
 }
 
 // Divide the LDS tensor by its largest modulus; returns ln(divisor).
 template <typename T>
 __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
   T mx = 0;
-  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) {
+  for (int i = threadIdx.x; i < cnt; i += PEPS_NT) {
     const T a = fabs(t[i]);
     mx = a > mx ? a : mx;
   }
@@ -58,14 +58,14 @@ __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
     return 0.0;
   }
   const T inv = T(1) / mx;
-  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) t[i] *= inv;
+  for (int i = threadIdx.x; i < cnt; i += PEPS_NT) t[i] *= inv;
   __syncthreads();
   return log((double)mx);
 }
 
 inline size_t env_lds_elems_(int bmax, int D) {
   const size_t BD = (size_t)bmax * D;
-  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + 3 * BD * BD + 2 * BD + 2 * BD * bmax +
+  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + 3 * BD * BD + 8 * BD + 2 * BD * bmax +
          4 * BD + 16;
 }
 
@@ -82,8 +82,8 @@ struct EnvSmem {
     // stacked QR buffer (left) / C then Z (right); rows padded by one
     // element so rows of the LDS matrices fall on different banks
     S = P + BD * BD;
-    Z = S + BD * (BD + 1);
-    W = S + 2 * BD * (BD + 1);
+    Z = S + BD * (BD + 4);
+    W = S + 2 * BD * (BD + 4);
     Bn = W + BD * B;
     vv = Bn + B * BD;
     ww = vv + 2 * BD;
@@ -112,7 +112,7 @@ __device__ void env_first_row(const Lattice& L, const int* tab, const typename M
     const SiteView v = site_view(tab, L, nsite, bottom);
     const T* a = site_tensor(theta, tab, L, s, nsite);
     const int cnt = v.Dl * v.Dout * v.Dr;
-    for (int i = tid; i < cnt; i += PEPS_BLOCK) {
+    for (int i = tid; i < cnt; i += PEPS_NT) {
       const int l = i / (v.Dout * v.Dr), rem = i - l * (v.Dout * v.Dr);
       const int k = rem / v.Dr, r = rem - k * v.Dr;
       Ebuf[i] = a[l * v.s_l + r * v.s_r + k * v.s_out];
@@ -120,7 +120,7 @@ __device__ void env_first_row(const Lattice& L, const int* tab, const typename M
     __syncthreads();
     logacc += normalize_lds(Ebuf, cnt, red, flp);
     T* dst = envs + (size_t)slot0 * slot_elems + (size_t)y * L.site_box;
-    for (int i = tid; i < cnt; i += PEPS_BLOCK) dst[i] = Ebuf[i];
+    for (int i = tid; i < cnt; i += PEPS_NT) dst[i] = Ebuf[i];
     __syncthreads();
   }
   if (tid == 0) lg[slot0] = logacc;
@@ -170,7 +170,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       for (int k = 0; k < v.Dout; ++k) {
         // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k]
         const int tot = Pl * Pr;
-        for (int i = tid; i < tot; i += PEPS_BLOCK) {
+        for (int i = tid; i < tot; i += PEPS_NT) {
           const int row = i / Pr, col = i - row * Pr;
           const int aa = row / v.Dl, l = row - aa * v.Dl;
           const int b = col / v.Dr, r = col - b * v.Dr;
@@ -183,18 +183,18 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         __syncthreads();
         // M_k = R_{y-1} P_k into rows kr.. of the stack
         if (y == 0) {
-          for (int i = tid; i < Pr; i += PEPS_BLOCK) S[kr * (Pr + 1) + i] = P[i];
+          for (int i = tid; i < Pr; i += PEPS_NT) S[kr * (Pr + 1) + i] = P[i];
         } else {
           gemm<M>(kprev, Pr, Pl, Rp, Pl, 1, P, Pr, 1, S + kr * (Pr + 1), Pr + 1, 1, false);
         }
         __syncthreads();
         const int m = kr + kprev;
-        house_qr_stacked(S, kr, m, Pr, Pr + 1, vv, red);
+        house_qr_stacked(S, kr, m, Pr, Pr + 1, red);
         kr = m < Pr ? m : Pr;
       }
       // store R_y (kr x Pr, row stride Pr)
       T* Ry = R + (size_t)y * BD * BD;
-      for (int i = tid; i < kr * Pr; i += PEPS_BLOCK) Ry[i] = S[(i / Pr) * (Pr + 1) + i % Pr];
+      for (int i = tid; i < kr * Pr; i += PEPS_NT) Ry[i] = S[(i / Pr) * (Pr + 1) + i % Pr];
       __syncthreads();
       kprev = kr;
     }
@@ -224,7 +224,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       const int zc = v.Dout * nbr;
       {
         const int tot = Pl * zc;
-        for (int i = tid; i < tot; i += PEPS_BLOCK) {
+        for (int i = tid; i < tot; i += PEPS_NT) {
           const int row = i / zc, col = i - row * zc;
           const int aa = row / v.Dl, l = row - aa * v.Dl;
           const int k = col / nbr, c = col - k * nbr;
@@ -251,18 +251,20 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         }
         const T* Rp = R + (size_t)(y - 1) * BD * BD;
         // C = R_{y-1} Z  (kp x zc)
-        const int ldc = zc + 1;
+        // row stride: 16-byte aligned and shifted by 16 bytes per row so the
+        // Jacobi's vector LDS accesses of neighbouring rows use other banks
+        const int ldc = zc + (int)(16 / sizeof(T));
         gemm<M>(kp, zc, Pl, Rp, Pl, 1, Z, zc, 1, S, ldc, 1, false);
         __syncthreads();
         int m = kp;
         if (m > zc) {
-          house_qr_stacked(S, 0, m, zc, ldc, vv, red);
+          house_qr_stacked(S, 0, m, zc, ldc, red);
           m = zc;
         }
-        const int used = jacobi_rows(S, m, zc, ldc, tol, jac_sweeps, sflag);
+        const int used = jacobi_rows(S, m, zc, ldc, tol, jac_sweeps, sflag, vv);
         if (used < 0 && tid == 0) fl |= 4;
         // row norms
-        for (int i = tid; i < m; i += PEPS_BLOCK) {
+        for (int i = tid; i < m; i += PEPS_NT) {
           T q = 0;
           for (int e = 0; e < zc; ++e) q += S[i * ldc + e] * S[i * ldc + e];
           sig[i] = sqrt(q);
@@ -270,7 +272,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         __syncthreads();
         rnew = edims[(sn * L.Ly + y) * 3 + 0];
         // rank rows by descending norm (ties by index)
-        for (int i = tid; i < m; i += PEPS_BLOCK) {
+        for (int i = tid; i < m; i += PEPS_NT) {
           int rk = 0;
           const T si = sig[i];
           for (int j = 0; j < m; ++j) {
@@ -294,7 +296,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
           if (sa > T(0) && (sa - sb) < T(1e-8) * sa) fl |= 8;
         }
         const T thresh = smax * Eps<T>::v * T(4);
-        for (int i = tid; i < rnew * zc; i += PEPS_BLOCK) {
+        for (int i = tid; i < rnew * zc; i += PEPS_NT) {
           const int j = i / zc, e = i - j * zc;
           const T sj = sig[sel[j]];
           Bn[i] = (sj > thresh) ? S[sel[j] * ldc + e] / sj : T(0);
@@ -311,7 +313,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       const int cnt = rnew * zc;
       logrow += normalize_lds(newt, cnt, red, flp);
       T* dst = Enew + (size_t)y * L.site_box;
-      for (int i = tid; i < cnt; i += PEPS_BLOCK) dst[i] = newt[i];
+      for (int i = tid; i < cnt; i += PEPS_NT) dst[i] = newt[i];
       nbr = rnew;
       __syncthreads();
     }

@@ -198,7 +198,7 @@ __global__ void k_colsum(int B, int C, const float* __restrict__ in, float* __re
 __global__ void k_made_loss(int B, const double* __restrict__ logq, double* __restrict__ loss) {
   __shared__ double red[8];
   double s = 0.0;
-  for (int b = threadIdx.x; b < B; b += PEPS_BLOCK) s += logq[b];
+  for (int b = threadIdx.x; b < B; b += PEPS_NT) s += logq[b];
   s = block_sum(s, red);
   if (threadIdx.x == 0) *loss = -s / B;
 }
@@ -353,7 +353,7 @@ hipError_t launch_made_backward(int N, int H, int n_up, int bf16, const float* P
   hipLaunchKernelGGL((k_gemm<LDaT, LX, EgW1>), grid2(H, N), dim3(256), 0, st, H, N, B,
                      LDaT{da, H}, LX{x, N}, EgW1{gW1, p});
   hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, B, H, da, gb1);
-  hipLaunchKernelGGL(k_made_loss, dim3(1), dim3(PEPS_BLOCK), 0, st, B, logq, loss);
+  hipLaunchKernelGGL(k_made_loss, dim3(1), dim3(256), 0, st, B, logq, loss);
   return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ __global__ void k_colmean(Lattice L, const int* __restrict__ tab, const TO* __re
 
 // a_s = sum_k O_sk m_k (block per sample); slot n holds |m|^2 (block n).
 template <typename TO>
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_proj_mean(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
             const uint8_t* __restrict__ samples, int n, const double* __restrict__ mean,
             double* __restrict__ a) {
@@ -42,7 +42,7 @@ k_proj_mean(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
   const int s = blockIdx.x;
   double acc = 0.0;
   if (s < n) {
-    for (int jc = threadIdx.x; jc < L.n_compact; jc += PEPS_BLOCK) {
+    for (int jc = threadIdx.x; jc < L.n_compact; jc += PEPS_NT) {
       const int site = tab[L.off_csite + jc];
       const int j = jc - tab[L.off_compact + site];
       const int p = pbit(samples[(size_t)s * L.N + site]);
@@ -50,7 +50,7 @@ k_proj_mean(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
              mean[tab[L.off_param + site] + p * tab[L.off_block + site] + j];
     }
   } else {
-    for (int k = threadIdx.x; k < L.n_params; k += PEPS_BLOCK) acc += mean[k] * mean[k];
+    for (int k = threadIdx.x; k < L.n_params; k += PEPS_NT) acc += mean[k] * mean[k];
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) a[s] = acc;
@@ -61,7 +61,7 @@ __global__ void k_estats(const double* __restrict__ eloc, int n, double* __restr
                          int* __restrict__ bad) {
   __shared__ double red[8];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += PEPS_BLOCK) {
+  for (int i = threadIdx.x; i < n; i += PEPS_NT) {
     const double v = eloc[2 * i];
     if (!isfinite(v) || !isfinite(eloc[2 * i + 1])) atomicOr(bad, 1);
     s += v;
@@ -69,7 +69,7 @@ __global__ void k_estats(const double* __restrict__ eloc, int n, double* __restr
   s = block_sum(s, red);
   const double mu = s / n;
   double q = 0.0;
-  for (int i = threadIdx.x; i < n; i += PEPS_BLOCK) {
+  for (int i = threadIdx.x; i < n; i += PEPS_NT) {
     const double v = eloc[2 * i] - mu;
     q += v * v;
   }
@@ -163,7 +163,7 @@ k_gram(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
 __global__ void k_trace(const double* __restrict__ Tm, int n, double eps, double* __restrict__ ws) {
   __shared__ double red[8];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += PEPS_BLOCK) s += Tm[(size_t)i * n + i] - eps;
+  for (int i = threadIdx.x; i < n; i += PEPS_NT) s += Tm[(size_t)i * n + i] - eps;
   s = block_sum(s, red);
   if (threadIdx.x == 0) ws[2] = s;
 }
@@ -339,7 +339,7 @@ __global__ void k_dtheta(Lattice L, const int* __restrict__ tab, const TO* __res
 __global__ void k_sum_y(const double* __restrict__ y, int n, double* __restrict__ ws) {
   __shared__ double red[8];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += PEPS_BLOCK) s += y[i];
+  for (int i = threadIdx.x; i < n; i += PEPS_NT) s += y[i];
   s = block_sum(s, red);
   if (threadIdx.x == 0) ws[7] = s;
 }
@@ -384,13 +384,13 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
   hipMemsetAsync(bad, 0, sizeof(int), st);
   const int cb = (L.n_compact + 255) / 256;
   hipLaunchKernelGGL(k_colmean<TO>, dim3(cb), dim3(256), 0, st, L, tab, O, samples, n, mean);
-  hipLaunchKernelGGL(k_proj_mean<TO>, dim3(n + 1), dim3(PEPS_BLOCK), 0, st, L, tab, O, samples, n,
+  hipLaunchKernelGGL(k_proj_mean<TO>, dim3(n + 1), dim3(256), 0, st, L, tab, O, samples, n,
                      (const double*)mean, a);
-  hipLaunchKernelGGL(k_estats, dim3(1), dim3(PEPS_BLOCK), 0, st, eloc, n, ws, bad);
+  hipLaunchKernelGGL(k_estats, dim3(1), dim3(256), 0, st, eloc, n, ws, bad);
   const int nt = (n + GT - 1) / GT;
   hipLaunchKernelGGL(k_gram<TO>, dim3(nt, nt), dim3(256), 0, st, L, tab, O, samples, n,
                      (const double*)a, eps, Tm);
-  hipLaunchKernelGGL(k_trace, dim3(1), dim3(PEPS_BLOCK), 0, st, (const double*)Tm, n, eps, ws);
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, (const double*)Tm, n, eps, ws);
   const int nkb = (n + CB - 1) / CB;
   for (int kb = 0; kb < nkb; ++kb) {
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, Tm, n, kb, ws);
@@ -404,7 +404,7 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
   hipLaunchKernelGGL(k_certify, dim3(1), dim3(64), 0, st, n, eps, rcond, ws, diag);
   hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), 0, st, (const double*)Tm, n, eloc,
                      (const double*)ws, y);
-  hipLaunchKernelGGL(k_sum_y, dim3(1), dim3(PEPS_BLOCK), 0, st, (const double*)y, n, ws);
+  hipLaunchKernelGGL(k_sum_y, dim3(1), dim3(256), 0, st, (const double*)y, n, ws);
   hipLaunchKernelGGL(k_dtheta<TO>, dim3(cb), dim3(256), 0, st, L, tab, O, samples, n,
                      (const double*)y, (const double*)mean, (const double*)ws, dtheta);
   return hipGetLastError();

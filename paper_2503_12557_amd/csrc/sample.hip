@@ -24,7 +24,7 @@ namespace pm {
 #define TAG_INIT 0x494E4954u
 
 template <int M>
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
              int kind, int n_chains, int per_chain, int burn_in, int thin, uint32_t k0, uint32_t k1,
              uint64_t offset, uint8_t* __restrict__ samples, int* __restrict__ accepted,
@@ -73,7 +73,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   const int* ed = tab + L.off_env;
 
   // initial state
-  for (int n = tid; n < N; n += PEPS_BLOCK) {
+  for (int n = tid; n < N; n += PEPS_NT) {
     u4 c;
     c.x = (uint32_t)n;
     c.y = 0u;
@@ -87,7 +87,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
     one[0] = T(1);
   }
   __syncthreads();
-  for (int n = tid; n < N; n += PEPS_BLOCK) {
+  for (int n = tid; n < N; n += PEPS_NT) {
     if (kind == 0) {
       int rk = 0;
       const uint32_t kn = keys[n];
@@ -191,7 +191,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
         legs_of(tab, L, n1, Dl, Dr, Du, Dd);
         s1_step_left<M>(Lf, upT(y), ua_(y), ub_(y), tens(n1, s[n1]), Dl, Dr, Du, Dd, dnT(y),
                         ba_(y), bb_(y), X1, X2, Lt);
-        for (int i = tid; i < ub_(y) * Dr * bb_(y); i += PEPS_BLOCK) Lf[i] = Lt[i];
+        for (int i = tid; i < ub_(y) * Dr * bb_(y); i += PEPS_NT) Lf[i] = Lt[i];
         __syncthreads();
       }
 
@@ -244,7 +244,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
           s2_step_left<M>(Lf2, upT(y), ua_(y), uk_(y), ub_(y), tens(n1, s[n1]), Dl1, Dr1, Dd1,
                           tens(n2, s[n2]), Dl2, Dr2, Dd2, dn2(y), ba2(y), bb2(y), Y1, Y2, Y3, Lu);
           const int cnt = ub_(y) * Dr1 * Dr2 * bb2(y);
-          for (int i = tid; i < cnt; i += PEPS_BLOCK) Lf2[i] = Lu[i];
+          for (int i = tid; i < cnt; i += PEPS_NT) Lf2[i] = Lu[i];
           __syncthreads();
         }
       }
@@ -257,7 +257,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
     }
     if (sw >= burn_in && (sw - burn_in) % thin == thin - 1) {
       uint8_t* dst = samples + ((size_t)chain * per_chain + rec) * N;
-      for (int n = tid; n < N; n += PEPS_BLOCK) dst[n] = s[n];
+      for (int n = tid; n < N; n += PEPS_NT) dst[n] = s[n];
       ++rec;
     }
     __syncthreads();
@@ -287,7 +287,7 @@ hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta
   const size_t lds = sample_lds_elems(L.bmax, L.D) * sizeof(T);
   hipFuncSetAttribute((const void*)k_metropolis<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
-  hipLaunchKernelGGL(k_metropolis<M>, dim3(n_chains), dim3(PEPS_BLOCK), lds, st, L, tab,
+  hipLaunchKernelGGL(k_metropolis<M>, dim3(n_chains), dim3(env_threads(M)), lds, st, L, tab,
                      (const T*)theta, kind, n_chains, per_chain, burn_in, thin,
                      (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), offset, samples,
                      accepted, (T*)envscr, logscr, (T*)rscr, (T*)rt1, (T*)rt2, jac_sweeps);

@@ -22,7 +22,7 @@ size_t strip1_lds_elems(int bmax, int D) {
 }
 
 template <int M>
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
@@ -114,7 +114,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
       gemm<M>(ub * Dr, ba * Dd, bb, Rn, bb, 1, Bt, 1, bb, X2, ba * Dd, 1, false);
       __syncthreads();
       // Env[m,r,u,d] = sum_{c,b} X1[m,c,u,b] Q[b,r,c,d]
-      for (int i = tid; i < nA; i += PEPS_BLOCK) {
+      for (int i = tid; i < nA; i += PEPS_NT) {
         int t = i;
         const int d = t % Dd; t /= Dd;
         const int u = t % Du; t /= Du;
@@ -131,7 +131,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
       const T psi_loc = lds_dot(Env, A, nA, red);
       T* o = Oout + (size_t)smp * L.n_compact + tab[L.off_compact + ns];
       const T inv = T(1) / psi_loc;
-      for (int i = tid; i < nA; i += PEPS_BLOCK) o[i] = Env[i] * inv;
+      for (int i = tid; i < nA; i += PEPS_NT) o[i] = Env[i] * inv;
     }
     if (want_e) {
       while (mi < m1 && H.moves[8 * mi] == y) {
@@ -165,7 +165,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     }
     // Lf <- step(Lf, A_y)
     s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
-    for (int i = tid; i < ub * Dr * bb; i += PEPS_BLOCK) Lf[i] = Lt[i];
+    for (int i = tid; i < ub * Dr * bb; i += PEPS_NT) Lf[i] = Lt[i];
     __syncthreads();
     if (want_e) {
       const T z = lds_dot(Lf, (const T*)Rn, ub * Dr * bb, red);
@@ -194,7 +194,7 @@ size_t strip2_lds_elems(int bmax, int D) {
 }
 
 template <int M>
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
@@ -318,7 +318,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
                     Dl1, Dr1, Dd1, tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2,
                     dnT(y), ba_(y), bb_(y), X1, X2, X3, Lt);
     const int cnt = ub_(y) * Dr1 * Dr2 * bb_(y);
-    for (int i = tid; i < cnt; i += PEPS_BLOCK) Lf[i] = Lt[i];
+    for (int i = tid; i < cnt; i += PEPS_NT) Lf[i] = Lt[i];
     __syncthreads();
     const T z = lds_dot(Lf, (const T*)(Rt + (size_t)(y + 1) * box2), cnt, red);
     if (tid == 0) zv[y] = (double)z;
@@ -336,7 +336,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
 }
 
 // Diagonal part of E_loc plus the sum of the strip parts, one block per sample.
-__global__ void __launch_bounds__(PEPS_BLOCK)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_energy_diag_sum(Lattice L, HamDev H, const uint8_t* __restrict__ samples,
                   const double* __restrict__ epart, int nparts, double* __restrict__ eloc, int n) {
   __shared__ double red[8];
@@ -344,7 +344,7 @@ k_energy_diag_sum(Lattice L, HamDev H, const uint8_t* __restrict__ samples,
   if (smp >= n) return;
   const uint8_t* s = samples + (size_t)smp * L.N;
   double re = 0.0, im = 0.0;
-  for (int t = threadIdx.x; t < H.n_terms; t += PEPS_BLOCK) {
+  for (int t = threadIdx.x; t < H.n_terms; t += PEPS_NT) {
     const int* tt = H.terms + 4 * t;
     int c = 0;
     for (int j = 0; j < tt[0]; ++j) c = 2 * c + pbit(s[tt[1 + j]]);
@@ -352,12 +352,12 @@ k_energy_diag_sum(Lattice L, HamDev H, const uint8_t* __restrict__ samples,
     re += h[0];
     im += h[1];
   }
-  for (int p = threadIdx.x; p < H.n_pairs; p += PEPS_BLOCK) {
+  for (int p = threadIdx.x; p < H.n_pairs; p += PEPS_NT) {
     const int i = H.pair_ij[2 * p], j = H.pair_ij[2 * p + 1];
     if (pbit(s[i]) && pbit(s[j])) re += H.pair_v[p];
   }
   if (H.onsite)
-    for (int q = threadIdx.x; q < L.N; q += PEPS_BLOCK) re += H.onsite[2 * q + pbit(s[q])];
+    for (int q = threadIdx.x; q < L.N; q += PEPS_NT) re += H.onsite[2 * q + pbit(s[q])];
   re = block_sum(re, red);
   im = block_sum(im, red);
   if (threadIdx.x == 0) {
@@ -379,7 +379,7 @@ hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
   const size_t lds = strip1_lds_elems(L.bmax, L.D) * sizeof(T);
   hipFuncSetAttribute((const void*)k_strip1<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
-  hipLaunchKernelGGL(k_strip1<M>, dim3(n, L.Lx), dim3(PEPS_BLOCK), lds, st, L, tab,
+  hipLaunchKernelGGL(k_strip1<M>, dim3(n, L.Lx), dim3(512), lds, st, L, tab,
                      (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O, flags, n,
                      want_e ? 1 : 0, want_o ? 1 : 0);
   return hipGetLastError();
@@ -393,7 +393,7 @@ hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
   const size_t lds = strip2_lds_elems(L.bmax, L.D) * sizeof(T);
   hipFuncSetAttribute((const void*)k_strip2<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
-  hipLaunchKernelGGL(k_strip2<M>, dim3(n, L.Lx - 1), dim3(PEPS_BLOCK), lds, st, L, tab,
+  hipLaunchKernelGGL(k_strip2<M>, dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
                      (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n);
   return hipGetLastError();
 }
@@ -401,7 +401,7 @@ hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
 hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8_t* samples,
                                   const double* epart, int nparts, double* eloc, int n,
                                   hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_diag_sum, dim3(n), dim3(PEPS_BLOCK), 0, st, L, H, samples, epart,
+  hipLaunchKernelGGL(k_energy_diag_sum, dim3(n), dim3(256), 0, st, L, H, samples, epart,
                      nparts, eloc, n);
   return hipGetLastError();
 }

@@ -44,7 +44,7 @@ __device__ void s1_step_left(const T* Lp, const T* U, int ua, int ub, const T* A
   __syncthreads();
   // X2[b,r,c,d] = sum_{m,u} X1[m,c,u,b] A[m,r,u,d]
   const int tot = ub * Dr * ba * Dd;
-  for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+  for (int i = threadIdx.x; i < tot; i += PEPS_NT) {
     int t = i;
     const int d = t % Dd; t /= Dd;
     const int c = t % ba; t /= ba;
@@ -71,7 +71,7 @@ __device__ void s1_step_right(const T* Rp, const T* U, int ua, int ub, const T* 
   __syncthreads();
   // X2[(a,m),(d,e)] = sum_{u,r} X1[a,u,r,e] A[m,r,u,d]
   const int tot = ua * Dl * Dd * bb;
-  for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+  for (int i = threadIdx.x; i < tot; i += PEPS_NT) {
     int t = i;
     const int e = t % bb; t /= bb;
     const int d = t % Dd; t /= Dd;
@@ -93,7 +93,7 @@ __device__ void s1_step_right(const T* Rp, const T* U, int ua, int ub, const T* 
 template <typename T>
 __device__ T lds_dot(const T* a, const T* b, int cnt, T* red) {
   T s = 0;
-  for (int i = threadIdx.x; i < cnt; i += PEPS_BLOCK) s += a[i] * b[i];
+  for (int i = threadIdx.x; i < cnt; i += PEPS_NT) s += a[i] * b[i];
   return block_sum(s, red);
 }
 
@@ -142,7 +142,7 @@ __device__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, co
     // X2[m2,c,r1,t] = sum_{m1,u} X1[m1,m2,c,u] A1[m1,r1,u,t]
     {
       const int tot = Dl2 * ba * Dr1 * Dd1;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+      for (int i = threadIdx.x; i < tot; i += PEPS_NT) {
         int q = i;
         const int t = q % Dd1; q /= Dd1;
         const int r1 = q % Dr1; q /= Dr1;
@@ -160,7 +160,7 @@ __device__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, co
     // X3[r1,s,c,d] = sum_{m2,t} X2[m2,c,r1,t] A2[m2,s,t,d]
     {
       const int tot = Dr1 * Dr2 * ba * Dd2;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+      for (int i = threadIdx.x; i < tot; i += PEPS_NT) {
         int q = i;
         const int d = q % Dd2; q /= Dd2;
         const int c = q % ba; q /= ba;
@@ -194,7 +194,7 @@ __device__ void s2_step_right(const T* Rp, const T* U, int ua, int uk, int ub, c
     // Y2[m1,t,s,e] = sum_{u,r1} A1[m1,r1,u,t] Y1[u,r1,s,e]
     {
       const int tot = Dl1 * Dd1 * Dr2 * bb;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+      for (int i = threadIdx.x; i < tot; i += PEPS_NT) {
         int q = i;
         const int e = q % bb; q /= bb;
         const int sidx = q % Dr2; q /= Dr2;
@@ -212,7 +212,7 @@ __device__ void s2_step_right(const T* Rp, const T* U, int ua, int uk, int ub, c
     // Y3[(m1,m2),(d,e)] = sum_{t,s} A2[m2,s,t,d] Y2[m1,t,s,e]
     {
       const int tot = Dl1 * Dl2 * Dd2 * bb;
-      for (int i = threadIdx.x; i < tot; i += PEPS_BLOCK) {
+      for (int i = threadIdx.x; i < tot; i += PEPS_NT) {
         int q = i;
         const int e = q % bb; q /= bb;
         const int d = q % Dd2; q /= Dd2;
