@@ -321,13 +321,17 @@ def main():
     # dominant kernel and its roofline
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
     env_avg_ms = per_kernel["env"]["ms_avg"]
-    env_flops = env_flops_per_sample(Lx, Ly, D, chi) * n
+    # samples one launch processes: the batch is split into equal chunks
+    env_launches_per_step = per_kernel["env"]["launches"] / args.steps
+    samples_per_launch = n / env_launches_per_step
+    env_flops = env_flops_per_sample(Lx, Ly, D, chi) * samples_per_launch
     peak = PEAK["fp64_vector_tflops"] if args.dtype == "f64" else PEAK["fp32_vector_tflops"]
     achieved = env_flops / (env_avg_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_env_sweep", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
                 "traffic": env_traffic(args.dtype),
                 "algorithmic_flops_per_launch": env_flops,
+                "samples_per_launch": samples_per_launch,
                 "avg_launch_ms": env_avg_ms, "dominant_kernel_by_time": dom}
 
     res = {

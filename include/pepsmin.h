@@ -15,8 +15,9 @@
  *    columns y = 0..Ly-1, site n = x*Ly + y. Physical dimension d = 2.
  *  - Parameters theta: the entries of the site tensors T[x,y] of shape
  *    (d, Dl, Dr, Du, Dd) in C order, sites concatenated in row-major order;
- *    virtual legs on an open edge have dimension 1. theta is FP64 (real
- *    modes) and is converted to the compute precision inside the call.
+ *    virtual legs on an open edge have dimension 1. theta is FP64 [N_p]
+ *    (real modes) or interleaved (re, im) FP64 pairs [N_p][2] (complex
+ *    modes), converted to the compute precision inside the call.
  *  - Samples: uint8 [n][Lx*Ly], one physical index per site (0 = spin up /
  *    atom in |g>, 1 = spin down / atom in |r>).
  *  - Amplitudes are contracted with boundary MPS of bond chi (Sec. "On the
@@ -54,12 +55,16 @@ typedef enum {
   PEPS_ERR_NONFINITE = 5     /* non-finite input (theta, E_loc) */
 } peps_status;
 
-/* Compute precision of the contractions. Log scales, local energies and the
- * minSR solve are always FP64. */
+/* Compute precision of the contractions (Sec. "On Numerical Stability"
+ * discusses reduced precision). Log scales, local energies and the minSR
+ * solve are always FP64 (complex FP64 for complex parameters). */
 typedef enum {
-  PEPS_F64 = 0,   /* FP64 everywhere */
-  PEPS_F32 = 1,   /* FP32 contractions, QR and SVD */
-  PEPS_BF16 = 2   /* BF16 contraction operands with FP32 accumulation; QR/SVD in FP32 */
+  PEPS_F64 = 0,   /* real tensors, FP64 everywhere */
+  PEPS_F32 = 1,   /* real tensors, FP32 contractions, QR and SVD */
+  PEPS_BF16 = 2,  /* real tensors, BF16 contraction operands with FP32
+                     accumulation; QR/SVD in FP32 */
+  PEPS_C128 = 3,  /* complex tensors, complex128 contractions, QR and SVD */
+  PEPS_C64 = 4    /* complex tensors, complex64 contractions, QR and SVD */
 } peps_dtype;
 
 /* Per-sample flags (bit set = condition seen for that sample). */
@@ -84,7 +89,9 @@ typedef struct {
 typedef struct peps_ctx peps_ctx;
 
 /* Create a context for one geometry and precision; *out receives it.
- * PEPS_ERR_UNSUPPORTED if chi*D exceeds what the kernels hold on chip. */
+ * Kernels whose per-workgroup matrices do not fit in LDS keep them in a
+ * global-memory slab per workgroup instead (slower, same results).
+ * PEPS_ERR_UNSUPPORTED if max(chi, D) * D > 256 or D > 16. */
 peps_status peps_create(const peps_geom* geom, peps_ctx** out);
 void peps_destroy(peps_ctx* ctx);
 
@@ -96,8 +103,8 @@ size_t peps_num_params(const peps_ctx* ctx);
 
 /* Bytes of the environment cache for n samples: every top environment
  * E^u[0..Lx-2] and bottom environment E^l[1..Lx-1] of every sample, each site
- * tensor padded to chi*D*chi entries of the compute precision, plus the FP64
- * log scales. */
+ * tensor padded to chi*D*chi entries of the compute type (complex entries
+ * for complex modes), plus the FP64 log scales. */
 size_t peps_env_cache_bytes(const peps_ctx* ctx, int n);
 
 /* Hamiltonian H = sum_t h_t + sum_(i<j) V_ij n_i n_j + sum_i onsite[i][s_i].
@@ -141,8 +148,10 @@ peps_status peps_local_energy(peps_ctx* ctx, const double* theta, const uint8_t*
  * parameter k of a site (x, y) with physical index s_xy (the hole network
  * of row x between E^u[x-1] and E^l[x+1], divided by that strip's
  * amplitude); parameters with p != s_xy have O = 0 and are not stored.
- * O: compact [n][N_p/d] in FP64 (PEPS_F64) or FP32 (PEPS_F32, PEPS_BF16),
- * site-major with the (l, r, u, d) entries of each site in C order.
+ * O: compact [n][N_p/d] in FP64 (PEPS_F64), FP32 (PEPS_F32, PEPS_BF16),
+ * interleaved FP64 pairs (PEPS_C128) or FP32 pairs (PEPS_C64), site-major
+ * with the (l, r, u, d) entries of each site in C order. For complex
+ * tensors O is the holomorphic derivative (no conjugation).
  * env_cache as for peps_local_energy. */
 peps_status peps_logderiv(peps_ctx* ctx, const double* theta, const uint8_t* samples,
                           int n, const void* env_cache, void* O, void* stream);
@@ -150,7 +159,8 @@ peps_status peps_logderiv(peps_ctx* ctx, const double* theta, const uint8_t* sam
 /* Vector-Jacobian product of ln Psi over a batch (the backward pass of the
  * log-amplitude): grad_theta[k] = sum_s g[s] O_k(S_s) with O from
  * peps_logderiv (compact, compute precision) expanded with zeros where
- * p != s_xy. g: FP64 [n]; grad_theta: FP64 [N_p], overwritten. */
+ * p != s_xy. g: FP64 [n]; grad_theta: FP64 [N_p], overwritten.
+ * Real modes only (PEPS_ERR_UNSUPPORTED for complex parameters). */
 peps_status peps_logderiv_vjp(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
                               const double* g, double* grad_theta, void* stream);
 
@@ -171,12 +181,15 @@ peps_status peps_evaluate(peps_ctx* ctx, const double* theta, const uint8_t* sam
  * T + eps I, which equals the pseudo-inverse whenever no eigenvalue is
  * dropped; that holds when trace(T) + eps <= eps / rcond, which is checked on
  * the device. If the check fails diag[3] is set to 1 and dtheta is filled
- * with NaN. The real part of eloc is used (real PEPS). dtheta: FP64 [N_p],
- * the direction of Eq. tdvp: theta moves as theta - tau * dtheta.
+ * with NaN. Real modes use the real part of eloc and give dtheta FP64
+ * [N_p]. Complex modes use the Hermitian forms T = Obar Obar^H,
+ * dtheta = Obar^H (T + eps I)^+ ebar with complex ebar, and give dtheta as
+ * interleaved FP64 pairs [N_p][2]. dtheta is the direction of Eq. tdvp:
+ * theta moves as theta - tau * dtheta.
  * diag (device, FP64 [8]): [0] trace(T)+eps (bound on the largest
  * eigenvalue), [1] eps, [2] number of dropped eigenvalues (0), [3] 1 if the
- * certificate failed, [4] <E>, [5] Var(E)/1, [6] n, [7] smallest Cholesky
- * pivot. */
+ * certificate failed, [4] Re <E>, [5] mean |E - <E>|^2 (real modes: of
+ * Re E), [6] n, [7] smallest Cholesky pivot. */
 peps_status minsr_step(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
                        const double* eloc, double eps, double rcond, double* dtheta,
                        double* diag, void* stream);
@@ -189,7 +202,8 @@ peps_status minsr_step(peps_ctx* ctx, const void* O, const uint8_t* samples, int
  * ratio taken in the strip holding the move and u from Philox4x32-10 keyed
  * by seed (counter: move id, sweep + offset, chain, tag). Chain c writes
  * samples[c*per_chain + j] = its state after sweep burn_in + (j+1)*thin - 1.
- * accepted: int32 [n_chains] accepted-move counts (or NULL). */
+ * accepted: int32 [n_chains] accepted-move counts (or NULL). At most 1024
+ * sites (PEPS_ERR_UNSUPPORTED above). */
 peps_status peps_sample(peps_ctx* ctx, const double* theta, int kind, int n_chains,
                         int per_chain, int burn_in, int thin, uint64_t seed,
                         uint64_t offset, uint8_t* samples, int32_t* accepted,

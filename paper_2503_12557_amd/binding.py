@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libpepsmin.so")
 PEPS_OK = 0
 STATUS_NAMES = {0: "PEPS_OK", 1: "PEPS_ERR_ARG", 2: "PEPS_ERR_UNSUPPORTED", 3: "PEPS_ERR_HIP",
                 4: "PEPS_ERR_OOM", 5: "PEPS_ERR_NONFINITE"}
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "c128": 3, "c64": 4}
+COMPLEX = ("c128", "c64")
 FLAG_ZERO, FLAG_NONFINITE, FLAG_NOCONV, FLAG_DEGENERATE = 1, 2, 4, 8
 SAMPLE_EXCHANGE, SAMPLE_FLIP = 0, 1
 
@@ -105,6 +106,11 @@ def load():
     return lib
 
 
+def torch_uint8():
+    import torch
+    return torch.uint8
+
+
 def _check(st):
     if st != PEPS_OK:
         raise PepsError(st, load().peps_last_error().decode())
@@ -145,9 +151,19 @@ class Context:
             pass
 
     @property
+    def is_complex(self):
+        return self.dtype in COMPLEX
+
+    @property
+    def theta_dtype(self):
+        import torch
+        return torch.complex128 if self.is_complex else torch.float64
+
+    @property
     def o_dtype(self):
         import torch
-        return torch.float64 if self.dtype == "f64" else torch.float32
+        return {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32,
+                "c128": torch.complex128, "c64": torch.complex64}[self.dtype]
 
     def env_cache_bytes(self, n):
         return load().peps_env_cache_bytes(self._h, n)
@@ -167,12 +183,17 @@ class Context:
         _check(load().peps_set_hamiltonian(self._h, nt, c(ns), c(st), c(mats), len(pv), c(pij),
                                           c(pv), c(on)))
 
+    def _theta(self, theta):
+        """theta as the library reads it: FP64, or interleaved (re, im) FP64
+        pairs for complex parameters."""
+        assert theta.dtype == self.theta_dtype and theta.is_cuda and theta.numel() == self.n_params
+        theta = theta.contiguous()
+        return theta
+
     def _args(self, theta, samples):
-        import torch
-        assert theta.dtype == torch.float64 and theta.is_cuda and theta.numel() == self.n_params
-        assert samples.dtype == torch.uint8 and samples.is_cuda
+        assert samples.dtype == torch_uint8() and samples.is_cuda
         assert samples.dim() == 2 and samples.shape[1] == self.Lx * self.Ly
-        return theta.contiguous(), samples.contiguous()
+        return self._theta(theta), samples.contiguous()
 
     def amplitude(self, theta, samples, env_cache=None, flags=None):
         import torch
@@ -227,7 +248,7 @@ class Context:
         import torch
         n = samples.shape[0]
         assert O.dtype == self.o_dtype and O.shape == (n, self.n_compact)
-        dtheta = torch.empty(self.n_params, dtype=torch.float64, device=O.device)
+        dtheta = torch.empty(self.n_params, dtype=self.theta_dtype, device=O.device)
         diag = torch.zeros(8, dtype=torch.float64, device=O.device)
         _check(load().minsr_step(self._h, _ptr(O.contiguous()), _ptr(samples.contiguous()), n,
                                  _ptr(eloc.contiguous()), float(eps), float(rcond), _ptr(dtheta),
@@ -260,7 +281,7 @@ class Context:
     def sample(self, theta, kind="exchange", n_chains=256, per_chain=4, burn_in=32, thin=1,
                seed=0, offset=0):
         import torch
-        assert theta.dtype == torch.float64 and theta.is_cuda
+        theta = self._theta(theta)
         n = n_chains * per_chain
         samples = torch.empty(n, self.Lx * self.Ly, dtype=torch.uint8, device=theta.device)
         acc = torch.zeros(n_chains, dtype=torch.int32, device=theta.device)

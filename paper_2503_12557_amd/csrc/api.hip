@@ -78,6 +78,9 @@ struct peps_ctx {
   double* d_hdbl = nullptr;
   // workspace
   DevBuf theta_c, env_int, rscr, rt1, rt2, epart, bad, mean, Tm, vec, eloc_tmp, logpsi_tmp;
+  // global working sets of the kernels whose matrices do not fit in LDS
+  bool env_gm = false, s1_gm = false, s2_gm = false, smp_gm = false;
+  DevBuf gws_env, gws_s1, gws_s2, gws_smp;
   int jac_sweeps = 40;
   // optional per-kernel timing with HIP events on the launch stream
   bool prof = false;
@@ -85,7 +88,7 @@ struct peps_ctx {
   std::vector<Ev> pending;
   double prof_ms[PEPS_PROF_KINDS] = {};
   long prof_n[PEPS_PROF_KINDS] = {};
-  size_t chunk_budget = (size_t)6 << 30;  // bytes of per-chunk scratch
+  size_t chunk_budget = (size_t)12 << 30;  // bytes of per-chunk scratch
 };
 
 // Bracket one launch with events when profiling is on.
@@ -109,7 +112,10 @@ struct ProfScope {
   }
 };
 
-static size_t elem_bytes(int dtype) { return dtype == PEPS_F64 ? 8 : 4; }
+static size_t elem_bytes(int dtype) { return mode_elem_bytes(dtype); }
+static bool is_complex(int dtype) { return dtype == PEPS_C128 || dtype == PEPS_C64; }
+// dynamic LDS a workgroup may request (the static arrays take the rest of 160 KiB)
+static const size_t kLdsDyn = 150 * 1024;
 
 static size_t env_tensor_elems_per_sample(const Lattice& L) {
   return (size_t)L.n_slots * L.Ly * L.site_box;
@@ -221,17 +227,13 @@ peps_status peps_create(const peps_geom* geom, peps_ctx** out) {
     return fail(PEPS_ERR_ARG, "lattice %dx%d outside 2..32", g.Lx, g.Ly);
   if (g.d != 2) return fail(PEPS_ERR_UNSUPPORTED, "physical dimension %d (only d = 2)", g.d);
   if (g.D < 1 || g.chi < 1) return fail(PEPS_ERR_ARG, "D = %d, chi = %d must be >= 1", g.D, g.chi);
-  if (g.dtype != PEPS_F64 && g.dtype != PEPS_F32 && g.dtype != PEPS_BF16)
-    return fail(PEPS_ERR_ARG, "unknown dtype %d", g.dtype);
+  if (g.dtype < PEPS_F64 || g.dtype > PEPS_C64) return fail(PEPS_ERR_ARG, "unknown dtype %d", g.dtype);
   const int bmax = std::max(g.chi, g.D);
-  if (bmax * g.D > 128)
-    return fail(PEPS_ERR_UNSUPPORTED, "chi*D = %d above the on-chip limit 128", bmax * g.D);
+  // the Householder and the cut selection index at most 256 columns / rows
+  if (bmax * g.D > 256)
+    return fail(PEPS_ERR_UNSUPPORTED, "chi*D = %d above the limit 256", bmax * g.D);
+  if (g.D > 16) return fail(PEPS_ERR_UNSUPPORTED, "D = %d above 16", g.D);
   const size_t eb = elem_bytes(g.dtype);
-  const size_t lds = std::max(std::max(env_lds_elems(bmax, g.D), strip1_lds_elems(bmax, g.D)),
-                              strip2_lds_elems(bmax, g.D)) * eb;
-  if (lds > 160 * 1024)
-    return fail(PEPS_ERR_UNSUPPORTED, "chi = %d, D = %d needs %zu bytes of LDS per workgroup",
-                g.chi, g.D, lds);
   peps_ctx* c = new peps_ctx();
   c->g = g;
   c->tsize = eb;
@@ -241,6 +243,10 @@ peps_status peps_create(const peps_geom* geom, peps_ctx** out) {
     peps_destroy(c);
     return st;
   }
+  c->env_gm = env_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
+  c->s1_gm = strip1_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
+  c->s2_gm = strip2_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
+  c->smp_gm = sample_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
   *out = c;
   return PEPS_OK;
 }
@@ -250,8 +256,10 @@ void peps_destroy(peps_ctx* c) {
   if (c->d_tab) hipFree(c->d_tab);
   if (c->d_hint) hipFree(c->d_hint);
   if (c->d_hdbl) hipFree(c->d_hdbl);
-  DevBuf* bufs[] = {&c->theta_c, &c->env_int, &c->rscr,  &c->rt1, &c->rt2,      &c->epart,
-                    &c->bad,     &c->mean,    &c->Tm,    &c->vec, &c->eloc_tmp, &c->logpsi_tmp};
+  DevBuf* bufs[] = {&c->theta_c, &c->env_int,   &c->rscr,       &c->rt1,    &c->rt2,
+                    &c->epart,   &c->bad,       &c->mean,       &c->Tm,     &c->vec,
+                    &c->eloc_tmp, &c->logpsi_tmp, &c->gws_env,   &c->gws_s1, &c->gws_s2,
+                    &c->gws_smp};
   for (DevBuf* b : bufs) b->release();
   delete c;
 }
@@ -431,8 +439,8 @@ static peps_status prepare_theta(peps_ctx* c, const double* theta, hipStream_t s
   s = c->bad.ensure(64);
   if (s != PEPS_OK) return s;
   HIPCHK(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
-  HIPCHK(launch_convert_theta(c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, theta, c->theta_c.p,
-                              np, (int*)c->bad.p, st));
+  HIPCHK(launch_convert_theta(c->g.dtype == PEPS_BF16 ? MODE_F32 : c->g.dtype, theta,
+                              c->theta_c.p, np, (int*)c->bad.p, st));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -440,7 +448,10 @@ static peps_status prepare_theta(peps_ctx* c, const double* theta, hipStream_t s
   return PEPS_OK;
 }
 
-static size_t per_sample_scratch(const peps_ctx* c) {
+// Device bytes one sample needs per evaluation chunk: R factors, strip right
+// partials, the global working sets of kernels that do not fit in LDS and,
+// when the caller keeps no cache, its environments.
+static size_t per_sample_scratch(const peps_ctx* c, bool env_internal) {
   const Lattice& L = c->L;
   const size_t BD = (size_t)L.bmax * L.D;
   const size_t box = L.site_box;
@@ -448,83 +459,90 @@ static size_t per_sample_scratch(const peps_ctx* c) {
   size_t r = 2 * (size_t)L.Ly * BD * BD;
   size_t s1 = (size_t)L.Lx * (L.Ly + 1) * box;
   size_t s2 = (size_t)(L.Lx - 1) * (L.Ly + 1) * box2;
-  return (r + s1 + s2) * c->tsize;
+  size_t g = 0;
+  if (c->env_gm) g += 2 * env_slab_elems(L);
+  if (c->s1_gm) g += (size_t)L.Lx * strip1_slab_elems(L);
+  if (c->s2_gm) g += (size_t)(L.Lx - 1) * strip2_slab_elems(L);
+  size_t e = env_internal ? env_tensor_elems_per_sample(L) : 0;
+  return (r + s1 + s2 + g + e) * c->tsize + (env_internal ? L.n_slots * sizeof(double) : 0);
 }
 
-static int chunk_size(const peps_ctx* c, int n) {
-  const size_t per = per_sample_scratch(c);
+static int chunk_size(const peps_ctx* c, int n, bool env_internal) {
+  const size_t per = per_sample_scratch(c, env_internal);
   size_t ch = c->chunk_budget / (per ? per : 1);
-  if (ch < 64) ch = 64;
+  if (ch < 16) ch = 16;
   if (ch >= (size_t)n) return n;
   // equal chunks: no small tail launch
   const size_t nch = ((size_t)n + ch - 1) / ch;
   return (int)(((size_t)n + nch - 1) / nch);
 }
 
+// environments of one chunk of m samples
 template <int M>
-static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int n, char* env_t,
+static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int m, char* env_t,
                             double* env_l, int* flags, hipStream_t st) {
   const Lattice& L = c->L;
-  const int ch = chunk_size(c, n);
   const size_t BD = (size_t)L.bmax * L.D;
-  peps_status s = c->rscr.ensure((size_t)ch * 2 * L.Ly * BD * BD * c->tsize);
+  peps_status s = c->rscr.ensure((size_t)m * 2 * L.Ly * BD * BD * c->tsize);
   if (s != PEPS_OK) return s;
-  const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
-  for (int c0 = 0; c0 < n; c0 += ch) {
-    const int m = std::min(ch, n - c0);
-    ProfScope ps(c, st, PEPS_PROF_ENV);
-    HIPCHK(launch_env_sweep<M>(L, c->d_tab, c->theta_c.p, samples + (size_t)c0 * L.N,
-                               env_t + (size_t)c0 * per_t, env_l + (size_t)c0 * L.n_slots,
-                               c->rscr.p, flags ? flags + c0 : nullptr, m, c->jac_sweeps, st));
+  void* gws = nullptr;
+  if (c->env_gm) {
+    if ((s = c->gws_env.ensure((size_t)m * 2 * env_slab_elems(L) * c->tsize)) != PEPS_OK) return s;
+    gws = c->gws_env.p;
   }
+  ProfScope ps(c, st, PEPS_PROF_ENV);
+  HIPCHK(launch_env_sweep<M>(L, c->d_tab, c->theta_c.p, samples, env_t, env_l, c->rscr.p, flags,
+                             m, c->jac_sweeps, gws, st));
   return PEPS_OK;
 }
 
+// strips of one chunk of m samples
 template <int M>
-static peps_status run_strips(peps_ctx* c, const uint8_t* samples, int n, const char* env_t,
+static peps_status run_strips(peps_ctx* c, const uint8_t* sm, int m, const char* et,
                               double* eloc, void* O, int* flags, hipStream_t st) {
   const Lattice& L = c->L;
-  const int ch = chunk_size(c, n);
   const size_t box = L.site_box;
   const size_t box2 = (size_t)L.bmax * L.bmax * L.D * L.D;
   const int nparts = 1 + L.Lx + (L.Lx - 1);
   const bool want_e = eloc != nullptr;
   const bool want_o = O != nullptr;
-  peps_status s = c->rt1.ensure((size_t)ch * L.Lx * (L.Ly + 1) * box * c->tsize);
+  peps_status s = c->rt1.ensure((size_t)m * L.Lx * (L.Ly + 1) * box * c->tsize);
   if (s != PEPS_OK) return s;
-  if (want_e) {
-    s = c->rt2.ensure((size_t)ch * (L.Lx - 1) * (L.Ly + 1) * box2 * c->tsize);
-    if (s != PEPS_OK) return s;
-    s = c->epart.ensure((size_t)ch * nparts * 2 * sizeof(double));
-    if (s != PEPS_OK) return s;
+  void* g1 = nullptr;
+  void* g2 = nullptr;
+  if (c->s1_gm) {
+    if ((s = c->gws_s1.ensure((size_t)m * L.Lx * strip1_slab_elems(L) * c->tsize)) != PEPS_OK)
+      return s;
+    g1 = c->gws_s1.p;
   }
   HamDev H = c->H;
-  if (!c->has_ham) {
-    H = HamDev{};
+  if (!c->has_ham) H = HamDev{};
+  if (want_e) {
+    s = c->rt2.ensure((size_t)m * (L.Lx - 1) * (L.Ly + 1) * box2 * c->tsize);
+    if (s != PEPS_OK) return s;
+    s = c->epart.ensure((size_t)m * nparts * 2 * sizeof(double));
+    if (s != PEPS_OK) return s;
+    if (c->s2_gm && H.n_strips) {
+      if ((s = c->gws_s2.ensure((size_t)m * (L.Lx - 1) * strip2_slab_elems(L) * c->tsize)) !=
+          PEPS_OK)
+        return s;
+      g2 = c->gws_s2.p;
+    }
   }
-  const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
-  const size_t ob = (c->g.dtype == PEPS_F64 ? 8 : 4);
-  for (int c0 = 0; c0 < n; c0 += ch) {
-    const int m = std::min(ch, n - c0);
-    const uint8_t* sm = samples + (size_t)c0 * L.N;
-    const char* et = env_t + (size_t)c0 * per_t;
-    char* Oc = want_o ? (char*)O + (size_t)c0 * L.n_compact * ob : nullptr;
-    if (want_e) HIPCHK(hipMemsetAsync(c->epart.p, 0, (size_t)m * nparts * 2 * sizeof(double), st));
-    {
-      ProfScope ps(c, st, PEPS_PROF_STRIP1);
-      HIPCHK(launch_strip1<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt1.p, (double*)c->epart.p,
-                            Oc, flags ? flags + c0 : nullptr, m, want_e, want_o, st));
+  if (want_e) HIPCHK(hipMemsetAsync(c->epart.p, 0, (size_t)m * nparts * 2 * sizeof(double), st));
+  {
+    ProfScope ps(c, st, PEPS_PROF_STRIP1);
+    HIPCHK(launch_strip1<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt1.p, (double*)c->epart.p,
+                            O, flags, m, want_e, want_o, g1, st));
+  }
+  if (want_e) {
+    if (H.n_strips) {
+      ProfScope ps(c, st, PEPS_PROF_STRIP2);
+      HIPCHK(launch_strip2<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt2.p,
+                              (double*)c->epart.p, flags, m, g2, st));
     }
-    if (want_e) {
-      if (H.n_strips) {
-        ProfScope ps(c, st, PEPS_PROF_STRIP2);
-        HIPCHK(launch_strip2<M>(L, c->d_tab, c->theta_c.p, sm, et, H, c->rt2.p,
-                                (double*)c->epart.p, flags ? flags + c0 : nullptr, m, st));
-      }
-      ProfScope ps(c, st, PEPS_PROF_ESUM);
-      HIPCHK(launch_energy_diag_sum(L, H, sm, (const double*)c->epart.p, nparts,
-                                    eloc + (size_t)c0 * 2, m, st));
-    }
+    ProfScope ps(c, st, PEPS_PROF_ESUM);
+    HIPCHK(launch_energy_diag_sum(L, H, sm, (const double*)c->epart.p, nparts, eloc, m, st));
   }
   return PEPS_OK;
 }
@@ -537,36 +555,57 @@ static peps_status check_common(peps_ctx* c, const double* theta, const uint8_t*
   return PEPS_OK;
 }
 
+// Every requested output of n samples, chunk by chunk: environments (unless
+// the caller's cache already holds them), the amplitude, then the strips.
+// Without a caller cache the environments of one chunk live in the
+// context's workspace only, so the batch size is not bounded by memory.
 template <int M>
 static peps_status evaluate_impl(peps_ctx* c, const double* theta, const uint8_t* samples, int n,
                                  void* env_cache, bool env_given, double* logpsi, double* eloc,
                                  void* O, int* flags, hipStream_t st) {
+  (void)theta;
   const Lattice& L = c->L;
-  char* env_t;
-  double* env_l;
-  const size_t tbytes = (size_t)n * env_tensor_elems_per_sample(L) * c->tsize;
-  if (env_cache) {
-    env_t = (char*)env_cache;
-    env_l = (double*)((char*)env_cache + tbytes);
-  } else {
-    peps_status s = c->env_int.ensure(peps_env_cache_bytes(c, n));
+  const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
+  const bool internal = env_cache == nullptr;
+  const int ch = chunk_size(c, n, internal);
+  char* cache_t = nullptr;
+  double* cache_l = nullptr;
+  if (internal) {
+    peps_status s = c->env_int.ensure((size_t)ch * (per_t + L.n_slots * sizeof(double)));
     if (s != PEPS_OK) return s;
-    env_t = (char*)c->env_int.p;
-    env_l = (double*)((char*)c->env_int.p + tbytes);
+  } else {
+    cache_t = (char*)env_cache;
+    cache_l = (double*)((char*)env_cache + (size_t)n * per_t);
   }
   if (flags) HIPCHK(hipMemsetAsync(flags, 0, (size_t)n * sizeof(int32_t), st));
-  if (!env_given) {
-    peps_status s = run_envs<M>(c, samples, n, env_t, env_l, flags, st);
-    if (s != PEPS_OK) return s;
-  }
-  if (logpsi) {
-    ProfScope ps(c, st, PEPS_PROF_OVERLAP);
-    HIPCHK(launch_overlap<M>(L, c->d_tab, env_t, env_l, c->icut, logpsi, flags, n, st));
-  }
-  if (eloc || O) {
-    if (eloc && !c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
-    peps_status s = run_strips<M>(c, samples, n, env_t, eloc, O, flags, st);
-    if (s != PEPS_OK) return s;
+  const size_t ob = c->tsize;  // bytes of one O entry
+  for (int c0 = 0; c0 < n; c0 += ch) {
+    const int m = std::min(ch, n - c0);
+    const uint8_t* sm = samples + (size_t)c0 * L.N;
+    char* et;
+    double* el;
+    if (internal) {
+      et = (char*)c->env_int.p;
+      el = (double*)((char*)c->env_int.p + (size_t)m * per_t);
+    } else {
+      et = cache_t + (size_t)c0 * per_t;
+      el = cache_l + (size_t)c0 * L.n_slots;
+    }
+    int* fl = flags ? flags + c0 : nullptr;
+    if (!env_given) {
+      peps_status s = run_envs<M>(c, sm, m, et, el, fl, st);
+      if (s != PEPS_OK) return s;
+    }
+    if (logpsi) {
+      ProfScope ps(c, st, PEPS_PROF_OVERLAP);
+      HIPCHK(launch_overlap<M>(L, c->d_tab, et, el, c->icut, logpsi + (size_t)c0 * 2, fl, m, st));
+    }
+    if (eloc || O) {
+      peps_status s = run_strips<M>(c, sm, m, et, eloc ? eloc + (size_t)c0 * 2 : nullptr,
+                                    O ? (char*)O + (size_t)c0 * L.n_compact * ob : nullptr, fl,
+                                    st);
+      if (s != PEPS_OK) return s;
+    }
   }
   return PEPS_OK;
 }
@@ -576,6 +615,7 @@ static peps_status dispatch(peps_ctx* c, const double* theta, const uint8_t* sam
                             int* flags, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n == 0) return PEPS_OK;
+  if (eloc && !c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
   peps_status s = prepare_theta(c, theta, st);
   if (s != PEPS_OK) return s;
   switch (c->g.dtype) {
@@ -585,9 +625,15 @@ static peps_status dispatch(peps_ctx* c, const double* theta, const uint8_t* sam
     case PEPS_F32:
       return evaluate_impl<MODE_F32>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
                                      flags, st);
-    default:
+    case PEPS_BF16:
       return evaluate_impl<MODE_BF16>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
                                       flags, st);
+    case PEPS_C128:
+      return evaluate_impl<MODE_C128>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                      flags, st);
+    default:
+      return evaluate_impl<MODE_C64>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                     flags, st);
   }
 }
 
@@ -639,11 +685,14 @@ peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n
   if ((size_t)n * n > ((size_t)1 << 33)) return fail(PEPS_ERR_UNSUPPORTED, "n = %d too large", n);
   hipStream_t st = (hipStream_t)stream;
   const Lattice& L = c->L;
-  peps_status s = c->mean.ensure((size_t)L.n_params * sizeof(double));
+  const int mode = c->g.dtype == PEPS_BF16 ? MODE_F32 : c->g.dtype;
+  size_t b_mean, b_T, b_vec;
+  minsr_ws_bytes(L, mode, n, &b_mean, &b_T, &b_vec);
+  peps_status s = c->mean.ensure(b_mean);
   if (s != PEPS_OK) return s;
-  s = c->Tm.ensure((size_t)n * n * sizeof(double));
+  s = c->Tm.ensure(b_T);
   if (s != PEPS_OK) return s;
-  s = c->vec.ensure(((size_t)2 * n + 1 + 16 + 2) * sizeof(double));
+  s = c->vec.ensure(b_vec);
   if (s != PEPS_OK) return s;
   // reject non-finite E before any work
   {
@@ -655,9 +704,8 @@ peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n
       if (!std::isfinite(v)) return fail(PEPS_ERR_NONFINITE, "eloc contains non-finite values");
   }
   ProfScope ps(c, st, PEPS_PROF_MINSR);
-  HIPCHK(launch_minsr(L, c->d_tab, c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, O, samples, n,
-                      eloc, eps, rcond, dtheta, diag, (double*)c->mean.p, (double*)c->Tm.p,
-                      (double*)c->vec.p, st));
+  HIPCHK(launch_minsr(L, c->d_tab, mode, O, samples, n, eloc, eps, rcond, dtheta, diag,
+                      c->mean.p, c->Tm.p, c->vec.p, st));
   return PEPS_OK;
 }
 
@@ -666,6 +714,8 @@ peps_status peps_logderiv_vjp(peps_ctx* c, const void* O, const uint8_t* samples
   if (!c) return fail(PEPS_ERR_ARG, "null context");
   if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
   if (!grad_theta || (n > 0 && (!O || !samples || !g))) return fail(PEPS_ERR_ARG, "null pointer");
+  if (is_complex(c->g.dtype))
+    return fail(PEPS_ERR_UNSUPPORTED, "the vector-Jacobian product is for real parameters");
   hipStream_t st = (hipStream_t)stream;
   if (n == 0) {
     HIPCHK(hipMemsetAsync(grad_theta, 0, (size_t)c->L.n_params * sizeof(double), st));
@@ -717,9 +767,7 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
   if ((long long)burn_in + (long long)per_chain * thin > (1LL << 30))
     return fail(PEPS_ERR_ARG, "too many sweeps");
   const Lattice& L = c->L;
-  const size_t lds = sample_lds_elems(L.bmax, L.D) * c->tsize;
-  if (lds + 8 * 1024 > 160 * 1024)
-    return fail(PEPS_ERR_UNSUPPORTED, "sampler needs %zu bytes of LDS per workgroup", lds);
+  if (L.N > 1024) return fail(PEPS_ERR_UNSUPPORTED, "sampler holds at most 1024 sites");
   hipStream_t st = (hipStream_t)stream;
   peps_status s = prepare_theta(c, theta, st);
   if (s != PEPS_OK) return s;
@@ -732,26 +780,25 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
   if ((s = c->rscr.ensure(nc * L.Ly * BD * BD * c->tsize)) != PEPS_OK) return s;
   if ((s = c->rt1.ensure(nc * (L.Ly + 1) * box * c->tsize)) != PEPS_OK) return s;
   if ((s = c->rt2.ensure(nc * (L.Ly + 1) * box2 * c->tsize)) != PEPS_OK) return s;
-  ProfScope ps(c, st, PEPS_PROF_SAMPLE);
-  switch (c->g.dtype) {
-    case PEPS_F64:
-      HIPCHK(launch_metropolis<MODE_F64>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain,
-                                         burn_in, thin, seed, offset, samples, accepted,
-                                         c->env_int.p, (double*)c->eloc_tmp.p, c->rscr.p,
-                                         c->rt1.p, c->rt2.p, c->jac_sweeps, st));
-      break;
-    case PEPS_F32:
-      HIPCHK(launch_metropolis<MODE_F32>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain,
-                                         burn_in, thin, seed, offset, samples, accepted,
-                                         c->env_int.p, (double*)c->eloc_tmp.p, c->rscr.p,
-                                         c->rt1.p, c->rt2.p, c->jac_sweeps, st));
-      break;
-    default:
-      HIPCHK(launch_metropolis<MODE_BF16>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain,
-                                          burn_in, thin, seed, offset, samples, accepted,
-                                          c->env_int.p, (double*)c->eloc_tmp.p, c->rscr.p,
-                                          c->rt1.p, c->rt2.p, c->jac_sweeps, st));
+  void* gws = nullptr;
+  if (c->smp_gm) {
+    if ((s = c->gws_smp.ensure(nc * sample_slab_elems(L) * c->tsize)) != PEPS_OK) return s;
+    gws = c->gws_smp.p;
   }
+  ProfScope ps(c, st, PEPS_PROF_SAMPLE);
+#define MET(MODE)                                                                               \
+  HIPCHK(launch_metropolis<MODE>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain, burn_in, \
+                                 thin, seed, offset, samples, accepted, c->env_int.p,           \
+                                 (double*)c->eloc_tmp.p, c->rscr.p, c->rt1.p, c->rt2.p,         \
+                                 c->jac_sweeps, gws, st))
+  switch (c->g.dtype) {
+    case PEPS_F64: MET(MODE_F64); break;
+    case PEPS_F32: MET(MODE_F32); break;
+    case PEPS_BF16: MET(MODE_BF16); break;
+    case PEPS_C128: MET(MODE_C128); break;
+    default: MET(MODE_C64);
+  }
+#undef MET
   return PEPS_OK;
 }
 

@@ -17,17 +17,161 @@ namespace pm {
 // In BF16 mode every contraction operand is rounded to bfloat16 (round to
 // nearest even) and the products are accumulated in FP32.
 // ---------------------------------------------------------------------------
-enum Mode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
+enum Mode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2, MODE_C128 = 3, MODE_C64 = 4 };
 
-// Threads per environment / sampler workgroup: FP64 holds more LDS per
-// workgroup (one per CU), so it runs eight waves; the FP32 modes fit two
-// workgroups per CU and run four waves each.
-__host__ __device__ constexpr int env_threads(int mode) { return mode == 0 ? 512 : 256; }
+// Threads per environment / sampler workgroup: the 8-byte and 16-byte
+// element modes hold more LDS per workgroup (one per CU), so they run eight
+// waves; FP32 and BF16 fit two workgroups per CU and run four waves each.
+__host__ __device__ constexpr int env_threads(int mode) {
+  return (mode == MODE_F32 || mode == MODE_BF16) ? 256 : 512;
+}
+
+// ---------------------------------------------------------------------------
+// Complex scalar for the complex-tensor modes. Contractions of the network
+// never conjugate (the amplitude is holomorphic in the tensors); the
+// orthogonalisations (Householder, Jacobi) and the minSR Gram use conjx.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct cplx {
+  R re, im;
+  cplx() = default;
+  template <typename U>
+  __host__ __device__ constexpr cplx(U r) : re(R(r)), im(0) {}
+  __host__ __device__ constexpr cplx(R r, R i) : re(r), im(i) {}
+  __host__ __device__ cplx& operator+=(const cplx& b) {
+    re += b.re;
+    im += b.im;
+    return *this;
+  }
+  __host__ __device__ cplx& operator-=(const cplx& b) {
+    re -= b.re;
+    im -= b.im;
+    return *this;
+  }
+  __host__ __device__ cplx& operator*=(const cplx& b) {
+    const R r = re * b.re - im * b.im;
+    im = re * b.im + im * b.re;
+    re = r;
+    return *this;
+  }
+  __host__ __device__ cplx& operator*=(R s) {
+    re *= s;
+    im *= s;
+    return *this;
+  }
+};
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) {
+  return cplx<R>(a.re + b.re, a.im + b.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) {
+  return cplx<R>(a.re - b.re, a.im - b.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator-(cplx<R> a) {
+  return cplx<R>(-a.re, -a.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(cplx<R> a, cplx<R> b) {
+  return cplx<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(cplx<R> a, R s) {
+  return cplx<R>(a.re * s, a.im * s);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(R s, cplx<R> a) {
+  return cplx<R>(a.re * s, a.im * s);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator/(cplx<R> a, R s) {
+  return cplx<R>(a.re / s, a.im / s);
+}
+template <typename R>
+__host__ __device__ __forceinline__ bool operator==(cplx<R> a, cplx<R> b) {
+  return a.re == b.re && a.im == b.im;
+}
+template <typename R>
+__host__ __device__ __forceinline__ bool operator!=(cplx<R> a, cplx<R> b) {
+  return !(a == b);
+}
+
+template <typename T> struct RealOf { typedef T type; };
+template <typename R> struct RealOf<cplx<R>> { typedef R type; };
+template <typename T> struct IsCplx { static constexpr bool value = false; };
+template <typename R> struct IsCplx<cplx<R>> { static constexpr bool value = true; };
+
+__host__ __device__ __forceinline__ float conjx(float x) { return x; }
+__host__ __device__ __forceinline__ double conjx(double x) { return x; }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> conjx(cplx<R> x) { return cplx<R>(x.re, -x.im); }
+__host__ __device__ __forceinline__ float abs2x(float x) { return x * x; }
+__host__ __device__ __forceinline__ double abs2x(double x) { return x * x; }
+template <typename R>
+__host__ __device__ __forceinline__ R abs2x(cplx<R> x) { return x.re * x.re + x.im * x.im; }
+__device__ __forceinline__ float absx(float x) { return fabsf(x); }
+__device__ __forceinline__ double absx(double x) { return fabs(x); }
+template <typename R>
+__device__ __forceinline__ R absx(cplx<R> x) { return sqrt(x.re * x.re + x.im * x.im); }
+__host__ __device__ __forceinline__ float realx(float x) { return x; }
+__host__ __device__ __forceinline__ double realx(double x) { return x; }
+template <typename R>
+__host__ __device__ __forceinline__ R realx(cplx<R> x) { return x.re; }
+__host__ __device__ __forceinline__ float imagx(float) { return 0.f; }
+__host__ __device__ __forceinline__ double imagx(double) { return 0.0; }
+template <typename R>
+__host__ __device__ __forceinline__ R imagx(cplx<R> x) { return x.im; }
+__device__ __forceinline__ bool finitex(float x) { return isfinite(x); }
+__device__ __forceinline__ bool finitex(double x) { return isfinite(x); }
+template <typename R>
+__device__ __forceinline__ bool finitex(cplx<R> x) { return isfinite(x.re) && isfinite(x.im); }
+// 1 / x
+__device__ __forceinline__ float recipx(float x) { return 1.f / x; }
+__device__ __forceinline__ double recipx(double x) { return 1.0 / x; }
+template <typename R>
+__device__ __forceinline__ cplx<R> recipx(cplx<R> x) {
+  // Smith's scaling: no overflow of |x|^2 for large entries
+  if (fabs(x.re) >= fabs(x.im)) {
+    const R r = x.im / x.re, den = x.re + x.im * r;
+    return cplx<R>(R(1) / den, -r / den);
+  }
+  const R r = x.re / x.im, den = x.re * r + x.im;
+  return cplx<R>(r / den, R(-1) / den);
+}
+// (nr + i ni) / (dr + i di) in FP64 by Smith's algorithm; for di = 0 it
+// reduces exactly to the two real divisions.
+__device__ __forceinline__ void cdiv(double nr, double ni, double dr, double di, double& qr,
+                                     double& qi) {
+  if (fabs(di) <= fabs(dr)) {
+    const double r = di / dr, den = dr + di * r;
+    qr = (nr + ni * r) / den;
+    qi = (ni - nr * r) / den;
+  } else {
+    const double r = dr / di, den = dr * r + di;
+    qr = (nr * r + ni) / den;
+    qi = (ni * r - nr) / den;
+  }
+}
+
+__device__ __forceinline__ float shfl_xor_x(float v, int o) { return __shfl_xor(v, o, 64); }
+__device__ __forceinline__ double shfl_xor_x(double v, int o) { return __shfl_xor(v, o, 64); }
+template <typename R>
+__device__ __forceinline__ cplx<R> shfl_xor_x(cplx<R> v, int o) {
+  return cplx<R>(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64));
+}
+
+// bytes per element of the compute type of a mode
+__host__ __device__ constexpr size_t mode_elem_bytes(int mode) {
+  return mode == MODE_C128 ? 16 : (mode == MODE_F64 || mode == MODE_C64) ? 8 : 4;
+}
 
 template <int M> struct ModeT;
 template <> struct ModeT<MODE_F64> { typedef double T; };
 template <> struct ModeT<MODE_F32> { typedef float T; };
 template <> struct ModeT<MODE_BF16> { typedef float T; };
+template <> struct ModeT<MODE_C128> { typedef cplx<double> T; };
+template <> struct ModeT<MODE_C64> { typedef cplx<float> T; };
 
 __device__ __forceinline__ float bf16_round(float x) {
   uint32_t u = __float_as_uint(x);
@@ -50,6 +194,7 @@ __device__ __forceinline__ int pbit(uint8_t v) { return v & 1; }
 template <typename T> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 template <> struct Eps<float> { static constexpr float v = 1.1920929e-7f; };
+template <typename R> struct Eps<cplx<R>> { static constexpr R v = Eps<R>::v; };
 
 // ---------------------------------------------------------------------------
 // Lattice tables (host-computed, device-resident int array).
@@ -80,7 +225,7 @@ __device__ __forceinline__ int slot_bottom(const Lattice& L, int x) { return L.L
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = 32; o >= 1; o >>= 1) v += shfl_xor_x(v, o);
   return v;
 }
 
@@ -125,7 +270,7 @@ __device__ T block_max(T v, T* red) {
 // Sum over groups of G consecutive lanes (G a power of two, G <= 64).
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-  for (int o = G >> 1; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = G >> 1; o >= 1; o >>= 1) v += shfl_xor_x(v, o);
   return v;
 }
 
@@ -134,9 +279,9 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 // written to C[i*sci + j*scj]. Operands may live in LDS or global memory.
 // Lanes run over j (a power of two >= n, at most 64), the rest of the block
 // over i, two rows per thread so each B element is read once for both.
-// The caller synchronises before reading C.
+// The caller synchronises before reading C. CB conjugates the B operand.
 // ---------------------------------------------------------------------------
-template <int M, typename T>
+template <int M, bool CB = false, typename T>
 __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T* B, int sbk,
                      int sbj, T* C, int sci, int scj, bool acc) {
   int lj = 0;
@@ -153,7 +298,8 @@ __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T*
       const T* bp = B + j * sbj;
       T s1 = 0, s2 = 0;
       for (int kk = 0; kk < k; ++kk) {
-        const T bv = opnd<M>(bp[kk * sbk]);
+        T bv = opnd<M>(bp[kk * sbk]);
+        if constexpr (CB) bv = conjx(bv);
         s1 += opnd<M>(a1[kk * sak]) * bv;
         s2 += opnd<M>(a2[kk * sak]) * bv;
       }
@@ -177,10 +323,13 @@ __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T*
 // lanes share a column and split its rows, so the reflector's dot products
 // reduce over four lanes without touching LDS, and each column costs one
 // barrier: the wave that owns column j+1 also sums its squares for the next
-// reflector. nrm: LDS scratch of >= 2 elements.
+// reflector. nrm: LDS scratch of >= 2 elements. For complex T the reflectors
+// are unitary, H = I - tau v v^H, and R has a complex diagonal.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* nrm) {
+__device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda,
+                                 typename RealOf<T>::type* nrm) {
+  typedef typename RealOf<T>::type R;
   const int NW = PEPS_NT / 64;  // waves in the block
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int sub = lane & 3, cl = lane >> 2;  // row subset, column slot in the wave
@@ -189,22 +338,22 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* nrm) {
   // squares of column 0 below its diagonal (rows >= max(kr, 1))
   if (wv == 0) {
     const int r0 = kr > 1 ? kr : 1;
-    T sq = 0;
-    for (int i = r0 + lane; i < m; i += 64) sq += A[i * lda] * A[i * lda];
+    R sq = 0;
+    for (int i = r0 + lane; i < m; i += 64) sq += abs2x(A[i * lda]);
     sq = wave_sum(sq);
     if (lane == 0) nrm[0] = sq;
   }
   __syncthreads();
   for (int j = 0; j < kmax; ++j) {
     const int r0 = kr > j + 1 ? kr : j + 1;
-    const T s = nrm[j & 1];
+    const R s = nrm[j & 1];
     const int r0n = kr > j + 2 ? kr : j + 2;  // rows of the next reflector
-    if (s == T(0)) {
+    if (s == R(0)) {
       // nothing to eliminate in column j; the next column's squares are
       // still needed
       if (j + 1 < kmax && ((j + 1) % NW) == wv) {
-        T sq = 0;
-        for (int i = r0n + lane; i < m; i += 64) sq += A[i * lda + j + 1] * A[i * lda + j + 1];
+        R sq = 0;
+        for (int i = r0n + lane; i < m; i += 64) sq += abs2x(A[i * lda + j + 1]);
         sq = wave_sum(sq);
         if (lane == 0) nrm[(j + 1) & 1] = sq;
       }
@@ -212,10 +361,22 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* nrm) {
       continue;
     }
     const T ajj = A[j * lda + j];
-    const T nr = sqrt(ajj * ajj + s);
-    const T alpha = ajj > T(0) ? -nr : nr;
-    const T v0 = ajj - alpha;
-    const T tau = T(2) / (v0 * v0 + s);
+    T alpha, v0;
+    R tau;
+    if constexpr (IsCplx<T>::value) {
+      // H = I - tau v v^H with v = (ajj - alpha, column below); alpha takes
+      // the opposite phase of ajj so v0 suffers no cancellation
+      const R aa = absx(ajj);
+      const R nr = sqrt(aa * aa + s);
+      alpha = aa > R(0) ? ajj * (-nr / aa) : T(-nr);
+      v0 = ajj - alpha;
+      tau = R(2) / (abs2x(v0) + s);
+    } else {
+      const T nr = sqrt(ajj * ajj + s);
+      alpha = ajj > T(0) ? -nr : nr;
+      v0 = ajj - alpha;
+      tau = T(2) / (v0 * v0 + s);
+    }
     // columns c > j owned by this lane: c = NW * (16 q + cl) + wv
     for (int q = 0; q < 256 / (16 * NW); ++q) {
       const int c = NW * (16 * q + cl) + wv;
@@ -224,23 +385,23 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* nrm) {
       T rowj = 0;
       if (own) {
         rowj = A[j * lda + c];
-        for (int i = r0 + sub; i < m; i += 4) d += A[i * lda + j] * A[i * lda + c];
+        for (int i = r0 + sub; i < m; i += 4) d += conjx(A[i * lda + j]) * A[i * lda + c];
       }
-      d += __shfl_xor(d, 1, 64);
-      d += __shfl_xor(d, 2, 64);
-      T sqn = 0;
+      d += shfl_xor_x(d, 1);
+      d += shfl_xor_x(d, 2);
+      R sqn = 0;
       if (own) {
-        const T w = tau * (v0 * rowj + d);
+        const T w = tau * (conjx(v0) * rowj + d);
         if (sub == 0) A[j * lda + c] = rowj - v0 * w;
         for (int i = r0 + sub; i < m; i += 4) {
           const T nv = A[i * lda + c] - A[i * lda + j] * w;
           A[i * lda + c] = nv;
-          if (i >= r0n) sqn += nv * nv;
+          if (i >= r0n) sqn += abs2x(nv);
         }
       }
       if (c == j + 1 && j + 1 < kmax) {  // this column feeds the next reflector
-        sqn += __shfl_xor(sqn, 1, 64);
-        sqn += __shfl_xor(sqn, 2, 64);
+        sqn += shfl_xor_x(sqn, 1);
+        sqn += shfl_xor_x(sqn, 2);
         if (sub == 0) nrm[(j + 1) & 1] = sqn;
       }
     }
@@ -264,38 +425,28 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda, T* nrm) {
 // NC contiguous elements through 16-byte LDS accesses (caller checks alignment)
 template <typename T, int NC>
 __device__ __forceinline__ void load16(const T* src, T* dst) {
-  constexpr int W = 16 / sizeof(T);
+  constexpr int W = sizeof(T) >= 16 ? 1 : 16 / (int)sizeof(T);
 #pragma unroll
-  for (int t = 0; t < NC; t += W) {
-    if constexpr (sizeof(T) == 4) {
-      const float4 v = *reinterpret_cast<const float4*>(src + t);
-      dst[t] = v.x;
-      dst[t + 1] = v.y;
-      dst[t + 2] = v.z;
-      dst[t + 3] = v.w;
-    } else {
-      const double2 v = *reinterpret_cast<const double2*>(src + t);
-      dst[t] = v.x;
-      dst[t + 1] = v.y;
-    }
+  for (int t = 0; t + W <= NC; t += W) {
+    const float4 v = *reinterpret_cast<const float4*>(src + t);
+    __builtin_memcpy(dst + t, &v, 16);
   }
 }
 template <typename T, int NC>
 __device__ __forceinline__ void store16(T* dst, const T* src) {
-  constexpr int W = 16 / sizeof(T);
+  constexpr int W = sizeof(T) >= 16 ? 1 : 16 / (int)sizeof(T);
 #pragma unroll
-  for (int t = 0; t < NC; t += W) {
-    if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4*>(dst + t) = make_float4(src[t], src[t + 1], src[t + 2], src[t + 3]);
-    } else {
-      *reinterpret_cast<double2*>(dst + t) = make_double2(src[t], src[t + 1]);
-    }
+  for (int t = 0; t + W <= NC; t += W) {
+    float4 v;
+    __builtin_memcpy(&v, src + t, 16);
+    *reinterpret_cast<float4*>(dst + t) = v;
   }
 }
 
 template <typename T, int NC>
-__device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag,
-                              int G, T* nrm) {
+__device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::type tol,
+                              int max_sweeps, int* sflag, int G, typename RealOf<T>::type* nrm) {
+  typedef typename RealOf<T>::type R;
   const int tid = threadIdx.x;
   const int mp = m + (m & 1);
   const int npairs = mp >> 1;
@@ -304,15 +455,15 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
   // lane owns the contiguous elements [lane*NC, lane*NC + NC) of both rows
   const int e0 = lane * NC;
   const bool full = e0 + NC <= n;
-  // 16-byte LDS accesses when every owned run is 16-byte aligned
+  // 16-byte accesses when every owned run is 16-byte aligned
   const bool vec = (NC * sizeof(T)) % 16 == 0 && (ldx * sizeof(T)) % 16 == 0 &&
                    (reinterpret_cast<uintptr_t>(X) & 15) == 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // squared row norms, refreshed every sweep and then carried through the
-    // rotations: a' = a - t c, b' = b + t c
+    // rotations: a' = a - t |c|, b' = b + t |c|
     for (int i = tid; i < m; i += PEPS_NT) {
-      T q2 = 0;
-      for (int e = 0; e < n; ++e) q2 += X[i * ldx + e] * X[i * ldx + e];
+      R q2 = 0;
+      for (int e = 0; e < n; ++e) q2 += abs2x(X[i * ldx + e]);
       nrm[i] = q2;
     }
     if (tid == 0) *sflag = 0;
@@ -355,23 +506,37 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
         }
         T c = 0;
 #pragma unroll
-        for (int t = 0; t < NC; ++t) c += xp[t] * xq[t];
+        for (int t = 0; t < NC; ++t) c += conjx(xp[t]) * xq[t];
         c = group_sum(c, G);
-        const T a = act ? nrm[p] : T(0), b = act ? nrm[q] : T(0);
-        if (act && c != T(0) && fabs(c) > tol * sqrt(a * b)) {
-          const T zeta = (b - a) / (T(2) * c);
-          const T az = fabs(zeta);
-          T t;
-          if (az > T(1) / Eps<T>::v) t = T(0.5) / zeta;
-          else t = (zeta >= T(0) ? T(1) : T(-1)) / (az + sqrt(T(1) + zeta * zeta));
-          const T cs = T(1) / sqrt(T(1) + t * t);
-          const T sn = cs * t;
+        const R a = act ? nrm[p] : R(0), b = act ? nrm[q] : R(0);
+        // |c| (real: the signed value, whose sign the rotation absorbs)
+        R cm;
+        if constexpr (IsCplx<T>::value) cm = absx(c);
+        else cm = c;
+        if (act && cm != R(0) && fabs(cm) > tol * sqrt(a * b)) {
+          const R zeta = (b - a) / (R(2) * cm);
+          const R az = fabs(zeta);
+          R t;
+          if (az > R(1) / Eps<R>::v) t = R(0.5) / zeta;
+          else t = (zeta >= R(0) ? R(1) : R(-1)) / (az + sqrt(R(1) + zeta * zeta));
+          const R cs = R(1) / sqrt(R(1) + t * t);
+          const R sn = cs * t;
+          // complex: rotate (p, e* q) with e = c/|c|, which makes <p, e* q> real
+          T sq, cq;
+          if constexpr (IsCplx<T>::value) {
+            const T ec = conjx(c) * (R(1) / cm);
+            sq = ec * sn;
+            cq = ec * cs;
+          } else {
+            sq = sn;
+            cq = cs;
+          }
           if (full) {
             T yp[NC], yq[NC];
 #pragma unroll
             for (int u = 0; u < NC; ++u) {
-              yp[u] = cs * xp[u] - sn * xq[u];
-              yq[u] = sn * xp[u] + cs * xq[u];
+              yp[u] = cs * xp[u] - sq * xq[u];
+              yq[u] = sn * xp[u] + cq * xq[u];
             }
             if (vec) {
               store16<T, NC>(rp, yp);
@@ -387,14 +552,98 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
 #pragma unroll
             for (int u = 0; u < NC; ++u)
               if (e0 + u < n) {
-                rp[u] = cs * xp[u] - sn * xq[u];
-                rq[u] = sn * xp[u] + cs * xq[u];
+                rp[u] = cs * xp[u] - sq * xq[u];
+                rq[u] = sn * xp[u] + cq * xq[u];
               }
           }
           if (lane == 0) {
             *sflag = 1;
-            nrm[p] = a - t * c;
-            nrm[q] = b + t * c;
+            nrm[p] = a - t * cm;
+            nrm[q] = b + t * cm;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int f = *sflag;
+    __syncthreads();
+    if (f == 0) return sweep + 1;
+  }
+  return -1;
+}
+
+// The same sweep for rows too long to hold in registers (nc > 32): each lane
+// strides over the row twice, once for the dot product and once to rotate.
+template <typename T>
+__device__ int jacobi_rows_long(T* X, int m, int n, int ldx, typename RealOf<T>::type tol,
+                                int max_sweeps, int* sflag, int G,
+                                typename RealOf<T>::type* nrm) {
+  typedef typename RealOf<T>::type R;
+  const int tid = threadIdx.x;
+  const int mp = m + (m & 1);
+  const int npairs = mp >> 1;
+  const int pr = tid / G, lane = tid - (tid / G) * G;
+  const int per_pass = PEPS_NT / G;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int i = tid; i < m; i += PEPS_NT) {
+      R q2 = 0;
+      for (int e = 0; e < n; ++e) q2 += abs2x(X[i * ldx + e]);
+      nrm[i] = q2;
+    }
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < mp - 1; ++r) {
+      for (int pb = 0; pb < npairs; pb += per_pass) {
+        const int pi = pb + pr;
+        int p = -1, q = -1;
+        if (pi < npairs) {
+          if (pi == 0) {
+            p = mp - 1;
+            q = r;
+          } else {
+            p = r + pi;
+            if (p >= mp - 1) p -= mp - 1;
+            q = r - pi;
+            if (q < 0) q += mp - 1;
+          }
+        }
+        const bool act = (pi < npairs) && p < m && q < m;
+        T* rp = X + (act ? p : 0) * ldx;
+        T* rq = X + (act ? q : 0) * ldx;
+        T c = 0;
+        if (act)
+          for (int e = lane; e < n; e += G) c += conjx(rp[e]) * rq[e];
+        c = group_sum(c, G);
+        const R a = act ? nrm[p] : R(0), b = act ? nrm[q] : R(0);
+        R cm;
+        if constexpr (IsCplx<T>::value) cm = absx(c);
+        else cm = c;
+        if (act && cm != R(0) && fabs(cm) > tol * sqrt(a * b)) {
+          const R zeta = (b - a) / (R(2) * cm);
+          const R az = fabs(zeta);
+          R t;
+          if (az > R(1) / Eps<R>::v) t = R(0.5) / zeta;
+          else t = (zeta >= R(0) ? R(1) : R(-1)) / (az + sqrt(R(1) + zeta * zeta));
+          const R cs = R(1) / sqrt(R(1) + t * t);
+          const R sn = cs * t;
+          T sq, cq;
+          if constexpr (IsCplx<T>::value) {
+            const T ec = conjx(c) * (R(1) / cm);
+            sq = ec * sn;
+            cq = ec * cs;
+          } else {
+            sq = sn;
+            cq = cs;
+          }
+          for (int e = lane; e < n; e += G) {
+            const T xp = rp[e], xq = rq[e];
+            rp[e] = cs * xp - sq * xq;
+            rq[e] = sn * xp + cq * xq;
+          }
+          if (lane == 0) {
+            *sflag = 1;
+            nrm[p] = a - t * cm;
+            nrm[q] = b + t * cm;
           }
         }
       }
@@ -408,8 +657,8 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, T tol, int max_sweeps
 }
 
 template <typename T>
-__device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, int* sflag,
-                           T* nrm) {
+__device__ int jacobi_rows(T* X, int m, int n, int ldx, typename RealOf<T>::type tol,
+                           int max_sweeps, int* sflag, typename RealOf<T>::type* nrm) {
   if (m < 2) return 0;
   const int npairs = (m + (m & 1)) >> 1;
   int G = 64;
@@ -420,7 +669,8 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, T tol, int max_sweeps, i
   if (nc <= 4) return jacobi_rows_nc<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
   if (nc <= 8) return jacobi_rows_nc<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
   if (nc <= 16) return jacobi_rows_nc<T, 16>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
-  return jacobi_rows_nc<T, 32>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  if (nc <= 32) return jacobi_rows_nc<T, 32>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+  return jacobi_rows_long<T>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
 }
 
 // ---------------------------------------------------------------------------

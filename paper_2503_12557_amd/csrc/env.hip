@@ -22,18 +22,24 @@ namespace pm {
 
 size_t env_lds_elems(int bmax, int D) { return env_lds_elems_(bmax, D); }
 
-template <int M>
+// GM: the matrices live in a per-workgroup slab of gws (slab elements each)
+// instead of LDS, for shapes whose working set exceeds the on-chip memory.
+template <int M, bool GM>
 __global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
             const uint8_t* __restrict__ samples, typename ModeT<M>::T* __restrict__ env,
             double* __restrict__ logs, typename ModeT<M>::T* __restrict__ rscr,
-            int* __restrict__ flags, int n, int jac_sweeps) {
+            int* __restrict__ flags, int n, int jac_sweeps, typename ModeT<M>::T* __restrict__ gws,
+            size_t slab) {
   typedef typename ModeT<M>::T T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int smp = blockIdx.x;
   const bool bottom = blockIdx.y == 1;
   if (smp >= n) return;
-  const EnvSmem<T> sh(reinterpret_cast<T*>(smem_raw), L);
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  T* big = GM ? gws + ((size_t)smp * 2 + blockIdx.y) * slab : lds;
+  T* small = GM ? lds : lds + env_big_elems(L.bmax, L.D);
+  const EnvSmem<T> sh(big, small, L);
   const int BD = L.bmax * L.D;
   __shared__ int sflag, fl;
   __shared__ int sel[256];
@@ -88,40 +94,72 @@ k_overlap(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __
     dc = bd;
   }
   if (tid == 0) {
-    const double v = (double)Lm[0];
     const double* lg = logs + (size_t)smp * L.n_slots;
     const double sc = lg[su] + lg[sb];
     int f = 0;
-    if (v == 0.0) f |= 1;
-    if (!isfinite(v)) f |= 2;
-    logpsi[2 * smp] = log(fabs(v)) + sc;
-    logpsi[2 * smp + 1] = v < 0 ? 3.14159265358979323846 : 0.0;
+    if constexpr (IsCplx<T>::value) {
+      const double vr = (double)Lm[0].re, vi = (double)Lm[0].im;
+      if (vr == 0.0 && vi == 0.0) f |= 1;
+      if (!isfinite(vr) || !isfinite(vi)) f |= 2;
+      logpsi[2 * smp] = log(hypot(vr, vi)) + sc;
+      logpsi[2 * smp + 1] = atan2(vi, vr);
+    } else {
+      const double v = (double)Lm[0];
+      if (v == 0.0) f |= 1;
+      if (!isfinite(v)) f |= 2;
+      logpsi[2 * smp] = log(fabs(v)) + sc;
+      logpsi[2 * smp + 1] = v < 0 ? 3.14159265358979323846 : 0.0;
+    }
     if (f && flags) atomicOr(flags + smp, f);
   }
 }
 
+// theta (FP64, or interleaved FP64 pairs for complex modes) to the compute type
 template <typename T>
 __global__ void k_convert_theta(const double* __restrict__ src, T* __restrict__ dst, int n,
                                 int* __restrict__ bad) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double v = src[i];
-    if (!isfinite(v)) atomicOr(bad, 1);
-    dst[i] = (T)v;
+    if constexpr (IsCplx<T>::value) {
+      typedef typename RealOf<T>::type R;
+      const double a = src[2 * i], b = src[2 * i + 1];
+      if (!isfinite(a) || !isfinite(b)) atomicOr(bad, 1);
+      dst[i] = T((R)a, (R)b);
+    } else {
+      const double v = src[i];
+      if (!isfinite(v)) atomicOr(bad, 1);
+      dst[i] = (T)v;
+    }
   }
 }
 
 // ---- host launchers ----
+size_t env_lds_bytes(int mode, const Lattice& L, bool gm) {
+  const size_t es = mode_elem_bytes(mode);
+  return (gm ? env_small_elems(L.bmax, L.D) : env_lds_elems_(L.bmax, L.D)) * es;
+}
+size_t env_slab_elems(const Lattice& L) { return (env_big_elems(L.bmax, L.D) + 15) / 16 * 16; }
+
 template <int M>
 hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
                             const uint8_t* samples, void* env, double* logs, void* rscr,
-                            int* flags, int n, int jac_sweeps, hipStream_t st) {
+                            int* flags, int n, int jac_sweeps, void* gws, hipStream_t st) {
   typedef typename ModeT<M>::T T;
-  const size_t lds = env_lds_elems(L.bmax, L.D) * sizeof(T);
-  hipFuncSetAttribute((const void*)k_env_sweep<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
   dim3 grid(n, 2);
-  hipLaunchKernelGGL(k_env_sweep<M>, grid, dim3(env_threads(M)), lds, st, L, tab, (const T*)theta,
-                     samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps);
+  if (gws) {
+    const size_t lds = env_lds_bytes(M, L, true);
+    hipFuncSetAttribute((const void*)k_env_sweep<M, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_env_sweep<M, true>), grid, dim3(env_threads(M)), lds, st, L, tab,
+                       (const T*)theta, samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps,
+                       (T*)gws, env_slab_elems(L));
+  } else {
+    const size_t lds = env_lds_bytes(M, L, false);
+    hipFuncSetAttribute((const void*)k_env_sweep<M, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_env_sweep<M, false>), grid, dim3(env_threads(M)), lds, st, L, tab,
+                       (const T*)theta, samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps,
+                       (T*)nullptr, (size_t)0);
+  }
   return hipGetLastError();
 }
 
@@ -130,6 +168,8 @@ hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, con
                           int icut, double* logpsi, int* flags, int n, hipStream_t st) {
   typedef typename ModeT<M>::T T;
   const size_t lds = (size_t)(L.bmax * L.bmax + L.bmax * L.D * L.bmax) * sizeof(T);
+  hipFuncSetAttribute((const void*)k_overlap<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
   hipLaunchKernelGGL(k_overlap<M>, dim3(n), dim3(256), lds, st, L, tab, (const T*)env,
                      logs, icut, logpsi, flags, n);
   return hipGetLastError();
@@ -138,29 +178,31 @@ hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, con
 hipError_t launch_convert_theta(int mode, const double* src, void* dst, int n, int* bad,
                                 hipStream_t st) {
   const int blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+  const dim3 g(blocks > 0 ? blocks : 1);
   if (mode == MODE_F64)
-    hipLaunchKernelGGL(k_convert_theta<double>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st,
-                       src, (double*)dst, n, bad);
+    hipLaunchKernelGGL(k_convert_theta<double>, g, dim3(256), 0, st, src, (double*)dst, n, bad);
+  else if (mode == MODE_C128)
+    hipLaunchKernelGGL(k_convert_theta<cplx<double>>, g, dim3(256), 0, st, src,
+                       (cplx<double>*)dst, n, bad);
+  else if (mode == MODE_C64)
+    hipLaunchKernelGGL(k_convert_theta<cplx<float>>, g, dim3(256), 0, st, src,
+                       (cplx<float>*)dst, n, bad);
   else
-    hipLaunchKernelGGL(k_convert_theta<float>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st,
-                       src, (float*)dst, n, bad);
+    hipLaunchKernelGGL(k_convert_theta<float>, g, dim3(256), 0, st, src, (float*)dst, n, bad);
   return hipGetLastError();
 }
 
-template hipError_t launch_env_sweep<MODE_F64>(const Lattice&, const int*, const void*,
-                                               const uint8_t*, void*, double*, void*, int*, int,
-                                               int, hipStream_t);
-template hipError_t launch_env_sweep<MODE_F32>(const Lattice&, const int*, const void*,
-                                               const uint8_t*, void*, double*, void*, int*, int,
-                                               int, hipStream_t);
-template hipError_t launch_env_sweep<MODE_BF16>(const Lattice&, const int*, const void*,
-                                                const uint8_t*, void*, double*, void*, int*, int,
-                                                int, hipStream_t);
-template hipError_t launch_overlap<MODE_F64>(const Lattice&, const int*, const void*,
-                                             const double*, int, double*, int*, int, hipStream_t);
-template hipError_t launch_overlap<MODE_F32>(const Lattice&, const int*, const void*,
-                                             const double*, int, double*, int*, int, hipStream_t);
-template hipError_t launch_overlap<MODE_BF16>(const Lattice&, const int*, const void*,
-                                              const double*, int, double*, int*, int, hipStream_t);
+#define INST(M)                                                                                 \
+  template hipError_t launch_env_sweep<M>(const Lattice&, const int*, const void*,             \
+                                          const uint8_t*, void*, double*, void*, int*, int, int, \
+                                          void*, hipStream_t);                                  \
+  template hipError_t launch_overlap<M>(const Lattice&, const int*, const void*, const double*, \
+                                        int, double*, int*, int, hipStream_t);
+INST(MODE_F64)
+INST(MODE_F32)
+INST(MODE_BF16)
+INST(MODE_C128)
+INST(MODE_C64)
+#undef INST
 
 }  // namespace pm

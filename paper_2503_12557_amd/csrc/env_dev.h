@@ -43,49 +43,56 @@ __device__ void load_lds(T* dst, const T* src, int cnt) {
   for (int i = threadIdx.x; i < cnt; i += PEPS_NT) dst[i] = src[i];
 }
 
-// Divide the LDS tensor by its largest modulus; returns ln(divisor).
+// Divide the tensor by its largest modulus; returns ln(divisor).
 template <typename T>
 __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
-  T mx = 0;
+  typedef typename RealOf<T>::type R;
+  R mx = 0;
   for (int i = threadIdx.x; i < cnt; i += PEPS_NT) {
-    const T a = fabs(t[i]);
+    const R a = absx(t[i]);
     mx = a > mx ? a : mx;
   }
-  mx = block_max(mx, red);
-  if (!(mx > T(0)) || !isfinite((double)mx)) {
-    if (threadIdx.x == 0) *flag |= (mx == T(0)) ? 1 : 2;
+  mx = block_max(mx, reinterpret_cast<R*>(red));
+  if (!(mx > R(0)) || !isfinite((double)mx)) {
+    if (threadIdx.x == 0) *flag |= (mx == R(0)) ? 1 : 2;
     __syncthreads();
     return 0.0;
   }
-  const T inv = T(1) / mx;
+  const R inv = R(1) / mx;
   for (int i = threadIdx.x; i < cnt; i += PEPS_NT) t[i] *= inv;
   __syncthreads();
   return log((double)mx);
 }
 
-inline size_t env_lds_elems_(int bmax, int D) {
+// Working set of one environment workgroup, in elements: the matrices
+// ("big": in LDS, or in a global slab when they do not fit on chip) and
+// the vectors and reduction scratch ("small": always in LDS).
+__host__ __device__ inline size_t env_big_elems(int bmax, int D) {
   const size_t BD = (size_t)bmax * D;
-  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + 3 * BD * BD + 8 * BD + 2 * BD * bmax +
-         4 * BD + 16;
+  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + BD * BD + 2 * BD * (BD + 4) +
+         2 * BD * bmax;
+}
+__host__ __device__ inline size_t env_small_elems(int bmax, int D) { return 4 * (size_t)bmax * D + 16; }
+__host__ __device__ inline size_t env_lds_elems_(int bmax, int D) {
+  return env_big_elems(bmax, D) + env_small_elems(bmax, D);
 }
 
-
-// LDS carve-up of one workgroup for the environment code.
+// Carve-up of the working set.
 template <typename T>
 struct EnvSmem {
   T *Ebuf, *Abuf, *P, *S, *Z, *W, *Bn, *vv, *ww, *sig, *red;
-  __device__ EnvSmem(T* sm, const Lattice& L) {
+  __device__ EnvSmem(T* big, T* small, const Lattice& L) {
     const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
-    Ebuf = sm;
+    Ebuf = big;
     Abuf = Ebuf + B * D * B;
     P = Abuf + D * D * D * D;   // P_k (left) / T1 (right)
-    // stacked QR buffer (left) / C then Z (right); rows padded by one
-    // element so rows of the LDS matrices fall on different banks
+    // stacked QR buffer (left) / C then Z (right); rows padded so rows of
+    // the LDS matrices fall on different banks
     S = P + BD * BD;
     Z = S + BD * (BD + 4);
     W = S + 2 * BD * (BD + 4);
     Bn = W + BD * B;
-    vv = Bn + B * BD;
+    vv = small;
     ww = vv + 2 * BD;
     sig = ww + BD;
     red = sig + BD;
@@ -137,16 +144,20 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
                                const EnvSmem<typename ModeT<M>::T>& sh, int* sel, int* sflag,
                                int* flp, int jac_sweeps) {
   typedef typename ModeT<M>::T T;
+  typedef typename RealOf<T>::type Rl;
   const int tid = threadIdx.x;
   const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
   T *Ebuf = sh.Ebuf, *Abuf = sh.Abuf, *P = sh.P, *S = sh.S, *Z = sh.Z, *W = sh.W, *Bn = sh.Bn;
-  T *vv = sh.vv, *ww = sh.ww, *sig = sh.sig, *red = sh.red;
+  T* red = sh.red;
+  Rl* vv = reinterpret_cast<Rl*>(sh.vv);    // row norms of the Jacobi
+  Rl* sig = reinterpret_cast<Rl*>(sh.sig);  // singular values
+  Rl* rred = reinterpret_cast<Rl*>(sh.red);
   int& fl = *flp;
   (void)B;
   (void)D;
   const size_t slot_elems = (size_t)L.Ly * L.site_box;
   const int* edims = tab + L.off_env;
-  const T tol = Eps<T>::v * T(4);
+  const Rl tol = Eps<Rl>::v * Rl(4);
     const int x = bottom ? L.Lx - 1 - t : t;
     const int sp = bottom ? slot_bottom(L, x + 1) : slot_top(L, x - 1);
     const int sn = bottom ? slot_bottom(L, x) : slot_top(L, x);
@@ -189,7 +200,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         }
         __syncthreads();
         const int m = kr + kprev;
-        house_qr_stacked(S, kr, m, Pr, Pr + 1, red);
+        house_qr_stacked(S, kr, m, Pr, Pr + 1, rred);
         kr = m < Pr ? m : Pr;
       }
       // store R_y (kr x Pr, row stride Pr)
@@ -258,15 +269,15 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         __syncthreads();
         int m = kp;
         if (m > zc) {
-          house_qr_stacked(S, 0, m, zc, ldc, red);
+          house_qr_stacked(S, 0, m, zc, ldc, rred);
           m = zc;
         }
         const int used = jacobi_rows(S, m, zc, ldc, tol, jac_sweeps, sflag, vv);
         if (used < 0 && tid == 0) fl |= 4;
         // row norms
         for (int i = tid; i < m; i += PEPS_NT) {
-          T q = 0;
-          for (int e = 0; e < zc; ++e) q += S[i * ldc + e] * S[i * ldc + e];
+          Rl q = 0;
+          for (int e = 0; e < zc; ++e) q += abs2x(S[i * ldc + e]);
           sig[i] = sqrt(q);
         }
         __syncthreads();
@@ -274,36 +285,36 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         // rank rows by descending norm (ties by index)
         for (int i = tid; i < m; i += PEPS_NT) {
           int rk = 0;
-          const T si = sig[i];
+          const Rl si = sig[i];
           for (int j = 0; j < m; ++j) {
-            const T sj = sig[j];
+            const Rl sj = sig[j];
             rk += (sj > si) || (sj == si && j < i);
           }
           if (rk < rnew) sel[rk] = i;
         }
         __syncthreads();
-        T smax = 0;
+        Rl smax = 0;
         for (int i = 0; i < m; ++i) smax = sig[i] > smax ? sig[i] : smax;
         if (tid == 0 && rnew < m) {
-          const T sa = sig[sel[rnew - 1]];
+          const Rl sa = sig[sel[rnew - 1]];
           // the largest discarded value
-          T sb = 0;
+          Rl sb = 0;
           for (int i = 0; i < m; ++i) {
             bool kept = false;
             for (int j = 0; j < rnew; ++j) kept |= (sel[j] == i);
             if (!kept && sig[i] > sb) sb = sig[i];
           }
-          if (sa > T(0) && (sa - sb) < T(1e-8) * sa) fl |= 8;
+          if (sa > Rl(0) && (sa - sb) < Rl(1e-8) * sa) fl |= 8;
         }
-        const T thresh = smax * Eps<T>::v * T(4);
+        const Rl thresh = smax * Eps<Rl>::v * Rl(4);
         for (int i = tid; i < rnew * zc; i += PEPS_NT) {
           const int j = i / zc, e = i - j * zc;
-          const T sj = sig[sel[j]];
+          const Rl sj = sig[sel[j]];
           Bn[i] = (sj > thresh) ? S[sel[j] * ldc + e] / sj : T(0);
         }
         __syncthreads();
-        // W_y[(a,l), j] = sum_e Z[(a,l), e] Bn[j, e]
-        gemm<M>(Pl, rnew, zc, Z, zc, 1, Bn, 1, zc, W, rnew, 1, false);
+        // W_y[(a,l), j] = sum_e Z[(a,l), e] conj(Bn[j, e])
+        gemm<M, IsCplx<T>::value>(Pl, rnew, zc, Z, zc, 1, Bn, 1, zc, W, rnew, 1, false);
         newt = Bn;
       } else {
         rnew = 1;

@@ -30,14 +30,27 @@ struct HamDev {
   const double* onsite;  // [N][2] or null
 };
 
+// Per-workgroup working sets. Each kernel keeps its matrices in LDS when
+// they fit ("_lds_bytes" with gm = false); otherwise the host passes a
+// global working-set buffer gws of one slab ("_slab_elems" elements of the
+// compute type) per workgroup of the grid, and only the small vectors stay
+// in LDS (gm = true).
 size_t env_lds_elems(int bmax, int D);
 size_t strip1_lds_elems(int bmax, int D);
 size_t strip2_lds_elems(int bmax, int D);
+size_t env_lds_bytes(int mode, const Lattice& L, bool gm);
+size_t strip1_lds_bytes(int mode, const Lattice& L, bool gm);
+size_t strip2_lds_bytes(int mode, const Lattice& L, bool gm);
+size_t sample_lds_bytes(int mode, const Lattice& L, bool gm);
+size_t env_slab_elems(const Lattice& L);
+size_t strip1_slab_elems(const Lattice& L);
+size_t strip2_slab_elems(const Lattice& L);
+size_t sample_slab_elems(const Lattice& L);
 
 template <int M>
 hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
                             const uint8_t* samples, void* env, double* logs, void* rscr,
-                            int* flags, int n, int jac_sweeps, hipStream_t st);
+                            int* flags, int n, int jac_sweeps, void* gws, hipStream_t st);
 template <int M>
 hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, const double* logs,
                           int icut, double* logpsi, int* flags, int n, hipStream_t st);
@@ -48,11 +61,11 @@ template <int M>
 hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
                          const uint8_t* samples, const void* env, const HamDev& H, void* rt,
                          double* epart, void* O, int* flags, int n, bool want_e, bool want_o,
-                         hipStream_t st);
+                         void* gws, hipStream_t st);
 template <int M>
 hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
                          const uint8_t* samples, const void* env, const HamDev& H, void* rt,
-                         double* epart, int* flags, int n, hipStream_t st);
+                         double* epart, int* flags, int n, void* gws, hipStream_t st);
 hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8_t* samples,
                                   const double* epart, int nparts, double* eloc, int n,
                                   hipStream_t st);
@@ -64,7 +77,7 @@ hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta
                              int n_chains, int per_chain, int burn_in, int thin, uint64_t seed,
                              uint64_t offset, uint8_t* samples, int* accepted, void* envscr,
                              double* logscr, void* rscr, void* rt1, void* rt2, int jac_sweeps,
-                             hipStream_t st);
+                             void* gws, hipStream_t st);
 
 // learned proposal
 hipError_t launch_made_forward(int N, int H, int n_up, int bf16, const float* P,
@@ -89,9 +102,12 @@ hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
                       hipStream_t st);
 
 // minSR
+// mode: MODE_F64 / MODE_F32 (FP64 solve of real parameters) or MODE_C128 /
+// MODE_C64 (complex FP64 solve); workspaces sized by minsr_ws_bytes.
+void minsr_ws_bytes(const Lattice& L, int mode, int n, size_t* mean, size_t* T, size_t* vec);
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,
-                        double rcond, double* dtheta, double* diag, double* ws_mean,
-                        double* ws_T, double* ws_vec, hipStream_t st);
+                        double rcond, double* dtheta, double* diag, void* ws_mean, void* ws_T,
+                        void* ws_vec, hipStream_t st);
 
 }  // namespace pm

@@ -23,17 +23,33 @@ namespace pm {
 #define TAG_MOVE 0x4D4F5645u
 #define TAG_INIT 0x494E4954u
 
-template <int M>
+// Working set of a chain: the matrices of whichever phase runs ("big": in
+// LDS, or in a global slab for large shapes) and the vectors and reduction
+// scratch ("small": LDS).
+__host__ __device__ static size_t sample_big(int bmax, int D) {
+  const size_t BD = (size_t)bmax * D;
+  const size_t box = (size_t)bmax * D * bmax;
+  const size_t box2 = (size_t)bmax * bmax * D * D;
+  const size_t bd3 = (size_t)bmax * D * D * D;
+  const size_t one_row = 3 * box + 2 * BD * BD;
+  const size_t two_row = 2 * box2 + 3 * bd3;
+  size_t m = env_big_elems(bmax, D);
+  m = one_row > m ? one_row : m;
+  return two_row > m ? two_row : m;
+}
+
+template <int M, bool GM>
 __global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
              int kind, int n_chains, int per_chain, int burn_in, int thin, uint32_t k0, uint32_t k1,
              uint64_t offset, uint8_t* __restrict__ samples, int* __restrict__ accepted,
              typename ModeT<M>::T* __restrict__ envscr, double* __restrict__ logscr,
              typename ModeT<M>::T* __restrict__ rscr, typename ModeT<M>::T* __restrict__ rt1,
-             typename ModeT<M>::T* __restrict__ rt2, int jac_sweeps) {
+             typename ModeT<M>::T* __restrict__ rt2, int jac_sweeps,
+             typename ModeT<M>::T* __restrict__ gws, size_t slab) {
   typedef typename ModeT<M>::T T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
+  T* lds = reinterpret_cast<T*>(smem_raw);
   const int chain = blockIdx.x;
   if (chain >= n_chains) return;
   const int tid = threadIdx.x;
@@ -42,22 +58,24 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   const int box = B * D * B;
   const int box2 = B * B * D * D;
   const int bd3 = B * D * D * D;
-  const EnvSmem<T> sh(sm, L);
+  T* sm = GM ? gws + (size_t)chain * slab : lds;
+  T* small = GM ? lds : lds + sample_big(B, D);
+  const EnvSmem<T> sh(sm, small, L);
   // strip buffers alias the environment buffers (used in different phases)
-  // one-row pass: Lf | Lt | Lt2 (box each) | X1 | X2 (BD^2 each) | red
+  // one-row pass: Lf | Lt | Lt2 (box each) | X1 | X2 (BD^2 each)
   T* Lf = sm;
   T* Lt = Lf + box;
   T* Lt2 = Lt + box;
   T* X1 = Lt2 + box;
   T* X2 = X1 + BD * BD;
-  T* red = X2 + BD * BD;
-  // two-row pass: Lf2 | Lu (box2 each) | Y1 | Y2 | Y3 (B D^3 each) | red2
+  T* red = small;
+  // two-row pass: Lf2 | Lu (box2 each) | Y1 | Y2 | Y3 (B D^3 each)
   T* Lf2 = sm;
   T* Lu = Lf2 + box2;
   T* Y1 = Lu + box2;
   T* Y2 = Y1 + bd3;
   T* Y3 = Y2 + bd3;
-  T* red2 = Y3 + bd3;
+  T* red2 = small;
   __shared__ uint8_t s[1024];
   __shared__ int sflag, fl, acc;
   __shared__ int sel[256];
@@ -102,7 +120,8 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   auto tens = [&](int n, int p) -> const T* {
     return theta + tab[L.off_param + n] + p * tab[L.off_block + n];
   };
-  auto decide = [&](int move, uint32_t sweep, double ratio) -> bool {
+  // accept iff u < |R|^2
+  auto decide = [&](int move, uint32_t sweep, double r2) -> bool {
     u4 c;
     c.x = (uint32_t)move;
     c.y = sweep;
@@ -110,7 +129,15 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
     c.w = TAG_MOVE;
     const u4 o = philox(c, k0, k1);
     const double u = philox_uniform(o.x, o.y);
-    return u < ratio * ratio;
+    return u < r2;
+  };
+  auto ratio2 = [&](const T& num, const T& den) -> double {
+    if constexpr (IsCplx<T>::value) {
+      return (double)abs2x(num) / (double)abs2x(den);
+    } else {
+      const double ratio = (double)num / (double)den;
+      return ratio * ratio;
+    }
   };
 
   const int total = burn_in + per_chain * thin;
@@ -172,8 +199,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
             const int cnt = ub_(ye) * tab[L.off_legs + 4 * (x * Ly + ye) + 1] * bb_(ye);
             val[which] = lds_dot(cur, (const T*)(Rt + (size_t)(ye + 1) * box), cnt, red);
           }
-          const double ratio = (double)val[1] / (double)val[0];
-          if (decide(move, sweep_ctr, ratio)) {
+          if (decide(move, sweep_ctr, ratio2(val[1], val[0]))) {
             if (tid == 0) {
               if (kind == 0) {
                 const uint8_t a = s[n1];
@@ -230,8 +256,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
               const int cnt = ub_(y) * Dr1 * Dr2 * bb2(y);
               val[which] = lds_dot(Lu, (const T*)(Rt2 + (size_t)(y + 1) * box2), cnt, red2);
             }
-            const double ratio = (double)val[1] / (double)val[0];
-            if (decide(x * (2 * Ly - 1) + Ly - 1 + y, sweep_ctr, ratio)) {
+            if (decide(x * (2 * Ly - 1) + Ly - 1 + y, sweep_ctr, ratio2(val[1], val[0]))) {
               if (tid == 0) {
                 const uint8_t a = s[n1];
                 s[n1] = s[n2];
@@ -265,42 +290,48 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   if (tid == 0 && accepted) accepted[chain] = acc;
 }
 
-size_t sample_lds_elems(int bmax, int D) {
-  const size_t BD = (size_t)bmax * D;
-  const size_t box = (size_t)bmax * D * bmax;
-  const size_t box2 = (size_t)bmax * bmax * D * D;
-  const size_t bd3 = (size_t)bmax * D * D * D;
-  const size_t one_row = 3 * box + 2 * BD * BD + 16;
-  const size_t two_row = 2 * box2 + 3 * bd3 + 16;
-  size_t m = env_lds_elems(bmax, D);
-  m = one_row > m ? one_row : m;
-  return two_row > m ? two_row : m;
+size_t sample_lds_elems(int bmax, int D) { return sample_big(bmax, D) + env_small_elems(bmax, D); }
+size_t sample_lds_bytes(int mode, const Lattice& L, bool gm) {
+  return (gm ? env_small_elems(L.bmax, L.D) : sample_lds_elems(L.bmax, L.D)) *
+         mode_elem_bytes(mode);
 }
+size_t sample_slab_elems(const Lattice& L) { return (sample_big(L.bmax, L.D) + 15) / 16 * 16; }
 
 template <int M>
 hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta, int kind,
                              int n_chains, int per_chain, int burn_in, int thin, uint64_t seed,
                              uint64_t offset, uint8_t* samples, int* accepted, void* envscr,
                              double* logscr, void* rscr, void* rt1, void* rt2, int jac_sweeps,
-                             hipStream_t st) {
+                             void* gws, hipStream_t st) {
   typedef typename ModeT<M>::T T;
-  const size_t lds = sample_lds_elems(L.bmax, L.D) * sizeof(T);
-  hipFuncSetAttribute((const void*)k_metropolis<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  hipLaunchKernelGGL(k_metropolis<M>, dim3(n_chains), dim3(env_threads(M)), lds, st, L, tab,
-                     (const T*)theta, kind, n_chains, per_chain, burn_in, thin,
-                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), offset, samples,
-                     accepted, (T*)envscr, logscr, (T*)rscr, (T*)rt1, (T*)rt2, jac_sweeps);
+  const bool gm = gws != nullptr;
+  const size_t lds = sample_lds_bytes(M, L, gm);
+  const void* fn = gm ? (const void*)k_metropolis<M, true> : (const void*)k_metropolis<M, false>;
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  if (gm)
+    hipLaunchKernelGGL((k_metropolis<M, true>), dim3(n_chains), dim3(env_threads(M)), lds, st, L,
+                       tab, (const T*)theta, kind, n_chains, per_chain, burn_in, thin, k0, k1,
+                       offset, samples, accepted, (T*)envscr, logscr, (T*)rscr, (T*)rt1, (T*)rt2,
+                       jac_sweeps, (T*)gws, sample_slab_elems(L));
+  else
+    hipLaunchKernelGGL((k_metropolis<M, false>), dim3(n_chains), dim3(env_threads(M)), lds, st, L,
+                       tab, (const T*)theta, kind, n_chains, per_chain, burn_in, thin, k0, k1,
+                       offset, samples, accepted, (T*)envscr, logscr, (T*)rscr, (T*)rt1, (T*)rt2,
+                       jac_sweeps, (T*)nullptr, (size_t)0);
   return hipGetLastError();
 }
 
 #define INST(M)                                                                                  \
   template hipError_t launch_metropolis<M>(const Lattice&, const int*, const void*, int, int,   \
                                            int, int, int, uint64_t, uint64_t, uint8_t*, int*,   \
-                                           void*, double*, void*, void*, void*, int, hipStream_t);
+                                           void*, double*, void*, void*, void*, int, void*,     \
+                                           hipStream_t);
 INST(MODE_F64)
 INST(MODE_F32)
 INST(MODE_BF16)
+INST(MODE_C128)
+INST(MODE_C64)
 #undef INST
 
 }  // namespace pm

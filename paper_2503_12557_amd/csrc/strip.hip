@@ -16,32 +16,38 @@
 
 namespace pm {
 
-size_t strip1_lds_elems(int bmax, int D) {
+// working set of a one-row strip workgroup: partials and intermediates
+// ("big": LDS, or a global slab for large shapes) and the hole tensor plus
+// reduction scratch ("small": LDS)
+static size_t strip1_big(int bmax, int D) {
   const size_t BD = (size_t)bmax * D;
-  return 3 * (size_t)bmax * D * bmax + 2 * BD * BD + (size_t)D * D * D * D + 16;
+  return 3 * (size_t)bmax * D * bmax + 2 * BD * BD;
 }
+static size_t strip1_small(int D) { return (size_t)D * D * D * D + 16; }
+size_t strip1_lds_elems(int bmax, int D) { return strip1_big(bmax, D) + strip1_small(D); }
 
-template <int M>
+template <int M, bool GM>
 __global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
          typename ModeT<M>::T* __restrict__ Oout, int* __restrict__ flags, int n, int want_e,
-         int want_o) {
+         int want_o, typename ModeT<M>::T* __restrict__ gws, size_t slab) {
   typedef typename ModeT<M>::T T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
+  T* lds = reinterpret_cast<T*>(smem_raw);
   const int smp = blockIdx.x, x = blockIdx.y;
   if (smp >= n) return;
   const int tid = threadIdx.x;
   const int B = L.bmax, D = L.D, BD = B * D;
   const int box = B * D * B;
+  T* sm = GM ? gws + ((size_t)smp * gridDim.y + x) * slab : lds;
   T* Lf = sm;
   T* Lt = Lf + box;
   T* Lt2 = Lt + box;
   T* X1 = Lt2 + box;
   T* X2 = X1 + BD * BD;
-  T* Env = X2 + BD * BD;
+  T* Env = GM ? lds : X2 + BD * BD;
   T* red = Env + D * D * D * D;
   __shared__ T one[1];
   __shared__ int fl;
@@ -79,7 +85,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
                      dnT(y), ba_(y), bb_(y), X1, X2, Rt + (size_t)y * box);
   }
   const T psi_row = Rt[0];
-  if (tid == 0 && (psi_row == T(0) || !isfinite((double)psi_row))) fl |= (psi_row == T(0)) ? 1 : 2;
+  if (tid == 0 && (psi_row == T(0) || !finitex(psi_row))) fl |= (psi_row == T(0)) ? 1 : 2;
 
   // moves of this strip
   const int m0 = H.n_strips ? H.mstart[x] : 0;
@@ -89,11 +95,12 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   // numerators summed per window end y1; each is divided by the strip value
   // taken along the same left-partial path, <L_y1, R_y1+1>, so the two
   // carry the same rounding
-  __shared__ double nre[32], nim[32], zv[32];
+  __shared__ double nre[32], nim[32], zre[32], zim[32];
   if (tid < 32) {
     nre[tid] = 0.0;
     nim[tid] = 0.0;
-    zv[tid] = 1.0;
+    zre[tid] = 1.0;
+    zim[tid] = 0.0;
   }
   if (tid == 0) Lf[0] = T(1);
   __syncthreads();
@@ -130,7 +137,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
       __syncthreads();
       const T psi_loc = lds_dot(Env, A, nA, red);
       T* o = Oout + (size_t)smp * L.n_compact + tab[L.off_compact + ns];
-      const T inv = T(1) / psi_loc;
+      const T inv = recipx(psi_loc);
       for (int i = tid; i < nA; i += PEPS_NT) o[i] = Env[i] * inv;
     }
     if (want_e) {
@@ -156,8 +163,9 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           const int cnt = ub_(y1) * tab[L.off_legs + 4 * (x * L.Ly + y1) + 1] * bb_(y1);
           const T num = lds_dot(cur, (const T*)(Rt + (size_t)(y1 + 1) * box), cnt, red);
           if (tid == 0) {
-            nre[y1] += cre * (double)num;
-            nim[y1] += cim * (double)num;
+            const double nr = (double)realx(num), ni = (double)imagx(num);
+            nre[y1] += cre * nr - cim * ni;
+            nim[y1] += cre * ni + cim * nr;
           }
         }
         ++mi;
@@ -169,15 +177,20 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     __syncthreads();
     if (want_e) {
       const T z = lds_dot(Lf, (const T*)Rn, ub * Dr * bb, red);
-      if (tid == 0) zv[y] = (double)z;
+      if (tid == 0) {
+        zre[y] = (double)realx(z);
+        zim[y] = (double)imagx(z);
+      }
     }
   }
   if (tid == 0) {
     if (want_e) {
       for (int y = 0; y < L.Ly; ++y)
         if (nre[y] != 0.0 || nim[y] != 0.0) {
-          ere += nre[y] / zv[y];
-          eim += nim[y] / zv[y];
+          double qr, qi;
+          cdiv(nre[y], nim[y], zre[y], zim[y], qr, qi);
+          ere += qr;
+          eim += qi;
         }
       const int nparts = 1 + L.Lx + (L.Lx - 1);
       epart[((size_t)smp * nparts + 1 + x) * 2] = ere;
@@ -187,34 +200,36 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   }
 }
 
-size_t strip2_lds_elems(int bmax, int D) {
+static size_t strip2_big(int bmax, int D) {
   const size_t B2D2 = (size_t)bmax * bmax * D * D;
   const size_t BD3 = (size_t)bmax * D * D * D;
-  return 3 * B2D2 + 3 * BD3 + 16;
+  return 3 * B2D2 + 3 * BD3;
 }
+size_t strip2_lds_elems(int bmax, int D) { return strip2_big(bmax, D) + 16; }
 
-template <int M>
+template <int M, bool GM>
 __global__ void __launch_bounds__(PEPS_BLOCK_MAX)
 k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
-         int* __restrict__ flags, int n) {
+         int* __restrict__ flags, int n, typename ModeT<M>::T* __restrict__ gws, size_t slab) {
   typedef typename ModeT<M>::T T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
+  T* lds = reinterpret_cast<T*>(smem_raw);
   const int smp = blockIdx.x, x = blockIdx.y;
   if (smp >= n) return;
   const int tid = threadIdx.x;
   const int B = L.bmax, D = L.D;
   const int box2 = B * B * D * D;
   const int bd3 = B * D * D * D;
+  T* sm = GM ? gws + ((size_t)smp * gridDim.y + x) * slab : lds;
   T* Lf = sm;
   T* Lt = Lf + box2;
   T* Lt2 = Lt + box2;
   T* X1 = Lt2 + box2;
   T* X2 = X1 + bd3;
   T* X3 = X2 + bd3;
-  T* red = X3 + bd3;
+  T* red = GM ? lds : X3 + bd3;
   __shared__ T one[1];
   __shared__ int fl;
   if (tid == 0) {
@@ -262,15 +277,16 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
                      bb_(y), X1, X2, X3, Rt + (size_t)y * box2);
   }
   const T psi2 = Rt[0];
-  if (tid == 0 && (psi2 == T(0) || !isfinite((double)psi2))) fl |= (psi2 == T(0)) ? 1 : 2;
+  if (tid == 0 && (psi2 == T(0) || !finitex(psi2))) fl |= (psi2 == T(0)) ? 1 : 2;
 
   int mi = m0;
   double ere = 0.0, eim = 0.0;
-  __shared__ double nre[32], nim[32], zv[32];
+  __shared__ double nre[32], nim[32], zre[32], zim[32];
   if (tid < 32) {
     nre[tid] = 0.0;
     nim[tid] = 0.0;
-    zv[tid] = 1.0;
+    zre[tid] = 1.0;
+    zim[tid] = 0.0;
   }
   int yneed = -1;
   if (tid == 0) Lf[0] = T(1);
@@ -303,8 +319,9 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
                         tab[L.off_legs + 4 * (a1 + L.Ly) + 1] * bb_(y1);
         const T num = lds_dot(cur, (const T*)(Rt + (size_t)(y1 + 1) * box2), cnt, red);
         if (tid == 0) {
-          nre[y1] += cre * (double)num;
-          nim[y1] += cim * (double)num;
+          const double nr = (double)realx(num), ni = (double)imagx(num);
+          nre[y1] += cre * nr - cim * ni;
+          nim[y1] += cre * ni + cim * nr;
         }
         yneed = y1 > yneed ? y1 : yneed;
       }
@@ -321,13 +338,18 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     for (int i = tid; i < cnt; i += PEPS_NT) Lf[i] = Lt[i];
     __syncthreads();
     const T z = lds_dot(Lf, (const T*)(Rt + (size_t)(y + 1) * box2), cnt, red);
-    if (tid == 0) zv[y] = (double)z;
+    if (tid == 0) {
+      zre[y] = (double)realx(z);
+      zim[y] = (double)imagx(z);
+    }
   }
   if (tid == 0) {
     for (int y = 0; y < L.Ly; ++y)
       if (nre[y] != 0.0 || nim[y] != 0.0) {
-        ere += nre[y] / zv[y];
-        eim += nim[y] / zv[y];
+        double qr, qi;
+        cdiv(nre[y], nim[y], zre[y], zim[y], qr, qi);
+        ere += qr;
+        eim += qi;
       }
     epart[((size_t)smp * nparts + strip + 1) * 2] = ere;
     epart[((size_t)smp * nparts + strip + 1) * 2 + 1] = eim;
@@ -370,31 +392,53 @@ k_energy_diag_sum(Lattice L, HamDev H, const uint8_t* __restrict__ samples,
   }
 }
 
+size_t strip1_lds_bytes(int mode, const Lattice& L, bool gm) {
+  return (gm ? strip1_small(L.D) : strip1_lds_elems(L.bmax, L.D)) * mode_elem_bytes(mode);
+}
+size_t strip2_lds_bytes(int mode, const Lattice& L, bool gm) {
+  return (gm ? 16 : strip2_lds_elems(L.bmax, L.D)) * mode_elem_bytes(mode);
+}
+size_t strip1_slab_elems(const Lattice& L) { return (strip1_big(L.bmax, L.D) + 15) / 16 * 16; }
+size_t strip2_slab_elems(const Lattice& L) { return (strip2_big(L.bmax, L.D) + 15) / 16 * 16; }
+
 template <int M>
 hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
                          const uint8_t* samples, const void* env, const HamDev& H, void* rt,
                          double* epart, void* O, int* flags, int n, bool want_e, bool want_o,
-                         hipStream_t st) {
+                         void* gws, hipStream_t st) {
   typedef typename ModeT<M>::T T;
-  const size_t lds = strip1_lds_elems(L.bmax, L.D) * sizeof(T);
-  hipFuncSetAttribute((const void*)k_strip1<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  hipLaunchKernelGGL(k_strip1<M>, dim3(n, L.Lx), dim3(512), lds, st, L, tab,
-                     (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O, flags, n,
-                     want_e ? 1 : 0, want_o ? 1 : 0);
+  const bool gm = gws != nullptr;
+  const size_t lds = strip1_lds_bytes(M, L, gm);
+  const void* fn = gm ? (const void*)k_strip1<M, true> : (const void*)k_strip1<M, false>;
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (gm)
+    hipLaunchKernelGGL((k_strip1<M, true>), dim3(n, L.Lx), dim3(512), lds, st, L, tab,
+                       (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O, flags, n,
+                       want_e ? 1 : 0, want_o ? 1 : 0, (T*)gws, strip1_slab_elems(L));
+  else
+    hipLaunchKernelGGL((k_strip1<M, false>), dim3(n, L.Lx), dim3(512), lds, st, L, tab,
+                       (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O, flags, n,
+                       want_e ? 1 : 0, want_o ? 1 : 0, (T*)nullptr, (size_t)0);
   return hipGetLastError();
 }
 
 template <int M>
 hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
                          const uint8_t* samples, const void* env, const HamDev& H, void* rt,
-                         double* epart, int* flags, int n, hipStream_t st) {
+                         double* epart, int* flags, int n, void* gws, hipStream_t st) {
   typedef typename ModeT<M>::T T;
-  const size_t lds = strip2_lds_elems(L.bmax, L.D) * sizeof(T);
-  hipFuncSetAttribute((const void*)k_strip2<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  hipLaunchKernelGGL(k_strip2<M>, dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
-                     (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n);
+  const bool gm = gws != nullptr;
+  const size_t lds = strip2_lds_bytes(M, L, gm);
+  const void* fn = gm ? (const void*)k_strip2<M, true> : (const void*)k_strip2<M, false>;
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (gm)
+    hipLaunchKernelGGL((k_strip2<M, true>), dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
+                       (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n,
+                       (T*)gws, strip2_slab_elems(L));
+  else
+    hipLaunchKernelGGL((k_strip2<M, false>), dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
+                       (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n,
+                       (T*)nullptr, (size_t)0);
   return hipGetLastError();
 }
 
@@ -409,13 +453,15 @@ hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8
 #define INST(M)                                                                                 \
   template hipError_t launch_strip1<M>(const Lattice&, const int*, const void*, const uint8_t*, \
                                        const void*, const HamDev&, void*, double*, void*, int*, \
-                                       int, bool, bool, hipStream_t);                           \
+                                       int, bool, bool, void*, hipStream_t);                    \
   template hipError_t launch_strip2<M>(const Lattice&, const int*, const void*, const uint8_t*, \
                                        const void*, const HamDev&, void*, double*, int*, int,   \
-                                       hipStream_t);
+                                       void*, hipStream_t);
 INST(MODE_F64)
 INST(MODE_F32)
 INST(MODE_BF16)
+INST(MODE_C128)
+INST(MODE_C64)
 #undef INST
 
 }  // namespace pm

@@ -29,7 +29,8 @@ def test_create_rejects_bad_geometry():
     binding, lib = _lib()
     h = ctypes.c_void_p()
     for g, code in [((1, 4, 2, 2, 2, 0), 1), ((4, 4, 3, 2, 2, 0), 2), ((4, 4, 2, 0, 2, 0), 1),
-                    ((4, 4, 2, 2, 2, 9), 1), ((4, 4, 2, 8, 64, 0), 2), ((40, 4, 2, 2, 2, 0), 1)]:
+                    ((4, 4, 2, 2, 2, 9), 1), ((4, 4, 2, 8, 64, 0), 2), ((40, 4, 2, 2, 2, 0), 1),
+                    ((4, 4, 2, 6, 48, 4), 2), ((4, 4, 2, 2, 2, -1), 1)]:
         geom = binding.Geom(*g)
         st = lib.peps_create(ctypes.byref(geom), ctypes.byref(h))
         assert st == code, (g, st, lib.peps_last_error())
