@@ -267,6 +267,36 @@ __device__ T block_max(T v, T* red) {
   return s;
 }
 
+// Largest modulus of t[0..cnt) (row stride ld for rows of width w) over the block.
+template <typename T>
+__device__ typename RealOf<T>::type block_absmax(const T* t, int rows, int w, int ld, T* red) {
+  typedef typename RealOf<T>::type R;
+  R mx = 0;
+  for (int i = threadIdx.x; i < rows * w; i += PEPS_NT) {
+    const int r = i / w, c = i - r * w;
+    const R a = absx(t[r * ld + c]);
+    mx = a > mx ? a : mx;
+  }
+  return block_max(mx, reinterpret_cast<R*>(red));
+}
+
+// Exponent e with mx * 2^-e in [0.5, 1); 0 when mx is zero or not finite.
+__device__ __forceinline__ int pow2_exponent(double mx) {
+  if (!(mx > 0.0) || !isfinite(mx)) return 0;
+  int e;
+  frexp(mx, &e);
+  return e;
+}
+
+// t *= 2^-e (exact: a power of two changes no mantissa).
+template <typename T>
+__device__ void scale_pow2(T* t, int cnt, int e) {
+  typedef typename RealOf<T>::type R;
+  if (e == 0) return;
+  const R f = (R)ldexp(1.0, -e);
+  for (int i = threadIdx.x; i < cnt; i += PEPS_NT) t[i] *= f;
+}
+
 // Sum over groups of G consecutive lanes (G a power of two, G <= 64).
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {

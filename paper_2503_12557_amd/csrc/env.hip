@@ -78,6 +78,7 @@ k_overlap(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __
   if (tid == 0) Lm[0] = T(1);
   __syncthreads();
   int da = 1, dc = 1;
+  int esum = 0;  // powers of two taken out of the transfer matrix
   for (int y = 0; y < L.Ly; ++y) {
     const T* U = envs + (size_t)su * slot_elems + (size_t)y * L.site_box;
     const T* Bt = envs + (size_t)sb * slot_elems + (size_t)y * L.site_box;
@@ -90,12 +91,19 @@ k_overlap(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __
     // L'[b,d] = sum_{c,k} X[(c,k), b] B[(c,k), d]
     gemm<M>(ub, bd, bc * uk, X, 1, ub, Bt, bd, 1, Lm, bd, 1, false);
     __syncthreads();
+    if (y + 1 < L.Ly) {
+      // unit scale between columns (the FP32 range is exceeded otherwise)
+      const int e = pow2_exponent((double)block_absmax(Lm, ub, bd, bd, X));
+      scale_pow2(Lm, ub * bd, e);
+      esum += e;
+      __syncthreads();
+    }
     da = ub;
     dc = bd;
   }
   if (tid == 0) {
     const double* lg = logs + (size_t)smp * L.n_slots;
-    const double sc = lg[su] + lg[sb];
+    const double sc = lg[su] + lg[sb] + esum * 0.69314718055994530942;
     int f = 0;
     if constexpr (IsCplx<T>::value) {
       const double vr = (double)Lm[0].re, vi = (double)Lm[0].im;

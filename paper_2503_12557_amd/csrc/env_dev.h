@@ -203,9 +203,14 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         house_qr_stacked(S, kr, m, Pr, Pr + 1, rred);
         kr = m < Pr ? m : Pr;
       }
-      // store R_y (kr x Pr, row stride Pr)
+      // store R_y (kr x Pr, row stride Pr) at unit scale: only its row space
+      // and the ratios of its singular values matter downstream, and
+      // without rescaling its norm grows by |P| per column (beyond the FP32
+      // range on wide lattices)
+      const int er = pow2_exponent((double)block_absmax(S, kr, Pr, Pr + 1, red));
+      const Rl fr = (Rl)ldexp(1.0, -er);
       T* Ry = R + (size_t)y * BD * BD;
-      for (int i = tid; i < kr * Pr; i += PEPS_NT) Ry[i] = S[(i / Pr) * (Pr + 1) + i % Pr];
+      for (int i = tid; i < kr * Pr; i += PEPS_NT) Ry[i] = S[(i / Pr) * (Pr + 1) + i % Pr] * fr;
       __syncthreads();
       kprev = kr;
     }
@@ -315,6 +320,12 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         __syncthreads();
         // W_y[(a,l), j] = sum_e Z[(a,l), e] conj(Bn[j, e])
         gemm<M, IsCplx<T>::value>(Pl, rnew, zc, Z, zc, 1, Bn, 1, zc, W, rnew, 1, false);
+        __syncthreads();
+        // W carries the weight of the sites to its right: keep it at unit
+        // scale and move the power of two into the log scale
+        const int ew = pow2_exponent((double)block_absmax(W, Pl, rnew, rnew, red));
+        scale_pow2(W, Pl * rnew, ew);
+        logrow += ew * 0.69314718055994530942;
         newt = Bn;
       } else {
         rnew = 1;

@@ -81,6 +81,8 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   __shared__ int sel[256];
   __shared__ T one[1];
   __shared__ uint32_t keys[1024];
+  __shared__ int dex[32];  // powers of two of the strip's right partials
+  typedef typename RealOf<T>::type Rl;
 
   const size_t slot_elems = (size_t)Ly * L.site_box;
   T* envs = envscr + (size_t)chain * L.n_slots * slot_elems;
@@ -160,15 +162,22 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
       auto ba_ = [&](int y) { return has_dn ? ed[(sd * Ly + y) * 3 + 0] : 1; };
       auto bb_ = [&](int y) { return has_dn ? ed[(sd * Ly + y) * 3 + 2] : 1; };
 
-      // ---- one-row strip: right partials of the current row ----
+      // ---- one-row strip: right partials of the current row, each at unit
+      // scale (power of two in dex[y], taken out of the left steps too) ----
       if (tid == 0) Rt[(size_t)Ly * box] = T(1);
       __syncthreads();
       for (int y = Ly - 1; y >= 0; --y) {
         const int ns = x * Ly + y;
         int Dl, Dr, Du, Dd;
         legs_of(tab, L, ns, Dl, Dr, Du, Dd);
+        T* Ry = Rt + (size_t)y * box;
         s1_step_right<M>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), tens(ns, s[ns]), Dl,
-                         Dr, Du, Dd, dnT(y), ba_(y), bb_(y), X1, X2, Rt + (size_t)y * box);
+                         Dr, Du, Dd, dnT(y), ba_(y), bb_(y), X1, X2, Ry);
+        const int cnt = ua_(y) * Dl * ba_(y);
+        const int e = pow2_exponent((double)block_absmax(Ry, 1, cnt, cnt, red));
+        scale_pow2(Ry, cnt, e);
+        if (tid == 0) dex[y] = e;
+        __syncthreads();
       }
       if (tid == 0) Lf[0] = T(1);
       __syncthreads();
@@ -192,6 +201,8 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
               legs_of(tab, L, nn, dl, dr, du, dd);
               s1_step_left<M>(cur, upT(y + j), ua_(y + j), ub_(y + j), tens(nn, p), dl, dr, du,
                               dd, dnT(y + j), ba_(y + j), bb_(y + j), X1, X2, nxt);
+              scale_pow2(nxt, ub_(y + j) * dr * bb_(y + j), dex[y + j]);
+              __syncthreads();
               cur = nxt;
               nxt = (nxt == Lt) ? Lt2 : Lt;
             }
@@ -217,7 +228,10 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
         legs_of(tab, L, n1, Dl, Dr, Du, Dd);
         s1_step_left<M>(Lf, upT(y), ua_(y), ub_(y), tens(n1, s[n1]), Dl, Dr, Du, Dd, dnT(y),
                         ba_(y), bb_(y), X1, X2, Lt);
-        for (int i = tid; i < ub_(y) * Dr * bb_(y); i += PEPS_NT) Lf[i] = Lt[i];
+        {
+          const Rl f = (Rl)ldexp(1.0, -dex[y]);
+          for (int i = tid; i < ub_(y) * Dr * bb_(y); i += PEPS_NT) Lf[i] = Lt[i] * f;
+        }
         __syncthreads();
       }
 
@@ -235,9 +249,15 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
           int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
           legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
           legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
+          T* Ry = Rt2 + (size_t)y * box2;
           s2_step_right<M>(Rt2 + (size_t)(y + 1) * box2, upT(y), ua_(y), uk_(y), ub_(y),
                            tens(n1, s[n1]), Dl1, Dr1, Dd1, tens(n2, s[n2]), Dl2, Dr2, Dd2, dn2(y),
-                           ba2(y), bb2(y), Y1, Y2, Y3, Rt2 + (size_t)y * box2);
+                           ba2(y), bb2(y), Y1, Y2, Y3, Ry);
+          const int cnt = ua_(y) * Dl1 * Dl2 * ba2(y);
+          const int e = pow2_exponent((double)block_absmax(Ry, 1, cnt, cnt, red2));
+          scale_pow2(Ry, cnt, e);
+          if (tid == 0) dex[y] = e;
+          __syncthreads();
         }
         if (tid == 0) Lf2[0] = T(1);
         __syncthreads();
@@ -269,7 +289,10 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
           s2_step_left<M>(Lf2, upT(y), ua_(y), uk_(y), ub_(y), tens(n1, s[n1]), Dl1, Dr1, Dd1,
                           tens(n2, s[n2]), Dl2, Dr2, Dd2, dn2(y), ba2(y), bb2(y), Y1, Y2, Y3, Lu);
           const int cnt = ub_(y) * Dr1 * Dr2 * bb2(y);
-          for (int i = tid; i < cnt; i += PEPS_NT) Lf2[i] = Lu[i];
+          {
+            const Rl f = (Rl)ldexp(1.0, -dex[y]);
+            for (int i = tid; i < cnt; i += PEPS_NT) Lf2[i] = Lu[i] * f;
+          }
           __syncthreads();
         }
       }

@@ -72,7 +72,11 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   auto ba_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 0] : 1; };
   auto bb_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 2] : 1; };
 
-  // right partials Rt[y] (y = Ly .. 0), Rt[y] has dims (ua(y), Dl(y), ba(y))
+  // right partials Rt[y] (y = Ly .. 0), Rt[y] has dims (ua(y), Dl(y), ba(y)),
+  // each brought to unit scale by a power of two 2^dex[y]; the left steps
+  // take out the same powers column by column, so every ratio and hole
+  // tensor sees one common scale and nothing leaves the FP32 range
+  __shared__ int dex[32];
   T* RtL = Rt + (size_t)L.Ly * box;
   if (tid == 0) RtL[0] = T(1);
   __syncthreads();
@@ -81,8 +85,14 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     int Dl, Dr, Du, Dd;
     legs_of(tab, L, ns, Dl, Dr, Du, Dd);
     const T* A = tensor_of(theta, tab, L, ns, pbit(s[ns]));
+    T* Ry = Rt + (size_t)y * box;
     s1_step_right<M>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
-                     dnT(y), ba_(y), bb_(y), X1, X2, Rt + (size_t)y * box);
+                     dnT(y), ba_(y), bb_(y), X1, X2, Ry);
+    const int cnt = ua_(y) * Dl * ba_(y);
+    const int e = pow2_exponent((double)block_absmax(Ry, 1, cnt, cnt, red));
+    scale_pow2(Ry, cnt, e);
+    if (tid == 0) dex[y] = e;
+    __syncthreads();
   }
   const T psi_row = Rt[0];
   if (tid == 0 && (psi_row == T(0) || !finitex(psi_row))) fl |= (psi_row == T(0)) ? 1 : 2;
@@ -157,6 +167,8 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
             const int p = in_move(mv, n2) ? 1 - pbit(s[n2]) : pbit(s[n2]);
             s1_step_left<M>(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p), dl,
                             dr, du, dd, dnT(yy), ba_(yy), bb_(yy), X1, X2, nxt);
+            scale_pow2(nxt, ub_(yy) * dr * bb_(yy), dex[yy]);
+            __syncthreads();
             cur = nxt;
             nxt = (nxt == Lt) ? Lt2 : Lt;
           }
@@ -173,7 +185,11 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     }
     // Lf <- step(Lf, A_y)
     s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
-    for (int i = tid; i < ub * Dr * bb; i += PEPS_NT) Lf[i] = Lt[i];
+    {
+      typedef typename RealOf<T>::type R;
+      const R f = (R)ldexp(1.0, -dex[y]);
+      for (int i = tid; i < ub * Dr * bb; i += PEPS_NT) Lf[i] = Lt[i] * f;
+    }
     __syncthreads();
     if (want_e) {
       const T z = lds_dot(Lf, (const T*)Rn, ub * Dr * bb, red);
@@ -263,6 +279,8 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   auto ba_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 0] : 1; };
   auto bb_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 2] : 1; };
 
+  // right partials at unit scale, powers of two in dex[y] (as in k_strip1)
+  __shared__ int dex[32];
   T* RtL = Rt + (size_t)L.Ly * box2;
   if (tid == 0) RtL[0] = T(1);
   __syncthreads();
@@ -271,10 +289,16 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
     legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
+    T* Ry = Rt + (size_t)y * box2;
     s2_step_right<M>(Rt + (size_t)(y + 1) * box2, upT(y), ua_(y), uk_(y), ub_(y),
                      tensor_of(theta, tab, L, n1, pbit(s[n1])), Dl1, Dr1, Dd1,
                      tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2, dnT(y), ba_(y),
-                     bb_(y), X1, X2, X3, Rt + (size_t)y * box2);
+                     bb_(y), X1, X2, X3, Ry);
+    const int cnt = ua_(y) * Dl1 * Dl2 * ba_(y);
+    const int e = pow2_exponent((double)block_absmax(Ry, 1, cnt, cnt, red));
+    scale_pow2(Ry, cnt, e);
+    if (tid == 0) dex[y] = e;
+    __syncthreads();
   }
   const T psi2 = Rt[0];
   if (tid == 0 && (psi2 == T(0) || !finitex(psi2))) fl |= (psi2 == T(0)) ? 1 : 2;
@@ -311,6 +335,8 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           s2_step_left<M>(cur, upT(yy), ua_(yy), uk_(yy), ub_(yy), tensor_of(theta, tab, L, a1, p1),
                           Dl1, Dr1, Dd1, tensor_of(theta, tab, L, a2, p2), Dl2, Dr2, Dd2, dnT(yy),
                           ba_(yy), bb_(yy), X1, X2, X3, nxt);
+          scale_pow2(nxt, ub_(yy) * Dr1 * Dr2 * bb_(yy), dex[yy]);
+          __syncthreads();
           cur = nxt;
           nxt = (nxt == Lt) ? Lt2 : Lt;
         }
@@ -335,7 +361,11 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
                     Dl1, Dr1, Dd1, tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2,
                     dnT(y), ba_(y), bb_(y), X1, X2, X3, Lt);
     const int cnt = ub_(y) * Dr1 * Dr2 * bb_(y);
-    for (int i = tid; i < cnt; i += PEPS_NT) Lf[i] = Lt[i];
+    {
+      typedef typename RealOf<T>::type R;
+      const R f = (R)ldexp(1.0, -dex[y]);
+      for (int i = tid; i < cnt; i += PEPS_NT) Lf[i] = Lt[i] * f;
+    }
     __syncthreads();
     const T z = lds_dot(Lf, (const T*)(Rt + (size_t)(y + 1) * box2), cnt, red);
     if (tid == 0) {
