@@ -169,7 +169,7 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     N = Lx * Ly
     ctx = Context(Lx, Ly, D, chi, "f32")
     ctx.set_hamiltonian(ham)
-    chains, T = 256, 32
+    chains, T = 256, 64
     init, _ = ctx.sample(theta, "exchange", n_chains=chains, per_chain=1, burn_in=16, seed=21)
     _sync()
     t0 = time.perf_counter()
@@ -372,8 +372,10 @@ def main():
         res["learned_proposal"] = ess_comparison(Context, theta, Lx, Ly, D, chi, ham,
                                                  args.made_steps)
     if not args.no_cpu:
-        k = min(n, 64)
-        res["cpu_baseline"] = cpu_baseline(theta_np, Lx, Ly, D, chi, samples[:k].cpu().numpy())
+        # a bounded sample of the batch: up to 512 configurations or ~15 s
+        k = min(n, 512)
+        res["cpu_baseline"] = cpu_baseline(theta_np, Lx, Ly, D, chi, samples[:k].cpu().numpy(),
+                                           seconds=15.0)
     print(json.dumps(res))
 
 

@@ -136,9 +136,10 @@ def exact_imh_acceptance(p_psi, q):
 
 def integrated_autocorr(series, c=5.0):
     """tau_int with Sokal's automatic window (smallest W >= c * tau(W)), the
-    autocorrelation averaged over chains. series: [chains, T]."""
+    autocorrelation averaged over chains that start stationary, centred on
+    the mean over all chains. series: [chains, T]."""
     x = np.asarray(series, dtype=np.float64)
-    x = x - x.mean(axis=1, keepdims=True)
+    x = x - x.mean()
     C, T = x.shape
     var = (x * x).mean()
     if var == 0:

@@ -3,7 +3,10 @@
 tau_int of a scalar series observed on many chains, with Sokal's automatic
 window: the autocorrelation rho(t) is averaged over chains and the window W
 is the smallest with W >= c * tau(W), tau(W) = 1 + 2 sum_{t=1..W} rho(t).
-The effective sample size of chains x T observations is chains*T / tau_int.
+The chains start from stationary states, so the series is centred on the
+mean over all chains (centring each short chain on its own mean would bias
+rho(t) low). The effective sample size of chains x T observations is
+chains*T / tau_int.
 """
 from __future__ import annotations
 
@@ -12,7 +15,7 @@ import numpy as np
 
 def tau_int(series, c=5.0):
     x = np.asarray(series, dtype=np.float64)
-    x = x - x.mean(axis=1, keepdims=True)
+    x = x - x.mean()
     T = x.shape[1]
     var = float((x * x).mean())
     if var == 0.0 or T < 2:

@@ -117,3 +117,18 @@ def test_product_tau_int_matches_oracle_definition():
     for t in range(1, T):
         x[:, t] = a * x[:, t - 1] + e[:, t]
     assert abs(analysis.tau_int(x) - made.integrated_autocorr(x)) < 1e-8
+
+
+def test_tau_int_of_short_sticky_chains():
+    # an independence chain that keeps its value with probability p has
+    # rho(t) = p^t, tau_int = (1 + p) / (1 - p); short chains started from
+    # the stationary law (T = 64, as in the sampler comparison)
+    p, C, T = 0.67, 4096, 64
+    rng = np.random.default_rng(5)
+    x = np.empty((C, T))
+    x[:, 0] = rng.standard_normal(C)
+    for t in range(1, T):
+        keep = rng.random(C) < p
+        x[:, t] = np.where(keep, x[:, t - 1], rng.standard_normal(C))
+    tau = made.integrated_autocorr(x)
+    assert abs(tau - (1 + p) / (1 - p)) < 0.3
