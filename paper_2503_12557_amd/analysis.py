@@ -7,6 +7,14 @@ The chains start from stationary states, so the series is centred on the
 mean over all chains (centring each short chain on its own mean would bias
 rho(t) low). The effective sample size of chains x T observations is
 chains*T / tau_int.
+
+Local energies of unconverged states are heavy-tailed (a few near-zero
+amplitudes carry almost all of the variance), which makes the plain
+autocorrelation a statistic of a handful of outliers. tau_int_ranked
+applies the estimator to rank-normalised values (normal scores of the
+pooled ranks, Blom's offsets, as in the rank-normalised effective sample
+size of Vehtari et al., 2021), which is invariant under monotone maps of
+the observable.
 """
 from __future__ import annotations
 
@@ -35,3 +43,17 @@ def tau_int(series, c=5.0):
 def ess(series, c=5.0):
     x = np.asarray(series)
     return x.size / tau_int(x, c)
+
+
+def rank_normalise(series):
+    """Normal scores Phi^-1((r - 3/8) / (S + 1/4)) of the pooled ranks r
+    (ties share their average rank); S = number of values."""
+    from scipy.special import ndtri
+    from scipy.stats import rankdata
+    x = np.asarray(series, dtype=np.float64)
+    r = rankdata(x.ravel(), method="average").reshape(x.shape)
+    return ndtri((r - 0.375) / (x.size + 0.25))
+
+
+def tau_int_ranked(series, c=5.0):
+    return tau_int(rank_normalise(series), c)

@@ -132,3 +132,25 @@ def test_tau_int_of_short_sticky_chains():
         x[:, t] = np.where(keep, x[:, t - 1], rng.standard_normal(C))
     tau = made.integrated_autocorr(x)
     assert abs(tau - (1 + p) / (1 - p)) < 0.3
+
+
+def test_ranked_tau_int_is_robust_to_heavy_tails():
+    # the sticky chains above with Cauchy values: the ranked estimate keeps
+    # the closed form, and for Gaussian AR(1) values it agrees with the
+    # plain estimate (the product estimator of the sampler comparison)
+    from paper_2503_12557_amd import analysis
+    p, C, T = 0.67, 4096, 64
+    rng = np.random.default_rng(6)
+    x = np.empty((C, T))
+    x[:, 0] = rng.standard_cauchy(C)
+    for t in range(1, T):
+        keep = rng.random(C) < p
+        x[:, t] = np.where(keep, x[:, t - 1], rng.standard_cauchy(C))
+    assert abs(analysis.tau_int_ranked(x) - (1 + p) / (1 - p)) < 0.3
+    a = 0.6
+    y = np.zeros((64, 800))
+    e = rng.standard_normal(y.shape)
+    y[:, 0] = e[:, 0] / np.sqrt(1 - a * a)
+    for t in range(1, y.shape[1]):
+        y[:, t] = a * y[:, t - 1] + e[:, t]
+    assert abs(analysis.tau_int_ranked(y) - made.integrated_autocorr(y)) < 0.2
