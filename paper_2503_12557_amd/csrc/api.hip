@@ -460,7 +460,7 @@ static size_t per_sample_scratch(const peps_ctx* c, bool env_internal) {
   size_t s1 = (size_t)L.Lx * (L.Ly + 1) * box;
   size_t s2 = (size_t)(L.Lx - 1) * (L.Ly + 1) * box2;
   size_t g = 0;
-  if (c->env_gm) g += 2 * env_slab_elems(L);
+  if (c->env_gm) g += 2 * env_slab_elems(L, c->g.dtype);
   if (c->s1_gm) g += (size_t)L.Lx * strip1_slab_elems(L);
   if (c->s2_gm) g += (size_t)(L.Lx - 1) * strip2_slab_elems(L);
   size_t e = env_internal ? env_tensor_elems_per_sample(L) : 0;
@@ -487,7 +487,7 @@ static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int m, char* en
   if (s != PEPS_OK) return s;
   void* gws = nullptr;
   if (c->env_gm) {
-    if ((s = c->gws_env.ensure((size_t)m * 2 * env_slab_elems(L) * c->tsize)) != PEPS_OK) return s;
+    if ((s = c->gws_env.ensure((size_t)m * 2 * env_slab_elems(L, c->g.dtype) * c->tsize)) != PEPS_OK) return s;
     gws = c->gws_env.p;
   }
   ProfScope ps(c, st, PEPS_PROF_ENV);
@@ -782,7 +782,7 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
   if ((s = c->rt2.ensure(nc * (L.Ly + 1) * box2 * c->tsize)) != PEPS_OK) return s;
   void* gws = nullptr;
   if (c->smp_gm) {
-    if ((s = c->gws_smp.ensure(nc * sample_slab_elems(L) * c->tsize)) != PEPS_OK) return s;
+    if ((s = c->gws_smp.ensure(nc * sample_slab_elems(L, c->g.dtype) * c->tsize)) != PEPS_OK) return s;
     gws = c->gws_smp.p;
   }
   ProfScope ps(c, st, PEPS_PROF_SAMPLE);

@@ -20,7 +20,7 @@
 
 namespace pm {
 
-size_t env_lds_elems(int bmax, int D) { return env_lds_elems_(bmax, D); }
+size_t env_lds_elems(int bmax, int D, int mode) { return env_lds_elems_(bmax, D, mode); }
 
 // GM: the matrices live in a per-workgroup slab of gws (slab elements each)
 // instead of LDS, for shapes whose working set exceeds the on-chip memory.
@@ -38,7 +38,7 @@ k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* 
   if (smp >= n) return;
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* big = GM ? gws + ((size_t)smp * 2 + blockIdx.y) * slab : lds;
-  T* small = GM ? lds : lds + env_big_elems(L.bmax, L.D);
+  T* small = GM ? lds : lds + env_big_elems(L.bmax, L.D, M);
   const EnvSmem<T> sh(big, small, L);
   const int BD = L.bmax * L.D;
   __shared__ int sflag, fl;
@@ -143,9 +143,11 @@ __global__ void k_convert_theta(const double* __restrict__ src, T* __restrict__ 
 // ---- host launchers ----
 size_t env_lds_bytes(int mode, const Lattice& L, bool gm) {
   const size_t es = mode_elem_bytes(mode);
-  return (gm ? env_small_elems(L.bmax, L.D) : env_lds_elems_(L.bmax, L.D)) * es;
+  return (gm ? env_small_elems(L.bmax, L.D) : env_lds_elems_(L.bmax, L.D, mode)) * es;
 }
-size_t env_slab_elems(const Lattice& L) { return (env_big_elems(L.bmax, L.D) + 15) / 16 * 16; }
+size_t env_slab_elems(const Lattice& L, int mode) {
+  return (env_big_elems(L.bmax, L.D, mode) + 15) / 16 * 16;
+}
 
 template <int M>
 hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
@@ -159,7 +161,7 @@ hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_env_sweep<M, true>), grid, dim3(env_threads(M)), lds, st, L, tab,
                        (const T*)theta, samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps,
-                       (T*)gws, env_slab_elems(L));
+                       (T*)gws, env_slab_elems(L, M));
   } else {
     const size_t lds = env_lds_bytes(M, L, false);
     hipFuncSetAttribute((const void*)k_env_sweep<M, false>,

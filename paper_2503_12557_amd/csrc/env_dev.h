@@ -64,17 +64,151 @@ __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
   return log((double)mx);
 }
 
+// ---------------------------------------------------------------------------
+// Left-sweep tree QR for FP32 / BF16 with chi*D <= 64 and D <= 4 (four
+// waves). Lane c of a wave holds column c of a 64-row block in registers.
+// A block [t; u], t upper triangular in LDS (packed by rows, 64 columns) and
+// u dense in registers, is reduced to one triangular factor by Householder
+// reflectors whose vectors are broadcast across the wave with readlane, so
+// no workgroup barrier is needed inside a factorisation. Wave k builds
+// M_k = R_{y-1} P_k in registers and eliminates it into a zero t; the waves
+// then merge their factors pairwise (a reduction tree of QR factorisations).
+// ---------------------------------------------------------------------------
+#define TQ_N 64
+#define TQ_PACK (TQ_N * (TQ_N + 1) / 2)
+
+__host__ __device__ inline bool tsqr_path(int mode, int bmax, int D) {
+  return (mode == MODE_F32 || mode == MODE_BF16) && bmax * D <= TQ_N && D <= 4;
+}
+
 // Working set of one environment workgroup, in elements: the matrices
 // ("big": in LDS, or in a global slab when they do not fit on chip) and
 // the vectors and reduction scratch ("small": always in LDS).
-__host__ __device__ inline size_t env_big_elems(int bmax, int D) {
+__host__ __device__ inline size_t env_big_elems(int bmax, int D, int mode) {
   const size_t BD = (size_t)bmax * D;
-  return (size_t)bmax * D * bmax + (size_t)D * D * D * D + BD * BD + 2 * BD * (BD + 4) +
-         2 * BD * bmax;
+  const size_t head = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
+  size_t rest = BD * BD + 2 * BD * (BD + 4) + 2 * BD * bmax;
+  // the tree QR keeps four packed factors and the dense previous R from P on
+  const size_t tq = 4 * (size_t)TQ_PACK + (size_t)TQ_N * TQ_N;
+  if (tsqr_path(mode, bmax, D) && rest < tq) rest = tq;
+  return head + rest;
 }
-__host__ __device__ inline size_t env_small_elems(int bmax, int D) { return 4 * (size_t)bmax * D + 16; }
-__host__ __device__ inline size_t env_lds_elems_(int bmax, int D) {
-  return env_big_elems(bmax, D) + env_small_elems(bmax, D);
+__host__ __device__ inline size_t env_small_elems(int bmax, int D) {
+  return 4 * (size_t)bmax * D + 16;
+}
+__host__ __device__ inline size_t env_lds_elems_(int bmax, int D, int mode) {
+  return env_big_elems(bmax, D, mode) + env_small_elems(bmax, D);
+}
+
+__device__ __forceinline__ float bcast_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// start of row j in a packed upper-triangular TQ_N x TQ_N matrix (by rows)
+__host__ __device__ __forceinline__ int prow(int j) { return j * TQ_N - (j * (j - 1)) / 2; }
+
+// Eliminate u (lane c < n holds column c of 64 rows) into t (packed rows,
+// this wave's LDS slot); on exit t is the triangular factor of [t; u].
+// kmax = min(n, rows of t + rows of u): later columns hold only rounding
+// residue, which is dropped rather than reflected (as in LAPACK's larfg, a
+// column whose norm is below the normal range is left alone).
+__device__ void wave_merge(float* t, float (&u)[TQ_N], int n, int kmax) {
+  const int c = threadIdx.x & 63;
+  for (int j = 0; j < kmax; ++j) {
+    float v[TQ_N];
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+    for (int i = 0; i < TQ_N; i += 4) {
+      v[i] = bcast_lane(u[i], j);
+      v[i + 1] = bcast_lane(u[i + 1], j);
+      v[i + 2] = bcast_lane(u[i + 2], j);
+      v[i + 3] = bcast_lane(u[i + 3], j);
+      s0 = fmaf(v[i], v[i], s0);
+      s1 = fmaf(v[i + 1], v[i + 1], s1);
+      s2 = fmaf(v[i + 2], v[i + 2], s2);
+      s3 = fmaf(v[i + 3], v[i + 3], s3);
+    }
+    const float s = (s0 + s1) + (s2 + s3);
+    if (!(s > 1e-36f)) continue;  // column j of u is already zero
+    float* trow = t + prow(j) - j;  // trow[c] = t[j][c] for c >= j
+    const float ajj = trow[j];
+    const float nr = sqrtf(ajj * ajj + s);
+    const float alpha = ajj > 0.f ? -nr : nr;
+    const float v0 = ajj - alpha;
+    const float tau = 2.f / (v0 * v0 + s);
+    const bool own = c >= j && c < n;
+    const float tj = own ? trow[c] : 0.f;
+    float d0 = v0 * tj, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+#pragma unroll
+    for (int i = 0; i < TQ_N; i += 4) {
+      d0 = fmaf(v[i], u[i], d0);
+      d1 = fmaf(v[i + 1], u[i + 1], d1);
+      d2 = fmaf(v[i + 2], u[i + 2], d2);
+      d3 = fmaf(v[i + 3], u[i + 3], d3);
+    }
+    const float w = tau * ((d0 + d1) + (d2 + d3));
+    if (own) trow[c] = tj - v0 * w;
+#pragma unroll
+    for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(-v[i], w, u[i]);
+  }
+}
+
+// One site of the left sweep on the tree-QR path: from the previous factor
+// Rpk (LDS, dense 64 x 64 column-major, zero below the diagonal and outside
+// kprev x Pl) and the site's
+// E and A in LDS, leave R_y in slot 0 (packed rows). slots: 4 packed
+// factors of TQ_PACK elements.
+template <int M>
+__device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk, float* slots,
+                          int kprev, int bl, int br, int Dl, int Dr, int Din, int Dout, int s_l,
+                          int s_r, int s_in, int s_out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int Pl = bl * Dl, Pr = br * Dr;
+  // rows of the factor of the blocks [w0, w0 + span)
+  auto rows = [&](int w0, int span) {
+    const int e = w0 + span < Dout ? w0 + span : Dout;
+    const int k = kprev * (e - w0);
+    return k < Pr ? k : Pr;
+  };
+  if (wv < Dout) {
+    float* t = slots + wv * TQ_PACK;
+    for (int i = lane; i < TQ_PACK; i += 64) t[i] = 0.f;
+    // u = R_{y-1} P_k for column c = (b, r) of P_k, with
+    // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k] formed row by row;
+    // R_{y-1} is dense column-major in LDS (zeros below the diagonal)
+    const int c = lane;
+    const bool colok = c < Pr;
+    const int b = colok ? c / Dr : 0, r = colok ? c - (c / Dr) * Dr : 0;
+    float u[TQ_N];
+#pragma unroll
+    for (int i = 0; i < TQ_N; ++i) u[i] = 0.f;
+    for (int l = 0; l < Pl; ++l) {
+      float pl = 0.f;
+      if (colok) {
+        const int aa = l / Dl, li = l - (l / Dl) * Dl;
+        for (int in = 0; in < Din; ++in)
+          pl = fmaf(opnd<M>(Ebuf[(aa * Din + in) * br + b]),
+                    opnd<M>(Abuf[li * s_l + r * s_r + in * s_in + wv * s_out]), pl);
+      }
+      pl = opnd<M>(pl);
+      const float* col = Rpk + l * TQ_N;
+#pragma unroll
+      for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(opnd<M>(col[i]), pl, u[i]);
+    }
+    wave_merge(t, u, Pr, rows(wv, 1));
+  }
+  // pairwise merges: wave w takes the factor of wave w + step
+  for (int step = 1; step < Dout; step *= 2) {
+    __syncthreads();
+    if ((wv % (2 * step)) == 0 && wv + step < Dout) {
+      const float* tp = slots + (wv + step) * TQ_PACK;
+      float u[TQ_N];
+#pragma unroll
+      for (int i = 0; i < TQ_N; ++i) u[i] = (i <= lane) ? tp[prow(i) - i + lane] : 0.f;
+      const int k2 = rows(wv, step) + rows(wv + step, step);
+      wave_merge(slots + wv * TQ_PACK, u, Pr, k2 < Pr ? k2 : Pr);
+    }
+  }
+  __syncthreads();
 }
 
 // Carve-up of the working set.
@@ -166,6 +300,15 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
 
     // left-to-right QR sweep: R_y of R_{y-1} P_y
     int kprev = 1;  // rows of R_{y-1}
+    bool tree = false;
+    if constexpr (M == MODE_F32 || M == MODE_BF16) {
+      tree = tsqr_path(M, L.bmax, L.D) && PEPS_NT == 256;
+      if (tree) {
+        // R_{-1} = [1], dense column-major after the four factor slots
+        float* Rpk = P + 4 * TQ_PACK;
+        for (int i = tid; i < TQ_N * TQ_N; i += PEPS_NT) Rpk[i] = i == 0 ? 1.f : 0.f;
+      }
+    }
     for (int y = 0; y < L.Ly - 1; ++y) {
       const int nsite = x * L.Ly + y;
       const SiteView v = site_view(tab, L, nsite, bottom);
@@ -176,6 +319,35 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       const T* a = site_tensor(theta, tab, L, s, nsite);
       load_lds(Abuf, a, v.Dl * v.Dr * v.Din * v.Dout);
       __syncthreads();
+      if constexpr (M == MODE_F32 || M == MODE_BF16) {
+        if (tree) {
+          float* Rpk = P + 4 * TQ_PACK;
+          tsqr_site<M>(Ebuf, Abuf, Rpk, P, kprev, bl, br, v.Dl, v.Dr, v.Din, v.Dout, v.s_l,
+                       v.s_r, v.s_in, v.s_out);
+          const int kr = min(kprev * v.Dout, Pr);
+          // R_y at unit scale (see below) to global rows and to Rpk
+          const float* t0 = P;
+          Rl mx = 0;
+          for (int i = tid; i < kr * Pr; i += PEPS_NT) {
+            const int ii = i / Pr, cc = i - ii * Pr;
+            if (cc >= ii) mx = fmaxf(mx, fabsf(t0[prow(ii) - ii + cc]));
+          }
+          mx = block_max(mx, rred);
+          const Rl fr = (Rl)ldexp(1.0, -pow2_exponent((double)mx));
+          T* Ry = R + (size_t)y * BD * BD;
+          for (int i = tid; i < kr * Pr; i += PEPS_NT) {
+            const int ii = i / Pr, cc = i - ii * Pr;
+            Ry[i] = cc >= ii ? t0[prow(ii) - ii + cc] * fr : 0.f;
+          }
+          for (int i = tid; i < TQ_N * TQ_N; i += PEPS_NT) {
+            const int cc = i / TQ_N, ii = i - cc * TQ_N;  // column-major
+            Rpk[i] = (ii <= cc && ii < kr && cc < Pr) ? t0[prow(ii) - ii + cc] * fr : 0.f;
+          }
+          __syncthreads();
+          kprev = kr;
+          continue;
+        }
+      }
       const T* Rp = (y > 0) ? R + (size_t)(y - 1) * BD * BD : nullptr;
       int kr = 0;
       for (int k = 0; k < v.Dout; ++k) {

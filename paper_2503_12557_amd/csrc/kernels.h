@@ -35,17 +35,17 @@ struct HamDev {
 // global working-set buffer gws of one slab ("_slab_elems" elements of the
 // compute type) per workgroup of the grid, and only the small vectors stay
 // in LDS (gm = true).
-size_t env_lds_elems(int bmax, int D);
+size_t env_lds_elems(int bmax, int D, int mode);
 size_t strip1_lds_elems(int bmax, int D);
 size_t strip2_lds_elems(int bmax, int D);
 size_t env_lds_bytes(int mode, const Lattice& L, bool gm);
 size_t strip1_lds_bytes(int mode, const Lattice& L, bool gm);
 size_t strip2_lds_bytes(int mode, const Lattice& L, bool gm);
 size_t sample_lds_bytes(int mode, const Lattice& L, bool gm);
-size_t env_slab_elems(const Lattice& L);
+size_t env_slab_elems(const Lattice& L, int mode);
 size_t strip1_slab_elems(const Lattice& L);
 size_t strip2_slab_elems(const Lattice& L);
-size_t sample_slab_elems(const Lattice& L);
+size_t sample_slab_elems(const Lattice& L, int mode);
 
 template <int M>
 hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
@@ -71,7 +71,7 @@ hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8
                                   hipStream_t st);
 
 // Metropolis sampler
-size_t sample_lds_elems(int bmax, int D);
+size_t sample_lds_elems(int bmax, int D, int mode);
 template <int M>
 hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta, int kind,
                              int n_chains, int per_chain, int burn_in, int thin, uint64_t seed,

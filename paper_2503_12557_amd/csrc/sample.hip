@@ -26,14 +26,14 @@ namespace pm {
 // Working set of a chain: the matrices of whichever phase runs ("big": in
 // LDS, or in a global slab for large shapes) and the vectors and reduction
 // scratch ("small": LDS).
-__host__ __device__ static size_t sample_big(int bmax, int D) {
+__host__ __device__ static size_t sample_big(int bmax, int D, int mode) {
   const size_t BD = (size_t)bmax * D;
   const size_t box = (size_t)bmax * D * bmax;
   const size_t box2 = (size_t)bmax * bmax * D * D;
   const size_t bd3 = (size_t)bmax * D * D * D;
   const size_t one_row = 3 * box + 2 * BD * BD;
   const size_t two_row = 2 * box2 + 3 * bd3;
-  size_t m = env_big_elems(bmax, D);
+  size_t m = env_big_elems(bmax, D, mode);
   m = one_row > m ? one_row : m;
   return two_row > m ? two_row : m;
 }
@@ -59,7 +59,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   const int box2 = B * B * D * D;
   const int bd3 = B * D * D * D;
   T* sm = GM ? gws + (size_t)chain * slab : lds;
-  T* small = GM ? lds : lds + sample_big(B, D);
+  T* small = GM ? lds : lds + sample_big(B, D, M);
   const EnvSmem<T> sh(sm, small, L);
   // strip buffers alias the environment buffers (used in different phases)
   // one-row pass: Lf | Lt | Lt2 (box each) | X1 | X2 (BD^2 each)
@@ -313,12 +313,16 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   if (tid == 0 && accepted) accepted[chain] = acc;
 }
 
-size_t sample_lds_elems(int bmax, int D) { return sample_big(bmax, D) + env_small_elems(bmax, D); }
+size_t sample_lds_elems(int bmax, int D, int mode) {
+  return sample_big(bmax, D, mode) + env_small_elems(bmax, D);
+}
 size_t sample_lds_bytes(int mode, const Lattice& L, bool gm) {
-  return (gm ? env_small_elems(L.bmax, L.D) : sample_lds_elems(L.bmax, L.D)) *
+  return (gm ? env_small_elems(L.bmax, L.D) : sample_lds_elems(L.bmax, L.D, mode)) *
          mode_elem_bytes(mode);
 }
-size_t sample_slab_elems(const Lattice& L) { return (sample_big(L.bmax, L.D) + 15) / 16 * 16; }
+size_t sample_slab_elems(const Lattice& L, int mode) {
+  return (sample_big(L.bmax, L.D, mode) + 15) / 16 * 16;
+}
 
 template <int M>
 hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta, int kind,
@@ -336,7 +340,7 @@ hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta
     hipLaunchKernelGGL((k_metropolis<M, true>), dim3(n_chains), dim3(env_threads(M)), lds, st, L,
                        tab, (const T*)theta, kind, n_chains, per_chain, burn_in, thin, k0, k1,
                        offset, samples, accepted, (T*)envscr, logscr, (T*)rscr, (T*)rt1, (T*)rt2,
-                       jac_sweeps, (T*)gws, sample_slab_elems(L));
+                       jac_sweeps, (T*)gws, sample_slab_elems(L, M));
   else
     hipLaunchKernelGGL((k_metropolis<M, false>), dim3(n_chains), dim3(env_threads(M)), lds, st, L,
                        tab, (const T*)theta, kind, n_chains, per_chain, burn_in, thin, k0, k1,
