@@ -187,6 +187,27 @@ template <int M> __device__ __forceinline__ typename ModeT<M>::T opnd(typename M
   else return x;
 }
 
+// Exact n / d for 0 <= n < 2^16 and 1 <= d <= 2^16 by a multiply-high with
+// m = floor(2^32 / d) + 1: n m / 2^32 = n / d + n (1 - frac(2^32/d)) / 2^32,
+// and the added term is below 2^-16 <= 1/d, so the floor is unchanged. The
+// element loops decode their coordinates with it instead of runtime division.
+struct FastDiv {
+  uint32_t m;
+  int d;
+  __device__ explicit FastDiv(int d_)
+      : m(d_ <= 1 ? 0u : 0xffffffffu / (uint32_t)d_ + 1u), d(d_) {}
+  __device__ __forceinline__ int div(int n) const {
+    return d <= 1 ? n : (int)__umulhi((uint32_t)n, m);
+  }
+};
+// q <- q / d, returns q mod d
+__device__ __forceinline__ int divmod(int& q, const FastDiv& f) {
+  const int nq = f.div(q);
+  const int r = q - nq * f.d;
+  q = nq;
+  return r;
+}
+
 // Physical index of a site; masked so a malformed sample byte cannot index
 // outside the parameter block (samples with values > 1 are flagged).
 __device__ __forceinline__ int pbit(uint8_t v) { return v & 1; }
@@ -327,6 +348,7 @@ __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T*
     for (int j = tx; j < n; j += LJ) {
       const T* bp = B + j * sbj;
       T s1 = 0, s2 = 0;
+#pragma unroll 4
       for (int kk = 0; kk < k; ++kk) {
         T bv = opnd<M>(bp[kk * sbk]);
         if constexpr (CB) bv = conjx(bv);

@@ -353,10 +353,14 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       for (int k = 0; k < v.Dout; ++k) {
         // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k]
         const int tot = Pl * Pr;
+        const FastDiv fPr(Pr), fDl(v.Dl), fDr(v.Dr);
         for (int i = tid; i < tot; i += PEPS_NT) {
-          const int row = i / Pr, col = i - row * Pr;
-          const int aa = row / v.Dl, l = row - aa * v.Dl;
-          const int b = col / v.Dr, r = col - b * v.Dr;
+          int row = i;
+          int col = divmod(row, fPr);
+          const int l = divmod(row, fDl);
+          const int aa = row;
+          const int r = divmod(col, fDr);
+          const int b = col;
           T acc = 0;
           for (int in = 0; in < v.Din; ++in)
             acc += opnd<M>(Ebuf[(aa * v.Din + in) * br + b]) *
@@ -412,10 +416,14 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       const int zc = v.Dout * nbr;
       {
         const int tot = Pl * zc;
+        const FastDiv fzc(zc), fDl(v.Dl), fnbr(nbr);
         for (int i = tid; i < tot; i += PEPS_NT) {
-          const int row = i / zc, col = i - row * zc;
-          const int aa = row / v.Dl, l = row - aa * v.Dl;
-          const int k = col / nbr, c = col - k * nbr;
+          int row = i;
+          int col = divmod(row, fzc);
+          const int l = divmod(row, fDl);
+          const int aa = row;
+          const int c = divmod(col, fnbr);
+          const int k = col;
           T acc = 0;
           for (int in = 0; in < v.Din; ++in)
             for (int r = 0; r < v.Dr; ++r)

@@ -32,7 +32,7 @@ __host__ __device__ static size_t sample_big(int bmax, int D, int mode) {
   const size_t box2 = (size_t)bmax * bmax * D * D;
   const size_t bd3 = (size_t)bmax * D * D * D;
   const size_t one_row = 3 * box + 2 * BD * BD;
-  const size_t two_row = 2 * box2 + 3 * bd3;
+  const size_t two_row = 2 * box2 + 3 * S2G * bd3;
   size_t m = env_big_elems(bmax, D, mode);
   m = one_row > m ? one_row : m;
   return two_row > m ? two_row : m;
@@ -73,8 +73,8 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   T* Lf2 = sm;
   T* Lu = Lf2 + box2;
   T* Y1 = Lu + box2;
-  T* Y2 = Y1 + bd3;
-  T* Y3 = Y2 + bd3;
+  T* Y2 = Y1 + S2G * bd3;
+  T* Y3 = Y2 + S2G * bd3;
   T* red2 = small;
   __shared__ uint8_t s[1024];
   __shared__ int sflag, fl, acc;

@@ -131,11 +131,12 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
       gemm<M>(ub * Dr, ba * Dd, bb, Rn, bb, 1, Bt, 1, bb, X2, ba * Dd, 1, false);
       __syncthreads();
       // Env[m,r,u,d] = sum_{c,b} X1[m,c,u,b] Q[b,r,c,d]
+      const FastDiv fDd(Dd), fDu(Du), fDr(Dr);
       for (int i = tid; i < nA; i += PEPS_NT) {
         int t = i;
-        const int d = t % Dd; t /= Dd;
-        const int u = t % Du; t /= Du;
-        const int r = t % Dr; t /= Dr;
+        const int d = divmod(t, fDd);
+        const int u = divmod(t, fDu);
+        const int r = divmod(t, fDr);
         const int m = t;
         T acc = 0;
         for (int c = 0; c < ba; ++c)
@@ -219,7 +220,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
 static size_t strip2_big(int bmax, int D) {
   const size_t B2D2 = (size_t)bmax * bmax * D * D;
   const size_t BD3 = (size_t)bmax * D * D * D;
-  return 3 * B2D2 + 3 * BD3;
+  return 3 * B2D2 + 3 * S2G * BD3;
 }
 size_t strip2_lds_elems(int bmax, int D) { return strip2_big(bmax, D) + 16; }
 
@@ -243,9 +244,9 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   T* Lt = Lf + box2;
   T* Lt2 = Lt + box2;
   T* X1 = Lt2 + box2;
-  T* X2 = X1 + bd3;
-  T* X3 = X2 + bd3;
-  T* red = GM ? lds : X3 + bd3;
+  T* X2 = X1 + S2G * bd3;
+  T* X3 = X2 + S2G * bd3;
+  T* red = GM ? lds : X3 + S2G * bd3;
   __shared__ T one[1];
   __shared__ int fl;
   if (tid == 0) {
