@@ -260,7 +260,8 @@ def main():
     t_sample = None
     if args.sampler in ("auto", "metropolis"):
         try:
-            ctx_s = Context(Lx, Ly, D, chi, "f32")
+            # the FP64 sampler: the batch does not move with FP32 rounding
+            ctx_s = ctx64
             chains = min(n, 1024)
             per = (n + chains - 1) // chains
             t0 = time.perf_counter()
@@ -268,7 +269,7 @@ def main():
                                         burn_in=8, thin=1, seed=1)
             _sync()
             t_sample = time.perf_counter() - t0
-            sampler_used = (f"local exchange Metropolis (library sampler, FP32, {chains} chains x "
+            sampler_used = (f"local exchange Metropolis (library sampler, FP64, {chains} chains x "
                             f"{per}, burn-in 8 sweeps, seed 1)")
         except PepsError:
             if args.sampler == "metropolis":
@@ -313,6 +314,10 @@ def main():
     e_lo = el[:, 0].double().mean().item()
     e_hi = e64[:, 0].mean().item()
     rel_e = abs(e_lo - e_hi) / abs(e_hi)
+    # per-configuration errors: the batch mean of random tensors is carried
+    # by a few near-zero amplitudes with huge E_loc, so report quantiles too
+    per_e = ((el[:, 0].double() - e64[:, 0]).abs() / e64[:, 0].abs().clamp_min(1.0)).cpu().numpy()
+    per_psi = (lp[:, 0] - lp64[:, 0]).abs().cpu().numpy()
     flags = int(torch.bitwise_or(fl, f64).max().item())
 
     # minSR step on the batch (FP64 solve), timed separately
@@ -361,6 +366,11 @@ def main():
                                f"{n} configurations, tensors N(0,1) seed 2",
                    "samples": sampler_used, "global_batch": n},
         "energy_rel_err_vs_f64": rel_e,
+        "eloc_rel_err_per_config": {"median": float(np.median(per_e)),
+                                    "p99": float(np.quantile(per_e, 0.99)),
+                                    "max": float(per_e.max())},
+        "ln_psi_abs_err_per_config": {"median": float(np.median(per_psi)),
+                                      "p99": float(np.quantile(per_psi, 0.99))},
         "energy_mean_f64": e_hi,
         "value_f64": round(n / t64, 2),
         "minsr_step_ms": round(t_minsr * 1e3, 2),

@@ -166,6 +166,27 @@ __host__ __device__ constexpr size_t mode_elem_bytes(int mode) {
   return mode == MODE_C128 ? 16 : (mode == MODE_F64 || mode == MODE_C64) ? 8 : 4;
 }
 
+// Data-parallel-primitive (DPP) lane moves inside a row of 16 lanes:
+// 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = quad_perm [2,3,0,1]
+// (lane ^ 2), 0x141 = half-row mirror (lane i <- 7 - i in each group of 8),
+// 0x140 = row mirror (lane i <- 15 - i). Summing a value with its partner
+// under these four in turn reduces groups of 2, 4, 8 and 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dppx(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppx(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, typename R>
+__device__ __forceinline__ cplx<R> dppx(cplx<R> v) {
+  return cplx<R>(dppx<CTRL>(v.re), dppx<CTRL>(v.im));
+}
+
 template <int M> struct ModeT;
 template <> struct ModeT<MODE_F64> { typedef double T; };
 template <> struct ModeT<MODE_F32> { typedef float T; };
@@ -245,18 +266,29 @@ __device__ __forceinline__ int slot_bottom(const Lattice& L, int x) { return L.L
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += shfl_xor_x(v, o);
+  v += dppx<0xB1>(v);
+  v += dppx<0x4E>(v);
+  v += dppx<0x141>(v);
+  v += dppx<0x140>(v);
+  v += shfl_xor_x(v, 16);
+  v += shfl_xor_x(v, 32);
   return v;
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    T w = __shfl_xor(v, o, 64);
-    v = w > v ? w : v;
-  }
+  T w = dppx<0xB1>(v);
+  v = w > v ? w : v;
+  w = dppx<0x4E>(v);
+  v = w > v ? w : v;
+  w = dppx<0x141>(v);
+  v = w > v ? w : v;
+  w = dppx<0x140>(v);
+  v = w > v ? w : v;
+  w = __shfl_xor(v, 16, 64);
+  v = w > v ? w : v;
+  w = __shfl_xor(v, 32, 64);
+  v = w > v ? w : v;
   return v;
 }
 
@@ -321,7 +353,12 @@ __device__ void scale_pow2(T* t, int cnt, int e) {
 // Sum over groups of G consecutive lanes (G a power of two, G <= 64).
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-  for (int o = G >> 1; o >= 1; o >>= 1) v += shfl_xor_x(v, o);
+  if (G >= 2) v += dppx<0xB1>(v);
+  if (G >= 4) v += dppx<0x4E>(v);
+  if (G >= 8) v += dppx<0x141>(v);
+  if (G >= 16) v += dppx<0x140>(v);
+  if (G >= 32) v += shfl_xor_x(v, 16);
+  if (G >= 64) v += shfl_xor_x(v, 32);
   return v;
 }
 
@@ -439,8 +476,8 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda,
         rowj = A[j * lda + c];
         for (int i = r0 + sub; i < m; i += 4) d += conjx(A[i * lda + j]) * A[i * lda + c];
       }
-      d += shfl_xor_x(d, 1);
-      d += shfl_xor_x(d, 2);
+      d += dppx<0xB1>(d);
+      d += dppx<0x4E>(d);
       R sqn = 0;
       if (own) {
         const T w = tau * (conjx(v0) * rowj + d);
@@ -452,8 +489,8 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda,
         }
       }
       if (c == j + 1 && j + 1 < kmax) {  // this column feeds the next reflector
-        sqn += shfl_xor_x(sqn, 1);
-        sqn += shfl_xor_x(sqn, 2);
+        sqn += dppx<0xB1>(sqn);
+        sqn += dppx<0x4E>(sqn);
         if (sub == 0) nrm[(j + 1) & 1] = sqn;
       }
     }
