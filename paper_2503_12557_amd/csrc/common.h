@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define PEPS_BLOCK_MAX 512
 // threads of the running block (launches use 256 or 512)
 #define PEPS_NT ((int)blockDim.x)
@@ -602,13 +604,25 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::t
         R cm;
         if constexpr (IsCplx<T>::value) cm = absx(c);
         else cm = c;
-        if (act && cm != R(0) && fabs(cm) > tol * sqrt(a * b)) {
-          const R zeta = (b - a) / (R(2) * cm);
-          const R az = fabs(zeta);
-          R t;
-          if (az > R(1) / Eps<R>::v) t = R(0.5) / zeta;
-          else t = (zeta >= R(0) ? R(1) : R(-1)) / (az + sqrt(R(1) + zeta * zeta));
-          const R cs = R(1) / sqrt(R(1) + t * t);
+        if (act && cm != R(0) && cm * cm > tol * tol * (a * b)) {
+          R zeta, az, t, cs;
+          if constexpr (std::is_same<T, float>::value) {
+            // FP32: hardware reciprocal and reciprocal square root (1 ulp);
+            // the rotation only needs to be orthogonal to rounding
+            zeta = (b - a) * (0.5f * __builtin_amdgcn_rcpf(cm));
+            az = fabsf(zeta);
+            if (az > 1.f / Eps<float>::v) t = 0.5f * __builtin_amdgcn_rcpf(zeta);
+            else
+              t = copysignf(__builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + zeta * zeta)),
+                            zeta);
+            cs = __builtin_amdgcn_rsqf(1.f + t * t);
+          } else {
+            zeta = (b - a) / (R(2) * cm);
+            az = fabs(zeta);
+            if (az > R(1) / Eps<R>::v) t = R(0.5) / zeta;
+            else t = (zeta >= R(0) ? R(1) : R(-1)) / (az + sqrt(R(1) + zeta * zeta));
+            cs = R(1) / sqrt(R(1) + t * t);
+          }
           const R sn = cs * t;
           // complex: rotate (p, e* q) with e = c/|c|, which makes <p, e* q> real
           T sq, cq;
