@@ -510,8 +510,8 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda,
 // to relative tolerance tol. Pairs follow the circle (round-robin) schedule,
 // m-1 rounds of m/2 disjoint pairs per sweep; each pair is held by G lanes,
 // each lane keeping its NC elements of both rows in registers between the
-// dot products and the rotation. Returns the number of sweeps used, or -1
-// if max_sweeps was reached.
+// dot products and the rotation. sflag: LDS int. Returns the number of
+// sweeps used, or -1 if max_sweeps was reached.
 // ---------------------------------------------------------------------------
 // NC contiguous elements through 16-byte LDS accesses (caller checks alignment)
 template <typename T, int NC>
@@ -557,7 +557,7 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::t
       for (int e = 0; e < n; ++e) q2 += abs2x(X[i * ldx + e]);
       nrm[i] = q2;
     }
-    if (tid == 0) *sflag = 0;
+    if (tid == 0) sflag[0] = 0;
     __syncthreads();
     for (int r = 0; r < mp - 1; ++r) {
       for (int pb = 0; pb < npairs; pb += per_pass) {
@@ -660,7 +660,7 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::t
               }
           }
           if (lane == 0) {
-            *sflag = 1;
+            sflag[0] = 1;
             nrm[p] = a - t * cm;
             nrm[q] = b + t * cm;
           }
@@ -668,7 +668,7 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::t
       }
       __syncthreads();
     }
-    const int f = *sflag;
+    const int f = sflag[0];
     __syncthreads();
     if (f == 0) return sweep + 1;
   }
@@ -693,7 +693,7 @@ __device__ int jacobi_rows_long(T* X, int m, int n, int ldx, typename RealOf<T>:
       for (int e = 0; e < n; ++e) q2 += abs2x(X[i * ldx + e]);
       nrm[i] = q2;
     }
-    if (tid == 0) *sflag = 0;
+    if (tid == 0) sflag[0] = 0;
     __syncthreads();
     for (int r = 0; r < mp - 1; ++r) {
       for (int pb = 0; pb < npairs; pb += per_pass) {
@@ -744,7 +744,7 @@ __device__ int jacobi_rows_long(T* X, int m, int n, int ldx, typename RealOf<T>:
             rq[e] = sn * xp + cq * xq;
           }
           if (lane == 0) {
-            *sflag = 1;
+            sflag[0] = 1;
             nrm[p] = a - t * cm;
             nrm[q] = b + t * cm;
           }
@@ -752,7 +752,7 @@ __device__ int jacobi_rows_long(T* X, int m, int n, int ldx, typename RealOf<T>:
       }
       __syncthreads();
     }
-    const int f = *sflag;
+    const int f = sflag[0];
     __syncthreads();
     if (f == 0) return sweep + 1;
   }

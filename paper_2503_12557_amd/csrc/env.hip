@@ -41,7 +41,7 @@ k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* 
   T* small = GM ? lds : lds + env_big_elems(L.bmax, L.D, M);
   const EnvSmem<T> sh(big, small, L);
   const int BD = L.bmax * L.D;
-  __shared__ int sflag, fl;
+  __shared__ int sflag[2], fl;
   __shared__ int sel[256];
   if (threadIdx.x == 0) fl = 0;
   __syncthreads();
@@ -52,7 +52,7 @@ k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* 
   T* R = rscr + ((size_t)smp * 2 + (bottom ? 1 : 0)) * (size_t)L.Ly * BD * BD;
   env_first_row<M>(L, tab, theta, s, bottom, envs, lg, sh, &fl);
   for (int t = 1; t <= L.Lx - 2; ++t)
-    env_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, R, sh, sel, &sflag, &fl, jac_sweeps);
+    env_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, R, sh, sel, sflag, &fl, jac_sweeps);
   if (threadIdx.x == 0 && fl && flags) atomicOr(flags + smp, fl);
 }
 

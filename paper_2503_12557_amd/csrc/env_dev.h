@@ -459,15 +459,20 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         }
         const int used = jacobi_rows(S, m, zc, ldc, tol, jac_sweeps, sflag, vv);
         if (used < 0 && tid == 0) fl |= 4;
-        // row norms
-        for (int i = tid; i < m; i += PEPS_NT) {
+        // row norms, four lanes per row
+        for (int i4 = tid; i4 < 4 * m; i4 += PEPS_NT) {
+          const int i = i4 >> 2, part = i4 & 3;
           Rl q = 0;
-          for (int e = 0; e < zc; ++e) q += abs2x(S[i * ldc + e]);
-          sig[i] = sqrt(q);
+          for (int e = part; e < zc; e += 4) q += abs2x(S[i * ldc + e]);
+          q += dppx<0xB1>(q);
+          q += dppx<0x4E>(q);
+          if (part == 0) sig[i] = sqrt(q);
         }
         __syncthreads();
         rnew = edims[(sn * L.Ly + y) * 3 + 0];
-        // rank rows by descending norm (ties by index)
+        // rank rows by descending norm (ties by index); the largest value and
+        // the largest discarded one (for the degenerate-cut flag)
+        Rl smx = 0, sdis = 0;
         for (int i = tid; i < m; i += PEPS_NT) {
           int rk = 0;
           const Rl si = sig[i];
@@ -476,19 +481,13 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
             rk += (sj > si) || (sj == si && j < i);
           }
           if (rk < rnew) sel[rk] = i;
+          else sdis = si > sdis ? si : sdis;
+          smx = si > smx ? si : smx;
         }
-        __syncthreads();
-        Rl smax = 0;
-        for (int i = 0; i < m; ++i) smax = sig[i] > smax ? sig[i] : smax;
+        const Rl smax = block_max(smx, rred);
+        const Rl sb = block_max(sdis, rred);
         if (tid == 0 && rnew < m) {
           const Rl sa = sig[sel[rnew - 1]];
-          // the largest discarded value
-          Rl sb = 0;
-          for (int i = 0; i < m; ++i) {
-            bool kept = false;
-            for (int j = 0; j < rnew; ++j) kept |= (sel[j] == i);
-            if (!kept && sig[i] > sb) sb = sig[i];
-          }
           if (sa > Rl(0) && (sa - sb) < Rl(1e-8) * sa) fl |= 8;
         }
         const Rl thresh = smax * Eps<Rl>::v * Rl(4);

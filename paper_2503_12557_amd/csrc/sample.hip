@@ -77,7 +77,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   T* Y3 = Y2 + S2G * bd3;
   T* red2 = small;
   __shared__ uint8_t s[1024];
-  __shared__ int sflag, fl, acc;
+  __shared__ int sflag[2], fl, acc;
   __shared__ int sel[256];
   __shared__ T one[1];
   __shared__ uint32_t keys[1024];
@@ -149,7 +149,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
     // bottom environments of the current state
     env_first_row<M>(L, tab, theta, s, true, envs, lg, sh, &fl);
     for (int t = 1; t <= Lx - 2; ++t)
-      env_absorb_row<M>(L, tab, theta, s, true, t, envs, lg, R, sh, sel, &sflag, &fl, jac_sweeps);
+      env_absorb_row<M>(L, tab, theta, s, true, t, envs, lg, R, sh, sel, sflag, &fl, jac_sweeps);
     for (int x = 0; x < Lx; ++x) {
       const bool has_up = x > 0, has_dn = x < Lx - 1;
       const int su = has_up ? slot_top(L, x - 1) : -1;
@@ -300,7 +300,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
       // ---- absorb the updated row into the top environment ----
       if (x == 0) env_first_row<M>(L, tab, theta, s, false, envs, lg, sh, &fl);
       else if (x < Lx - 1)
-        env_absorb_row<M>(L, tab, theta, s, false, x, envs, lg, R, sh, sel, &sflag, &fl,
+        env_absorb_row<M>(L, tab, theta, s, false, x, envs, lg, R, sh, sel, sflag, &fl,
                           jac_sweeps);
     }
     if (sw >= burn_in && (sw - burn_in) % thin == thin - 1) {
