@@ -510,8 +510,8 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda,
 // to relative tolerance tol. Pairs follow the circle (round-robin) schedule,
 // m-1 rounds of m/2 disjoint pairs per sweep; each pair is held by G lanes,
 // each lane keeping its NC elements of both rows in registers between the
-// dot products and the rotation. sflag: LDS int. Returns the number of
-// sweeps used, or -1 if max_sweeps was reached.
+// dot products and the rotation. sflag: LDS int; nrm: 2m reals of LDS.
+// Returns the number of sweeps used, or -1 if max_sweeps was reached.
 // ---------------------------------------------------------------------------
 // NC contiguous elements through 16-byte LDS accesses (caller checks alignment)
 template <typename T, int NC>
@@ -675,6 +675,166 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::t
   return -1;
 }
 
+// Real rows, m a power of two (4 <= m <= 64): the same one-sided Jacobi with
+// the pairs of a sweep in recursive block order. For b = m/2, m/4, ..., 1 the
+// rows fall into blocks of 2b; during b rounds the first half of each block
+// (resident rows, held in the registers of one group for the whole phase)
+// meets every row of the second half (travelling rows, read from LDS each
+// round). A sweep is again m-1 rounds of m/2 disjoint pairs covering every
+// pair once, but only the travelling row goes through LDS.
+// Rotations are applied in scaled form (fast plane rotations, Gentleman;
+// with the scales kept apart as in Anda and Park): row i is stored as
+// X_i = d_i Y_i, and the rotation [c -s; s c] of rows p, q with t = s/c
+// becomes Y_p -= (t d_q / d_p) Y_q, Y_q += (t d_p / d_q) Y_p, d_{p,q} *= c:
+// one multiply-add per element instead of two. c >= 2^-1/2 and a row meets
+// m-1 <= 63 partners per sweep, so a scale stays above 2^-32; the scales are
+// folded back into the rows at the start of every sweep and on exit.
+// nrm holds 2m reals: the squared norms of X, then the scales d.
+template <typename T, int NC>
+__device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, int max_sweeps,
+                                            int* sflag, int G, T* nrm) {
+  static_assert(!IsCplx<T>::value, "scaled rotations are for real rows");
+  T* dd = nrm + m;
+  const int tid = threadIdx.x;
+  const int npairs = m >> 1;
+  const int pi = tid / G, lane = tid - (tid / G) * G;
+  const bool grp = pi < npairs;
+  const int e0 = lane * NC;
+  const bool full = e0 + NC <= n;
+  const bool vec = (NC * sizeof(T)) % 16 == 0 && (ldx * sizeof(T)) % 16 == 0 &&
+                   (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  auto ld = [&](int row, T (&y)[NC]) __attribute__((always_inline)) {
+    const T* src = X + row * ldx + e0;
+    if (full && vec) {
+      load16<T, NC>(src, y);
+    } else {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) y[u] = e0 + u < n ? src[u] : T(0);
+    }
+  };
+  auto st = [&](int row, const T (&y)[NC]) __attribute__((always_inline)) {
+    T* dst = X + row * ldx + e0;
+    if (full && vec) {
+      store16<T, NC>(dst, y);
+    } else {
+#pragma unroll
+      for (int u = 0; u < NC; ++u)
+        if (e0 + u < n) dst[u] = y[u];
+    }
+  };
+  // fold the scales into the rows (X_i = d_i Y_i), refresh the squared norms
+  auto fold = [&]() __attribute__((always_inline)) {
+    if (grp) {
+      for (int h = 0; h < 2; ++h) {
+        const int row = 2 * pi + h;
+        T y[NC];
+        ld(row, y);
+        const T d = dd[row];
+        T q2 = 0;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+          y[u] *= d;
+          q2 += y[u] * y[u];
+        }
+        st(row, y);
+        q2 = group_sum(q2, G);
+        if (lane == 0) {
+          nrm[row] = q2;
+          dd[row] = T(1);
+        }
+      }
+    }
+    __syncthreads();
+  };
+  for (int i = tid; i < m; i += PEPS_NT) dd[i] = T(1);
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    fold();
+    if (tid == 0) sflag[0] = 0;
+    __syncthreads();
+    for (int b = npairs; b >= 1; b >>= 1) {
+      const int i = pi & (b - 1);
+      const int base = 2 * (pi - i);  // first row of this group's block
+      const int rr = base + i;        // resident row
+      T yr[NC];
+      T dr = 1, ar = 0;
+      if (grp) {
+        ld(rr, yr);
+        dr = dd[rr];
+        ar = nrm[rr];
+      }
+      bool moved = false;
+      for (int k = 0; k < b; ++k) {
+        const int q = base + b + ((i + k) & (b - 1));
+        T yq[NC];
+        T c = 0, dq = 1, bq = 0;
+        if (grp) {
+          ld(q, yq);
+          dq = dd[q];
+          bq = nrm[q];
+#pragma unroll
+          for (int u = 0; u < NC; ++u) c += yr[u] * yq[u];
+        }
+        c = group_sum(c, G) * (dr * dq);
+        if (grp && c != T(0) && c * c > tol * tol * (ar * bq)) {
+          T zeta, t, cs, idr, idq;
+          if constexpr (std::is_same<T, float>::value) {
+            // hardware reciprocal and reciprocal square root (1 ulp): the
+            // rotation only needs to be orthogonal to rounding
+            zeta = (bq - ar) * (0.5f * __builtin_amdgcn_rcpf(c));
+            const float az = fabsf(zeta);
+            if (az > 1.f / Eps<float>::v) t = 0.5f * __builtin_amdgcn_rcpf(zeta);
+            else
+              t = copysignf(__builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + zeta * zeta)),
+                            zeta);
+            cs = __builtin_amdgcn_rsqf(1.f + t * t);
+            idr = __builtin_amdgcn_rcpf(dr);
+            idq = __builtin_amdgcn_rcpf(dq);
+          } else {
+            zeta = (bq - ar) / (T(2) * c);
+            const T az = fabs(zeta);
+            if (az > T(1) / Eps<T>::v) t = T(0.5) / zeta;
+            else t = (zeta >= T(0) ? T(1) : T(-1)) / (az + sqrt(T(1) + zeta * zeta));
+            cs = T(1) / sqrt(T(1) + t * t);
+            idr = T(1) / dr;
+            idq = T(1) / dq;
+          }
+          const T t1 = t * dq * idr, t2 = t * dr * idq;
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            const T yp = yr[u];
+            yr[u] = yp - t1 * yq[u];
+            yq[u] = yq[u] + t2 * yp;
+          }
+          st(q, yq);
+          dr *= cs;
+          ar -= t * c;
+          moved = true;
+          if (lane == 0) {
+            sflag[0] = 1;
+            dd[q] = dq * cs;
+            nrm[q] = bq + t * c;
+          }
+        }
+        __syncthreads();
+      }
+      if (moved) {
+        st(rr, yr);
+        if (lane == 0) {
+          dd[rr] = dr;
+          nrm[rr] = ar;
+        }
+      }
+      __syncthreads();
+    }
+    const int f = sflag[0];
+    __syncthreads();
+    if (f == 0) return sweep + 1;
+  }
+  fold();
+  return -1;
+}
+
 // The same sweep for rows too long to hold in registers (nc > 32): each lane
 // strides over the row twice, once for the dot product and once to rotate.
 template <typename T>
@@ -767,6 +927,15 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, typename RealOf<T>::type
   int G = 64;
   while (G > 1 && G * npairs > PEPS_NT) G >>= 1;
   const int nc = (n + G - 1) / G;
+  // FP32 rows (FP32 and BF16 modes) take the block order with scaled
+  // rotations; in FP64 its two extra divisions per rotation cost more than
+  // the LDS traffic it saves
+  if constexpr (std::is_same<T, float>::value) {
+    if (m >= 4 && m <= 64 && (m & (m - 1)) == 0) {
+      if (nc <= 4) return jacobi_rows_blk<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+      if (nc <= 8) return jacobi_rows_blk<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
+    }
+  }
   if (nc <= 1) return jacobi_rows_nc<T, 1>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
   if (nc <= 2) return jacobi_rows_nc<T, 2>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
   if (nc <= 4) return jacobi_rows_nc<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
