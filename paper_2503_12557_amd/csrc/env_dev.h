@@ -65,17 +65,16 @@ __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
 }
 
 // ---------------------------------------------------------------------------
-// Left-sweep tree QR for FP32 / BF16 with chi*D <= 64 and D <= 4 (four
-// waves). Lane c of a wave holds column c of a 64-row block in registers.
-// A block [t; u], t upper triangular in LDS (packed by rows, 64 columns) and
-// u dense in registers, is reduced to one triangular factor by Householder
-// reflectors whose vectors are broadcast across the wave with readlane, so
-// no workgroup barrier is needed inside a factorisation. Wave k builds
-// M_k = R_{y-1} P_k in registers and eliminates it into a zero t; the waves
-// then merge their factors pairwise (a reduction tree of QR factorisations).
+// Left-sweep QR on registers for FP32 / BF16 with chi*D <= 64 and D <= 4
+// (four waves). Wave k builds the block M_k = R_{y-1} P_k of the stack
+// [M_0; ...; M_{D-1}] with lane c holding column c (64 rows) in registers;
+// the four waves then run one Householder QR of the whole stack together,
+// exchanging only partial dot products through LDS.
 // ---------------------------------------------------------------------------
 #define TQ_N 64
 #define TQ_PACK (TQ_N * (TQ_N + 1) / 2)
+// partial dot products of the four waves, double buffered
+#define TQ_XCH (2 * 4 * TQ_N)
 
 __host__ __device__ inline bool tsqr_path(int mode, int bmax, int D) {
   return (mode == MODE_F32 || mode == MODE_BF16) && bmax * D <= TQ_N && D <= 4;
@@ -88,8 +87,9 @@ __host__ __device__ inline size_t env_big_elems(int bmax, int D, int mode) {
   const size_t BD = (size_t)bmax * D;
   const size_t head = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
   size_t rest = BD * BD + 2 * BD * (BD + 4) + 2 * BD * bmax;
-  // the tree QR keeps four packed factors and the dense previous R from P on
-  const size_t tq = 4 * (size_t)TQ_PACK + (size_t)TQ_N * TQ_N;
+  // the register QR keeps the packed factor, its exchange buffer and the
+  // dense previous R from P on
+  const size_t tq = (size_t)TQ_PACK + TQ_XCH + (size_t)TQ_N * TQ_N;
   if (tsqr_path(mode, bmax, D) && rest < tq) rest = tq;
   return head + rest;
 }
@@ -106,81 +106,36 @@ __device__ __forceinline__ float bcast_lane(float v, int l) {
 // start of row j in a packed upper-triangular TQ_N x TQ_N matrix (by rows)
 __host__ __device__ __forceinline__ int prow(int j) { return j * TQ_N - (j * (j - 1)) / 2; }
 
-// Eliminate u (lane c < n holds column c of 64 rows) into t (packed rows,
-// this wave's LDS slot); on exit t is the triangular factor of [t; u].
-// kmax = min(n, rows of t + rows of u): later columns hold only rounding
-// residue, which is dropped rather than reflected (as in LAPACK's larfg, a
-// column whose norm is below the normal range is left alone).
-__device__ void wave_merge(float* t, float (&u)[TQ_N], int n, int kmax) {
-  const int c = threadIdx.x & 63;
-  for (int j = 0; j < kmax; ++j) {
-    float v[TQ_N];
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-#pragma unroll
-    for (int i = 0; i < TQ_N; i += 4) {
-      v[i] = bcast_lane(u[i], j);
-      v[i + 1] = bcast_lane(u[i + 1], j);
-      v[i + 2] = bcast_lane(u[i + 2], j);
-      v[i + 3] = bcast_lane(u[i + 3], j);
-      s0 = fmaf(v[i], v[i], s0);
-      s1 = fmaf(v[i + 1], v[i + 1], s1);
-      s2 = fmaf(v[i + 2], v[i + 2], s2);
-      s3 = fmaf(v[i + 3], v[i + 3], s3);
-    }
-    const float s = (s0 + s1) + (s2 + s3);
-    if (!(s > 1e-36f)) continue;  // column j of u is already zero
-    float* trow = t + prow(j) - j;  // trow[c] = t[j][c] for c >= j
-    const float ajj = trow[j];
-    const float nr = sqrtf(ajj * ajj + s);
-    const float alpha = ajj > 0.f ? -nr : nr;
-    const float v0 = ajj - alpha;
-    const float tau = 2.f / (v0 * v0 + s);
-    const bool own = c >= j && c < n;
-    const float tj = own ? trow[c] : 0.f;
-    float d0 = v0 * tj, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-#pragma unroll
-    for (int i = 0; i < TQ_N; i += 4) {
-      d0 = fmaf(v[i], u[i], d0);
-      d1 = fmaf(v[i + 1], u[i + 1], d1);
-      d2 = fmaf(v[i + 2], u[i + 2], d2);
-      d3 = fmaf(v[i + 3], u[i + 3], d3);
-    }
-    const float w = tau * ((d0 + d1) + (d2 + d3));
-    if (own) trow[c] = tj - v0 * w;
-#pragma unroll
-    for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(-v[i], w, u[i]);
-  }
-}
-
-// One site of the left sweep on the tree-QR path: from the previous factor
-// Rpk (LDS, dense 64 x 64 column-major, zero below the diagonal and outside
-// kprev x Pl) and the site's
-// E and A in LDS, leave R_y in slot 0 (packed rows). slots: 4 packed
-// factors of TQ_PACK elements.
+// One site of the left sweep on the register path. Each wave k < Dout
+// forms its block M_k = R_{y-1} P_k (R_{y-1}: Rpk, dense 64 x 64
+// column-major, zero below the diagonal and outside kprev x Pl; P_k from E
+// and A in LDS), then the stack is factorised by Householder QR of
+// [0; stack]: reflector j maps (0, column j) to (sqrt(s), 0), s the squared
+// norm of column j, so its vector is (-sqrt(s), column j) and tau = 1/s.
+// Per column each wave forms the dot products of column j (broadcast from
+// lane j) with all of its columns; the four partial sums meet in LDS (xch)
+// behind one barrier, and each wave updates its block. Row j of the factor
+// is sqrt(s) times the dot products over s. On exit t (packed rows, LDS)
+// holds R_y. Columns j >= min(Pr, kprev * Dout) hold only rounding residue
+// and are not reflected, nor is a column whose squared norm is below the
+// normal range (as in LAPACK's larfg).
 template <int M>
-__device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk, float* slots,
-                          int kprev, int bl, int br, int Dl, int Dr, int Din, int Dout, int s_l,
-                          int s_r, int s_in, int s_out) {
+__device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk, float* t,
+                          float* xch, int kprev, int bl, int br, int Dl, int Dr, int Din,
+                          int Dout, int s_l, int s_r, int s_in, int s_out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int Pl = bl * Dl, Pr = br * Dr;
-  // rows of the factor of the blocks [w0, w0 + span)
-  auto rows = [&](int w0, int span) {
-    const int e = w0 + span < Dout ? w0 + span : Dout;
-    const int k = kprev * (e - w0);
-    return k < Pr ? k : Pr;
-  };
-  if (wv < Dout) {
-    float* t = slots + wv * TQ_PACK;
-    for (int i = lane; i < TQ_PACK; i += 64) t[i] = 0.f;
+  const bool blk = wv < Dout;
+  for (int i = threadIdx.x; i < TQ_PACK; i += PEPS_NT) t[i] = 0.f;
+  float u[TQ_N];
+#pragma unroll
+  for (int i = 0; i < TQ_N; ++i) u[i] = 0.f;
+  if (blk) {
     // u = R_{y-1} P_k for column c = (b, r) of P_k, with
-    // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k] formed row by row;
-    // R_{y-1} is dense column-major in LDS (zeros below the diagonal)
+    // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k] formed row by row
     const int c = lane;
     const bool colok = c < Pr;
     const int b = colok ? c / Dr : 0, r = colok ? c - (c / Dr) * Dr : 0;
-    float u[TQ_N];
-#pragma unroll
-    for (int i = 0; i < TQ_N; ++i) u[i] = 0.f;
     for (int l = 0; l < Pl; ++l) {
       float pl = 0.f;
       if (colok) {
@@ -194,18 +149,36 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
 #pragma unroll
       for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(opnd<M>(col[i]), pl, u[i]);
     }
-    wave_merge(t, u, Pr, rows(wv, 1));
   }
-  // pairwise merges: wave w takes the factor of wave w + step
-  for (int step = 1; step < Dout; step *= 2) {
-    __syncthreads();
-    if ((wv % (2 * step)) == 0 && wv + step < Dout) {
-      const float* tp = slots + (wv + step) * TQ_PACK;
-      float u[TQ_N];
+  const int kmax = min(Pr, kprev * Dout);
+  for (int j = 0; j < kmax; ++j) {
+    float v[TQ_N];
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+    if (blk) {
 #pragma unroll
-      for (int i = 0; i < TQ_N; ++i) u[i] = (i <= lane) ? tp[prow(i) - i + lane] : 0.f;
-      const int k2 = rows(wv, step) + rows(wv + step, step);
-      wave_merge(slots + wv * TQ_PACK, u, Pr, k2 < Pr ? k2 : Pr);
+      for (int i = 0; i < TQ_N; i += 4) {
+        v[i] = bcast_lane(u[i], j);
+        v[i + 1] = bcast_lane(u[i + 1], j);
+        v[i + 2] = bcast_lane(u[i + 2], j);
+        v[i + 3] = bcast_lane(u[i + 3], j);
+        d0 = fmaf(v[i], u[i], d0);
+        d1 = fmaf(v[i + 1], u[i + 1], d1);
+        d2 = fmaf(v[i + 2], u[i + 2], d2);
+        d3 = fmaf(v[i + 3], u[i + 3], d3);
+      }
+    }
+    float* xb = xch + (j & 1) * (4 * TQ_N);
+    xb[wv * TQ_N + lane] = (d0 + d1) + (d2 + d3);
+    __syncthreads();
+    // the same sums in every wave: s decides uniformly
+    const float dc = (xb[lane] + xb[TQ_N + lane]) + (xb[2 * TQ_N + lane] + xb[3 * TQ_N + lane]);
+    const float s = (xb[j] + xb[TQ_N + j]) + (xb[2 * TQ_N + j] + xb[3 * TQ_N + j]);
+    if (!(s > 1e-36f)) continue;  // column j is already zero
+    const float w = dc * (1.f / s);
+    if (wv == 0 && lane >= j && lane < Pr) t[prow(j) - j + lane] = sqrtf(s) * w;
+    if (blk) {
+#pragma unroll
+      for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(-v[i], w, u[i]);
     }
   }
   __syncthreads();
@@ -304,8 +277,8 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
     if constexpr (M == MODE_F32 || M == MODE_BF16) {
       tree = tsqr_path(M, L.bmax, L.D) && PEPS_NT == 256;
       if (tree) {
-        // R_{-1} = [1], dense column-major after the four factor slots
-        float* Rpk = P + 4 * TQ_PACK;
+        // R_{-1} = [1], dense column-major after the factor and exchange buffer
+        float* Rpk = P + TQ_PACK + TQ_XCH;
         for (int i = tid; i < TQ_N * TQ_N; i += PEPS_NT) Rpk[i] = i == 0 ? 1.f : 0.f;
       }
     }
@@ -321,9 +294,9 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       __syncthreads();
       if constexpr (M == MODE_F32 || M == MODE_BF16) {
         if (tree) {
-          float* Rpk = P + 4 * TQ_PACK;
-          tsqr_site<M>(Ebuf, Abuf, Rpk, P, kprev, bl, br, v.Dl, v.Dr, v.Din, v.Dout, v.s_l,
-                       v.s_r, v.s_in, v.s_out);
+          float* Rpk = P + TQ_PACK + TQ_XCH;
+          tsqr_site<M>(Ebuf, Abuf, Rpk, P, P + TQ_PACK, kprev, bl, br, v.Dl, v.Dr, v.Din,
+                       v.Dout, v.s_l, v.s_r, v.s_in, v.s_out);
           const int kr = min(kprev * v.Dout, Pr);
           // R_y at unit scale (see below) to global rows and to Rpk
           const float* t0 = P;
