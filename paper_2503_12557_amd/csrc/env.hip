@@ -39,7 +39,7 @@ k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* 
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* big = GM ? gws + ((size_t)smp * 2 + blockIdx.y) * slab : lds;
   T* small = GM ? lds : lds + env_big_elems(L.bmax, L.D, M);
-  const EnvSmem<T> sh(big, small, L);
+  const EnvSmem<T> sh(big, small, L, tsqr_path(M, L.bmax, L.D) && PEPS_NT == 256);
   const int BD = L.bmax * L.D;
   __shared__ int sflag[2], fl;
   __shared__ int sel[256];

@@ -87,10 +87,14 @@ __host__ __device__ inline size_t env_big_elems(int bmax, int D, int mode) {
   const size_t BD = (size_t)bmax * D;
   const size_t head = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
   size_t rest = BD * BD + 2 * BD * (BD + 4) + 2 * BD * bmax;
-  // the register QR keeps the packed factor, its exchange buffer and the
-  // dense previous R from P on
-  const size_t tq = (size_t)TQ_PACK + TQ_XCH + (size_t)TQ_N * TQ_N;
-  if (tsqr_path(mode, bmax, D) && rest < tq) rest = tq;
+  if (tsqr_path(mode, bmax, D)) {
+    // register-QR path (launched with 256 threads): the left sweep keeps
+    // the packed factor, its exchange buffer and the dense previous R from
+    // P on, and the right sweep's C overlays T1 (dead once Z is formed)
+    const size_t tq = (size_t)TQ_PACK + TQ_XCH + (size_t)TQ_N * TQ_N;
+    rest = 2 * BD * (BD + 4) + 2 * BD * bmax;
+    if (rest < tq) rest = tq;
+  }
   return head + rest;
 }
 __host__ __device__ inline size_t env_small_elems(int bmax, int D) {
@@ -152,19 +156,14 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
   }
   const int kmax = min(Pr, kprev * Dout);
   for (int j = 0; j < kmax; ++j) {
-    float v[TQ_N];
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
     if (blk) {
 #pragma unroll
       for (int i = 0; i < TQ_N; i += 4) {
-        v[i] = bcast_lane(u[i], j);
-        v[i + 1] = bcast_lane(u[i + 1], j);
-        v[i + 2] = bcast_lane(u[i + 2], j);
-        v[i + 3] = bcast_lane(u[i + 3], j);
-        d0 = fmaf(v[i], u[i], d0);
-        d1 = fmaf(v[i + 1], u[i + 1], d1);
-        d2 = fmaf(v[i + 2], u[i + 2], d2);
-        d3 = fmaf(v[i + 3], u[i + 3], d3);
+        d0 = fmaf(bcast_lane(u[i], j), u[i], d0);
+        d1 = fmaf(bcast_lane(u[i + 1], j), u[i + 1], d1);
+        d2 = fmaf(bcast_lane(u[i + 2], j), u[i + 2], d2);
+        d3 = fmaf(bcast_lane(u[i + 3], j), u[i + 3], d3);
       }
     }
     float* xb = xch + (j & 1) * (4 * TQ_N);
@@ -177,8 +176,13 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
     const float w = dc * (1.f / s);
     if (wv == 0 && lane >= j && lane < Pr) t[prow(j) - j + lane] = sqrtf(s) * w;
     if (blk) {
+      // broadcast column j again rather than keep 64 values live across
+      // the barrier (the empty asm hides that the lane index is unchanged,
+      // so the two broadcasts are not merged)
+      int jj = j;
+      asm volatile("" : "+s"(jj));
 #pragma unroll
-      for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(-v[i], w, u[i]);
+      for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(-bcast_lane(u[i], jj), w, u[i]);
     }
   }
   __syncthreads();
@@ -188,14 +192,16 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
 template <typename T>
 struct EnvSmem {
   T *Ebuf, *Abuf, *P, *S, *Z, *W, *Bn, *vv, *ww, *sig, *red;
-  __device__ EnvSmem(T* big, T* small, const Lattice& L) {
+  // overlay: the register-QR path, whose left sweep needs no S, so the
+  // right sweep's C can take T1's place
+  __device__ EnvSmem(T* big, T* small, const Lattice& L, bool overlay) {
     const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
     Ebuf = big;
     Abuf = Ebuf + B * D * B;
     P = Abuf + D * D * D * D;   // P_k (left) / T1 (right)
     // stacked QR buffer (left) / C then Z (right); rows padded so rows of
     // the LDS matrices fall on different banks
-    S = P + BD * BD;
+    S = overlay ? P : P + BD * BD;
     Z = S + BD * (BD + 4);
     W = S + 2 * BD * (BD + 4);
     Bn = W + BD * B;
@@ -256,7 +262,8 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
   const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
   T *Ebuf = sh.Ebuf, *Abuf = sh.Abuf, *P = sh.P, *S = sh.S, *Z = sh.Z, *W = sh.W, *Bn = sh.Bn;
   T* red = sh.red;
-  Rl* vv = reinterpret_cast<Rl*>(sh.vv);    // row norms of the Jacobi
+  // row norms and scales of the Jacobi: 3 BD reals (vv and ww after it)
+  Rl* vv = reinterpret_cast<Rl*>(sh.vv);
   Rl* sig = reinterpret_cast<Rl*>(sh.sig);  // singular values
   Rl* rred = reinterpret_cast<Rl*>(sh.red);
   int& fl = *flp;

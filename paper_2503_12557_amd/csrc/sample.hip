@@ -60,7 +60,7 @@ k_metropolis(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T*
   const int bd3 = B * D * D * D;
   T* sm = GM ? gws + (size_t)chain * slab : lds;
   T* small = GM ? lds : lds + sample_big(B, D, M);
-  const EnvSmem<T> sh(sm, small, L);
+  const EnvSmem<T> sh(sm, small, L, tsqr_path(M, L.bmax, L.D) && PEPS_NT == 256);
   // strip buffers alias the environment buffers (used in different phases)
   // one-row pass: Lf | Lt | Lt2 (box each) | X1 | X2 (BD^2 each)
   T* Lf = sm;
