@@ -217,10 +217,14 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   }
 }
 
+// Lf | Lt | Lt2 (partials) | X1 = X3 | X2 (chunk intermediates) | Us | Bs
+// (environments) | A1s | A2s (site tensors): every operand of a step is
+// staged on chip, so its contractions read LDS only
 static size_t strip2_big(int bmax, int D) {
   const size_t B2D2 = (size_t)bmax * bmax * D * D;
   const size_t BD3 = (size_t)bmax * D * D * D;
-  return 3 * B2D2 + 3 * S2G * BD3;
+  const size_t box = (size_t)bmax * D * bmax;
+  return 3 * B2D2 + 2 * S2G * BD3 + 2 * box + 2 * (size_t)D * D * D * D;
 }
 size_t strip2_lds_elems(int bmax, int D) { return strip2_big(bmax, D) + 16; }
 
@@ -239,14 +243,19 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   const int B = L.bmax, D = L.D;
   const int box2 = B * B * D * D;
   const int bd3 = B * D * D * D;
+  const int box = B * D * B;
   T* sm = GM ? gws + ((size_t)smp * gridDim.y + x) * slab : lds;
   T* Lf = sm;
   T* Lt = Lf + box2;
   T* Lt2 = Lt + box2;
+  // X3 of a chunk is formed after X1 is consumed and takes its place
   T* X1 = Lt2 + box2;
   T* X2 = X1 + S2G * bd3;
-  T* X3 = X2 + S2G * bd3;
-  T* red = GM ? lds : X3 + S2G * bd3;
+  T* Us = X2 + S2G * bd3;
+  T* Bs = Us + box;
+  T* A1s = Bs + box;
+  T* A2s = A1s + D * D * D * D;
+  T* red = GM ? lds : A2s + D * D * D * D;
   __shared__ T one[1];
   __shared__ int fl;
   if (tid == 0) {
@@ -279,29 +288,56 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   auto ub_ = [&](int y) { return has_up ? ed[(su * L.Ly + y) * 3 + 2] : 1; };
   auto ba_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 0] : 1; };
   auto bb_ = [&](int y) { return has_dn ? ed[(sd * L.Ly + y) * 3 + 2] : 1; };
+  // the operands of the step at column y (site tensors with physical
+  // indices p1, p2) to Us, Bs, A1s, A2s
+  auto stage = [&](int y, int p1, int p2) {
+    const int a1 = x * L.Ly + y, a2 = a1 + L.Ly;
+    const T* u = upT(y);
+    const T* bt = dnT(y);
+    const T* t1 = tensor_of(theta, tab, L, a1, p1);
+    const T* t2 = tensor_of(theta, tab, L, a2, p2);
+    const int nu = ua_(y) * uk_(y) * ub_(y);
+    const int nb = ba_(y) * tab[L.off_legs + 4 * a2 + 3] * bb_(y);
+    const int n1 = tab[L.off_block + a1], n2 = tab[L.off_block + a2];
+    for (int i = tid; i < nu; i += PEPS_NT) Us[i] = u[i];
+    for (int i = tid; i < nb; i += PEPS_NT) Bs[i] = bt[i];
+    for (int i = tid; i < n1; i += PEPS_NT) A1s[i] = t1[i];
+    for (int i = tid; i < n2; i += PEPS_NT) A2s[i] = t2[i];
+    __syncthreads();
+  };
 
-  // right partials at unit scale, powers of two in dex[y] (as in k_strip1)
+  // right partials at unit scale, powers of two in dex[y] (as in k_strip1);
+  // the running partial stays in LDS (Lt / Lt2) and each one is also kept
+  // in global scratch for the ratio windows
   __shared__ int dex[32];
   T* RtL = Rt + (size_t)L.Ly * box2;
-  if (tid == 0) RtL[0] = T(1);
+  if (tid == 0) {
+    RtL[0] = T(1);
+    Lt[0] = T(1);
+  }
   __syncthreads();
+  T* rcur = Lt;
+  T* rnxt = Lt2;
   for (int y = L.Ly - 1; y >= 0; --y) {
     const int n1 = x * L.Ly + y, n2 = n1 + L.Ly;
     int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
     legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
-    T* Ry = Rt + (size_t)y * box2;
-    s2_step_right<M>(Rt + (size_t)(y + 1) * box2, upT(y), ua_(y), uk_(y), ub_(y),
-                     tensor_of(theta, tab, L, n1, pbit(s[n1])), Dl1, Dr1, Dd1,
-                     tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2, dnT(y), ba_(y),
-                     bb_(y), X1, X2, X3, Ry);
+    stage(y, pbit(s[n1]), pbit(s[n2]));
+    s2_step_right<M>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
+                     Bs, ba_(y), bb_(y), X1, X2, X1, rnxt);
     const int cnt = ua_(y) * Dl1 * Dl2 * ba_(y);
-    const int e = pow2_exponent((double)block_absmax(Ry, 1, cnt, cnt, red));
-    scale_pow2(Ry, cnt, e);
+    const int e = pow2_exponent((double)block_absmax(rnxt, 1, cnt, cnt, red));
+    scale_pow2(rnxt, cnt, e);
     if (tid == 0) dex[y] = e;
     __syncthreads();
+    T* Ry = Rt + (size_t)y * box2;
+    for (int i = tid; i < cnt; i += PEPS_NT) Ry[i] = rnxt[i];
+    T* tmp = rcur;
+    rcur = rnxt;
+    rnxt = tmp;
   }
-  const T psi2 = Rt[0];
+  const T psi2 = rcur[0];
   if (tid == 0 && (psi2 == T(0) || !finitex(psi2))) fl |= (psi2 == T(0)) ? 1 : 2;
 
   int mi = m0;
@@ -333,9 +369,9 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           legs_of(tab, L, a2, Dl2, Dr2, Du2, Dd2);
           const int p1 = in_move(mv, a1) ? 1 - pbit(s[a1]) : pbit(s[a1]);
           const int p2 = in_move(mv, a2) ? 1 - pbit(s[a2]) : pbit(s[a2]);
-          s2_step_left<M>(cur, upT(yy), ua_(yy), uk_(yy), ub_(yy), tensor_of(theta, tab, L, a1, p1),
-                          Dl1, Dr1, Dd1, tensor_of(theta, tab, L, a2, p2), Dl2, Dr2, Dd2, dnT(yy),
-                          ba_(yy), bb_(yy), X1, X2, X3, nxt);
+          stage(yy, p1, p2);
+          s2_step_left<M>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2,
+                          Dd2, Bs, ba_(yy), bb_(yy), X1, X2, X1, nxt);
           scale_pow2(nxt, ub_(yy) * Dr1 * Dr2 * bb_(yy), dex[yy]);
           __syncthreads();
           cur = nxt;
@@ -358,9 +394,9 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     int Dl1, Dr1, Du1, Dd1, Dl2, Dr2, Du2, Dd2;
     legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
-    s2_step_left<M>(Lf, upT(y), ua_(y), uk_(y), ub_(y), tensor_of(theta, tab, L, n1, pbit(s[n1])),
-                    Dl1, Dr1, Dd1, tensor_of(theta, tab, L, n2, pbit(s[n2])), Dl2, Dr2, Dd2,
-                    dnT(y), ba_(y), bb_(y), X1, X2, X3, Lt);
+    stage(y, pbit(s[n1]), pbit(s[n2]));
+    s2_step_left<M>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2, Bs,
+                    ba_(y), bb_(y), X1, X2, X1, Lt);
     const int cnt = ub_(y) * Dr1 * Dr2 * bb_(y);
     {
       typedef typename RealOf<T>::type R;
