@@ -510,7 +510,7 @@ __device__ void house_qr_stacked(T* A, int kr, int m, int n, int lda,
 // to relative tolerance tol. Pairs follow the circle (round-robin) schedule,
 // m-1 rounds of m/2 disjoint pairs per sweep; each pair is held by G lanes,
 // each lane keeping its NC elements of both rows in registers between the
-// dot products and the rotation. sflag: LDS int; nrm: 3m reals of LDS.
+// dot products and the rotation. sflag: LDS int; nrm: 2m reals of LDS.
 // Returns the number of sweeps used, or -1 if max_sweeps was reached.
 // ---------------------------------------------------------------------------
 // NC contiguous elements through 16-byte LDS accesses (caller checks alignment)
@@ -689,17 +689,14 @@ __device__ int jacobi_rows_nc(T* X, int m, int n, int ldx, typename RealOf<T>::t
 // one multiply-add per element instead of two. c >= 2^-1/2 and a row meets
 // m-1 <= 63 partners per sweep, so a scale stays above 2^-32; the scales are
 // folded back into the rows at the start of every sweep and on exit.
-// The reciprocal scales are carried along (1/c = (1 + t^2) c), and t comes
-// from t = sgn(b - a) 2 g / (|b - a| + sqrt((b - a)^2 + 4 g^2)) (a, b the
-// squared norms, g the inner product): three transcendental operations per
-// rotation. nrm holds 3m reals: the squared norms of X, the scales d and
-// their reciprocals.
+// t comes from t = sgn(b - a) 2 g / (|b - a| + sqrt((b - a)^2 + 4 g^2))
+// (a, b the squared norms, g the inner product). nrm holds 2m reals: the
+// squared norms of X, then the scales d.
 template <typename T, int NC>
 __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, int max_sweeps,
                                             int* sflag, int G, T* nrm) {
   static_assert(!IsCplx<T>::value, "scaled rotations are for real rows");
   T* dd = nrm + m;
-  T* ee = nrm + 2 * m;
   const int tid = threadIdx.x;
   const int npairs = m >> 1;
   const int pi = tid / G, lane = tid - (tid / G) * G;
@@ -746,16 +743,12 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
         if (lane == 0) {
           nrm[row] = q2;
           dd[row] = T(1);
-          ee[row] = T(1);
         }
       }
     }
     __syncthreads();
   };
-  for (int i = tid; i < m; i += PEPS_NT) {
-    dd[i] = T(1);
-    ee[i] = T(1);
-  }
+  for (int i = tid; i < m; i += PEPS_NT) dd[i] = T(1);
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     fold();
@@ -766,22 +759,20 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
       const int base = 2 * (pi - i);  // first row of this group's block
       const int rr = base + i;        // resident row
       T yr[NC];
-      T dr = 1, er = 1, ar = 0;
+      T dr = 1, ar = 0;
       if (grp) {
         ld(rr, yr);
         dr = dd[rr];
-        er = ee[rr];
         ar = nrm[rr];
       }
       bool moved = false;
       for (int k = 0; k < b; ++k) {
         const int q = base + b + ((i + k) & (b - 1));
         T yq[NC];
-        T c = 0, dq = 1, eq = 1, bq = 0;
+        T c = 0, dq = 1, bq = 0;
         if (grp) {
           ld(q, yq);
           dq = dd[q];
-          eq = ee[q];
           bq = nrm[q];
 #pragma unroll
           for (int u = 0; u < NC; ++u) c += yr[u] * yq[u];
@@ -789,21 +780,23 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
         c = group_sum(c, G) * (dr * dq);
         if (grp && c != T(0) && c * c > tol * tol * (ar * bq)) {
           const T dlt = bq - ar;
-          T t, cs, g;
+          T t, cs, idr, idq;
           if constexpr (std::is_same<T, float>::value) {
             // hardware reciprocal, square root and reciprocal square root
             // (1 ulp): the rotation only needs to be orthogonal to rounding
             const float h = __builtin_amdgcn_sqrtf(fmaf(dlt, dlt, 4.f * c * c));
             t = (dlt >= 0.f ? 2.f * c : -2.f * c) * __builtin_amdgcn_rcpf(fabsf(dlt) + h);
-            g = fmaf(t, t, 1.f);
-            cs = __builtin_amdgcn_rsqf(g);
+            cs = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+            idr = __builtin_amdgcn_rcpf(dr);
+            idq = __builtin_amdgcn_rcpf(dq);
           } else {
             const T h = sqrt(dlt * dlt + T(4) * c * c);
             t = (dlt >= T(0) ? T(2) * c : T(-2) * c) / (fabs(dlt) + h);
-            g = T(1) + t * t;
-            cs = T(1) / sqrt(g);
+            cs = T(1) / sqrt(T(1) + t * t);
+            idr = T(1) / dr;
+            idq = T(1) / dq;
           }
-          const T t1 = t * dq * er, t2 = t * dr * eq;
+          const T t1 = t * dq * idr, t2 = t * dr * idq;
 #pragma unroll
           for (int u = 0; u < NC; ++u) {
             const T yp = yr[u];
@@ -811,15 +804,12 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
             yq[u] = yq[u] + t2 * yp;
           }
           st(q, yq);
-          const T ics = g * cs;  // 1 / cs
           dr *= cs;
-          er *= ics;
           ar -= t * c;
           moved = true;
           if (lane == 0) {
             sflag[0] = 1;
             dd[q] = dq * cs;
-            ee[q] = eq * ics;
             nrm[q] = bq + t * c;
           }
         }
@@ -829,7 +819,6 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
         st(rr, yr);
         if (lane == 0) {
           dd[rr] = dr;
-          ee[rr] = er;
           nrm[rr] = ar;
         }
       }

@@ -262,7 +262,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
   const int B = L.bmax, D = L.D, BD = L.bmax * L.D;
   T *Ebuf = sh.Ebuf, *Abuf = sh.Abuf, *P = sh.P, *S = sh.S, *Z = sh.Z, *W = sh.W, *Bn = sh.Bn;
   T* red = sh.red;
-  // row norms and scales of the Jacobi: 3 BD reals (vv and ww after it)
+  // row norms and scales of the Jacobi (2 BD reals)
   Rl* vv = reinterpret_cast<Rl*>(sh.vv);
   Rl* sig = reinterpret_cast<Rl*>(sh.sig);  // singular values
   Rl* rred = reinterpret_cast<Rl*>(sh.red);
