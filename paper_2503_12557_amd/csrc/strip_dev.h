@@ -135,10 +135,226 @@ __device__ __forceinline__ bool in_move(const int* mv, int n) {
 // ---------------------------------------------------------------------------
 #define S2G 2
 
+// ---------------------------------------------------------------------------
+// FP32 / BF16 two-row steps for the bulk of a D = 4 lattice: the physical
+// legs that carry the inner products (up leg of the upper row, down legs of
+// both rows) have dimension 4, so every contraction keeps four outputs per
+// thread and reads its operands as 16-byte vectors. Same contractions, same
+// chunking and buffers as the general steps below; each sum runs over its
+// index in the same order, only its partial sums are grouped differently.
+// Every operand (partials, staged environments and tensors, chunk
+// intermediates) must be 16-byte aligned.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+template <int M>
+__device__ __forceinline__ float4 op4(float4 v) {
+  return make_float4(opnd<M>(v.x), opnd<M>(v.y), opnd<M>(v.z), opnd<M>(v.w));
+}
+__device__ __forceinline__ void fma4(float4& acc, float w, float4 v) {
+  acc.x = fmaf(w, v.x, acc.x);
+  acc.y = fmaf(w, v.y, acc.y);
+  acc.z = fmaf(w, v.z, acc.z);
+  acc.w = fmaf(w, v.w, acc.w);
+}
+
+// left step with uk = Dd1 = Dd2 = 4 and Dl1 Dl2 ba a multiple of 4
+template <int M>
+__device__ __forceinline__ void s2_step_left_f4(const float* Lp, const float* U, int ua, int ub, const float* A1,
+                                int Dl1, int Dr1, const float* A2, int Dl2, int Dr2,
+                                const float* Bt, int ba, int bb, float* X1, float* X2, float* X3,
+                                float* Lout) {
+  const int tid = threadIdx.x;
+  const int inner = Dl1 * Dl2 * ba;
+  const int n1 = inner * 4, n2 = Dl2 * ba * Dr1 * 4, n3 = Dr1 * Dr2 * ba * 4;
+  const int q1 = inner >> 2, K4 = ba * 4, nrs = Dr1 * Dr2;
+  const FastDiv fq1(q1), fDr1(Dr1), fDr2(Dr2), fba(ba), fDl2(Dl2), fbb(bb), fnrs(nrs);
+  for (int b0 = 0; b0 < ub; b0 += S2G) {
+    const int nb = ub - b0 < S2G ? ub - b0 : S2G;
+    // X1[g][row][u] = sum_a L[a][row] U[a][u][b0+g]: four rows per thread
+    for (int task = tid; task < nb * inner; task += PEPS_NT) {
+      const int u = task & 3;
+      int q = task >> 2;
+      const int rq = divmod(q, fq1);
+      const int g = q;
+      const float* lp = Lp + rq * 4;
+      const float* up = U + u * ub + b0 + g;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 4
+      for (int a = 0; a < ua; ++a) fma4(acc, opnd<M>(up[a * 4 * ub]), op4<M>(ld4(lp + a * inner)));
+      float* x1 = X1 + g * n1 + rq * 16 + u;
+      x1[0] = acc.x;
+      x1[4] = acc.y;
+      x1[8] = acc.z;
+      x1[12] = acc.w;
+    }
+    __syncthreads();
+    // X2[g][m2][c][r1][t] = sum_{m1,u} X1[g][m1][m2][c][u] A1[m1][r1][u][t]
+    for (int task = tid; task < nb * Dl2 * ba * Dr1; task += PEPS_NT) {
+      int q = task;
+      const int r1 = divmod(q, fDr1);
+      const int c = divmod(q, fba);
+      const int m2 = divmod(q, fDl2);
+      const int g = q;
+      const float* x1 = X1 + g * n1 + (m2 * ba + c) * 4;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 2
+      for (int m1 = 0; m1 < Dl1; ++m1) {
+        const float4 xv = op4<M>(ld4(x1 + m1 * Dl2 * ba * 4));
+        const float* ap = A1 + (m1 * Dr1 + r1) * 16;
+        fma4(acc, xv.x, op4<M>(ld4(ap)));
+        fma4(acc, xv.y, op4<M>(ld4(ap + 4)));
+        fma4(acc, xv.z, op4<M>(ld4(ap + 8)));
+        fma4(acc, xv.w, op4<M>(ld4(ap + 12)));
+      }
+      st4(X2 + g * n2 + ((m2 * ba + c) * Dr1 + r1) * 4, acc);
+    }
+    __syncthreads();
+    // X3[g][r1][s][c][d] = sum_{m2,t} X2[g][m2][c][r1][t] A2[m2][s][t][d]
+    for (int task = tid; task < nb * nrs * ba; task += PEPS_NT) {
+      int q = task;
+      const int c = divmod(q, fba);
+      const int sx = divmod(q, fDr2);
+      const int r1 = divmod(q, fDr1);
+      const int g = q;
+      const float* x2 = X2 + g * n2 + (c * Dr1 + r1) * 4;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 2
+      for (int m2 = 0; m2 < Dl2; ++m2) {
+        const float4 xv = op4<M>(ld4(x2 + m2 * ba * Dr1 * 4));
+        const float* ap = A2 + (m2 * Dr2 + sx) * 16;
+        fma4(acc, xv.x, op4<M>(ld4(ap)));
+        fma4(acc, xv.y, op4<M>(ld4(ap + 4)));
+        fma4(acc, xv.z, op4<M>(ld4(ap + 8)));
+        fma4(acc, xv.w, op4<M>(ld4(ap + 12)));
+      }
+      st4(X3 + g * n3 + ((r1 * Dr2 + sx) * ba + c) * 4, acc);
+    }
+    __syncthreads();
+    // L'[b0+g][r1 s][e] = sum_{(c,d)} X3[g][r1 s][(c,d)] B[(c,d)][e]
+    for (int task = tid; task < nb * nrs * bb; task += PEPS_NT) {
+      int q = task;
+      const int e = divmod(q, fbb);
+      const int rs = divmod(q, fnrs);
+      const int g = q;
+      const float* x3 = X3 + g * n3 + rs * K4;
+      const float* bp = Bt + e;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll 2
+      for (int k = 0; k < K4; k += 4) {
+        const float4 xv = op4<M>(ld4(x3 + k));
+        s0 = fmaf(xv.x, opnd<M>(bp[k * bb]), s0);
+        s1 = fmaf(xv.y, opnd<M>(bp[(k + 1) * bb]), s1);
+        s2 = fmaf(xv.z, opnd<M>(bp[(k + 2) * bb]), s2);
+        s3 = fmaf(xv.w, opnd<M>(bp[(k + 3) * bb]), s3);
+      }
+      Lout[((b0 + g) * nrs + rs) * bb + e] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
+  }
+}
+
+// right step with uk = Dd1 = Dd2 = 4 and bb a multiple of 4
+template <int M>
+__device__ __forceinline__ void s2_step_right_f4(const float* Rp, const float* U, int ua, int ub, const float* A1,
+                                 int Dl1, int Dr1, const float* A2, int Dl2, int Dr2,
+                                 const float* Bt, int ba, int bb, float* Y1, float* Y2, float* Y3,
+                                 float* Rout) {
+  const int tid = threadIdx.x;
+  const int rw = Dr1 * Dr2 * bb;
+  const int n1 = 4 * rw, n2 = Dl1 * 4 * Dr2 * bb, n3 = Dl1 * Dl2 * 4 * bb;
+  const int q1 = rw >> 2, eq = bb >> 2, K = 4 * bb, nrow = Dl1 * Dl2;
+  const FastDiv fq1(q1), feq(eq), fDr2(Dr2), fDl1(Dl1), fDl2(Dl2), fba(ba), fnrow(nrow);
+  for (int a0 = 0; a0 < ua; a0 += S2G) {
+    const int na = ua - a0 < S2G ? ua - a0 : S2G;
+    // Y1[g][u][(r1,s,e)] = sum_b U[a0+g][u][b] R[b][(r1,s,e)]: four columns per thread
+    for (int task = tid; task < na * 4 * q1; task += PEPS_NT) {
+      int q = task;
+      const int cq = divmod(q, fq1);
+      const int u = q & 3;
+      const int g = q >> 2;
+      const float* up = U + ((a0 + g) * 4 + u) * ub;
+      const float* rp = Rp + cq * 4;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 4
+      for (int b = 0; b < ub; ++b) fma4(acc, opnd<M>(up[b]), op4<M>(ld4(rp + b * rw)));
+      st4(Y1 + g * n1 + u * rw + cq * 4, acc);
+    }
+    __syncthreads();
+    // Y2[g][m1][t][s][e] = sum_{u,r1} A1[m1][r1][u][t] Y1[g][u][r1][s][e]
+    for (int task = tid; task < na * Dl1 * 4 * Dr2 * eq; task += PEPS_NT) {
+      int q = task;
+      const int ei = divmod(q, feq);
+      const int sx = divmod(q, fDr2);
+      const int t = q & 3;
+      q >>= 2;
+      const int m1 = divmod(q, fDl1);
+      const int g = q;
+      const float* y1 = Y1 + g * n1 + sx * bb + ei * 4;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll 2
+        for (int r1 = 0; r1 < Dr1; ++r1)
+          fma4(acc, opnd<M>(A1[((m1 * Dr1 + r1) * 4 + u) * 4 + t]),
+               op4<M>(ld4(y1 + u * rw + r1 * Dr2 * bb)));
+      st4(Y2 + g * n2 + ((m1 * 4 + t) * Dr2 + sx) * bb + ei * 4, acc);
+    }
+    __syncthreads();
+    // Y3[g][m1][m2][d][e] = sum_{t,s} A2[m2][s][t][d] Y2[g][m1][t][s][e]
+    for (int task = tid; task < na * nrow * 4 * eq; task += PEPS_NT) {
+      int q = task;
+      const int ei = divmod(q, feq);
+      const int d = q & 3;
+      q >>= 2;
+      const int m2 = divmod(q, fDl2);
+      const int m1 = divmod(q, fDl1);
+      const int g = q;
+      const float* y2 = Y2 + g * n2 + m1 * 4 * Dr2 * bb + ei * 4;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int t = 0; t < 4; ++t)
+#pragma unroll 2
+        for (int sx = 0; sx < Dr2; ++sx)
+          fma4(acc, opnd<M>(A2[((m2 * Dr2 + sx) * 4 + t) * 4 + d]),
+               op4<M>(ld4(y2 + (t * Dr2 + sx) * bb)));
+      st4(Y3 + g * n3 + ((m1 * Dl2 + m2) * 4 + d) * bb + ei * 4, acc);
+    }
+    __syncthreads();
+    // R'[a0+g][(m1,m2)][c] = sum_{(d,e)} Y3[g][(m1,m2)][(d,e)] B[c][(d,e)]
+    for (int task = tid; task < na * nrow * ba; task += PEPS_NT) {
+      int q = task;
+      const int c = divmod(q, fba);
+      const int mm = divmod(q, fnrow);
+      const int g = q;
+      const float* y3 = Y3 + g * n3 + mm * K;
+      const float* bp = Bt + c * K;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 2
+      for (int k = 0; k < K; k += 4) {
+        const float4 yv = op4<M>(ld4(y3 + k));
+        const float4 bv = op4<M>(ld4(bp + k));
+        acc.x = fmaf(yv.x, bv.x, acc.x);
+        acc.y = fmaf(yv.y, bv.y, acc.y);
+        acc.z = fmaf(yv.z, bv.z, acc.z);
+        acc.w = fmaf(yv.w, bv.w, acc.w);
+      }
+      Rout[((a0 + g) * nrow + mm) * ba + c] = (acc.x + acc.y) + (acc.z + acc.w);
+    }
+    __syncthreads();
+  }
+}
+
 template <int M, typename T>
-__device__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
+__device__ __forceinline__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
                              int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2, int Dd2,
                              const T* Bt, int ba, int bb, T* X1, T* X2, T* X3, T* Lout) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (uk == 4 && Dd1 == 4 && Dd2 == 4 && ((Dl1 * Dl2 * ba) & 3) == 0) {
+      s2_step_left_f4<M>(Lp, U, ua, ub, A1, Dl1, Dr1, A2, Dl2, Dr2, Bt, ba, bb, X1, X2, X3, Lout);
+      return;
+    }
+  }
   const int inner = Dl1 * Dl2 * ba;
   const int n1 = inner * uk, n2 = Dl2 * ba * Dr1 * Dd1, n3 = Dr1 * Dr2 * ba * Dd2;
   const FastDiv fDd1(Dd1), fDr1(Dr1), fba(ba), fn2(n2);
@@ -195,9 +411,15 @@ __device__ void s2_step_left(const T* Lp, const T* U, int ua, int uk, int ub, co
 }
 
 template <int M, typename T>
-__device__ void s2_step_right(const T* Rp, const T* U, int ua, int uk, int ub, const T* A1,
+__device__ __forceinline__ void s2_step_right(const T* Rp, const T* U, int ua, int uk, int ub, const T* A1,
                               int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2, int Dd2,
                               const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Y3, T* Rout) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (uk == 4 && Dd1 == 4 && Dd2 == 4 && (bb & 3) == 0) {
+      s2_step_right_f4<M>(Rp, U, ua, ub, A1, Dl1, Dr1, A2, Dl2, Dr2, Bt, ba, bb, Y1, Y2, Y3, Rout);
+      return;
+    }
+  }
   const int rw = Dr1 * Dr2 * bb;
   const int n1 = uk * rw, n2 = Dl1 * Dd1 * Dr2 * bb, n3 = Dl1 * Dl2 * Dd2 * bb;
   const FastDiv fbb(bb), fDr2(Dr2), fDd1(Dd1), fn2(n2);
