@@ -75,6 +75,8 @@ __device__ double normalize_lds(T* t, int cnt, T* red, int* flag) {
 #define TQ_PACK (TQ_N * (TQ_N + 1) / 2)
 // partial dot products of the four waves, double buffered
 #define TQ_XCH (2 * 4 * TQ_N)
+// column j of each wave's block, broadcast to the wave through LDS
+#define TQ_VB (4 * TQ_N)
 
 __host__ __device__ inline bool tsqr_path(int mode, int bmax, int D) {
   return (mode == MODE_F32 || mode == MODE_BF16) && bmax * D <= TQ_N && D <= 4;
@@ -89,9 +91,9 @@ __host__ __device__ inline size_t env_big_elems(int bmax, int D, int mode) {
   size_t rest = BD * BD + 2 * BD * (BD + 4) + 2 * BD * bmax;
   if (tsqr_path(mode, bmax, D)) {
     // register-QR path (launched with 256 threads): the left sweep keeps
-    // the packed factor, its exchange buffer and the dense previous R from
+    // the packed factor, its exchange buffers and the dense previous R from
     // P on, and the right sweep's C overlays T1 (dead once Z is formed)
-    const size_t tq = (size_t)TQ_PACK + TQ_XCH + (size_t)TQ_N * TQ_N;
+    const size_t tq = (size_t)TQ_PACK + TQ_XCH + TQ_VB + (size_t)TQ_N * TQ_N;
     rest = 2 * BD * (BD + 4) + 2 * BD * bmax;
     if (rest < tq) rest = tq;
   }
@@ -104,9 +106,6 @@ __host__ __device__ inline size_t env_lds_elems_(int bmax, int D, int mode) {
   return env_big_elems(bmax, D, mode) + env_small_elems(bmax, D);
 }
 
-__device__ __forceinline__ float bcast_lane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
 // start of row j in a packed upper-triangular TQ_N x TQ_N matrix (by rows)
 __host__ __device__ __forceinline__ int prow(int j) { return j * TQ_N - (j * (j - 1)) / 2; }
 
@@ -117,9 +116,10 @@ __host__ __device__ __forceinline__ int prow(int j) { return j * TQ_N - (j * (j 
 // [0; stack]: reflector j maps (0, column j) to (sqrt(s), 0), s the squared
 // norm of column j, so its vector is (-sqrt(s), column j) and tau = 1/s.
 // Per column each wave forms the dot products of column j (broadcast from
-// lane j) with all of its columns; the four partial sums meet in LDS (xch)
-// behind one barrier, and each wave updates its block. Row j of the factor
-// is sqrt(s) times the dot products over s. On exit t (packed rows, LDS)
+// lane j through LDS) with all of its columns; the four partial sums meet in
+// LDS (xch: TQ_XCH floats, then TQ_VB for the column copies) behind one
+// barrier, and each wave updates its block. Row j of the factor is sqrt(s)
+// times the dot products over s. On exit t (packed rows, LDS)
 // holds R_y. Columns j >= min(Pr, kprev * Dout) hold only rounding residue
 // and are not reflected, nor is a column whose squared norm is below the
 // normal range (as in LAPACK's larfg).
@@ -155,15 +155,27 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
     }
   }
   const int kmax = min(Pr, kprev * Dout);
+  float* vbw = xch + TQ_XCH + wv * TQ_N;  // this wave's copy of column j
   for (int j = 0; j < kmax; ++j) {
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
     if (blk) {
+      // lane j publishes column j to its wave; every lane reads it back as
+      // 16-byte broadcasts (LDS instructions rather than 64 VALU lane reads)
+      if (lane == j) {
+#pragma unroll
+        for (int i = 0; i < TQ_N; i += 4)
+          *reinterpret_cast<float4*>(vbw + i) = make_float4(u[i], u[i + 1], u[i + 2], u[i + 3]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int i = 0; i < TQ_N; i += 4) {
-        d0 = fmaf(bcast_lane(u[i], j), u[i], d0);
-        d1 = fmaf(bcast_lane(u[i + 1], j), u[i + 1], d1);
-        d2 = fmaf(bcast_lane(u[i + 2], j), u[i + 2], d2);
-        d3 = fmaf(bcast_lane(u[i + 3], j), u[i + 3], d3);
+        const float4 v4 = *reinterpret_cast<const float4*>(vbw + i);
+        d0 = fmaf(v4.x, u[i], d0);
+        d1 = fmaf(v4.y, u[i + 1], d1);
+        d2 = fmaf(v4.z, u[i + 2], d2);
+        d3 = fmaf(v4.w, u[i + 3], d3);
       }
     }
     float* xb = xch + (j & 1) * (4 * TQ_N);
@@ -176,13 +188,15 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
     const float w = dc * (1.f / s);
     if (wv == 0 && lane >= j && lane < Pr) t[prow(j) - j + lane] = sqrtf(s) * w;
     if (blk) {
-      // broadcast column j again rather than keep 64 values live across
-      // the barrier (the empty asm hides that the lane index is unchanged,
-      // so the two broadcasts are not merged)
-      int jj = j;
-      asm volatile("" : "+s"(jj));
+      // column j again from LDS rather than 64 values held across the barrier
 #pragma unroll
-      for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(-bcast_lane(u[i], jj), w, u[i]);
+      for (int i = 0; i < TQ_N; i += 4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(vbw + i);
+        u[i] = fmaf(-v4.x, w, u[i]);
+        u[i + 1] = fmaf(-v4.y, w, u[i + 1]);
+        u[i + 2] = fmaf(-v4.z, w, u[i + 2]);
+        u[i + 3] = fmaf(-v4.w, w, u[i + 3]);
+      }
     }
   }
   __syncthreads();
@@ -284,8 +298,8 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
     if constexpr (M == MODE_F32 || M == MODE_BF16) {
       tree = tsqr_path(M, L.bmax, L.D) && PEPS_NT == 256;
       if (tree) {
-        // R_{-1} = [1], dense column-major after the factor and exchange buffer
-        float* Rpk = P + TQ_PACK + TQ_XCH;
+        // R_{-1} = [1], dense column-major after the factor and exchange buffers
+        float* Rpk = P + TQ_PACK + TQ_XCH + TQ_VB;
         for (int i = tid; i < TQ_N * TQ_N; i += PEPS_NT) Rpk[i] = i == 0 ? 1.f : 0.f;
       }
     }
@@ -301,7 +315,7 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       __syncthreads();
       if constexpr (M == MODE_F32 || M == MODE_BF16) {
         if (tree) {
-          float* Rpk = P + TQ_PACK + TQ_XCH;
+          float* Rpk = P + TQ_PACK + TQ_XCH + TQ_VB;
           tsqr_site<M>(Ebuf, Abuf, Rpk, P, P + TQ_PACK, kprev, bl, br, v.Dl, v.Dr, v.Din,
                        v.Dout, v.s_l, v.s_r, v.s_in, v.s_out);
           const int kr = min(kprev * v.Dout, Pr);
