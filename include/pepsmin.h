@@ -209,6 +209,25 @@ peps_status peps_sample(peps_ctx* ctx, const double* theta, int kind, int n_chai
                         uint64_t offset, uint8_t* samples, int32_t* accepted,
                         void* stream);
 
+/* One step of the optimisation loop (Eq. tdvp iterated, as in the
+ * optimisations of Sec. "Results"): n = n_chains * per_chain samples from
+ * peps_sample (same arguments), ln Psi, E_loc and O on them as in
+ * peps_evaluate, the minSR direction dtheta as in minsr_step (eps, rcond),
+ * then theta <- theta - tau * dtheta on the device.
+ * theta: device FP64 parameters (interleaved pairs for complex modes),
+ *   updated in place; left unchanged, with PEPS_ERR_NONFINITE returned, if
+ *   the minSR pseudo-inverse certificate fails.
+ * samples: device uint8 [n][N] (written); eloc: device FP64 [n][2]
+ *   (written); flags: device int32 [n] or NULL; diag: device FP64 [8] as
+ *   in minsr_step ([4] is the batch mean of Re E_loc before the update).
+ * The context's workspace holds O and dtheta (grown on demand). Returns
+ * after the step has finished on the stream. Needs a Hamiltonian and
+ * 2 <= n <= 2^24. */
+peps_status peps_vmc_step(peps_ctx* ctx, double* theta, int kind, int n_chains, int per_chain,
+                          int burn_in, int thin, uint64_t seed, uint64_t offset, double tau,
+                          double eps, double rcond, uint8_t* samples, double* eloc,
+                          int32_t* flags, double* diag, void* stream);
+
 /* Kernel timing. With profiling enabled every kernel launch of the context
  * is bracketed by two HIP events on its launch stream. peps_profile_read
  * waits for the recorded events and returns, per kernel kind, the summed

@@ -29,7 +29,7 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample",
            "peps_profile", "peps_profile_read", "made_create", "made_destroy",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
-           "imh_step", "peps_logderiv_vjp"]
+           "imh_step", "peps_logderiv_vjp", "peps_vmc_step"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -80,6 +80,8 @@ def load():
     lib.minsr_step.restype = I
     lib.peps_sample.argtypes = [P, P, I, I, I, I, I, U64, U64, P, P, P]
     lib.peps_sample.restype = I
+    lib.peps_vmc_step.argtypes = [P, P, I, I, I, I, I, U64, U64, D, D, D, P, P, P, P, P]
+    lib.peps_vmc_step.restype = I
     lib.peps_profile.argtypes = [P, I]
     lib.peps_profile.restype = I
     lib.peps_profile_read.argtypes = [P, P, P, I]
@@ -290,6 +292,39 @@ class Context:
                                   burn_in, thin, seed, offset, _ptr(samples), _ptr(acc),
                                   _stream()))
         return samples, acc
+
+    def vmc_step(self, theta, tau, kind="exchange", n_chains=256, per_chain=4, burn_in=32,
+                 thin=1, seed=0, offset=0, eps=1e-4, rcond=1e-12):
+        """One optimisation step (sample, evaluate, minSR, theta -= tau * dtheta);
+        theta (device, contiguous) is updated in place. Returns (samples,
+        eloc, flags, diag)."""
+        import torch
+        assert theta.is_contiguous()
+        th = self._theta(theta)
+        n = n_chains * per_chain
+        dev = theta.device
+        samples = torch.empty(n, self.Lx * self.Ly, dtype=torch.uint8, device=dev)
+        eloc = torch.empty(n, 2, dtype=torch.float64, device=dev)
+        flags = torch.zeros(n, dtype=torch.int32, device=dev)
+        diag = torch.zeros(8, dtype=torch.float64, device=dev)
+        k = SAMPLE_EXCHANGE if kind == "exchange" else SAMPLE_FLIP
+        _check(load().peps_vmc_step(self._h, _ptr(th), k, n_chains, per_chain, burn_in, thin,
+                                    seed, offset, tau, eps, rcond, _ptr(samples), _ptr(eloc),
+                                    _ptr(flags), _ptr(diag), _stream()))
+        return samples, eloc, flags, diag
+
+    def optimize(self, theta, steps, tau, kind="exchange", n_chains=256, per_chain=4,
+                 burn_in=32, thin=1, seed=0, offset0=0, eps=1e-4, rcond=1e-12):
+        """`steps` optimisation steps; step k uses sweep offset
+        offset0 + k * (burn_in + per_chain * thin). Returns the batch-mean
+        energy of every step (before its update); theta is updated in place."""
+        stride = burn_in + per_chain * thin
+        energies = []
+        for k in range(steps):
+            _, _, _, diag = self.vmc_step(theta, tau, kind, n_chains, per_chain, burn_in, thin,
+                                          seed, offset0 + k * stride, eps, rcond)
+            energies.append(float(diag[4].item()))
+        return energies
 
 
 class Made:

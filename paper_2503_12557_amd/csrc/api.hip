@@ -78,6 +78,8 @@ struct peps_ctx {
   double* d_hdbl = nullptr;
   // workspace
   DevBuf theta_c, env_int, rscr, rt1, rt2, epart, bad, mean, Tm, vec, eloc_tmp, logpsi_tmp;
+  // optimisation step: O, dtheta and ln Psi of its batch
+  DevBuf vmc_O, vmc_dth, vmc_lp;
   // global working sets of the kernels whose matrices do not fit in LDS
   bool env_gm = false, s1_gm = false, s2_gm = false, smp_gm = false;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
@@ -259,7 +261,7 @@ void peps_destroy(peps_ctx* c) {
   DevBuf* bufs[] = {&c->theta_c, &c->env_int,   &c->rscr,       &c->rt1,    &c->rt2,
                     &c->epart,   &c->bad,       &c->mean,       &c->Tm,     &c->vec,
                     &c->eloc_tmp, &c->logpsi_tmp, &c->gws_env,   &c->gws_s1, &c->gws_s2,
-                    &c->gws_smp};
+                    &c->gws_smp, &c->vmc_O,      &c->vmc_dth,    &c->vmc_lp};
   for (DevBuf* b : bufs) b->release();
   delete c;
 }
@@ -799,6 +801,42 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
     default: MET(MODE_C64);
   }
 #undef MET
+  return PEPS_OK;
+}
+
+peps_status peps_vmc_step(peps_ctx* c, double* theta, int kind, int n_chains, int per_chain,
+                          int burn_in, int thin, uint64_t seed, uint64_t offset, double tau,
+                          double eps, double rcond, uint8_t* samples, double* eloc,
+                          int32_t* flags, double* diag, void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (!theta || !samples || !eloc || !diag) return fail(PEPS_ERR_ARG, "null pointer");
+  if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
+  if (!std::isfinite(tau)) return fail(PEPS_ERR_ARG, "tau must be finite");
+  if (n_chains < 1 || per_chain < 1) return fail(PEPS_ERR_ARG, "need n_chains, per_chain >= 1");
+  const long long nl = (long long)n_chains * per_chain;
+  if (nl < 2 || nl > (1 << 24)) return fail(PEPS_ERR_ARG, "batch of %lld samples", nl);
+  const int n = (int)nl;
+  hipStream_t st = (hipStream_t)stream;
+  const Lattice& L = c->L;
+  const size_t nth = (size_t)L.n_params * (is_complex(c->g.dtype) ? 2 : 1);
+  peps_status s = c->vmc_O.ensure((size_t)n * L.n_compact * c->tsize);
+  if (s != PEPS_OK) return s;
+  if ((s = c->vmc_dth.ensure(nth * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->vmc_lp.ensure((size_t)n * 2 * sizeof(double))) != PEPS_OK) return s;
+  s = peps_sample(c, theta, kind, n_chains, per_chain, burn_in, thin, seed, offset, samples,
+                  nullptr, stream);
+  if (s != PEPS_OK) return s;
+  s = peps_evaluate(c, theta, samples, n, (double*)c->vmc_lp.p, eloc, c->vmc_O.p, flags, stream);
+  if (s != PEPS_OK) return s;
+  s = minsr_step(c, c->vmc_O.p, samples, n, eloc, eps, rcond, (double*)c->vmc_dth.p, diag,
+                 stream);
+  if (s != PEPS_OK) return s;
+  HIPCHK(launch_theta_update(theta, (const double*)c->vmc_dth.p, diag, tau, nth, st));
+  double cert = 0.0;
+  HIPCHK(hipMemcpyAsync(&cert, diag + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (cert != 0.0)
+    return fail(PEPS_ERR_NONFINITE, "minSR certificate failed; theta left unchanged");
   return PEPS_OK;
 }
 

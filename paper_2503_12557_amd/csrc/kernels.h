@@ -109,5 +109,9 @@ hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* 
                         const uint8_t* samples, int n, const double* eloc, double eps,
                         double rcond, double* dtheta, double* diag, void* ws_mean, void* ws_T,
                         void* ws_vec, hipStream_t st);
+// theta[i] -= tau * dtheta[i] for i < m, skipped when diag[3] (failed
+// pseudo-inverse certificate) is set
+hipError_t launch_theta_update(double* theta, const double* dtheta, const double* diag,
+                               double tau, size_t m, hipStream_t st);
 
 }  // namespace pm

@@ -531,6 +531,25 @@ hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
   return hipGetLastError();
 }
 
+// Parameter update of the optimisation loop (Eq. tdvp): theta moves by
+// -tau dtheta, element by element over the real (or interleaved complex)
+// FP64 parameters; a step whose certificate failed leaves theta unchanged.
+__global__ void k_theta_update(double* __restrict__ theta, const double* __restrict__ dtheta,
+                               const double* __restrict__ diag, double tau, size_t m) {
+  if (diag[3] != 0.0) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (size_t)gridDim.x * blockDim.x)
+    theta[i] = fma(-tau, dtheta[i], theta[i]);
+}
+
+hipError_t launch_theta_update(double* theta, const double* dtheta, const double* diag,
+                               double tau, size_t m, hipStream_t st) {
+  const size_t blocks = (m + 255) / 256 < 1024 ? (m + 255) / 256 : 1024;
+  hipLaunchKernelGGL(k_theta_update, dim3(blocks > 0 ? (unsigned)blocks : 1u), dim3(256), 0, st,
+                     theta, dtheta, diag, tau, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,
                         double rcond, double* dtheta, double* diag, void* ws_mean, void* ws_T,
