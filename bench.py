@@ -10,8 +10,9 @@ FP64 outside the timed region and the relative error of the batch-mean
 energy is reported.
 
 Prints one JSON line. Extra fields: the FP64 throughput, the minSR step time,
-the per-kernel split from HIP events, the roofline of the dominant kernel
-and the CPU oracle timed on a bounded sample.
+one step of the optimisation loop (sample + evaluate + minSR + update), the
+per-kernel split from HIP events, the roofline of the dominant kernel and
+the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -380,6 +381,24 @@ def main():
         "per_kernel": per_kernel,
         "roofline": roofline,
     }
+    # one step of the optimisation loop on the same workload, in the bench's
+    # compute dtype: sample (1024 chains x 4, burn-in 8) + evaluate + minSR +
+    # update, from a copy of theta
+    th_opt = theta.clone()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    _sync()
+    t0 = time.perf_counter()
+    ctx.vmc_step(th_opt, 0.05, n_chains=1024, per_chain=max(1, n // 1024), burn_in=8, seed=9)
+    _sync()
+    t_vmc = time.perf_counter() - t0
+    pv = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    res["optimisation_step"] = {
+        "seconds": round(t_vmc, 3), "samples": 1024 * max(1, n // 1024),
+        "sampler": "local exchange Metropolis, 1024 chains, burn-in 8 sweeps",
+        "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pv.items() if v[1]}}
+    del th_opt
     # energy error on the mu = 0.5 tensors (positive mean, less cancellation)
     th5 = torch.from_numpy(synth.theta(Lx, Ly, 2, D, seed=3, mu=0.5)).to(dev)
     ctx_s5 = Context(Lx, Ly, D, chi, "f32")
