@@ -832,6 +832,139 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
   return -1;
 }
 
+// The block-order scaled Jacobi above for its most common shape, with the
+// shape fixed at compile time: 64 FP32 rows of 64 elements in LDS (row
+// stride ldx a multiple of 4, 16-byte aligned), 256 threads, eight lanes
+// per pair holding eight elements each. Addressing is 32-bit LDS offsets
+// and the lane groups reduce with fixed DPP steps; the arithmetic and its
+// order are those of jacobi_rows_blk, so the results are identical.
+typedef float jf4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) float lds_float;
+typedef __attribute__((address_space(3))) jf4 lds_jf4;
+typedef __attribute__((address_space(3))) int lds_int;
+
+__device__ __noinline__ int jacobi64_lds(float* Xg, int ldx, float tol, int max_sweeps,
+                                         int* sflag_g, float* nrm_g) {
+  lds_float* X = (lds_float*)Xg;
+  lds_int* sflag = (lds_int*)sflag_g;
+  lds_float* nrm = (lds_float*)nrm_g;
+  lds_float* dd = nrm + 64;
+  const int tid = threadIdx.x;
+  const int pi = tid >> 3, lane = tid & 7;
+  const int e0 = lane * 8;
+  auto ld = [&](int row, jf4& a, jf4& b) __attribute__((always_inline)) {
+    const lds_jf4* q = (const lds_jf4*)(X + row * ldx + e0);
+    a = q[0];
+    b = q[1];
+  };
+  auto st = [&](int row, jf4 a, jf4 b) __attribute__((always_inline)) {
+    lds_jf4* q = (lds_jf4*)(X + row * ldx + e0);
+    q[0] = a;
+    q[1] = b;
+  };
+  auto gsum = [](float v) __attribute__((always_inline)) {
+    v += dppx<0xB1>(v);
+    v += dppx<0x4E>(v);
+    v += dppx<0x141>(v);
+    return v;
+  };
+  auto fold = [&]() __attribute__((always_inline)) {
+    for (int h = 0; h < 2; ++h) {
+      const int row = 2 * pi + h;
+      jf4 a, b;
+      ld(row, a, b);
+      const float d = dd[row];
+      a *= d;
+      b *= d;
+      float q2 = 0.f;
+      q2 += a.x * a.x;
+      q2 += a.y * a.y;
+      q2 += a.z * a.z;
+      q2 += a.w * a.w;
+      q2 += b.x * b.x;
+      q2 += b.y * b.y;
+      q2 += b.z * b.z;
+      q2 += b.w * b.w;
+      st(row, a, b);
+      q2 = gsum(q2);
+      if (lane == 0) {
+        nrm[row] = q2;
+        dd[row] = 1.f;
+      }
+    }
+    __syncthreads();
+  };
+  if (tid < 64) dd[tid] = 1.f;
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    fold();
+    if (tid == 0) sflag[0] = 0;
+    __syncthreads();
+    for (int b = 32; b >= 1; b >>= 1) {
+      const int i = pi & (b - 1);
+      const int base = 2 * (pi - i);
+      const int rr = base + i;
+      jf4 ra, rb;
+      ld(rr, ra, rb);
+      float dr = dd[rr], ar = nrm[rr];
+      bool moved = false;
+      for (int k = 0; k < b; ++k) {
+        const int q = base + b + ((i + k) & (b - 1));
+        jf4 qa, qb;
+        ld(q, qa, qb);
+        const float dq = dd[q], bq = nrm[q];
+        float c = 0.f;
+        c += ra.x * qa.x;
+        c += ra.y * qa.y;
+        c += ra.z * qa.z;
+        c += ra.w * qa.w;
+        c += rb.x * qb.x;
+        c += rb.y * qb.y;
+        c += rb.z * qb.z;
+        c += rb.w * qb.w;
+        c = gsum(c) * (dr * dq);
+        if (c != 0.f && c * c > tol * tol * (ar * bq)) {
+          const float dlt = bq - ar;
+          const float h = __builtin_amdgcn_sqrtf(fmaf(dlt, dlt, 4.f * c * c));
+          const float t = (dlt >= 0.f ? 2.f * c : -2.f * c) * __builtin_amdgcn_rcpf(fabsf(dlt) + h);
+          const float cs = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          const float idr = __builtin_amdgcn_rcpf(dr);
+          const float idq = __builtin_amdgcn_rcpf(dq);
+          const float t1 = t * dq * idr, t2 = t * dr * idq;
+          const jf4 pa = ra, pb = rb;
+          ra = pa - t1 * qa;
+          rb = pb - t1 * qb;
+          qa = qa + t2 * pa;
+          qb = qb + t2 * pb;
+          st(q, qa, qb);
+          dr *= cs;
+          ar -= t * c;
+          moved = true;
+          if (lane == 0) {
+            sflag[0] = 1;
+            dd[q] = dq * cs;
+            nrm[q] = bq + t * c;
+          }
+        }
+        __syncthreads();
+      }
+      if (moved) {
+        st(rr, ra, rb);
+        if (lane == 0) {
+          dd[rr] = dr;
+          nrm[rr] = ar;
+        }
+      }
+      __syncthreads();
+    }
+    const int f = sflag[0];
+    __syncthreads();
+    if (f == 0) return sweep + 1;
+  }
+  fold();
+  return -1;
+}
+
 // The same sweep for rows too long to hold in registers (nc > 32): each lane
 // strides over the row twice, once for the dot product and once to rotate.
 template <typename T>
@@ -928,6 +1061,10 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, typename RealOf<T>::type
   // rotations; in FP64 its two extra divisions per rotation cost more than
   // the LDS traffic it saves
   if constexpr (std::is_same<T, float>::value) {
+    if (m == 64 && n == 64 && PEPS_NT == 256 && (ldx & 3) == 0 &&
+        (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+        __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)X))
+      return jacobi64_lds(X, ldx, tol, max_sweeps, sflag, nrm);
     if (m >= 4 && m <= 64 && (m & (m - 1)) == 0) {
       if (nc <= 4) return jacobi_rows_blk<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
       if (nc <= 8) return jacobi_rows_blk<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
