@@ -965,6 +965,151 @@ __device__ __noinline__ int jacobi64_lds(float* Xg, int ldx, float tol, int max_
   return -1;
 }
 
+// The same for the other shapes on that path (m a power of two, 4 <= m <=
+// 64): G lanes per pair and NC elements per lane fixed at compile time,
+// rows in LDS (16-byte aligned, ldx a multiple of 4), runtime m and n with
+// the lanes past n masked. Same arithmetic and order as jacobi_rows_blk.
+template <int G>
+__device__ __forceinline__ float gsum_fixed(float v) {
+  if constexpr (G >= 2) v += dppx<0xB1>(v);
+  if constexpr (G >= 4) v += dppx<0x4E>(v);
+  if constexpr (G >= 8) v += dppx<0x141>(v);
+  if constexpr (G >= 16) v += dppx<0x140>(v);
+  if constexpr (G >= 32) v += shfl_xor_x(v, 16);
+  if constexpr (G >= 64) v += shfl_xor_x(v, 32);
+  return v;
+}
+
+template <int NC, int G>
+__device__ __noinline__ int jacobi_blk_lds(float* Xg, int m, int n, int ldx, float tol,
+                                           int max_sweeps, int* sflag_g, float* nrm_g) {
+  lds_float* X = (lds_float*)Xg;
+  lds_int* sflag = (lds_int*)sflag_g;
+  lds_float* nrm = (lds_float*)nrm_g;
+  lds_float* dd = nrm + m;
+  const int tid = threadIdx.x;
+  const int npairs = m >> 1;
+  const int pi = tid / G, lane = tid % G;
+  const bool grp = pi < npairs;
+  const int e0 = lane * NC;
+  const bool full = e0 + NC <= n;
+  auto ld = [&](int row, float (&y)[NC]) __attribute__((always_inline)) {
+    const lds_float* src = X + row * ldx + e0;
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) y[u] = src[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) y[u] = e0 + u < n ? src[u] : 0.f;
+    }
+  };
+  auto st = [&](int row, const float (&y)[NC]) __attribute__((always_inline)) {
+    lds_float* dst = X + row * ldx + e0;
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) dst[u] = y[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < NC; ++u)
+        if (e0 + u < n) dst[u] = y[u];
+    }
+  };
+  auto fold = [&]() __attribute__((always_inline)) {
+    if (grp) {
+      for (int h = 0; h < 2; ++h) {
+        const int row = 2 * pi + h;
+        float y[NC];
+        ld(row, y);
+        const float d = dd[row];
+        float q2 = 0.f;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+          y[u] *= d;
+          q2 += y[u] * y[u];
+        }
+        st(row, y);
+        q2 = gsum_fixed<G>(q2);
+        if (lane == 0) {
+          nrm[row] = q2;
+          dd[row] = 1.f;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  for (int i = tid; i < m; i += PEPS_NT) dd[i] = 1.f;
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    fold();
+    if (tid == 0) sflag[0] = 0;
+    __syncthreads();
+    for (int b = npairs; b >= 1; b >>= 1) {
+      const int i = pi & (b - 1);
+      const int base = 2 * (pi - i);
+      const int rr = base + i;
+      float yr[NC];
+      float dr = 1.f, ar = 0.f;
+      if (grp) {
+        ld(rr, yr);
+        dr = dd[rr];
+        ar = nrm[rr];
+      }
+      bool moved = false;
+      for (int k = 0; k < b; ++k) {
+        const int q = base + b + ((i + k) & (b - 1));
+        float yq[NC];
+        float c = 0.f, dq = 1.f, bq = 0.f;
+        if (grp) {
+          ld(q, yq);
+          dq = dd[q];
+          bq = nrm[q];
+#pragma unroll
+          for (int u = 0; u < NC; ++u) c += yr[u] * yq[u];
+        }
+        c = gsum_fixed<G>(c) * (dr * dq);
+        if (grp && c != 0.f && c * c > tol * tol * (ar * bq)) {
+          const float dlt = bq - ar;
+          const float h = __builtin_amdgcn_sqrtf(fmaf(dlt, dlt, 4.f * c * c));
+          const float t = (dlt >= 0.f ? 2.f * c : -2.f * c) * __builtin_amdgcn_rcpf(fabsf(dlt) + h);
+          const float cs = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          const float idr = __builtin_amdgcn_rcpf(dr);
+          const float idq = __builtin_amdgcn_rcpf(dq);
+          const float t1 = t * dq * idr, t2 = t * dr * idq;
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            const float yp = yr[u];
+            yr[u] = yp - t1 * yq[u];
+            yq[u] = yq[u] + t2 * yp;
+          }
+          st(q, yq);
+          dr *= cs;
+          ar -= t * c;
+          moved = true;
+          if (lane == 0) {
+            sflag[0] = 1;
+            dd[q] = dq * cs;
+            nrm[q] = bq + t * c;
+          }
+        }
+        __syncthreads();
+      }
+      if (moved) {
+        st(rr, yr);
+        if (lane == 0) {
+          dd[rr] = dr;
+          nrm[rr] = ar;
+        }
+      }
+      __syncthreads();
+    }
+    const int f = sflag[0];
+    __syncthreads();
+    if (f == 0) return sweep + 1;
+  }
+  fold();
+  return -1;
+}
+
 // The same sweep for rows too long to hold in registers (nc > 32): each lane
 // strides over the row twice, once for the dot product and once to rotate.
 template <typename T>
@@ -1065,6 +1210,20 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, typename RealOf<T>::type
         (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
         __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)X))
       return jacobi64_lds(X, ldx, tol, max_sweeps, sflag, nrm);
+    if (m >= 4 && m <= 64 && (m & (m - 1)) == 0 && PEPS_NT == 256 && (ldx & 3) == 0 &&
+        (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+        __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)X)) {
+      if (G == 64 && nc == 1)
+        return jacobi_blk_lds<1, 64>(X, m, n, ldx, tol, max_sweeps, sflag, nrm);
+      if (G == 32 && nc == 1)
+        return jacobi_blk_lds<1, 32>(X, m, n, ldx, tol, max_sweeps, sflag, nrm);
+      if (G == 32 && nc == 2)
+        return jacobi_blk_lds<2, 32>(X, m, n, ldx, tol, max_sweeps, sflag, nrm);
+      if (G == 16 && nc <= 4)
+        return jacobi_blk_lds<4, 16>(X, m, n, ldx, tol, max_sweeps, sflag, nrm);
+      if (G == 8 && nc <= 8)
+        return jacobi_blk_lds<8, 8>(X, m, n, ldx, tol, max_sweeps, sflag, nrm);
+    }
     if (m >= 4 && m <= 64 && (m & (m - 1)) == 0) {
       if (nc <= 4) return jacobi_rows_blk<T, 4>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
       if (nc <= 8) return jacobi_rows_blk<T, 8>(X, m, n, ldx, tol, max_sweeps, sflag, G, nrm);
