@@ -156,7 +156,8 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
   }
   const int kmax = min(Pr, kprev * Dout);
   float* vbw = xch + TQ_XCH + wv * TQ_N;  // this wave's copy of column j
-  for (int j = 0; j < kmax; ++j) {
+  const int k1 = kmax < TQ_N / 2 ? kmax : TQ_N / 2;
+  for (int j = 0; j < k1; ++j) {
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
     if (blk) {
       // lane j publishes column j to its wave; every lane reads it back as
@@ -196,6 +197,63 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
         u[i + 1] = fmaf(-v4.y, w, u[i + 1]);
         u[i + 2] = fmaf(-v4.z, w, u[i + 2]);
         u[i + 3] = fmaf(-v4.w, w, u[i + 3]);
+      }
+    }
+  }
+  if (kmax > TQ_N / 2) {
+    // Columns 32..63: only they are left, so the wave takes them two lanes
+    // per column: lane (c, h) holds rows 32h .. 32h+31 of column 32 + c,
+    // and each reflector costs half the instructions; a column's dot
+    // products add over the lane pair (lanes c and c + 32)
+    constexpr int HN = TQ_N / 2;
+    const int h = lane >> 5, cc = lane & (HN - 1), col = HN + cc;
+    if (blk) {
+#pragma unroll
+      for (int i = 0; i < HN; ++i) {
+        const float x = shfl_xor_x(u[i], HN);
+        u[i] = h == 0 ? x : u[HN + i];
+      }
+    }
+    float* vh = vbw + HN * h;
+    for (int j = HN; j < kmax; ++j) {
+      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      if (blk) {
+        if (cc == j - HN) {
+#pragma unroll
+          for (int i = 0; i < HN; i += 4)
+            *reinterpret_cast<float4*>(vh + i) = make_float4(u[i], u[i + 1], u[i + 2], u[i + 3]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int i = 0; i < HN; i += 4) {
+          const float4 v4 = *reinterpret_cast<const float4*>(vh + i);
+          d0 = fmaf(v4.x, u[i], d0);
+          d1 = fmaf(v4.y, u[i + 1], d1);
+          d2 = fmaf(v4.z, u[i + 2], d2);
+          d3 = fmaf(v4.w, u[i + 3], d3);
+        }
+      }
+      float dh = (d0 + d1) + (d2 + d3);
+      dh += shfl_xor_x(dh, HN);
+      float* xb = xch + (j & 1) * (4 * TQ_N);
+      if (h == 0) xb[wv * TQ_N + col] = dh;
+      __syncthreads();
+      const float dc = (xb[col] + xb[TQ_N + col]) + (xb[2 * TQ_N + col] + xb[3 * TQ_N + col]);
+      const float s = (xb[j] + xb[TQ_N + j]) + (xb[2 * TQ_N + j] + xb[3 * TQ_N + j]);
+      if (!(s > 1e-36f)) continue;  // column j is already zero
+      const float w = dc * (1.f / s);
+      if (wv == 0 && h == 0 && col >= j && col < Pr) t[prow(j) - j + col] = sqrtf(s) * w;
+      if (blk) {
+#pragma unroll
+        for (int i = 0; i < HN; i += 4) {
+          const float4 v4 = *reinterpret_cast<const float4*>(vh + i);
+          u[i] = fmaf(-v4.x, w, u[i]);
+          u[i + 1] = fmaf(-v4.y, w, u[i + 1]);
+          u[i + 2] = fmaf(-v4.z, w, u[i + 2]);
+          u[i + 3] = fmaf(-v4.w, w, u[i + 3]);
+        }
       }
     }
   }
