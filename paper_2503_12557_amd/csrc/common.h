@@ -832,98 +832,145 @@ __device__ __noinline__ int jacobi_rows_blk(T* X, int m, int n, int ldx, T tol, 
   return -1;
 }
 
-// The block-order scaled Jacobi above for its most common shape, with the
-// shape fixed at compile time: 64 FP32 rows of 64 elements in LDS (row
-// stride ldx a multiple of 4, 16-byte aligned), 256 threads, eight lanes
-// per pair holding eight elements each. Addressing is 32-bit LDS offsets
-// and the lane groups reduce with fixed DPP steps; the arithmetic and its
-// order are those of jacobi_rows_blk, so the results are identical.
+// The block-order scaled Jacobi above with its shape fixed at compile time:
+// MR FP32 rows of NR elements in LDS (row stride ldx a multiple of 4,
+// 16-byte aligned), 256 threads, G = min(64, 512 / MR, NR) lanes per pair
+// holding NC = NR / G elements each. Addressing is 32-bit LDS offsets with
+// vector accesses, the phases and rounds have fixed trip counts, and the
+// lane groups reduce with fixed DPP steps; the arithmetic and its order are
+// those of jacobi_rows_blk, so the results are identical.
 typedef float jf4 __attribute__((ext_vector_type(4)));
+typedef float jf2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) float lds_float;
 typedef __attribute__((address_space(3))) jf4 lds_jf4;
+typedef __attribute__((address_space(3))) jf2 lds_jf2;
 typedef __attribute__((address_space(3))) int lds_int;
 
-__device__ __noinline__ int jacobi64_lds(float* Xg, int ldx, float tol, int max_sweeps,
-                                         int* sflag_g, float* nrm_g) {
+template <int G>
+__device__ __forceinline__ float gsum_fixed(float v) {
+  if constexpr (G >= 2) v += dppx<0xB1>(v);
+  if constexpr (G >= 4) v += dppx<0x4E>(v);
+  if constexpr (G >= 8) v += dppx<0x141>(v);
+  if constexpr (G >= 16) v += dppx<0x140>(v);
+  if constexpr (G >= 32) v += shfl_xor_x(v, 16);
+  if constexpr (G >= 64) v += shfl_xor_x(v, 32);
+  return v;
+}
+
+template <int NC>
+__device__ __forceinline__ void ld_fixed(const lds_float* src, float (&y)[NC]) {
+  if constexpr (NC % 4 == 0) {
+#pragma unroll
+    for (int v = 0; v < NC / 4; ++v) {
+      const jf4 t = ((const lds_jf4*)src)[v];
+      y[4 * v] = t.x;
+      y[4 * v + 1] = t.y;
+      y[4 * v + 2] = t.z;
+      y[4 * v + 3] = t.w;
+    }
+  } else if constexpr (NC == 2) {
+    const jf2 t = *(const lds_jf2*)src;
+    y[0] = t.x;
+    y[1] = t.y;
+  } else {
+#pragma unroll
+    for (int u = 0; u < NC; ++u) y[u] = src[u];
+  }
+}
+template <int NC>
+__device__ __forceinline__ void st_fixed(lds_float* dst, const float (&y)[NC]) {
+  if constexpr (NC % 4 == 0) {
+#pragma unroll
+    for (int v = 0; v < NC / 4; ++v) {
+      jf4 t;
+      t.x = y[4 * v];
+      t.y = y[4 * v + 1];
+      t.z = y[4 * v + 2];
+      t.w = y[4 * v + 3];
+      ((lds_jf4*)dst)[v] = t;
+    }
+  } else if constexpr (NC == 2) {
+    jf2 t;
+    t.x = y[0];
+    t.y = y[1];
+    *(lds_jf2*)dst = t;
+  } else {
+#pragma unroll
+    for (int u = 0; u < NC; ++u) dst[u] = y[u];
+  }
+}
+
+template <int MR, int NR>
+__device__ __noinline__ int jacobi_fixed_lds(float* Xg, int ldx, float tol, int max_sweeps,
+                                             int* sflag_g, float* nrm_g) {
+  constexpr int NP = MR / 2;
+  constexpr int G0 = 512 / MR < 64 ? 512 / MR : 64;
+  constexpr int G = NR < G0 ? NR : G0;
+  constexpr int NC = NR / G;
+  static_assert(G * NC == NR && G * NP <= 256 && (MR & (MR - 1)) == 0, "shape");
   lds_float* X = (lds_float*)Xg;
   lds_int* sflag = (lds_int*)sflag_g;
   lds_float* nrm = (lds_float*)nrm_g;
-  lds_float* dd = nrm + 64;
+  lds_float* dd = nrm + MR;
   const int tid = threadIdx.x;
-  const int pi = tid >> 3, lane = tid & 7;
-  const int e0 = lane * 8;
-  auto ld = [&](int row, jf4& a, jf4& b) __attribute__((always_inline)) {
-    const lds_jf4* q = (const lds_jf4*)(X + row * ldx + e0);
-    a = q[0];
-    b = q[1];
-  };
-  auto st = [&](int row, jf4 a, jf4 b) __attribute__((always_inline)) {
-    lds_jf4* q = (lds_jf4*)(X + row * ldx + e0);
-    q[0] = a;
-    q[1] = b;
-  };
-  auto gsum = [](float v) __attribute__((always_inline)) {
-    v += dppx<0xB1>(v);
-    v += dppx<0x4E>(v);
-    v += dppx<0x141>(v);
-    return v;
-  };
+  const int pi = tid / G, lane = tid % G;
+  const bool grp = pi < NP;
+  const int e0 = lane * NC;
   auto fold = [&]() __attribute__((always_inline)) {
-    for (int h = 0; h < 2; ++h) {
-      const int row = 2 * pi + h;
-      jf4 a, b;
-      ld(row, a, b);
-      const float d = dd[row];
-      a *= d;
-      b *= d;
-      float q2 = 0.f;
-      q2 += a.x * a.x;
-      q2 += a.y * a.y;
-      q2 += a.z * a.z;
-      q2 += a.w * a.w;
-      q2 += b.x * b.x;
-      q2 += b.y * b.y;
-      q2 += b.z * b.z;
-      q2 += b.w * b.w;
-      st(row, a, b);
-      q2 = gsum(q2);
-      if (lane == 0) {
-        nrm[row] = q2;
-        dd[row] = 1.f;
+    if (grp) {
+      for (int h = 0; h < 2; ++h) {
+        const int row = 2 * pi + h;
+        float y[NC];
+        ld_fixed<NC>(X + row * ldx + e0, y);
+        const float d = dd[row];
+        float q2 = 0.f;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+          y[u] *= d;
+          q2 += y[u] * y[u];
+        }
+        st_fixed<NC>(X + row * ldx + e0, y);
+        q2 = gsum_fixed<G>(q2);
+        if (lane == 0) {
+          nrm[row] = q2;
+          dd[row] = 1.f;
+        }
       }
     }
     __syncthreads();
   };
-  if (tid < 64) dd[tid] = 1.f;
+  if (tid < MR) dd[tid] = 1.f;
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     fold();
     if (tid == 0) sflag[0] = 0;
     __syncthreads();
-    for (int b = 32; b >= 1; b >>= 1) {
+#pragma unroll
+    for (int b = NP; b >= 1; b >>= 1) {
       const int i = pi & (b - 1);
       const int base = 2 * (pi - i);
       const int rr = base + i;
-      jf4 ra, rb;
-      ld(rr, ra, rb);
-      float dr = dd[rr], ar = nrm[rr];
+      float yr[NC];
+      float dr = 1.f, ar = 0.f;
+      if (grp) {
+        ld_fixed<NC>(X + rr * ldx + e0, yr);
+        dr = dd[rr];
+        ar = nrm[rr];
+      }
       bool moved = false;
       for (int k = 0; k < b; ++k) {
         const int q = base + b + ((i + k) & (b - 1));
-        jf4 qa, qb;
-        ld(q, qa, qb);
-        const float dq = dd[q], bq = nrm[q];
-        float c = 0.f;
-        c += ra.x * qa.x;
-        c += ra.y * qa.y;
-        c += ra.z * qa.z;
-        c += ra.w * qa.w;
-        c += rb.x * qb.x;
-        c += rb.y * qb.y;
-        c += rb.z * qb.z;
-        c += rb.w * qb.w;
-        c = gsum(c) * (dr * dq);
-        if (c != 0.f && c * c > tol * tol * (ar * bq)) {
+        float yq[NC];
+        float c = 0.f, dq = 1.f, bq = 0.f;
+        if (grp) {
+          ld_fixed<NC>(X + q * ldx + e0, yq);
+          dq = dd[q];
+          bq = nrm[q];
+#pragma unroll
+          for (int u = 0; u < NC; ++u) c += yr[u] * yq[u];
+        }
+        c = gsum_fixed<G>(c) * (dr * dq);
+        if (grp && c != 0.f && c * c > tol * tol * (ar * bq)) {
           const float dlt = bq - ar;
           const float h = __builtin_amdgcn_sqrtf(fmaf(dlt, dlt, 4.f * c * c));
           const float t = (dlt >= 0.f ? 2.f * c : -2.f * c) * __builtin_amdgcn_rcpf(fabsf(dlt) + h);
@@ -931,12 +978,13 @@ __device__ __noinline__ int jacobi64_lds(float* Xg, int ldx, float tol, int max_
           const float idr = __builtin_amdgcn_rcpf(dr);
           const float idq = __builtin_amdgcn_rcpf(dq);
           const float t1 = t * dq * idr, t2 = t * dr * idq;
-          const jf4 pa = ra, pb = rb;
-          ra = pa - t1 * qa;
-          rb = pb - t1 * qb;
-          qa = qa + t2 * pa;
-          qb = qb + t2 * pb;
-          st(q, qa, qb);
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            const float yp = yr[u];
+            yr[u] = yp - t1 * yq[u];
+            yq[u] = yq[u] + t2 * yp;
+          }
+          st_fixed<NC>(X + q * ldx + e0, yq);
           dr *= cs;
           ar -= t * c;
           moved = true;
@@ -949,7 +997,7 @@ __device__ __noinline__ int jacobi64_lds(float* Xg, int ldx, float tol, int max_
         __syncthreads();
       }
       if (moved) {
-        st(rr, ra, rb);
+        st_fixed<NC>(X + rr * ldx + e0, yr);
         if (lane == 0) {
           dd[rr] = dr;
           nrm[rr] = ar;
@@ -969,17 +1017,6 @@ __device__ __noinline__ int jacobi64_lds(float* Xg, int ldx, float tol, int max_
 // 64): G lanes per pair and NC elements per lane fixed at compile time,
 // rows in LDS (16-byte aligned, ldx a multiple of 4), runtime m and n with
 // the lanes past n masked. Same arithmetic and order as jacobi_rows_blk.
-template <int G>
-__device__ __forceinline__ float gsum_fixed(float v) {
-  if constexpr (G >= 2) v += dppx<0xB1>(v);
-  if constexpr (G >= 4) v += dppx<0x4E>(v);
-  if constexpr (G >= 8) v += dppx<0x141>(v);
-  if constexpr (G >= 16) v += dppx<0x140>(v);
-  if constexpr (G >= 32) v += shfl_xor_x(v, 16);
-  if constexpr (G >= 64) v += shfl_xor_x(v, 32);
-  return v;
-}
-
 template <int NC, int G>
 __device__ __noinline__ int jacobi_blk_lds(float* Xg, int m, int n, int ldx, float tol,
                                            int max_sweeps, int* sflag_g, float* nrm_g) {
@@ -1209,10 +1246,15 @@ __device__ int jacobi_rows(T* X, int m, int n, int ldx, typename RealOf<T>::type
     if (m == 64 && n == 64 && PEPS_NT == 256 && (ldx & 3) == 0 &&
         (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
         __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)X))
-      return jacobi64_lds(X, ldx, tol, max_sweeps, sflag, nrm);
+      return jacobi_fixed_lds<64, 64>(X, ldx, tol, max_sweeps, sflag, nrm);
     if (m >= 4 && m <= 64 && (m & (m - 1)) == 0 && PEPS_NT == 256 && (ldx & 3) == 0 &&
         (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
         __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)X)) {
+      if (m == 16 && n == 64) return jacobi_fixed_lds<16, 64>(X, ldx, tol, max_sweeps, sflag, nrm);
+      if (m == 16 && n == 16) return jacobi_fixed_lds<16, 16>(X, ldx, tol, max_sweeps, sflag, nrm);
+      if (m == 4 && n == 64) return jacobi_fixed_lds<4, 64>(X, ldx, tol, max_sweeps, sflag, nrm);
+      if (m == 4 && n == 4) return jacobi_fixed_lds<4, 4>(X, ldx, tol, max_sweeps, sflag, nrm);
+      if (m == 32 && n == 64) return jacobi_fixed_lds<32, 64>(X, ldx, tol, max_sweeps, sflag, nrm);
       if (G == 64 && nc == 1)
         return jacobi_blk_lds<1, 64>(X, m, n, ldx, tol, max_sweeps, sflag, nrm);
       if (G == 32 && nc == 1)
