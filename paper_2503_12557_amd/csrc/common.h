@@ -364,6 +364,67 @@ __device__ __forceinline__ T group_sum(T v, int G) {
   return v;
 }
 
+// 16-byte vectors of FP32 (the caller guarantees alignment)
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+template <int M>
+__device__ __forceinline__ float4 op4(float4 v) {
+  return make_float4(opnd<M>(v.x), opnd<M>(v.y), opnd<M>(v.z), opnd<M>(v.w));
+}
+__device__ __forceinline__ void fma4(float4& acc, float w, float4 v) {
+  acc.x = fmaf(w, v.x, acc.x);
+  acc.y = fmaf(w, v.y, acc.y);
+  acc.z = fmaf(w, v.z, acc.z);
+  acc.w = fmaf(w, v.w, acc.w);
+}
+
+// The GEMM below for FP32 when B's and C's rows are contiguous, 16-byte
+// aligned and n is a multiple of 4: each thread keeps four columns of two
+// rows and reads B as 16-byte vectors. Every sum runs over k in order, as
+// in the general form, so the results are the same.
+template <int M>
+__device__ void gemm_f4(int m, int n, int k, const float* A, int sai, int sak, const float* B,
+                        int sbk, float* C, int sci, bool acc) {
+  const int nq = n >> 2;
+  int lj = 0;
+  while ((1 << lj) < nq && lj < 6) ++lj;
+  const int LJ = 1 << lj;
+  const int tx = threadIdx.x & (LJ - 1), ty = threadIdx.x >> lj;
+  const int rp = PEPS_NT >> lj;
+  for (int i = ty; i < m; i += 2 * rp) {
+    const int i2 = i + rp;
+    const bool two = i2 < m;
+    const float* a1 = A + i * sai;
+    const float* a2 = A + (two ? i2 : i) * sai;
+    for (int jq = tx; jq < nq; jq += LJ) {
+      const float* bp = B + 4 * jq;
+      float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
+#pragma unroll 4
+      for (int kk = 0; kk < k; ++kk) {
+        const float4 bv = op4<M>(ld4(bp + kk * sbk));
+        fma4(s1, opnd<M>(a1[kk * sak]), bv);
+        fma4(s2, opnd<M>(a2[kk * sak]), bv);
+      }
+      float* c1 = C + i * sci + 4 * jq;
+      if (acc) {
+        const float4 o = ld4(c1);
+        s1 = make_float4(o.x + s1.x, o.y + s1.y, o.z + s1.z, o.w + s1.w);
+      }
+      st4(c1, s1);
+      if (two) {
+        float* c2 = C + i2 * sci + 4 * jq;
+        if (acc) {
+          const float4 o = ld4(c2);
+          s2 = make_float4(o.x + s2.x, o.y + s2.y, o.z + s2.z, o.w + s2.w);
+        }
+        st4(c2, s2);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Strided GEMM over the block: C[i,j] (+)= sum_k A[i*sai + k*sak] * B[k*sbk + j*sbj]
 // written to C[i*sci + j*scj]. Operands may live in LDS or global memory.
@@ -374,6 +435,13 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 template <int M, bool CB = false, typename T>
 __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T* B, int sbk,
                      int sbj, T* C, int sci, int scj, bool acc) {
+  if constexpr (std::is_same<T, float>::value && !CB) {
+    if (sbj == 1 && scj == 1 && (n & 3) == 0 && (sbk & 3) == 0 && (sci & 3) == 0 &&
+        ((reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & 15) == 0) {
+      gemm_f4<M>(m, n, k, A, sai, sak, B, sbk, C, sci, acc);
+      return;
+    }
+  }
   int lj = 0;
   while ((1 << lj) < n && lj < 6) ++lj;
   const int LJ = 1 << lj;

@@ -150,8 +150,14 @@ __device__ void tsqr_site(const float* Ebuf, const float* Abuf, const float* Rpk
       }
       pl = opnd<M>(pl);
       const float* col = Rpk + l * TQ_N;
+      // R_{y-1} is upper triangular: column l has no entries below row l
 #pragma unroll
-      for (int i = 0; i < TQ_N; ++i) u[i] = fmaf(opnd<M>(col[i]), pl, u[i]);
+      for (int q = 0; q < TQ_N; q += 16) {
+        if (q <= l) {
+#pragma unroll
+          for (int i = q; i < q + 16; ++i) u[i] = fmaf(opnd<M>(col[i]), pl, u[i]);
+        }
+      }
     }
   }
   const int kmax = min(Pr, kprev * Dout);

@@ -145,20 +145,6 @@ __device__ __forceinline__ bool in_move(const int* mv, int n) {
 // Every operand (partials, staged environments and tensors, chunk
 // intermediates) must be 16-byte aligned.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float4 ld4(const float* p) {
-  return *reinterpret_cast<const float4*>(p);
-}
-__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
-template <int M>
-__device__ __forceinline__ float4 op4(float4 v) {
-  return make_float4(opnd<M>(v.x), opnd<M>(v.y), opnd<M>(v.z), opnd<M>(v.w));
-}
-__device__ __forceinline__ void fma4(float4& acc, float w, float4 v) {
-  acc.x = fmaf(w, v.x, acc.x);
-  acc.y = fmaf(w, v.y, acc.y);
-  acc.z = fmaf(w, v.z, acc.z);
-  acc.w = fmaf(w, v.w, acc.w);
-}
 
 // left step with uk = Dd1 = Dd2 = 4 and Dl1 Dl2 ba a multiple of 4
 template <int M>
