@@ -425,6 +425,50 @@ __device__ void gemm_f4(int m, int n, int k, const float* A, int sai, int sak, c
   }
 }
 
+// The GEMM below for FP32 when both A's rows and B's columns are
+// contiguous in k (C = A B^T of row-major A and B), 16-byte aligned, k a
+// multiple of 4: A and B are read as 16-byte vectors; every sum still runs
+// over k in order, so the results are the same.
+template <int M>
+__device__ void gemm_nt_f4(int m, int n, int k, const float* A, int sai, const float* B, int sbj,
+                           float* C, int sci, int scj, bool acc) {
+  int lj = 0;
+  while ((1 << lj) < n && lj < 6) ++lj;
+  const int LJ = 1 << lj;
+  const int tx = threadIdx.x & (LJ - 1), ty = threadIdx.x >> lj;
+  const int rp = PEPS_NT >> lj;
+  for (int i = ty; i < m; i += 2 * rp) {
+    const int i2 = i + rp;
+    const bool two = i2 < m;
+    const float* a1 = A + i * sai;
+    const float* a2 = A + (two ? i2 : i) * sai;
+    for (int j = tx; j < n; j += LJ) {
+      const float* bp = B + j * sbj;
+      float s1 = 0.f, s2 = 0.f;
+#pragma unroll 2
+      for (int kk = 0; kk < k; kk += 4) {
+        const float4 b4 = op4<M>(ld4(bp + kk));
+        const float4 x = op4<M>(ld4(a1 + kk));
+        const float4 y = op4<M>(ld4(a2 + kk));
+        s1 = fmaf(x.x, b4.x, s1);
+        s1 = fmaf(x.y, b4.y, s1);
+        s1 = fmaf(x.z, b4.z, s1);
+        s1 = fmaf(x.w, b4.w, s1);
+        s2 = fmaf(y.x, b4.x, s2);
+        s2 = fmaf(y.y, b4.y, s2);
+        s2 = fmaf(y.z, b4.z, s2);
+        s2 = fmaf(y.w, b4.w, s2);
+      }
+      float* c1 = C + i * sci + j * scj;
+      *c1 = acc ? *c1 + s1 : s1;
+      if (two) {
+        float* c2 = C + i2 * sci + j * scj;
+        *c2 = acc ? *c2 + s2 : s2;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Strided GEMM over the block: C[i,j] (+)= sum_k A[i*sai + k*sak] * B[k*sbk + j*sbj]
 // written to C[i*sci + j*scj]. Operands may live in LDS or global memory.
@@ -439,6 +483,11 @@ __device__ void gemm(int m, int n, int k, const T* A, int sai, int sak, const T*
     if (sbj == 1 && scj == 1 && (n & 3) == 0 && (sbk & 3) == 0 && (sci & 3) == 0 &&
         ((reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & 15) == 0) {
       gemm_f4<M>(m, n, k, A, sai, sak, B, sbk, C, sci, acc);
+      return;
+    }
+    if (sak == 1 && sbk == 1 && (k & 3) == 0 && (sai & 3) == 0 && (sbj & 3) == 0 &&
+        ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0) {
+      gemm_nt_f4<M>(m, n, k, A, sai, B, sbj, C, sci, scj, acc);
       return;
     }
   }

@@ -472,7 +472,30 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
       __syncthreads();
       // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]
       const int zc = v.Dout * nbr;
-      {
+      bool zdone = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if ((nbr & 3) == 0 &&
+            ((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(Z)) & 15) == 0) {
+          // four consecutive c per thread: T1 rows read as 16-byte vectors
+          const int nq = nbr >> 2, totq = Pl * v.Dout * nq;
+          const FastDiv fnq(nq), fDout(v.Dout), fDl(v.Dl);
+          for (int i = tid; i < totq; i += PEPS_NT) {
+            int q = i;
+            const int cq = divmod(q, fnq);
+            const int k = divmod(q, fDout);
+            const int l = divmod(q, fDl);
+            const int aa = q;
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int in = 0; in < v.Din; ++in)
+              for (int r = 0; r < v.Dr; ++r)
+                fma4(acc, opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]),
+                     op4<M>(ld4(P + (aa * v.Din + in) * (v.Dr * nbr) + r * nbr + 4 * cq)));
+            st4(Z + (aa * v.Dl + l) * zc + k * nbr + 4 * cq, acc);
+          }
+          zdone = true;
+        }
+      }
+      if (!zdone) {
         const int tot = Pl * zc;
         const FastDiv fzc(zc), fDl(v.Dl), fnbr(nbr);
         for (int i = tid; i < tot; i += PEPS_NT) {
