@@ -510,6 +510,41 @@ class SampleContraction:
         return out
 
 
+def local_energy_strict(theta, g: Geometry, configs, chi: int, ham, method='canonical'):
+    """E_loc with every amplitude taken from the full boundary-MPS contraction
+    at the one cut i* (Sec. "On Variational Upper Bound"):
+    E_loc(S) = sum_S' <S|H|S'> Psi(S')_i* / Psi(S)_i*. Averaged over
+    p(S) ~ |Psi(S)_i*|^2 this is the energy of the single vector
+    S -> Psi(S)_i*, so it cannot fall below the ground-state energy; the strip
+    ratios of ``SampleContraction.local_energy`` do not have that property at
+    a truncating chi."""
+    T = site_tensors(theta, g)
+    out = np.empty(len(configs), dtype=np.complex128)
+    for idx, s in enumerate(configs):
+        s = np.asarray(s)
+        l0 = SampleContraction(T, g, s, chi, method).logpsi
+        e = 0.0 + 0.0j
+        for sites, h in ham.terms:
+            k = len(sites)
+            c = 0
+            for n in sites:
+                c = 2 * c + int(s[n])
+            row = h[c]
+            for c2 in np.nonzero(row)[0]:
+                c2 = int(c2)
+                if c2 == c:
+                    e += row[c]
+                    continue
+                s2 = s.copy()
+                for j, n in enumerate(sites):
+                    s2[n] = (c2 >> (k - 1 - j)) & 1
+                l1 = SampleContraction(T, g, s2, chi, method).logpsi
+                e += row[c2] * np.exp(l1 - l0)
+        e += ham.diagonal(s)
+        out[idx] = e
+    return out
+
+
 def expand_compact(Oc, g: Geometry, s):
     """Full O row (N_p entries) from the compact one: zeros where p != s_xy."""
     out = np.zeros(g.n_params, dtype=Oc.dtype)
