@@ -399,6 +399,21 @@ def main():
         "sampler": "local exchange Metropolis, 1024 chains, burn-in 8 sweeps",
         "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pv.items() if v[1]}}
     del th_opt
+    # strict local energy (every amplitude at the one cut) on the first 64
+    # configurations of the batch, in the bench's compute dtype
+    ks = min(n, 64)
+    sk = samples[:ks].contiguous()
+    es = ctx.local_energy_strict(theta, sk)
+    _sync()
+    t0 = time.perf_counter()
+    es = ctx.local_energy_strict(theta, sk)
+    _sync()
+    t_strict = time.perf_counter() - t0
+    res["strict_local_energy"] = {
+        "samples": ks, "seconds": round(t_strict, 4),
+        "samples_per_s": round(ks / t_strict, 2),
+        "mean_re": float(es[:, 0].mean().item()),
+        "strip_mean_re_same_samples": float(el[:ks, 0].double().mean().item())}
     # energy error on the mu = 0.5 tensors (positive mean, less cancellation)
     th5 = torch.from_numpy(synth.theta(Lx, Ly, 2, D, seed=3, mu=0.5)).to(dev)
     ctx_s5 = Context(Lx, Ly, D, chi, "f32")

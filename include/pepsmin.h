@@ -144,6 +144,23 @@ peps_status peps_local_energy(peps_ctx* ctx, const double* theta, const uint8_t*
                               int n, const void* env_cache, double* eloc, int32_t* flags,
                               void* stream);
 
+/* Strict local energies (Sec. "On Variational Upper Bound"): eloc[n][2] as
+ * for peps_local_energy, except that every amplitude is the full contraction
+ * at the one cut i* of peps_amplitude, E_loc(S) = diag(S) +
+ * sum_S' <S|H|S'> Psi(S')_i* / Psi(S)_i*. The sampled mean over
+ * p(S) ~ |Psi(S)_i*|^2 is then the energy of the single vector
+ * S -> Psi(S)_i* and stays above the ground-state energy at any chi; the
+ * strip ratios of peps_local_energy carry no such bound when chi truncates.
+ * Cost: one amplitude per sample and per move of nonzero <S|H|S'> (moves
+ * are the distinct sets of sites that an off-diagonal term changes), held
+ * in the context's workspace. flags: int32 [n] or NULL, the OR of the flags
+ * of S and of all its neighbours. Needs a Hamiltonian; PEPS_ERR_UNSUPPORTED
+ * when n x (1 + moves) exceeds 2^31 - 1. Returns after the neighbour count
+ * has been read back; the rest is queued on the stream. */
+peps_status peps_local_energy_strict(peps_ctx* ctx, const double* theta,
+                                     const uint8_t* samples, int n, double* eloc,
+                                     int32_t* flags, void* stream);
+
 /* Log-derivatives O_k(S) = d ln Psi_row(x)(S) / d theta_k for every
  * parameter k of a site (x, y) with physical index s_xy (the hole network
  * of row x between E^u[x-1] and E^l[x+1], divided by that strip's

@@ -29,7 +29,7 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample",
            "peps_profile", "peps_profile_read", "made_create", "made_destroy",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
-           "imh_step", "peps_logderiv_vjp", "peps_vmc_step"]
+           "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -72,6 +72,8 @@ def load():
     lib.peps_amplitude.restype = I
     lib.peps_local_energy.argtypes = [P, P, P, I, P, P, P, P]
     lib.peps_local_energy.restype = I
+    lib.peps_local_energy_strict.argtypes = [P, P, P, I, P, P, P]
+    lib.peps_local_energy_strict.restype = I
     lib.peps_logderiv.argtypes = [P, P, P, I, P, P, P]
     lib.peps_logderiv.restype = I
     lib.peps_evaluate.argtypes = [P, P, P, I, P, P, P, P, P]
@@ -219,6 +221,17 @@ class Context:
         eloc = torch.empty(n, 2, dtype=torch.float64, device=theta.device)
         _check(load().peps_local_energy(self._h, _ptr(theta), _ptr(samples), n, _ptr(env_cache),
                                         _ptr(eloc), _ptr(flags), _stream()))
+        return eloc
+
+    def local_energy_strict(self, theta, samples, flags=None):
+        """E_loc with every amplitude from the full contraction at the one
+        cut (the variational-bound estimator); returns eloc [n, 2]."""
+        import torch
+        theta, samples = self._args(theta, samples)
+        n = samples.shape[0]
+        eloc = torch.empty(n, 2, dtype=torch.float64, device=theta.device)
+        _check(load().peps_local_energy_strict(self._h, _ptr(theta), _ptr(samples), n,
+                                               _ptr(eloc), _ptr(flags), _stream()))
         return eloc
 
     def logderiv(self, theta, samples, env_cache=None):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -80,6 +81,10 @@ struct peps_ctx {
   DevBuf theta_c, env_int, rscr, rt1, rt2, epart, bad, mean, Tm, vec, eloc_tmp, logpsi_tmp;
   // optimisation step: O, dtheta and ln Psi of its batch
   DevBuf vmc_O, vmc_dth, vmc_lp;
+  // strict local energy: neighbour counts/offsets, the amplitude batch
+  // [samples | neighbours], coefficients, ln Psi and flags of the batch
+  int n_moves = 0;
+  DevBuf str_idx, str_batch, str_coef, str_lp, str_fl;
   // global working sets of the kernels whose matrices do not fit in LDS
   bool env_gm = false, s1_gm = false, s2_gm = false, smp_gm = false;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
@@ -261,7 +266,8 @@ void peps_destroy(peps_ctx* c) {
   DevBuf* bufs[] = {&c->theta_c, &c->env_int,   &c->rscr,       &c->rt1,    &c->rt2,
                     &c->epart,   &c->bad,       &c->mean,       &c->Tm,     &c->vec,
                     &c->eloc_tmp, &c->logpsi_tmp, &c->gws_env,   &c->gws_s1, &c->gws_s2,
-                    &c->gws_smp, &c->vmc_O,      &c->vmc_dth,    &c->vmc_lp};
+                    &c->gws_smp, &c->vmc_O,      &c->vmc_dth,    &c->vmc_lp,
+                    &c->str_idx, &c->str_batch,  &c->str_coef,   &c->str_lp, &c->str_fl};
   for (DevBuf* b : bufs) b->release();
   delete c;
 }
@@ -425,6 +431,7 @@ peps_status peps_set_hamiltonian(peps_ctx* c, int n_terms, const int* term_nsite
   H.mats = c->d_hdbl;
   H.pair_v = c->d_hdbl + o_pv;
   H.onsite = onsite ? c->d_hdbl + o_on : nullptr;
+  c->n_moves = mstart[n_strips];
   c->has_ham = true;
   return PEPS_OK;
 }
@@ -657,6 +664,46 @@ peps_status peps_local_energy(peps_ctx* c, const double* theta, const uint8_t* s
   if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
   return dispatch(c, theta, samples, n, (void*)env_cache, env_cache != nullptr, nullptr, eloc,
                   nullptr, flags, stream);
+}
+
+peps_status peps_local_energy_strict(peps_ctx* c, const double* theta, const uint8_t* samples,
+                                     int n, double* eloc, int32_t* flags, void* stream) {
+  peps_status s = check_common(c, theta, samples, n);
+  if (s != PEPS_OK) return s;
+  if (n > 0 && !eloc) return fail(PEPS_ERR_ARG, "null eloc");
+  if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
+  if (n == 0) return PEPS_OK;
+  if ((long long)n * (1 + c->n_moves) > (long long)INT_MAX)
+    return fail(PEPS_ERR_UNSUPPORTED, "%d samples x %d moves exceed the int32 batch index", n,
+                c->n_moves);
+  hipStream_t st = (hipStream_t)stream;
+  const Lattice& L = c->L;
+  if ((s = c->str_idx.ensure((size_t)(2 * n + 1) * sizeof(int))) != PEPS_OK) return s;
+  int* cnt = (int*)c->str_idx.p;
+  int* off = cnt + n;
+  HIPCHK(launch_strict_count(L, c->H, c->n_moves, samples, n, cnt, off, st));
+  int nb = 0;
+  HIPCHK(hipMemcpyAsync(&nb, off + n, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (nb < n || (long long)nb > (long long)n * (1 + c->n_moves))
+    return fail(PEPS_ERR_ARG, "inconsistent neighbour count %d", nb);
+  if ((s = c->str_batch.ensure((size_t)nb * L.N)) != PEPS_OK) return s;
+  if ((s = c->str_coef.ensure(((size_t)(nb - n) + 1) * 2 * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->str_lp.ensure((size_t)nb * 2 * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->str_fl.ensure((size_t)nb * sizeof(int))) != PEPS_OK) return s;
+  uint8_t* batch = (uint8_t*)c->str_batch.p;
+  double* coef = (double*)c->str_coef.p;
+  double* lp = (double*)c->str_lp.p;
+  int* fl = (int*)c->str_fl.p;
+  HIPCHK(launch_strict_expand(L, c->H, c->n_moves, samples, n, off, batch, coef, st));
+  s = dispatch(c, theta, batch, nb, nullptr, false, lp, nullptr, nullptr, fl, stream);
+  if (s != PEPS_OK) return s;
+  {
+    ProfScope ps(c, st, PEPS_PROF_ESUM);
+    HIPCHK(launch_energy_diag_sum(L, c->H, samples, nullptr, 1, eloc, n, st));
+    HIPCHK(launch_strict_combine(n, off, coef, lp, fl, eloc, flags, st));
+  }
+  return PEPS_OK;
 }
 
 peps_status peps_logderiv(peps_ctx* c, const double* theta, const uint8_t* samples, int n,

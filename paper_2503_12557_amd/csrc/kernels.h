@@ -70,6 +70,17 @@ hipError_t launch_energy_diag_sum(const Lattice& L, const HamDev& H, const uint8
                                   const double* epart, int nparts, double* eloc, int n,
                                   hipStream_t st);
 
+// strict local energy: neighbour counts and offsets (off[n+1], starting at
+// n), the batch [samples | neighbours] with coefficients, the combination
+hipError_t launch_strict_count(const Lattice& L, const HamDev& H, int n_moves,
+                               const uint8_t* samples, int n, int* cnt, int* off,
+                               hipStream_t st);
+hipError_t launch_strict_expand(const Lattice& L, const HamDev& H, int n_moves,
+                                const uint8_t* samples, int n, const int* off, uint8_t* batch,
+                                double* coef, hipStream_t st);
+hipError_t launch_strict_combine(int n, const int* off, const double* coef, const double* lp,
+                                 const int* bfl, double* eloc, int* flags, hipStream_t st);
+
 // Metropolis sampler
 size_t sample_lds_elems(int bmax, int D, int mode);
 template <int M>

@@ -459,6 +459,138 @@ k_energy_diag_sum(Lattice L, HamDev H, const uint8_t* __restrict__ samples,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Strict local energy (Sec. "On Variational Upper Bound"): every amplitude
+// of E_loc is the full contraction at the one cut i*. The neighbours
+// S' = S with one move applied are listed per sample (moves whose summed
+// coefficient <S|H|S'> vanishes are left out), evaluated as one amplitude
+// batch, and combined as E_loc(S) = diag(S) + sum_S' coef * Psi(S')/Psi(S).
+// One thread per sample: these kernels move O(moves * N) bytes per sample,
+// negligible beside the contractions of the amplitudes.
+// ---------------------------------------------------------------------------
+__global__ void k_strict_count(Lattice L, HamDev H, int n_moves,
+                               const uint8_t* __restrict__ samples, int n, int* __restrict__ cnt) {
+  const int smp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (smp >= n) return;
+  const uint8_t* s = samples + (size_t)smp * L.N;
+  int k = 0;
+  for (int mi = 0; mi < n_moves; ++mi) {
+    double cre, cim;
+    move_coef(H, H.moves + 8 * mi, s, cre, cim);
+    k += (cre != 0.0 || cim != 0.0) ? 1 : 0;
+  }
+  cnt[smp] = k;
+}
+
+// off[i] = n + sum_{j<i} cnt[j] for i = 0..n: the neighbours of sample i sit
+// at rows off[i]..off[i+1]-1 of the amplitude batch, after the n samples.
+// One workgroup; every thread scans a contiguous slice.
+#define STRICT_SCAN 256
+__global__ void __launch_bounds__(STRICT_SCAN)
+k_strict_offsets(const int* __restrict__ cnt, int n, int* __restrict__ off) {
+  __shared__ int part[STRICT_SCAN];
+  const int t = threadIdx.x;
+  const int per = (n + STRICT_SCAN - 1) / STRICT_SCAN;
+  const int b = min(n, t * per), e = min(n, b + per);
+  int loc = 0;
+  for (int i = b; i < e; ++i) loc += cnt[i];
+  part[t] = loc;
+  __syncthreads();
+  if (t == 0) {
+    int acc = n;
+    for (int j = 0; j < STRICT_SCAN; ++j) {
+      const int v = part[j];
+      part[j] = acc;
+      acc += v;
+    }
+    off[n] = acc;
+  }
+  __syncthreads();
+  int acc = part[t];
+  for (int i = b; i < e; ++i) {
+    off[i] = acc;
+    acc += cnt[i];
+  }
+}
+
+// Rows 0..n-1 of the batch are the samples, then the listed neighbours with
+// their coefficients (coef row j - n).
+__global__ void k_strict_expand(Lattice L, HamDev H, int n_moves,
+                                const uint8_t* __restrict__ samples, int n,
+                                const int* __restrict__ off, uint8_t* __restrict__ batch,
+                                double* __restrict__ coef) {
+  const int smp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (smp >= n) return;
+  const int N = L.N;
+  const uint8_t* s = samples + (size_t)smp * N;
+  uint8_t* self = batch + (size_t)smp * N;
+  for (int q = 0; q < N; ++q) self[q] = s[q];
+  int row = off[smp];
+  for (int mi = 0; mi < n_moves; ++mi) {
+    const int* mv = H.moves + 8 * mi;
+    double cre, cim;
+    move_coef(H, mv, s, cre, cim);
+    if (cre == 0.0 && cim == 0.0) continue;
+    uint8_t* o = batch + (size_t)row * N;
+    for (int q = 0; q < N; ++q) o[q] = (uint8_t)pbit(s[q]);
+    for (int j = 0; j < mv[2]; ++j) o[mv[3 + j]] ^= 1;
+    coef[2 * (size_t)(row - n)] = cre;
+    coef[2 * (size_t)(row - n) + 1] = cim;
+    ++row;
+  }
+}
+
+// eloc[i] += sum_j coef_j exp(ln Psi(S'_j) - ln Psi(S_i)); flags of the
+// neighbours are ORed into the sample's.
+__global__ void k_strict_combine(int n, const int* __restrict__ off,
+                                 const double* __restrict__ coef, const double* __restrict__ lp,
+                                 const int* __restrict__ bfl, double* __restrict__ eloc,
+                                 int* __restrict__ flags) {
+  const int smp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (smp >= n) return;
+  const double l0 = lp[2 * smp], a0 = lp[2 * smp + 1];
+  double re = 0.0, im = 0.0;
+  int f = bfl[smp];
+  for (int j = off[smp]; j < off[smp + 1]; ++j) {
+    const double w = exp(lp[2 * (size_t)j] - l0);
+    const double ph = lp[2 * (size_t)j + 1] - a0;
+    const double xr = w * cos(ph), xi = w * sin(ph);
+    const double cr = coef[2 * (size_t)(j - n)], ci = coef[2 * (size_t)(j - n) + 1];
+    re += cr * xr - ci * xi;
+    im += cr * xi + ci * xr;
+    f |= bfl[j];
+  }
+  eloc[2 * smp] += re;
+  eloc[2 * smp + 1] += im;
+  if (flags) flags[smp] = f;
+}
+
+hipError_t launch_strict_count(const Lattice& L, const HamDev& H, int n_moves,
+                               const uint8_t* samples, int n, int* cnt, int* off,
+                               hipStream_t st) {
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_strict_count, dim3(nb), dim3(256), 0, st, L, H, n_moves, samples, n, cnt);
+  hipLaunchKernelGGL(k_strict_offsets, dim3(1), dim3(STRICT_SCAN), 0, st, cnt, n, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_strict_expand(const Lattice& L, const HamDev& H, int n_moves,
+                                const uint8_t* samples, int n, const int* off, uint8_t* batch,
+                                double* coef, hipStream_t st) {
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_strict_expand, dim3(nb), dim3(256), 0, st, L, H, n_moves, samples, n, off,
+                     batch, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_strict_combine(int n, const int* off, const double* coef, const double* lp,
+                                 const int* bfl, double* eloc, int* flags, hipStream_t st) {
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_strict_combine, dim3(nb), dim3(256), 0, st, n, off, coef, lp, bfl, eloc,
+                     flags);
+  return hipGetLastError();
+}
+
 size_t strip1_lds_bytes(int mode, const Lattice& L, bool gm) {
   return (gm ? strip1_small(L.D) : strip1_lds_elems(L.bmax, L.D)) * mode_elem_bytes(mode);
 }
