@@ -175,9 +175,34 @@ def absorb(mps, A, g: Geometry, x: int, from_top: bool):
     return out
 
 
-def compress_canonical(mps, chi: int):
+def kept_count(sv, chi: int, cutoff: float = 0.0) -> int:
+    """Singular values kept at one bond. Fixed chi: min(chi, len(sv)). With a
+    maximal truncated weight (Sec. "On the boundary MPS method": D_c chosen
+    dynamically, cutoff 1e-4 in the paper's runs) the smallest r <= chi whose
+    discarded weight sum_{k>=r} sv_k^2 / sum_k sv_k^2 is at most the cutoff;
+    chi itself when even chi values discard more."""
+    sv = np.asarray(sv, dtype=np.float64)
+    r = min(chi, len(sv))
+    if cutoff <= 0.0 or r <= 1:
+        return r
+    w = sv ** 2
+    lim = cutoff * w.sum()
+    tail = w[r:].sum()
+    if tail > lim:
+        return r
+    for j in range(r - 1, 0, -1):
+        t2 = tail + w[j]
+        if t2 > lim:
+            return j + 1
+        tail = t2
+    return 1
+
+
+def compress_canonical(mps, chi: int, cutoff: float = 0.0):
     """Truncate every bond to chi: left-to-right QR sweep, then a
-    right-to-left SVD sweep keeping the chi largest singular values.
+    right-to-left SVD sweep keeping the chi largest singular values (with a
+    cutoff > 0: the fewest that keep the discarded weight within it, see
+    ``kept_count``).
 
     This is the canonical way of truncating an MPS-MPO product; it yields the
     same truncated state as the density-matrix algorithm the paper uses
@@ -198,7 +223,7 @@ def compress_canonical(mps, chi: int):
         C = Q[y] if X is None else np.einsum('akb,bc->akc', Q[y], X)
         bl, k, br = C.shape
         u, sv, vh = np.linalg.svd(C.reshape(bl, k * br), full_matrices=False)
-        r = min(chi, len(sv))
+        r = kept_count(sv, chi, cutoff)
         out[y] = vh[:r].reshape(r, k, br)
         X = u[:, :r] * sv[:r]
     out[0] = np.einsum('akb,bc->akc', Q[0], X) if n > 1 else Q[0]
@@ -251,10 +276,18 @@ def normalize(mps):
     return out, logf
 
 
-def top_environments(A, g: Geometry, chi: int, method: str = 'canonical'):
+def _compressor(method: str, cutoff: float):
+    if method == 'canonical':
+        return lambda m, chi: compress_canonical(m, chi, cutoff)
+    if cutoff > 0.0:
+        raise ValueError('the truncated-weight cutoff is defined for the canonical method')
+    return compress_density_matrix
+
+
+def top_environments(A, g: Geometry, chi: int, method: str = 'canonical', cutoff: float = 0.0):
     """E^u[i] for i = 0..Lx-2 and their log scales: E^u[0] is row 0, each
     further one absorbs a row, truncates to chi and renormalises."""
-    comp = compress_canonical if method == 'canonical' else compress_density_matrix
+    comp = _compressor(method, cutoff)
     U, fU = {}, {}
     mps, f = normalize(top_row_mps(A, g, 0))
     U[0], fU[0] = mps, f
@@ -265,9 +298,10 @@ def top_environments(A, g: Geometry, chi: int, method: str = 'canonical'):
     return U, fU
 
 
-def bottom_environments(A, g: Geometry, chi: int, method: str = 'canonical'):
+def bottom_environments(A, g: Geometry, chi: int, method: str = 'canonical',
+                        cutoff: float = 0.0):
     """E^l[j] for j = Lx-1..1 (mirror image of ``top_environments``)."""
-    comp = compress_canonical if method == 'canonical' else compress_density_matrix
+    comp = _compressor(method, cutoff)
     B, fB = {}, {}
     L = g.Lx - 1
     mps, f = normalize(bottom_row_mps(A, g, L))
@@ -401,11 +435,12 @@ class SampleContraction:
     """Everything the estimators need for one configuration: the cached
     environments, the amplitude at the middle cut and lazily built strips."""
 
-    def __init__(self, T, g: Geometry, s, chi: int, method: str = 'canonical'):
+    def __init__(self, T, g: Geometry, s, chi: int, method: str = 'canonical',
+                 cutoff: float = 0.0):
         self.T, self.g, self.s, self.chi = T, g, np.asarray(s), chi
         self.A = project(T, g, s)
-        self.U, self.fU = top_environments(self.A, g, chi, method)
-        self.B, self.fB = bottom_environments(self.A, g, chi, method)
+        self.U, self.fU = top_environments(self.A, g, chi, method, cutoff)
+        self.B, self.fB = bottom_environments(self.A, g, chi, method, cutoff)
         self.istar = amplitude_row_index(g)
         self.logpsi = log_amplitude_at(self.U, self.fU, self.B, self.fB, self.istar)
         self._s1 = {}
@@ -510,7 +545,8 @@ class SampleContraction:
         return out
 
 
-def local_energy_strict(theta, g: Geometry, configs, chi: int, ham, method='canonical'):
+def local_energy_strict(theta, g: Geometry, configs, chi: int, ham, method='canonical',
+                        cutoff: float = 0.0):
     """E_loc with every amplitude taken from the full boundary-MPS contraction
     at the one cut i* (Sec. "On Variational Upper Bound"):
     E_loc(S) = sum_S' <S|H|S'> Psi(S')_i* / Psi(S)_i*. Averaged over
@@ -522,7 +558,7 @@ def local_energy_strict(theta, g: Geometry, configs, chi: int, ham, method='cano
     out = np.empty(len(configs), dtype=np.complex128)
     for idx, s in enumerate(configs):
         s = np.asarray(s)
-        l0 = SampleContraction(T, g, s, chi, method).logpsi
+        l0 = SampleContraction(T, g, s, chi, method, cutoff).logpsi
         e = 0.0 + 0.0j
         for sites, h in ham.terms:
             k = len(sites)
@@ -538,7 +574,7 @@ def local_energy_strict(theta, g: Geometry, configs, chi: int, ham, method='cano
                 s2 = s.copy()
                 for j, n in enumerate(sites):
                     s2[n] = (c2 >> (k - 1 - j)) & 1
-                l1 = SampleContraction(T, g, s2, chi, method).logpsi
+                l1 = SampleContraction(T, g, s2, chi, method, cutoff).logpsi
                 e += row[c2] * np.exp(l1 - l0)
         e += ham.diagonal(s)
         out[idx] = e
@@ -558,7 +594,7 @@ def expand_compact(Oc, g: Geometry, s):
 
 
 def evaluate(theta, g: Geometry, configs, chi: int, ham=None, want_O=False,
-             method='canonical'):
+             method='canonical', cutoff: float = 0.0):
     """ln Psi, E_loc and compact O for a batch, one configuration at a time."""
     T = site_tensors(theta, g)
     n = len(configs)
@@ -566,7 +602,7 @@ def evaluate(theta, g: Geometry, configs, chi: int, ham=None, want_O=False,
     eloc = np.empty(n, dtype=np.complex128) if ham is not None else None
     O = None
     for i, s in enumerate(configs):
-        sc = SampleContraction(T, g, s, chi, method)
+        sc = SampleContraction(T, g, s, chi, method, cutoff)
         logpsi[i] = sc.logpsi
         if ham is not None:
             eloc[i] = sc.local_energy(ham)
