@@ -399,6 +399,22 @@ def main():
         "sampler": "local exchange Metropolis, 1024 chains, burn-in 8 sweeps",
         "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pv.items() if v[1]}}
     del th_opt
+    # the same evaluation with a maximal truncated weight of 1e-4 per bond
+    # (the paper's cutoff) inside chi = 16, and the relative contraction
+    # error Delta psi against the fixed chi = 16 amplitudes
+    ctx.set_truncation(1e-4)
+    outc = ctx.evaluate(theta, samples)
+    _sync()
+    t0 = time.perf_counter()
+    ctx.evaluate(theta, samples, out=outc)
+    _sync()
+    t_cut = time.perf_counter() - t0
+    ctx.set_truncation(0.0)
+    dpsi = (torch.exp(outc[0][:, 0] - lp[:, 0]) - 1).abs().cpu().numpy()
+    res["truncated_weight_1e-4"] = {
+        "samples_per_s": round(n / t_cut, 2),
+        "delta_psi_median": float(np.median(dpsi)), "delta_psi_p99": float(np.quantile(dpsi, 0.99)),
+        "energy_mean": float(outc[1][:, 0].double().mean().item())}
     # strict local energy (every amplitude at the one cut) on the first 64
     # configurations of the batch, in the bench's compute dtype
     ks = min(n, 64)

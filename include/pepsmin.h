@@ -72,7 +72,8 @@ enum {
   PEPS_FLAG_ZERO = 1,        /* Psi(S) = 0 exactly */
   PEPS_FLAG_NONFINITE = 2,   /* a non-finite value appeared */
   PEPS_FLAG_NOCONV = 4,      /* a Jacobi SVD hit its sweep limit */
-  PEPS_FLAG_DEGENERATE = 8   /* relative gap at a truncation cut below 1e-8 */
+  PEPS_FLAG_DEGENERATE = 8   /* relative gap at a truncation cut below 1e-8, or a
+                                cutoff decision within its margin */
 };
 
 /* Sampler kinds for peps_sample. */
@@ -126,6 +127,20 @@ peps_status peps_set_hamiltonian(peps_ctx* ctx, int n_terms, const int* term_nsi
                                  const int* term_sites, const double* term_mats,
                                  int n_pairs, const int* pair_ij, const double* pair_v,
                                  const double* onsite);
+
+/* Truncation rule of every boundary-MPS compression of the context
+ * (environments, amplitudes, strips, sampler; Sec. "On the boundary MPS
+ * method": the contraction bond chosen dynamically from a maximal truncated
+ * weight, 1e-4 in the paper's runs). max_weight = 0 (the default) keeps chi
+ * singular values per bond. max_weight in (0, 1): at each bond the fewest
+ * r <= chi singular values sigma_k (descending) with
+ * sum_{k>=r} sigma_k^2 <= max_weight * sum_k sigma_k^2; chi when chi values
+ * discard more. The environments keep their chi-wide layout: the bond
+ * directions beyond r are zero. A cut whose kept count lies within a
+ * relative margin of the limit (1e-8 in FP64/complex128, 1e-4 in the FP32
+ * modes) sets flag 8, like a degenerate cut. Host-side setting, takes effect
+ * at the next call. PEPS_ERR_ARG outside [0, 1). */
+peps_status peps_set_truncation(peps_ctx* ctx, double max_weight);
 
 /* ln Psi(S)_i* = ln(E^u[i*] . E^l[i*+1]) with i* = floor(Lx/2) - 1
  * (Eq. boundary_MPS_approx), as (ln|Psi|, arg Psi) FP64 pairs in

@@ -29,7 +29,8 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_local_energy", "peps_logderiv", "peps_evaluate", "minsr_step", "peps_sample",
            "peps_profile", "peps_profile_read", "made_create", "made_destroy",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
-           "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict"]
+           "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
+           "peps_set_truncation"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -74,6 +75,8 @@ def load():
     lib.peps_local_energy.restype = I
     lib.peps_local_energy_strict.argtypes = [P, P, P, I, P, P, P]
     lib.peps_local_energy_strict.restype = I
+    lib.peps_set_truncation.argtypes = [P, ctypes.c_double]
+    lib.peps_set_truncation.restype = I
     lib.peps_logderiv.argtypes = [P, P, P, I, P, P, P]
     lib.peps_logderiv.restype = I
     lib.peps_evaluate.argtypes = [P, P, P, I, P, P, P, P, P]
@@ -222,6 +225,11 @@ class Context:
         _check(load().peps_local_energy(self._h, _ptr(theta), _ptr(samples), n, _ptr(env_cache),
                                         _ptr(eloc), _ptr(flags), _stream()))
         return eloc
+
+    def set_truncation(self, max_weight):
+        """Maximal truncated weight of every boundary-MPS truncation (0: keep
+        chi singular values per bond)."""
+        _check(load().peps_set_truncation(self._h, float(max_weight)))
 
     def local_energy_strict(self, theta, samples, flags=None):
         """E_loc with every amplitude from the full contraction at the one

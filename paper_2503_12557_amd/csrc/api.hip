@@ -137,6 +137,7 @@ static peps_status build_tables(peps_ctx* c) {
   L.D = D;
   L.chi = g.chi;
   L.N = N;
+  L.trunc_w = 0.0;
   L.bmax = std::max(g.chi, D);
   L.site_box = L.bmax * D * L.bmax;
   L.n_slots = 2 * (Lx - 1);
@@ -664,6 +665,14 @@ peps_status peps_local_energy(peps_ctx* c, const double* theta, const uint8_t* s
   if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
   return dispatch(c, theta, samples, n, (void*)env_cache, env_cache != nullptr, nullptr, eloc,
                   nullptr, flags, stream);
+}
+
+peps_status peps_set_truncation(peps_ctx* c, double max_weight) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (!std::isfinite(max_weight) || max_weight < 0.0 || max_weight >= 1.0)
+    return fail(PEPS_ERR_ARG, "maximal truncated weight %g outside [0, 1)", max_weight);
+  c->L.trunc_w = max_weight;
+  return PEPS_OK;
 }
 
 peps_status peps_local_energy_strict(peps_ctx* c, const double* theta, const uint8_t* samples,

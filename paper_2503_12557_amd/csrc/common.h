@@ -258,6 +258,8 @@ struct Lattice {
   int site_box;      // bmax * D * bmax elements per environment tensor
   int n_slots;       // 2 * (Lx - 1)
   int off_param, off_block, off_legs, off_compact, off_env, off_csite;  // into tab
+  // maximal truncated weight of a boundary-MPS truncation (0: keep chi)
+  double trunc_w;
 };
 
 __device__ __forceinline__ int slot_top(const Lattice& L, int x) { return x; }

@@ -552,8 +552,9 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
         __syncthreads();
         rnew = edims[(sn * L.Ly + y) * 3 + 0];
         // rank rows by descending norm (ties by index); the largest value and
-        // the largest discarded one (for the degenerate-cut flag)
-        Rl smx = 0, sdis = 0;
+        // the largest discarded one (for the degenerate-cut flag); squared
+        // norms of all rows and of the discarded ones (truncated weight)
+        Rl smx = 0, sdis = 0, wall = 0, wdis = 0;
         for (int i = tid; i < m; i += PEPS_NT) {
           int rk = 0;
           const Rl si = sig[i];
@@ -561,21 +562,63 @@ __device__ void env_absorb_row(const Lattice& L, const int* tab, const typename 
             const Rl sj = sig[j];
             rk += (sj > si) || (sj == si && j < i);
           }
-          if (rk < rnew) sel[rk] = i;
-          else sdis = si > sdis ? si : sdis;
+          if (rk < rnew) {
+            sel[rk] = i;
+          } else {
+            sdis = si > sdis ? si : sdis;
+            wdis += si * si;
+          }
           smx = si > smx ? si : smx;
+          wall += si * si;
         }
         const Rl smax = block_max(smx, rred);
         const Rl sb = block_max(sdis, rred);
-        if (tid == 0 && rnew < m) {
-          const Rl sa = sig[sel[rnew - 1]];
-          if (sa > Rl(0) && (sa - sb) < Rl(1e-8) * sa) fl |= 8;
+        // kept count: rnew, or with a maximal truncated weight w the fewest
+        // rows whose discarded weight is at most w times the total, the
+        // discarded squares added smallest first
+        __shared__ int s_keep;
+        if (L.trunc_w > 0.0) {
+          const Rl wa = block_sum(wall, rred);
+          const Rl wd = block_sum(wdis, rred);
+          if (tid == 0) {
+            const Rl lim = (Rl)L.trunc_w * wa;
+            int r = rnew;
+            Rl tail = wd;
+            if (tail <= lim) {
+              for (int j = rnew - 1; j >= 1; --j) {
+                const Rl sj = sig[sel[j]];
+                const Rl t2 = tail + sj * sj;
+                if (t2 > lim) break;
+                tail = t2;
+                r = j;
+              }
+            }
+            // a decision within a relative margin of the limit could fall
+            // the other way under rounding: flag it like a degenerate cut
+            const Rl marg = std::is_same<Rl, double>::value ? Rl(1e-8) : Rl(1e-4);
+            bool near = fabs((double)(tail - lim)) <= (double)(marg * lim);
+            if (r > 1 && tail <= lim) {
+              const Rl sp = sig[sel[r - 1]];
+              near = near || fabs((double)(tail + sp * sp - lim)) <= (double)(marg * lim);
+            }
+            if (near) fl |= 8;
+            s_keep = r;
+          }
+        } else if (tid == 0) {
+          s_keep = rnew;
+        }
+        __syncthreads();
+        const int rkeep = s_keep;
+        if (tid == 0 && rkeep < m) {
+          const Rl sa = sig[sel[rkeep - 1]];
+          const Rl sn = rkeep < rnew ? sig[sel[rkeep]] : sb;
+          if (sa > Rl(0) && (sa - sn) < Rl(1e-8) * sa) fl |= 8;
         }
         const Rl thresh = smax * Eps<Rl>::v * Rl(4);
         for (int i = tid; i < rnew * zc; i += PEPS_NT) {
           const int j = i / zc, e = i - j * zc;
           const Rl sj = sig[sel[j]];
-          Bn[i] = (sj > thresh) ? S[sel[j] * ldc + e] / sj : T(0);
+          Bn[i] = (j < rkeep && sj > thresh) ? S[sel[j] * ldc + e] / sj : T(0);
         }
         __syncthreads();
         // W_y[(a,l), j] = sum_e Z[(a,l), e] conj(Bn[j, e])
