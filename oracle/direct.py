@@ -64,6 +64,28 @@ def _unit(t):
     return t / m if m > 0 else t
 
 
+def _right_step(E, Tp, G, R1):
+    """One column, physical value p, absorbed into the right environment:
+    R[e,l,b,m,h] = E[e,u,f] Tp[l,r,u,d] G[b,d,w,g] conj(Tp)[m,s,v,w]
+    conj(E)[h,v,k] R1[f,r,g,s,k], contracted one tensor at a time."""
+    t = np.einsum('euf,frgsk->eurgsk', E, R1, optimize=True)
+    t = np.einsum('lrud,eurgsk->eldgsk', Tp, t, optimize=True)
+    t = np.einsum('bdwg,eldgsk->elbwsk', G, t, optimize=True)
+    t = np.einsum('msvw,elbwsk->elbmvk', Tp.conj(), t, optimize=True)
+    return np.einsum('hvk,elbmvk->elbmh', E.conj(), t, optimize=True)
+
+
+def _left_step(Lc, E, Tp, G):
+    """The same column absorbed into the left environment:
+    C[f,r,g,s,k] = Lc[e,l,b,m,h] E[e,u,f] Tp[l,r,u,d] G[b,d,w,g]
+    conj(Tp)[m,s,v,w] conj(E)[h,v,k]."""
+    t = np.einsum('elbmh,euf->lbmhuf', Lc, E, optimize=True)
+    t = np.einsum('lbmhuf,lrud->bmhfrd', t, Tp, optimize=True)
+    t = np.einsum('bmhfrd,bdwg->mhfrgw', t, G, optimize=True)
+    t = np.einsum('mhfrgw,msvw->hfrgsv', t, Tp.conj(), optimize=True)
+    return np.einsum('hfrgsv,hvk->frgsk', t, E.conj(), optimize=True)
+
+
 def _walk(T, g, chi, Dl_env, uniforms=None, fixed=None):
     """One configuration row by row. With ``uniforms`` the sites are drawn;
     with ``fixed`` they are forced. Returns (s, ln p(s))."""
@@ -88,17 +110,14 @@ def _walk(T, g, chi, Dl_env, uniforms=None, fixed=None):
         for y in range(Ly - 1, -1, -1):
             acc = 0
             for p in range(2):
-                acc = acc + np.einsum('euf,lrud,bdwg,msvw,hvk,frgsk->elbmh', Es[y], Ts[y][p],
-                                      Ds[y], Ts[y][p].conj(), Es[y].conj(), R[y + 1],
-                                      optimize='greedy')
+                acc = acc + _right_step(Es[y], Ts[y][p], Ds[y], R[y + 1])
             R[y] = _unit(acc)
         Lc = np.ones((1, 1, 1, 1, 1), dtype=dt)
         for y in range(Ly):
             n = i * Ly + y
             cand, q = [], []
             for p in range(2):
-                c = np.einsum('elbmh,euf,lrud,bdwg,msvw,hvk->frgsk', Lc, Es[y], Ts[y][p], Ds[y],
-                              Ts[y][p].conj(), Es[y].conj(), optimize='greedy')
+                c = _left_step(Lc, Es[y], Ts[y][p], Ds[y])
                 cand.append(c)
                 q.append(max(0.0, float(np.real(np.sum(c * R[y + 1])))))
             tot = q[0] + q[1]
