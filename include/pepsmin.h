@@ -128,6 +128,30 @@ peps_status peps_set_hamiltonian(peps_ctx* ctx, int n_terms, const int* term_nsi
                                  int n_pairs, const int* pair_ij, const double* pair_v,
                                  const double* onsite);
 
+/* Direct sampling (Sec. "On Direct Sampling"; App. "Direct sampling of
+ * PEPS", Eq. prob_from_cond_prob): n independent configurations drawn row by
+ * row from the top. Row i comes from the conditional density matrix
+ * T^u . D^l[i+1] . T^u*, where T^u is the top environment E^u[i-1] of the
+ * drawn rows (bond chi, truncated as in peps_amplitude) times the open row
+ * i (its bond chi*D is not truncated further), and D^l[i+1] the boundary
+ * MPS from the bottom of the double-layer network (site tensors
+ * sum_p T[p] x conj(T[p]), bond D^2) with bond chi_double, built once per
+ * call. Sites are drawn from the left: s = 0 iff u < q_0 / (q_0 + q_1) with
+ * u from Philox4x32-10 (key = seed; counter (site, j mod 2^32, j >> 32,
+ * 0x44495243), j = offset + index); a negative q counts as 0.
+ * samples: device uint8 [n][N] (written); logp: device FP64 [n], ln p(S)
+ * of the sampler (written); logw: device FP64 [n] or NULL, the unnormalised
+ * log importance weight ln|Psi(S)_i*|^2 - ln p(S) (the amplitude of
+ * peps_amplitude), which corrects the sampler's bias by reweighting; flags:
+ * int32 [n] or NULL (1: both q zero at some site, 2: non-finite value, and
+ * the amplitude's flags). Needs D^2 <= 16 and max(chi_double, D^2) * D^2 <=
+ * 256 (PEPS_ERR_UNSUPPORTED otherwise). The workspace (double-layer context,
+ * per-sample slabs of O(Ly chi^2 D^2 chi_double) elements) is grown on
+ * demand; returns with the work queued on the stream. */
+peps_status peps_direct_sample(peps_ctx* ctx, const double* theta, int n, int chi_double,
+                               uint64_t seed, uint64_t offset, uint8_t* samples, double* logp,
+                               double* logw, int32_t* flags, void* stream);
+
 /* Truncation rule of every boundary-MPS compression of the context
  * (environments, amplitudes, strips, sampler; Sec. "On the boundary MPS
  * method": the contraction bond chosen dynamically from a maximal truncated

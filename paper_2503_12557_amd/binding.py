@@ -30,7 +30,7 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_profile", "peps_profile_read", "made_create", "made_destroy",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
            "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
-           "peps_set_truncation"]
+           "peps_set_truncation", "peps_direct_sample"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -77,6 +77,9 @@ def load():
     lib.peps_local_energy_strict.restype = I
     lib.peps_set_truncation.argtypes = [P, ctypes.c_double]
     lib.peps_set_truncation.restype = I
+    lib.peps_direct_sample.argtypes = [P, P, I, I, ctypes.c_uint64, ctypes.c_uint64, P, P, P, P,
+                                       P]
+    lib.peps_direct_sample.restype = I
     lib.peps_logderiv.argtypes = [P, P, P, I, P, P, P]
     lib.peps_logderiv.restype = I
     lib.peps_evaluate.argtypes = [P, P, P, I, P, P, P, P, P]
@@ -225,6 +228,21 @@ class Context:
         _check(load().peps_local_energy(self._h, _ptr(theta), _ptr(samples), n, _ptr(env_cache),
                                         _ptr(eloc), _ptr(flags), _stream()))
         return eloc
+
+    def direct_sample(self, theta, n, chi_double, seed, offset=0, want_logw=True):
+        """n independent configurations from the direct sampler; returns
+        (samples [n, N] uint8, ln p [n], ln w [n] or None, flags [n])."""
+        import torch
+        theta = self._theta(theta)
+        dev = theta.device
+        samples = torch.empty(n, self.Lx * self.Ly, dtype=torch.uint8, device=dev)
+        logp = torch.empty(n, dtype=torch.float64, device=dev)
+        logw = torch.empty(n, dtype=torch.float64, device=dev) if want_logw else None
+        flags = torch.zeros(n, dtype=torch.int32, device=dev)
+        _check(load().peps_direct_sample(self._h, _ptr(theta), n, int(chi_double), int(seed),
+                                         int(offset), _ptr(samples), _ptr(logp), _ptr(logw),
+                                         _ptr(flags), _stream()))
+        return samples, logp, logw, flags
 
     def set_truncation(self, max_weight):
         """Maximal truncated weight of every boundary-MPS truncation (0: keep

@@ -85,6 +85,12 @@ struct peps_ctx {
   // [samples | neighbours], coefficients, ln Psi and flags of the batch
   int n_moves = 0;
   DevBuf str_idx, str_batch, str_coef, str_lp, str_fl;
+  // direct sampler: the double-layer context (D^2 lattice, bond chi_d) and
+  // its parameters, environments and dummy configuration; the row kernel's
+  // slabs, ln Psi and amplitude flags of the drawn batch
+  peps_ctx* dbl = nullptr;
+  int dbl_chi = 0;
+  DevBuf dir_th2, dir_zero, dir_env2, dir_lp2, dir_slab, dir_lp, dir_fl;
   // global working sets of the kernels whose matrices do not fit in LDS
   bool env_gm = false, s1_gm = false, s2_gm = false, smp_gm = false;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
@@ -268,7 +274,10 @@ void peps_destroy(peps_ctx* c) {
                     &c->epart,   &c->bad,       &c->mean,       &c->Tm,     &c->vec,
                     &c->eloc_tmp, &c->logpsi_tmp, &c->gws_env,   &c->gws_s1, &c->gws_s2,
                     &c->gws_smp, &c->vmc_O,      &c->vmc_dth,    &c->vmc_lp,
-                    &c->str_idx, &c->str_batch,  &c->str_coef,   &c->str_lp, &c->str_fl};
+                    &c->str_idx, &c->str_batch,  &c->str_coef,   &c->str_lp, &c->str_fl,
+                    &c->dir_th2, &c->dir_zero,   &c->dir_env2,   &c->dir_lp2, &c->dir_slab,
+                    &c->dir_lp,  &c->dir_fl};
+  if (c->dbl) peps_destroy(c->dbl);
   for (DevBuf* b : bufs) b->release();
   delete c;
 }
@@ -665,6 +674,115 @@ peps_status peps_local_energy(peps_ctx* c, const double* theta, const uint8_t* s
   if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
   return dispatch(c, theta, samples, n, (void*)env_cache, env_cache != nullptr, nullptr, eloc,
                   nullptr, flags, stream);
+}
+
+}  // extern "C"
+
+template <int M>
+static peps_status direct_rows(peps_ctx* c, int n, uint64_t seed, uint64_t offset,
+                               uint8_t* samples, double* logp, int32_t* flags, hipStream_t st) {
+  const Lattice& L = c->L;
+  peps_ctx* d = c->dbl;
+  const size_t BD = (size_t)L.bmax * L.D;
+  const size_t per_t = env_tensor_elems_per_sample(L) * c->tsize;
+  const size_t slab = direct_slab_elems(L, d->L);
+  size_t per = per_t + L.n_slots * sizeof(double) + (size_t)L.Ly * BD * BD * c->tsize +
+               slab * c->tsize;
+  if (c->env_gm) per += env_slab_elems(L, c->g.dtype) * c->tsize;
+  size_t ch = c->chunk_budget / per;
+  if (ch < 1) ch = 1;
+  if (ch > (size_t)n) ch = n;
+  peps_status s;
+  if ((s = c->env_int.ensure(ch * (per_t + L.n_slots * sizeof(double)))) != PEPS_OK) return s;
+  if ((s = c->rscr.ensure(ch * L.Ly * BD * BD * c->tsize)) != PEPS_OK) return s;
+  if ((s = c->dir_slab.ensure(ch * slab * c->tsize)) != PEPS_OK) return s;
+  void* gws = nullptr;
+  if (c->env_gm) {
+    if ((s = c->gws_env.ensure(ch * env_slab_elems(L, c->g.dtype) * c->tsize)) != PEPS_OK)
+      return s;
+    gws = c->gws_env.p;
+  }
+  HIPCHK(hipMemsetAsync(logp, 0, (size_t)n * sizeof(double), st));
+  if (flags) HIPCHK(hipMemsetAsync(flags, 0, (size_t)n * sizeof(int32_t), st));
+  for (size_t c0 = 0; c0 < (size_t)n; c0 += ch) {
+    const int m = (int)std::min(ch, (size_t)n - c0);
+    uint8_t* sm = samples + c0 * L.N;
+    char* et = (char*)c->env_int.p;
+    double* el = (double*)(et + (size_t)m * per_t);
+    int* fl = flags ? flags + c0 : nullptr;
+    for (int i = 0; i < L.Lx; ++i) {
+      {
+        ProfScope ps(c, st, PEPS_PROF_SAMPLE);
+        HIPCHK(launch_direct_row<M>(L, c->d_tab, c->theta_c.p, et, d->L, d->d_tab, c->dir_env2.p,
+                                    sm, logp + c0, fl, m, i, seed, offset + c0, c->dir_slab.p,
+                                    st));
+      }
+      if (i <= L.Lx - 2) {
+        ProfScope ps(c, st, PEPS_PROF_ENV);
+        HIPCHK(launch_env_top_step<M>(L, c->d_tab, c->theta_c.p, sm, et, el, c->rscr.p, fl, m, i,
+                                      c->jac_sweeps, gws, st));
+      }
+    }
+  }
+  return PEPS_OK;
+}
+
+extern "C" {
+
+peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_double,
+                               uint64_t seed, uint64_t offset, uint8_t* samples, double* logp,
+                               double* logw, int32_t* flags, void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (!theta || !samples || !logp) return fail(PEPS_ERR_ARG, "null theta, samples or logp");
+  if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
+  if (chi_double < 1) return fail(PEPS_ERR_ARG, "chi_double = %d must be >= 1", chi_double);
+  if (n == 0) return PEPS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const Lattice& L = c->L;
+  peps_status s;
+  if (!c->dbl || c->dbl_chi != chi_double) {
+    if (c->dbl) peps_destroy(c->dbl);
+    c->dbl = nullptr;
+    c->dbl_chi = 0;
+    peps_geom g2 = c->g;
+    g2.D = c->g.D * c->g.D;
+    g2.chi = chi_double;
+    if ((s = peps_create(&g2, &c->dbl)) != PEPS_OK) return s;
+    c->dbl_chi = chi_double;
+  }
+  peps_ctx* d = c->dbl;
+  const bool cx = is_complex(c->g.dtype);
+  const size_t nth2 = (size_t)d->L.n_params * (cx ? 2 : 1);
+  if ((s = c->dir_th2.ensure(nth2 * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->dir_zero.ensure((size_t)L.N)) != PEPS_OK) return s;
+  if ((s = c->dir_env2.ensure(peps_env_cache_bytes(d, 1))) != PEPS_OK) return s;
+  if ((s = c->dir_lp2.ensure(2 * sizeof(double) + sizeof(int32_t))) != PEPS_OK) return s;
+  HIPCHK(hipMemsetAsync(c->dir_zero.p, 0, (size_t)L.N, st));
+  HIPCHK(launch_double_theta(L, c->d_tab, d->L, d->d_tab, theta, (double*)c->dir_th2.p, cx, st));
+  // D^l of the double layer: the environments of one all-zero configuration
+  s = peps_amplitude(d, (const double*)c->dir_th2.p, (const uint8_t*)c->dir_zero.p, 1,
+                     c->dir_env2.p, (double*)c->dir_lp2.p,
+                     (int32_t*)((double*)c->dir_lp2.p + 2), stream);
+  if (s != PEPS_OK) return s;
+  if ((s = prepare_theta(c, theta, st)) != PEPS_OK) return s;
+  switch (c->g.dtype) {
+    case PEPS_F64: s = direct_rows<MODE_F64>(c, n, seed, offset, samples, logp, flags, st); break;
+    case PEPS_F32: s = direct_rows<MODE_F32>(c, n, seed, offset, samples, logp, flags, st); break;
+    case PEPS_BF16: s = direct_rows<MODE_BF16>(c, n, seed, offset, samples, logp, flags, st); break;
+    case PEPS_C128: s = direct_rows<MODE_C128>(c, n, seed, offset, samples, logp, flags, st); break;
+    default: s = direct_rows<MODE_C64>(c, n, seed, offset, samples, logp, flags, st);
+  }
+  if (s != PEPS_OK) return s;
+  if (logw) {
+    if ((s = c->dir_lp.ensure((size_t)n * 2 * sizeof(double))) != PEPS_OK) return s;
+    if ((s = c->dir_fl.ensure((size_t)n * sizeof(int32_t))) != PEPS_OK) return s;
+    s = dispatch(c, theta, samples, n, nullptr, false, (double*)c->dir_lp.p, nullptr, nullptr,
+                 (int*)c->dir_fl.p, stream);
+    if (s != PEPS_OK) return s;
+    HIPCHK(launch_direct_logw(n, (const double*)c->dir_lp.p, logp, (const int*)c->dir_fl.p, logw,
+                              flags, st));
+  }
+  return PEPS_OK;
 }
 
 peps_status peps_set_truncation(peps_ctx* c, double max_weight) {

@@ -81,6 +81,25 @@ hipError_t launch_strict_expand(const Lattice& L, const HamDev& H, int n_moves,
 hipError_t launch_strict_combine(int n, const int* off, const double* coef, const double* lp,
                                  const int* bfl, double* eloc, int* flags, hipStream_t st);
 
+// direct sampler: double-layer parameters, one top-environment step for a
+// batch, one row drawn for a batch, the importance weights
+size_t direct_slab_elems(const Lattice& L, const Lattice& L2);
+hipError_t launch_double_theta(const Lattice& L, const int* tab, const Lattice& L2,
+                               const int* tab2, const double* theta, double* dst, bool cplx_,
+                               hipStream_t st);
+template <int M>
+hipError_t launch_env_top_step(const Lattice& L, const int* tab, const void* theta,
+                               const uint8_t* samples, void* env, double* logs, void* rscr,
+                               int* flags, int n, int t, int jac_sweeps, void* gws,
+                               hipStream_t st);
+template <int M>
+hipError_t launch_direct_row(const Lattice& L, const int* tab, const void* theta, const void* env,
+                             const Lattice& L2, const int* tab2, const void* env2,
+                             uint8_t* samples, double* logp, int* flags, int n, int i,
+                             uint64_t seed, uint64_t offset, void* slab, hipStream_t st);
+hipError_t launch_direct_logw(int n, const double* lpsi, const double* logp, const int* afl,
+                              double* logw, int* flags, hipStream_t st);
+
 // Metropolis sampler
 size_t sample_lds_elems(int bmax, int D, int mode);
 template <int M>

@@ -1,0 +1,100 @@
+"""Direct sampler through the C-ABI (App. "Direct sampling of PEPS"):
+FP64 and complex128 draws identical to the oracle's (same Philox stream)
+with ln p at 1e-10; in the exact regime ln w = ln|Psi|^2 - ln p equals
+ln <Psi|Psi> for every draw; ln w consistent with the library's amplitude;
+at 8x8 D=4 chi=16 chi_d=4 the FP64 draws equal the oracle's and FP32 ln p
+matches the oracle's ln p of the same configurations."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, peps
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_12557_amd import load
+    load()
+    return torch.device("cuda:0")
+
+
+def _ctx(Lx, Ly, D, chi, dtype):
+    from paper_2503_12557_amd import Context
+    return Context(Lx, Ly, D, chi, dtype)
+
+
+@pytest.mark.parametrize("Lx,Ly,D,chi,chid,cplx", [(3, 3, 2, 4, 4, False), (4, 4, 2, 3, 2, False),
+                                                   (4, 3, 3, 4, 3, False), (2, 5, 2, 2, 3, False),
+                                                   (3, 3, 2, 4, 4, True), (4, 3, 2, 3, 2, True)])
+def test_draws_identical_to_oracle(dev, Lx, Ly, D, chi, chid, cplx):
+    n = 6
+    theta = synth.theta(Lx, Ly, 2, D, seed=80 + Lx + Ly + D, cplx=cplx)
+    ctx = _ctx(Lx, Ly, D, chi, "c128" if cplx else "f64")
+    th = torch.from_numpy(theta).to(dev)
+    s, lp, lw, fl = ctx.direct_sample(th, n, chid, seed=17, offset=5)
+    g = peps.Geometry(Lx, Ly, 2, D)
+    rs, rlp = direct.sample(theta, g, chi, chid, n, seed=17, offset=5)
+    assert (fl.cpu().numpy() & 3).max() == 0
+    assert np.array_equal(s.cpu().numpy(), rs)
+    assert np.abs(lp.cpu().numpy() - rlp).max() < 1e-10 * max(1.0, np.abs(rlp).max())
+
+
+def test_exact_regime_weights_are_the_norm(dev):
+    Lx, Ly, D = 3, 3, 2
+    theta = synth.theta(Lx, Ly, 2, D, seed=7)
+    ctx = _ctx(Lx, Ly, D, 4, "f64")
+    s, lp, lw, _ = ctx.direct_sample(torch.from_numpy(theta).to(dev), 64, 16, seed=3)
+    cf = np.array(list(itertools.product([0, 1], repeat=9)), dtype=np.uint8)
+    psi = peps.exact_amplitudes(theta, peps.Geometry(Lx, Ly, 2, D), cf)
+    lnz = np.log(np.sum(np.abs(psi) ** 2))
+    assert np.abs(lw.cpu().numpy() - lnz).max() < 1e-10 * max(1.0, abs(lnz))
+
+
+def test_log_weights_match_the_amplitude(dev):
+    Lx, Ly, D, chi, chid = 5, 4, 3, 4, 3
+    theta = synth.theta(Lx, Ly, 2, D, seed=12)
+    ctx = _ctx(Lx, Ly, D, chi, "f64")
+    th = torch.from_numpy(theta).to(dev)
+    s, lp, lw, _ = ctx.direct_sample(th, 32, chid, seed=8)
+    lpsi, _ = ctx.amplitude(th, s)
+    ref = 2 * lpsi[:, 0] - lp
+    assert torch.allclose(lw, ref, rtol=0, atol=1e-12)
+    # reweighted draws: a finite, positive effective sample size
+    w = torch.exp(lw - lw.max())
+    ess = (w.sum() ** 2 / (w * w).sum()).item()
+    assert 1.0 <= ess <= 32.0
+
+
+def test_8x8_D4_chi16(dev):
+    Lx = Ly = 8
+    D, chi, chid = 4, 16, 4
+    theta = synth.theta(Lx, Ly, 2, D, seed=70)
+    g = peps.Geometry(Lx, Ly, 2, D)
+    th = torch.from_numpy(theta).to(dev)
+    s64, lp64, _, fl = _ctx(Lx, Ly, D, chi, "f64").direct_sample(th, 2, chid, seed=3,
+                                                                 want_logw=False)
+    rs, rlp = direct.sample(theta, g, chi, chid, 2, seed=3)
+    assert np.array_equal(s64.cpu().numpy(), rs)
+    assert np.abs(lp64.cpu().numpy() - rlp).max() < 1e-9 * np.abs(rlp).max()
+    s32, lp32, _, _ = _ctx(Lx, Ly, D, chi, "f32").direct_sample(th, 2, chid, seed=4,
+                                                                want_logw=False)
+    ref = direct.log_prob(theta, g, chi, chid, s32.cpu().numpy())
+    assert np.abs(lp32.cpu().numpy() - ref).max() < 1e-3 * np.abs(ref).max()
+
+
+def test_direct_sample_argument_errors(dev):
+    from paper_2503_12557_amd import PepsError
+    th = torch.from_numpy(synth.theta(3, 3, 2, 5, seed=1)).to(dev)
+    with pytest.raises(PepsError):
+        _ctx(3, 3, 5, 4, "f64").direct_sample(th, 4, 4, seed=1)   # D^2 = 25 > 16
+    th2 = torch.from_numpy(synth.theta(3, 3, 2, 2, seed=1)).to(dev)
+    with pytest.raises(PepsError):
+        _ctx(3, 3, 2, 4, "f64").direct_sample(th2, 4, 0, seed=1)
