@@ -415,6 +415,26 @@ def main():
         "samples_per_s": round(n / t_cut, 2),
         "delta_psi_median": float(np.median(dpsi)), "delta_psi_p99": float(np.quantile(dpsi, 0.99)),
         "energy_mean": float(outc[1][:, 0].double().mean().item())}
+    # direct sampler (independent draws, importance weights) on the same
+    # workload: 1024 draws, chi_d = D, in the bench's compute dtype
+    nd = min(n, 1024)
+    ctx.direct_sample(theta, 64, D, seed=12, want_logw=False)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    _sync()
+    t0 = time.perf_counter()
+    sd, lpd, lwd, fld = ctx.direct_sample(theta, nd, D, seed=13)
+    _sync()
+    t_dir = time.perf_counter() - t0
+    pdir = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    wd = torch.exp(lwd - lwd.max())
+    ess = (wd.sum() ** 2 / (wd * wd).sum()).item()
+    res["direct_sampler"] = {
+        "samples": nd, "chi_double": D, "seconds": round(t_dir, 3),
+        "samples_per_s": round(nd / t_dir, 2), "importance_ess": round(ess, 2),
+        "ess_per_s": round(ess / t_dir, 2), "flags_or": int(fld.max().item()),
+        "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pdir.items() if v[1]}}
     # strict local energy (every amplitude at the one cut) on the first 64
     # configurations of the batch, in the bench's compute dtype
     ks = min(n, 64)
