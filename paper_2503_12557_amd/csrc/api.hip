@@ -90,6 +90,8 @@ struct peps_ctx {
   // slabs, ln Psi and amplitude flags of the drawn batch
   peps_ctx* dbl = nullptr;
   int dbl_chi = 0;
+  // environments from the bottom only (the double-layer context)
+  bool bottom_only = false;
   DevBuf dir_th2, dir_zero, dir_env2, dir_lp2, dir_slab, dir_lp, dir_fl;
   // global working sets of the kernels whose matrices do not fit in LDS
   bool env_gm = false, s1_gm = false, s2_gm = false, smp_gm = false;
@@ -511,7 +513,7 @@ static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int m, char* en
   }
   ProfScope ps(c, st, PEPS_PROF_ENV);
   HIPCHK(launch_env_sweep<M>(L, c->d_tab, c->theta_c.p, samples, env_t, env_l, c->rscr.p, flags,
-                             m, c->jac_sweeps, gws, st));
+                             m, c->jac_sweeps, gws, st, c->bottom_only));
   return PEPS_OK;
 }
 
@@ -748,6 +750,7 @@ peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_
     g2.D = c->g.D * c->g.D;
     g2.chi = chi_double;
     if ((s = peps_create(&g2, &c->dbl)) != PEPS_OK) return s;
+    c->dbl->bottom_only = true;
     c->dbl_chi = chi_double;
   }
   peps_ctx* d = c->dbl;
@@ -759,10 +762,10 @@ peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_
   if ((s = c->dir_lp2.ensure(2 * sizeof(double) + sizeof(int32_t))) != PEPS_OK) return s;
   HIPCHK(hipMemsetAsync(c->dir_zero.p, 0, (size_t)L.N, st));
   HIPCHK(launch_double_theta(L, c->d_tab, d->L, d->d_tab, theta, (double*)c->dir_th2.p, cx, st));
-  // D^l of the double layer: the environments of one all-zero configuration
+  // D^l of the double layer: the bottom environments of one all-zero
+  // configuration (no top sweep, no amplitude)
   s = peps_amplitude(d, (const double*)c->dir_th2.p, (const uint8_t*)c->dir_zero.p, 1,
-                     c->dir_env2.p, (double*)c->dir_lp2.p,
-                     (int32_t*)((double*)c->dir_lp2.p + 2), stream);
+                     c->dir_env2.p, nullptr, (int32_t*)((double*)c->dir_lp2.p + 2), stream);
   if (s != PEPS_OK) return s;
   if ((s = prepare_theta(c, theta, st)) != PEPS_OK) return s;
   switch (c->g.dtype) {

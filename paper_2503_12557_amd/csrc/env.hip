@@ -30,14 +30,15 @@ k_env_sweep(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* 
             const uint8_t* __restrict__ samples, typename ModeT<M>::T* __restrict__ env,
             double* __restrict__ logs, typename ModeT<M>::T* __restrict__ rscr,
             int* __restrict__ flags, int n, int jac_sweeps, typename ModeT<M>::T* __restrict__ gws,
-            size_t slab) {
+            size_t slab, int dir0) {
   typedef typename ModeT<M>::T T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int smp = blockIdx.x;
-  const bool bottom = blockIdx.y == 1;
+  const int dir = (int)blockIdx.y + dir0;  // 0: from the top, 1: from the bottom
+  const bool bottom = dir == 1;
   if (smp >= n) return;
   T* lds = reinterpret_cast<T*>(smem_raw);
-  T* big = GM ? gws + ((size_t)smp * 2 + blockIdx.y) * slab : lds;
+  T* big = GM ? gws + ((size_t)smp * 2 + dir) * slab : lds;
   T* small = GM ? lds : lds + env_big_elems(L.bmax, L.D, M);
   const EnvSmem<T> sh(big, small, L, tsqr_path(M, L.bmax, L.D) && PEPS_NT == 256);
   const int BD = L.bmax * L.D;
@@ -152,23 +153,25 @@ size_t env_slab_elems(const Lattice& L, int mode) {
 template <int M>
 hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
                             const uint8_t* samples, void* env, double* logs, void* rscr,
-                            int* flags, int n, int jac_sweeps, void* gws, hipStream_t st) {
+                            int* flags, int n, int jac_sweeps, void* gws, hipStream_t st,
+                            bool bottom_only) {
   typedef typename ModeT<M>::T T;
-  dim3 grid(n, 2);
+  const dim3 grid(n, bottom_only ? 1 : 2);
+  const int dir0 = bottom_only ? 1 : 0;
   if (gws) {
     const size_t lds = env_lds_bytes(M, L, true);
     hipFuncSetAttribute((const void*)k_env_sweep<M, true>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_env_sweep<M, true>), grid, dim3(env_threads(M)), lds, st, L, tab,
                        (const T*)theta, samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps,
-                       (T*)gws, env_slab_elems(L, M));
+                       (T*)gws, env_slab_elems(L, M), dir0);
   } else {
     const size_t lds = env_lds_bytes(M, L, false);
     hipFuncSetAttribute((const void*)k_env_sweep<M, false>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_env_sweep<M, false>), grid, dim3(env_threads(M)), lds, st, L, tab,
                        (const T*)theta, samples, (T*)env, logs, (T*)rscr, flags, n, jac_sweeps,
-                       (T*)nullptr, (size_t)0);
+                       (T*)nullptr, (size_t)0, dir0);
   }
   return hipGetLastError();
 }
@@ -205,7 +208,7 @@ hipError_t launch_convert_theta(int mode, const double* src, void* dst, int n, i
 #define INST(M)                                                                                 \
   template hipError_t launch_env_sweep<M>(const Lattice&, const int*, const void*,             \
                                           const uint8_t*, void*, double*, void*, int*, int, int, \
-                                          void*, hipStream_t);                                  \
+                                          void*, hipStream_t, bool);                            \
   template hipError_t launch_overlap<M>(const Lattice&, const int*, const void*, const double*, \
                                         int, double*, int*, int, hipStream_t);
 INST(MODE_F64)

@@ -50,7 +50,8 @@ size_t sample_slab_elems(const Lattice& L, int mode);
 template <int M>
 hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
                             const uint8_t* samples, void* env, double* logs, void* rscr,
-                            int* flags, int n, int jac_sweeps, void* gws, hipStream_t st);
+                            int* flags, int n, int jac_sweeps, void* gws, hipStream_t st,
+                            bool bottom_only = false);
 template <int M>
 hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, const double* logs,
                           int icut, double* logpsi, int* flags, int n, hipStream_t st);
