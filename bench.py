@@ -430,10 +430,15 @@ def main():
     ctx.profile(False)
     wd = torch.exp(lwd - lwd.max())
     ess = (wd.sum() ** 2 / (wd * wd).sum()).item()
+    # the reweighted energy of the direct draws (self-normalised importance
+    # sampling) beside the Metropolis batch mean
+    eld = ctx.local_energy(theta, sd)[:, 0].double()
+    e_dir = ((wd * eld).sum() / wd.sum()).item()
     res["direct_sampler"] = {
         "samples": nd, "chi_double": D, "seconds": round(t_dir, 3),
         "samples_per_s": round(nd / t_dir, 2), "importance_ess": round(ess, 2),
         "ess_per_s": round(ess / t_dir, 2), "flags_or": int(fld.max().item()),
+        "reweighted_energy": e_dir, "metropolis_energy_fp64": e_hi,
         "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pdir.items() if v[1]}}
     # strict local energy (every amplitude at the one cut) on the first 64
     # configurations of the batch, in the bench's compute dtype

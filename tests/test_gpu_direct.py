@@ -98,3 +98,35 @@ def test_direct_sample_argument_errors(dev):
     th2 = torch.from_numpy(synth.theta(3, 3, 2, 2, seed=1)).to(dev)
     with pytest.raises(PepsError):
         _ctx(3, 3, 2, 4, "f64").direct_sample(th2, 4, 0, seed=1)
+
+
+def test_reweighted_energy_is_unbiased_under_a_truncated_double_layer(dev):
+    # chi_d = 2 < D^2 makes p(S) differ from |Psi|^2; the importance weights
+    # |Psi|^2 / p restore the exact variational energy (3x4, D = 2, chi = 4:
+    # Psi itself is exact), within the statistical error of 8192 draws
+    from oracle import hamiltonian as OH
+    from tests.gpu_util import product_ham
+    Lx, Ly, D, chi = 3, 4, 2, 4
+    theta = synth.theta(Lx, Ly, 2, D, seed=9, mu=0.3)
+    ctx = _ctx(Lx, Ly, D, chi, "f64")
+    model = ("j1j2", dict(J1=1.0, J2=0.5))
+    ctx.set_hamiltonian(product_ham(model, Lx, Ly))
+    th = torch.from_numpy(theta).to(dev)
+    n = 8192
+    s, lp, lw, fl = ctx.direct_sample(th, n, 2, seed=31)
+    assert (fl.cpu().numpy() & 3).max() == 0
+    e = ctx.local_energy(th, s)[:, 0].cpu().numpy()
+    w = np.exp(lw.cpu().numpy() - lw.cpu().numpy().max())
+    w /= w.sum()
+    est = float(np.sum(w * e))
+    # delta-method standard error of the self-normalised estimator
+    se = float(np.sqrt(np.sum(w ** 2 * (e - est) ** 2)))
+    N = Lx * Ly
+    Hm = OH.sparse_matrix(OH.j1j2(Lx, Ly, 1.0, 0.5))
+    allc = np.array([OH.int_to_config(v, N) for v in range(1 << N)], dtype=np.uint8)
+    psi = peps.exact_amplitudes(theta, peps.Geometry(Lx, Ly, 2, D), allc)
+    exact = float(np.real(np.vdot(psi, Hm @ psi) / np.vdot(psi, psi)))
+    assert abs(est - exact) < 5 * se + 1e-9, (est, exact, se)
+    # the unweighted mean is biased by the truncation (p != |Psi|^2)
+    lp_true = 2 * np.log(np.abs(psi[[int(''.join(map(str, r)), 2) for r in s.cpu().numpy()]]))
+    assert np.abs(lp.cpu().numpy() + np.log(np.sum(np.abs(psi) ** 2)) - lp_true).max() > 1e-3
