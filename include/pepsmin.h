@@ -305,7 +305,7 @@ peps_status peps_profile_read(peps_ctx* ctx, double* ms, long* counts, int reset
 /* ------------------------------------------------------------------------
  * Learned proposal for independence Metropolis-Hastings (an extension: the
  * paper corrects approximate samples by importance weights, App. "direct
- * sampling of PEPS"; here the PEPS judges every proposal through the
+ * sampling of PEPS"; here the PEPS arbitrates every proposal through the
  * acceptance |Psi(S')|^2 q(S) / (|Psi(S)|^2 q(S'))).
  * q is a masked autoregressive network over the N sites in raster order with
  * one hidden ReLU layer of width H (H <= 256): hidden degrees

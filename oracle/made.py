@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``). Plain numpy FP64.
 
 The paper samples its PEPS directly and corrects approximate samples by
 importance weights (App. "direct sampling of PEPS"); the learned proposal is
-an extension: the PEPS stays the judge through the Metropolis-Hastings
+an extension: the PEPS stays the arbiter through the Metropolis-Hastings
 acceptance |Psi(S')|^2 q(S) / (|Psi(S)|^2 q(S')).
 
 Model (one hidden layer of width H, ReLU):

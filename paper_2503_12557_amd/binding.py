@@ -452,7 +452,7 @@ def imh_step(state, state_lp, state_lq, prop, prop_lp, prop_lq, seed, step, acce
 def run_imh(ctx, theta, made, params, n_chains, n_steps, seed=0, record=None, init=None):
     """Independence MH chains driven by the learned proposal: every step draws
     one proposal per chain from q, evaluates ln|Psi| of the proposals with
-    peps_amplitude and accepts with the PEPS as the judge. Chains start from
+    peps_amplitude and accepts with the PEPS as the arbiter. Chains start from
     `init` (uint8 [n_chains][N] on the device, e.g. local-Metropolis samples)
     or from a draw of q. Returns the final states, the visited states per
     step ([n_steps][n_chains][N] if record) and the acceptance counts."""

@@ -1,7 +1,7 @@
 // Learned proposal: a masked autoregressive network over the sites in
 // raster order (one hidden ReLU layer), trained on configurations drawn by
 // the PEPS sampler, and the independence Metropolis-Hastings step that keeps
-// the PEPS as the judge: accept S' with probability
+// the PEPS as the arbiter: accept S' with probability
 // min(1, |Psi(S')|^2 q(S) / (|Psi(S)|^2 q(S'))).
 //
 // Masks: hidden degree m(k) = (k mod (N-1)) + 1, input mask [m(k) >= n+1],
