@@ -428,6 +428,12 @@ def main():
     t_dir = time.perf_counter() - t0
     pdir = ctx.profile_read(reset=True)
     ctx.profile(False)
+    # the same draws reusing the double-layer environments just built
+    _sync()
+    t0 = time.perf_counter()
+    ctx.direct_sample(theta, nd, D, seed=13, refresh=False)
+    _sync()
+    t_reuse = time.perf_counter() - t0
     wd = torch.exp(lwd - lwd.max())
     ess = (wd.sum() ** 2 / (wd * wd).sum()).item()
     # the reweighted energy of the direct draws (self-normalised importance
@@ -439,6 +445,8 @@ def main():
         "samples_per_s": round(nd / t_dir, 2), "importance_ess": round(ess, 2),
         "ess_per_s": round(ess / t_dir, 2), "flags_or": int(fld.max().item()),
         "reweighted_energy": e_dir, "metropolis_energy_fp64": e_hi,
+        "seconds_reusing_double_layer": round(t_reuse, 3),
+        "samples_per_s_reusing_double_layer": round(nd / t_reuse, 2),
         "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pdir.items() if v[1]}}
     # strict local energy (every amplitude at the one cut) on the first 64
     # configurations of the batch, in the bench's compute dtype

@@ -135,8 +135,12 @@ peps_status peps_set_hamiltonian(peps_ctx* ctx, int n_terms, const int* term_nsi
  * drawn rows (bond chi, truncated as in peps_amplitude) times the open row
  * i (its bond chi*D is not truncated further), and D^l[i+1] the boundary
  * MPS from the bottom of the double-layer network (site tensors
- * sum_p T[p] x conj(T[p]), bond D^2) with bond chi_double, built once per
- * call. Sites are drawn from the left: s = 0 iff u < q_0 / (q_0 + q_1) with
+ * sum_p T[p] x conj(T[p]), bond D^2) with bond chi_double. refresh != 0
+ * builds D^l from theta; refresh = 0 reuses the D^l of the context's last
+ * refresh (same chi_double, else PEPS_ERR_ARG), possibly of older tensors:
+ * the paper's stale double-layer environments, which leave the importance
+ * weights exact because ln p is the sampler's own. n = 0 with refresh != 0
+ * only builds D^l. Sites are drawn from the left: s = 0 iff u < q_0 / (q_0 + q_1) with
  * u from Philox4x32-10 (key = seed; counter (site, j mod 2^32, j >> 32,
  * 0x44495243), j = offset + index); a negative q counts as 0.
  * samples: device uint8 [n][N] (written); logp: device FP64 [n], ln p(S)
@@ -149,8 +153,8 @@ peps_status peps_set_hamiltonian(peps_ctx* ctx, int n_terms, const int* term_nsi
  * per-sample slabs of O(Ly chi^2 D^2 chi_double) elements) is grown on
  * demand; returns with the work queued on the stream. */
 peps_status peps_direct_sample(peps_ctx* ctx, const double* theta, int n, int chi_double,
-                               uint64_t seed, uint64_t offset, uint8_t* samples, double* logp,
-                               double* logw, int32_t* flags, void* stream);
+                               int refresh, uint64_t seed, uint64_t offset, uint8_t* samples,
+                               double* logp, double* logw, int32_t* flags, void* stream);
 
 /* Truncation rule of every boundary-MPS compression of the context
  * (environments, amplitudes, strips, sampler; Sec. "On the boundary MPS

@@ -139,10 +139,15 @@ def _walk(T, g, chi, Dl_env, uniforms=None, fixed=None):
     return s, logp
 
 
-def sample(theta, g: peps.Geometry, chi: int, chi_d: int, n: int, seed: int, offset: int = 0):
-    """n independent configurations and ln p(S) of each."""
+def sample(theta, g: peps.Geometry, chi: int, chi_d: int, n: int, seed: int, offset: int = 0,
+           theta_double=None):
+    """n independent configurations and ln p(S) of each. theta_double: the
+    tensors D^l is built from, when they are older than theta (the stale
+    double-layer environments of the paper's asynchronous scheme; p stays
+    the sampler's own, so the importance weights remain exact)."""
     T = peps.site_tensors(theta, g)
-    Dl_env = double_bottom_environments(T, g, chi_d)
+    T2 = T if theta_double is None else peps.site_tensors(theta_double, g)
+    Dl_env = double_bottom_environments(T2, g, chi_d)
     key = seed_key(seed)
     out = np.zeros((n, g.N), dtype=np.uint8)
     logp = np.zeros(n)
@@ -156,8 +161,9 @@ def sample(theta, g: peps.Geometry, chi: int, chi_d: int, n: int, seed: int, off
     return out, logp
 
 
-def log_prob(theta, g: peps.Geometry, chi: int, chi_d: int, configs):
+def log_prob(theta, g: peps.Geometry, chi: int, chi_d: int, configs, theta_double=None):
     """ln p(S) of given configurations under the direct sampler."""
     T = peps.site_tensors(theta, g)
-    Dl_env = double_bottom_environments(T, g, chi_d)
+    T2 = T if theta_double is None else peps.site_tensors(theta_double, g)
+    Dl_env = double_bottom_environments(T2, g, chi_d)
     return np.array([_walk(T, g, chi, Dl_env, fixed=np.asarray(s))[1] for s in configs])

@@ -77,8 +77,8 @@ def load():
     lib.peps_local_energy_strict.restype = I
     lib.peps_set_truncation.argtypes = [P, ctypes.c_double]
     lib.peps_set_truncation.restype = I
-    lib.peps_direct_sample.argtypes = [P, P, I, I, ctypes.c_uint64, ctypes.c_uint64, P, P, P, P,
-                                       P]
+    lib.peps_direct_sample.argtypes = [P, P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P, P, P,
+                                       P, P]
     lib.peps_direct_sample.restype = I
     lib.peps_logderiv.argtypes = [P, P, P, I, P, P, P]
     lib.peps_logderiv.restype = I
@@ -229,9 +229,11 @@ class Context:
                                         _ptr(eloc), _ptr(flags), _stream()))
         return eloc
 
-    def direct_sample(self, theta, n, chi_double, seed, offset=0, want_logw=True):
+    def direct_sample(self, theta, n, chi_double, seed, offset=0, want_logw=True, refresh=True):
         """n independent configurations from the direct sampler; returns
-        (samples [n, N] uint8, ln p [n], ln w [n] or None, flags [n])."""
+        (samples [n, N] uint8, ln p [n], ln w [n] or None, flags [n]).
+        refresh=False reuses the double-layer environments of the last
+        refresh (possibly of older tensors)."""
         import torch
         theta = self._theta(theta)
         dev = theta.device
@@ -239,9 +241,10 @@ class Context:
         logp = torch.empty(n, dtype=torch.float64, device=dev)
         logw = torch.empty(n, dtype=torch.float64, device=dev) if want_logw else None
         flags = torch.zeros(n, dtype=torch.int32, device=dev)
-        _check(load().peps_direct_sample(self._h, _ptr(theta), n, int(chi_double), int(seed),
-                                         int(offset), _ptr(samples), _ptr(logp), _ptr(logw),
-                                         _ptr(flags), _stream()))
+        _check(load().peps_direct_sample(self._h, _ptr(theta), n, int(chi_double),
+                                         1 if refresh else 0, int(seed), int(offset),
+                                         _ptr(samples), _ptr(logp), _ptr(logw), _ptr(flags),
+                                         _stream()))
         return samples, logp, logw, flags
 
     def set_truncation(self, max_weight):

@@ -90,6 +90,7 @@ struct peps_ctx {
   // slabs, ln Psi and amplitude flags of the drawn batch
   peps_ctx* dbl = nullptr;
   int dbl_chi = 0;
+  bool dbl_built = false;  // dir_env2 holds D^l of the last refresh
   // environments from the bottom only (the double-layer context)
   bool bottom_only = false;
   DevBuf dir_th2, dir_zero, dir_env2, dir_lp2, dir_slab, dir_lp, dir_fl;
@@ -732,13 +733,17 @@ static peps_status direct_rows(peps_ctx* c, int n, uint64_t seed, uint64_t offse
 extern "C" {
 
 peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_double,
-                               uint64_t seed, uint64_t offset, uint8_t* samples, double* logp,
-                               double* logw, int32_t* flags, void* stream) {
+                               int refresh, uint64_t seed, uint64_t offset, uint8_t* samples,
+                               double* logp, double* logw, int32_t* flags, void* stream) {
   if (!c) return fail(PEPS_ERR_ARG, "null context");
-  if (!theta || !samples || !logp) return fail(PEPS_ERR_ARG, "null theta, samples or logp");
+  if (!theta) return fail(PEPS_ERR_ARG, "null theta");
   if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
+  if (n > 0 && (!samples || !logp)) return fail(PEPS_ERR_ARG, "null samples or logp");
   if (chi_double < 1) return fail(PEPS_ERR_ARG, "chi_double = %d must be >= 1", chi_double);
-  if (n == 0) return PEPS_OK;
+  if (!refresh && (!c->dbl || !c->dbl_built || c->dbl_chi != chi_double))
+    return fail(PEPS_ERR_ARG, "no double-layer environments with chi_double = %d to reuse",
+                chi_double);
+  if (n == 0 && !refresh) return PEPS_OK;
   hipStream_t st = (hipStream_t)stream;
   const Lattice& L = c->L;
   peps_status s;
@@ -746,6 +751,7 @@ peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_
     if (c->dbl) peps_destroy(c->dbl);
     c->dbl = nullptr;
     c->dbl_chi = 0;
+    c->dbl_built = false;
     peps_geom g2 = c->g;
     g2.D = c->g.D * c->g.D;
     g2.chi = chi_double;
@@ -754,19 +760,25 @@ peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_
     c->dbl_chi = chi_double;
   }
   peps_ctx* d = c->dbl;
-  const bool cx = is_complex(c->g.dtype);
-  const size_t nth2 = (size_t)d->L.n_params * (cx ? 2 : 1);
-  if ((s = c->dir_th2.ensure(nth2 * sizeof(double))) != PEPS_OK) return s;
-  if ((s = c->dir_zero.ensure((size_t)L.N)) != PEPS_OK) return s;
-  if ((s = c->dir_env2.ensure(peps_env_cache_bytes(d, 1))) != PEPS_OK) return s;
-  if ((s = c->dir_lp2.ensure(2 * sizeof(double) + sizeof(int32_t))) != PEPS_OK) return s;
-  HIPCHK(hipMemsetAsync(c->dir_zero.p, 0, (size_t)L.N, st));
-  HIPCHK(launch_double_theta(L, c->d_tab, d->L, d->d_tab, theta, (double*)c->dir_th2.p, cx, st));
-  // D^l of the double layer: the bottom environments of one all-zero
-  // configuration (no top sweep, no amplitude)
-  s = peps_amplitude(d, (const double*)c->dir_th2.p, (const uint8_t*)c->dir_zero.p, 1,
-                     c->dir_env2.p, nullptr, (int32_t*)((double*)c->dir_lp2.p + 2), stream);
-  if (s != PEPS_OK) return s;
+  if (refresh) {
+    c->dbl_built = false;
+    const bool cx = is_complex(c->g.dtype);
+    const size_t nth2 = (size_t)d->L.n_params * (cx ? 2 : 1);
+    if ((s = c->dir_th2.ensure(nth2 * sizeof(double))) != PEPS_OK) return s;
+    if ((s = c->dir_zero.ensure((size_t)L.N)) != PEPS_OK) return s;
+    if ((s = c->dir_env2.ensure(peps_env_cache_bytes(d, 1))) != PEPS_OK) return s;
+    if ((s = c->dir_lp2.ensure(2 * sizeof(double) + sizeof(int32_t))) != PEPS_OK) return s;
+    HIPCHK(hipMemsetAsync(c->dir_zero.p, 0, (size_t)L.N, st));
+    HIPCHK(launch_double_theta(L, c->d_tab, d->L, d->d_tab, theta, (double*)c->dir_th2.p, cx,
+                               st));
+    // D^l of the double layer: the bottom environments of one all-zero
+    // configuration (no top sweep, no amplitude)
+    s = peps_amplitude(d, (const double*)c->dir_th2.p, (const uint8_t*)c->dir_zero.p, 1,
+                       c->dir_env2.p, nullptr, (int32_t*)((double*)c->dir_lp2.p + 2), stream);
+    if (s != PEPS_OK) return s;
+    c->dbl_built = true;
+  }
+  if (n == 0) return PEPS_OK;
   if ((s = prepare_theta(c, theta, st)) != PEPS_OK) return s;
   switch (c->g.dtype) {
     case PEPS_F64: s = direct_rows<MODE_F64>(c, n, seed, offset, samples, logp, flags, st); break;

@@ -47,7 +47,7 @@ def test_null_context_is_rejected():
     assert lib.peps_env_cache_bytes(None, 4) == 0
     assert lib.peps_local_energy_strict(None, None, None, 1, None, None, None) == 1
     assert lib.peps_set_truncation(None, 1e-4) == 1
-    assert lib.peps_direct_sample(None, None, 4, 4, 1, 0, None, None, None, None, None) == 1
+    assert lib.peps_direct_sample(None, None, 4, 4, 1, 1, 0, None, None, None, None, None) == 1
     assert lib.peps_vmc_step(None, None, 0, 1, 1, 0, 1, 1, 0, 0.1, 1e-4, 1e-12, None, None,
                              None, None, None) == 1
 

@@ -130,3 +130,22 @@ def test_reweighted_energy_is_unbiased_under_a_truncated_double_layer(dev):
     # the unweighted mean is biased by the truncation (p != |Psi|^2)
     lp_true = 2 * np.log(np.abs(psi[[int(''.join(map(str, r)), 2) for r in s.cpu().numpy()]]))
     assert np.abs(lp.cpu().numpy() + np.log(np.sum(np.abs(psi) ** 2)) - lp_true).max() > 1e-3
+
+
+def test_reused_double_layer_matches_the_oracle_with_stale_tensors(dev):
+    from paper_2503_12557_amd import PepsError
+    Lx, Ly, D, chi, chid = 4, 3, 2, 3, 3
+    old = synth.theta(Lx, Ly, 2, D, seed=5)
+    new = synth.theta(Lx, Ly, 2, D, seed=6)
+    ctx = _ctx(Lx, Ly, D, chi, "f64")
+    with pytest.raises(PepsError):
+        ctx.direct_sample(torch.from_numpy(new).to(dev), 4, chid, seed=1, refresh=False)
+    ctx.direct_sample(torch.from_numpy(old).to(dev), 0, chid, seed=1)      # builds D^l only
+    s, lp, lw, _ = ctx.direct_sample(torch.from_numpy(new).to(dev), 6, chid, seed=2,
+                                     refresh=False)
+    g = peps.Geometry(Lx, Ly, 2, D)
+    rs, rlp = direct.sample(new, g, chi, chid, 6, seed=2, theta_double=old)
+    assert np.array_equal(s.cpu().numpy(), rs)
+    assert np.abs(lp.cpu().numpy() - rlp).max() < 1e-10 * max(1.0, np.abs(rlp).max())
+    with pytest.raises(PepsError):
+        ctx.direct_sample(torch.from_numpy(new).to(dev), 4, chid + 1, seed=1, refresh=False)

@@ -81,3 +81,17 @@ def test_histogram_matches_the_sampler_distribution():
     if e[-1] == 0:
         c, e = c[:-1], e[:-1]
     assert stats.chisquare(c, e).pvalue > 1e-3
+
+
+def test_stale_double_layer_keeps_p_normalised():
+    # D^l from older tensors (the asynchronous scheme): p is still a
+    # normalised distribution, now away from |Psi|^2 even at exact chi_d
+    Lx, Ly, D = 3, 3, 2
+    g = peps.Geometry(Lx, Ly, 2, D)
+    th = synth.theta(Lx, Ly, 2, D, seed=7)
+    old = synth.theta(Lx, Ly, 2, D, seed=70)
+    cf = _all_configs(9)
+    p = np.exp(direct.log_prob(th, g, 4, 16, cf, theta_double=old))
+    assert abs(p.sum() - 1) < 1e-12
+    psi = peps.exact_amplitudes(th, g, cf)
+    assert np.abs(p - np.abs(psi) ** 2 / np.sum(np.abs(psi) ** 2)).max() > 1e-4
