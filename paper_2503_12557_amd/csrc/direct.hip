@@ -142,6 +142,13 @@ k_direct_row(Lattice L, const int* __restrict__ tab,
   typedef typename ModeT<M>::T T;
   __shared__ T red[8];
   __shared__ double dred[8];
+  // the column's small tensors, read in every inner sum, staged in LDS:
+  // E (<= B D B), T[0], T[1] (<= D^4 each), D^l (<= Bd D^2 Bd)
+  extern __shared__ __align__(16) unsigned char dsm[];
+  T* sE = reinterpret_cast<T*>(dsm);
+  T* sT0 = sE + L.bmax * L.D * L.bmax;
+  T* sT1 = sT0 + L.D * L.D * L.D * L.D;
+  T* sG = sT1 + L.D * L.D * L.D * L.D;
   const int smp = blockIdx.x;
   if (smp >= n) return;
   const int tid = threadIdx.x, NT = blockDim.x;
@@ -200,12 +207,30 @@ k_direct_row(Lattice L, const int* __restrict__ tab,
     }
     return c;
   };
+  // copy the column's tensors to LDS and point the column at the copies
+  // (callers have passed a barrier since the previous column's last read)
+  auto stage = [&](Col& c) {
+    const int ne = c.ea * c.eu * c.eb, nt = c.Dl * c.Dr * c.Du * c.Dd;
+    const int ng = c.ga * c.Dd * c.Dd * c.gb;
+    for (int q = tid; q < ne; q += NT) sE[q] = c.E[q];
+    for (int q = tid; q < nt; q += NT) {
+      sT0[q] = c.Tp0[q];
+      sT1[q] = c.Tp1[q];
+    }
+    for (int q = tid; q < ng; q += NT) sG[q] = c.G[q];
+    __syncthreads();
+    c.E = sE;
+    c.Tp0 = sT0;
+    c.Tp1 = sT1;
+    c.G = sG;
+  };
 
   // ---- right environments R_y (sites y.. with their physical legs traced)
   if (tid == 0) Rb[(size_t)Ly * RS] = T(1);
   __syncthreads();
   for (int y = Ly - 1; y >= 0; --y) {
-    const Col c = col(y);
+    Col c = col(y);
+    stage(c);
     const int ea = c.ea, eu = c.eu, eb = c.eb, Dl = c.Dl, Dr = c.Dr, Du = c.Du, Dd = c.Dd;
     const int ga = c.ga, gb = c.gb;
     const T* R1 = Rb + (size_t)(y + 1) * RS;
@@ -311,7 +336,8 @@ k_direct_row(Lattice L, const int* __restrict__ tab,
   if (tid == 0) Lc[0] = T(1);
   __syncthreads();
   for (int y = 0; y < Ly; ++y) {
-    const Col c = col(y);
+    Col c = col(y);
+    stage(c);
     const int ea = c.ea, eu = c.eu, eb = c.eb, Dl = c.Dl, Dr = c.Dr, Du = c.Du, Dd = c.Dd;
     const int ga = c.ga, gb = c.gb;
     const T* R1 = Rb + (size_t)(y + 1) * RS;
@@ -459,7 +485,12 @@ hipError_t launch_direct_row(const Lattice& L, const int* tab, const void* theta
                              uint64_t seed, uint64_t offset, void* slab, hipStream_t st) {
   typedef typename ModeT<M>::T T;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  hipLaunchKernelGGL(k_direct_row<M>, dim3(n), dim3(256), 0, st, L, tab, (const T*)theta,
+  const size_t D4 = (size_t)L.D * L.D * L.D * L.D;
+  const size_t lds = ((size_t)L.bmax * L.D * L.bmax + 2 * D4 +
+                      (size_t)L2.bmax * L.D * L.D * L2.bmax) * sizeof(T);
+  hipFuncSetAttribute((const void*)k_direct_row<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL(k_direct_row<M>, dim3(n), dim3(256), lds, st, L, tab, (const T*)theta,
                      (const T*)env, L2, tab2, (const T*)env2, samples, logp, flags, n, i, k0, k1,
                      offset, (T*)slab, direct_slab_elems(L, L2));
   return hipGetLastError();
