@@ -123,3 +123,28 @@ def test_truncation_argument_errors(dev):
     for w in (-1e-3, 1.0, float("nan"), float("inf")):
         with pytest.raises(PepsError):
             c.set_truncation(w)
+
+
+def test_cutoff_matches_oracle_in_complex128(dev):
+    Lx, Ly, D, chi, cutoff = 5, 4, 2, 4, 1e-3
+    n = 8
+    model = ("chiral", dict(J1=1.0, J2=0.5, Jchi=0.2))
+    theta = synth.theta(Lx, Ly, 2, D, seed=44, cplx=True)
+    cf = synth.sz0_configs(Lx * Ly, n, seed=9)
+    ctx = _ctx(Lx, Ly, D, chi, "c128", cutoff, model=model)
+    th, sm = _to(dev, theta, cf)
+    lp, el, O, fl = ctx.evaluate(th, sm)
+    g = peps.Geometry(Lx, Ly, 2, D)
+    olp, oel, oO = peps.evaluate(theta, g, cf, chi, oracle_ham(model, Lx, Ly), want_O=True,
+                                 cutoff=cutoff)
+    fl = fl.cpu().numpy()
+    ok = (fl & 8) == 0
+    assert (fl & 3).max() == 0 and ok.sum() >= n // 2
+    assert rel_amp_err(lp.cpu().numpy(), olp)[ok].max() < 1e-10
+    e = el.cpu().numpy()
+    got = e[:, 0] + 1j * e[:, 1]
+    assert (np.abs(got - oel) / np.maximum(1.0, np.abs(oel)))[ok].max() < 1e-10
+    Og = O.cpu().numpy()
+    assert (np.abs(Og - oO).max(axis=1) / np.maximum(1.0, np.abs(oO).max(axis=1)))[ok].max() < 1e-9
+    ref0, _, _ = peps.evaluate(theta, g, cf, chi)
+    assert np.abs(np.exp(olp - ref0) - 1).max() > 1e-4
