@@ -149,3 +149,18 @@ def test_reused_double_layer_matches_the_oracle_with_stale_tensors(dev):
     assert np.abs(lp.cpu().numpy() - rlp).max() < 1e-10 * max(1.0, np.abs(rlp).max())
     with pytest.raises(PepsError):
         ctx.direct_sample(torch.from_numpy(new).to(dev), 4, chid + 1, seed=1, refresh=False)
+
+
+@pytest.mark.parametrize("dtype,cplx,bound", [("f32", False, 1e-4), ("c64", True, 1e-4)])
+def test_single_precision_log_probabilities(dev, dtype, cplx, bound):
+    # FP32 / complex64 draws may differ from the FP64 ones near a decision;
+    # their ln p must be the oracle's ln p of the same configurations
+    Lx, Ly, D, chi, chid = 4, 4, 2, 3, 3
+    theta = synth.theta(Lx, Ly, 2, D, seed=91, cplx=cplx)
+    ctx = _ctx(Lx, Ly, D, chi, dtype)
+    s, lp, lw, fl = ctx.direct_sample(torch.from_numpy(theta).to(dev), 16, chid, seed=5)
+    assert (fl.cpu().numpy() & 3).max() == 0
+    g = peps.Geometry(Lx, Ly, 2, D)
+    ref = direct.log_prob(theta, g, chi, chid, s.cpu().numpy())
+    assert np.abs(lp.cpu().numpy() - ref).max() < bound * max(1.0, np.abs(ref).max())
+    assert np.isfinite(lw.cpu().numpy()).all()
