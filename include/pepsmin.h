@@ -170,6 +170,28 @@ peps_status peps_direct_sample(peps_ctx* ctx, const double* theta, int n, int ch
  * at the next call. PEPS_ERR_ARG outside [0, 1). */
 peps_status peps_set_truncation(peps_ctx* ctx, double max_weight);
 
+/* Truncation algorithm of the context's environment kernel (the amplitude,
+ * energy and log-derivative calls; the Metropolis and direct samplers keep
+ * the canonical one). Both give the same truncated boundary MPS:
+ *   PEPS_COMPRESS_CANONICAL (default): left-to-right QR, right-to-left SVD
+ *     of the centre matrix (Sec. "On the boundary MPS method").
+ *   PEPS_COMPRESS_DENSMAT: the density-matrix MPS-MPO algorithm the paper
+ *     uses (same section): left Gram environments
+ *     G_{y+1} = sum_k P_k^H G_y P_k of the untruncated product, then from
+ *     the right the reduced density matrix rho_y = Z_y^H G_y Z_y of each
+ *     site and its chi leading eigenvectors (the new tensor) in the compute
+ *     precision; the Gram and density products run on the matrix cores.
+ * The cut flags (8) and a maximal truncated weight apply to both, the
+ * eigenvalues of rho_y being the squared singular values. PEPS_ERR_ARG for
+ * an unknown method; PEPS_ERR_UNSUPPORTED for DENSMAT when chi*D rounded
+ * up to 32 exceeds 256, chi exceeds 255 or the packed density matrix
+ * (n(n+1)/2 elements, n = that padded size) does not fit in LDS (e.g.
+ * complex128 or FP64 at chi*D > 128). Host-side setting, takes effect at
+ * the next call. */
+#define PEPS_COMPRESS_CANONICAL 0
+#define PEPS_COMPRESS_DENSMAT 1
+peps_status peps_set_compression(peps_ctx* ctx, int method);
+
 /* ln Psi(S)_i* = ln(E^u[i*] . E^l[i*+1]) with i* = floor(Lx/2) - 1
  * (Eq. boundary_MPS_approx), as (ln|Psi|, arg Psi) FP64 pairs in
  * logpsi[n][2]. env_cache: device buffer of peps_env_cache_bytes(n) that

@@ -22,6 +22,7 @@ DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "c128": 3, "c64": 4}
 COMPLEX = ("c128", "c64")
 FLAG_ZERO, FLAG_NONFINITE, FLAG_NOCONV, FLAG_DEGENERATE = 1, 2, 4, 8
 SAMPLE_EXCHANGE, SAMPLE_FLIP = 0, 1
+COMPRESS = {"canonical": 0, "densmat": 1}
 
 # every symbol the header declares
 EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
@@ -30,7 +31,7 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_profile", "peps_profile_read", "made_create", "made_destroy",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
            "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
-           "peps_set_truncation", "peps_direct_sample"]
+           "peps_set_truncation", "peps_direct_sample", "peps_set_compression"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -77,6 +78,8 @@ def load():
     lib.peps_local_energy_strict.restype = I
     lib.peps_set_truncation.argtypes = [P, ctypes.c_double]
     lib.peps_set_truncation.restype = I
+    lib.peps_set_compression.argtypes = [P, I]
+    lib.peps_set_compression.restype = I
     lib.peps_direct_sample.argtypes = [P, P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P, P, P,
                                        P, P]
     lib.peps_direct_sample.restype = I
@@ -251,6 +254,13 @@ class Context:
         """Maximal truncated weight of every boundary-MPS truncation (0: keep
         chi singular values per bond)."""
         _check(load().peps_set_truncation(self._h, float(max_weight)))
+
+    def set_compression(self, method):
+        """Truncation algorithm of the environment kernel: "canonical" (QR
+        then SVD) or "densmat" (the density-matrix algorithm on the matrix
+        cores)."""
+        _check(load().peps_set_compression(self._h, COMPRESS[method]))
+        self.compression = method
 
     def local_energy_strict(self, theta, samples, flags=None):
         """E_loc with every amplitude from the full contraction at the one

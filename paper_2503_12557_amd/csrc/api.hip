@@ -96,6 +96,11 @@ struct peps_ctx {
   DevBuf dir_th2, dir_zero, dir_env2, dir_lp2, dir_slab, dir_lp, dir_fl;
   // global working sets of the kernels whose matrices do not fit in LDS
   bool env_gm = false, s1_gm = false, s2_gm = false, smp_gm = false;
+  // truncation: canonical QR -> SVD (0) or the density-matrix algorithm on
+  // the matrix cores (1); dm_ok: the shape fits the density-matrix kernel
+  int compress = 0;
+  bool dm_ok = false;
+  DevBuf gws_dm;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
   int jac_sweeps = 40;
   // optional per-kernel timing with HIP events on the launch stream
@@ -264,6 +269,8 @@ peps_status peps_create(const peps_geom* geom, peps_ctx** out) {
   c->s1_gm = strip1_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
   c->s2_gm = strip2_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
   c->smp_gm = sample_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
+  c->dm_ok = env_dm_lds_bytes(c->L, g.dtype) <= kLdsDyn && g.chi + 1 <= 256 &&
+             ((c->L.bmax * g.D + 31) / 32 * 32) <= 256;
   *out = c;
   return PEPS_OK;
 }
@@ -279,7 +286,7 @@ void peps_destroy(peps_ctx* c) {
                     &c->gws_smp, &c->vmc_O,      &c->vmc_dth,    &c->vmc_lp,
                     &c->str_idx, &c->str_batch,  &c->str_coef,   &c->str_lp, &c->str_fl,
                     &c->dir_th2, &c->dir_zero,   &c->dir_env2,   &c->dir_lp2, &c->dir_slab,
-                    &c->dir_lp,  &c->dir_fl};
+                    &c->dir_lp,  &c->dir_fl,    &c->gws_dm};
   if (c->dbl) peps_destroy(c->dbl);
   for (DevBuf* b : bufs) b->release();
   delete c;
@@ -478,11 +485,12 @@ static size_t per_sample_scratch(const peps_ctx* c, bool env_internal) {
   const size_t BD = (size_t)L.bmax * L.D;
   const size_t box = L.site_box;
   const size_t box2 = (size_t)L.bmax * L.bmax * L.D * L.D;
-  size_t r = 2 * (size_t)L.Ly * BD * BD;
+  const bool dm = c->compress == PEPS_COMPRESS_DENSMAT;
+  size_t r = dm ? 0 : 2 * (size_t)L.Ly * BD * BD;
   size_t s1 = (size_t)L.Lx * (L.Ly + 1) * box;
   size_t s2 = (size_t)(L.Lx - 1) * (L.Ly + 1) * box2;
   size_t g = 0;
-  if (c->env_gm) g += 2 * env_slab_elems(L, c->g.dtype);
+  if (c->env_gm && !dm) g += 2 * env_slab_elems(L, c->g.dtype);
   if (c->s1_gm) g += (size_t)L.Lx * strip1_slab_elems(L);
   if (c->s2_gm) g += (size_t)(L.Lx - 1) * strip2_slab_elems(L);
   size_t e = env_internal ? env_tensor_elems_per_sample(L) : 0;
@@ -505,7 +513,18 @@ static peps_status run_envs(peps_ctx* c, const uint8_t* samples, int m, char* en
                             double* env_l, int* flags, hipStream_t st) {
   const Lattice& L = c->L;
   const size_t BD = (size_t)L.bmax * L.D;
-  peps_status s = c->rscr.ensure((size_t)m * 2 * L.Ly * BD * BD * c->tsize);
+  peps_status s;
+  if (c->compress == PEPS_COMPRESS_DENSMAT) {
+    const int grid = env_dm_grid(L, c->g.dtype, m * (c->bottom_only ? 1 : 2));
+    if ((s = c->gws_dm.ensure((size_t)grid * env_dm_slab_elems(L, c->g.dtype) * c->tsize)) !=
+        PEPS_OK)
+      return s;
+    ProfScope ps(c, st, PEPS_PROF_ENV);
+    HIPCHK(launch_env_dm<M>(L, c->d_tab, c->theta_c.p, samples, env_t, env_l, flags, m,
+                            c->gws_dm.p, grid, st, c->bottom_only));
+    return PEPS_OK;
+  }
+  s = c->rscr.ensure((size_t)m * 2 * L.Ly * BD * BD * c->tsize);
   if (s != PEPS_OK) return s;
   void* gws = nullptr;
   if (c->env_gm) {
@@ -805,6 +824,19 @@ peps_status peps_set_truncation(peps_ctx* c, double max_weight) {
   if (!std::isfinite(max_weight) || max_weight < 0.0 || max_weight >= 1.0)
     return fail(PEPS_ERR_ARG, "maximal truncated weight %g outside [0, 1)", max_weight);
   c->L.trunc_w = max_weight;
+  return PEPS_OK;
+}
+
+peps_status peps_set_compression(peps_ctx* c, int method) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (method != PEPS_COMPRESS_CANONICAL && method != PEPS_COMPRESS_DENSMAT)
+    return fail(PEPS_ERR_ARG, "unknown compression method %d", method);
+  if (method == PEPS_COMPRESS_DENSMAT && !c->dm_ok)
+    return fail(PEPS_ERR_UNSUPPORTED,
+                "density-matrix truncation: chi = %d, chi*D = %d and dtype %d exceed the "
+                "kernel's limits (chi*D padded to <= 256, packed rho in LDS)",
+                c->g.chi, c->L.bmax * c->g.D, (int)c->g.dtype);
+  c->compress = method;
   return PEPS_OK;
 }
 

@@ -1,0 +1,964 @@
+// Boundary-MPS environments by the density-matrix MPS-MPO truncation (Sec.
+// "On the boundary MPS method": the density-matrix algorithm the paper
+// uses), with every large contraction on the matrix cores.
+//
+// One workgroup of 512 threads owns one (sample, direction) task at a time
+// and loops over tasks (a persistent grid). For each absorbed row:
+//   left to right : G_{y+1} = sum_k P_k^H G_y P_k, the Gram (left density
+//                   environment) of the untruncated product MPS, where
+//                   P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k];
+//   right to left : Z_y = P_y W_{y+1}, rho_y = Z_y^H G_y Z_y, and the chi
+//                   eigenvectors of rho_y with the largest eigenvalues v_j
+//                   give the new tensor B_y[j, :] = conj(v_j) and the weight
+//                   W_y = Z_y [v_0 .. v_{chi-1}] carried to the left.
+// The eigenvalues of rho_y are the squared singular values of the canonical
+// centre matrix, and the kept eigenvectors its dominant right singular
+// vectors, so the truncated state equals the canonical QR -> SVD sweep's.
+//
+// The products G_y P_k, P_k^H X, G_y Z and Z^H Y run as MFMA tiles
+// (v_mfma_f32_16x16x4_f32 for FP32 / complex64, v_mfma_f64_16x16x4_f64 for
+// FP64 / complex128; a complex product is four real ones). The Hermitian
+// eigenproblem of rho_y is solved by Householder tridiagonalisation (rho in
+// LDS as a packed lower triangle), multisection bisection on Sturm counts
+// for the leading eigenvalues, inverse iteration with partial-pivoting LU
+// for their eigenvectors (Gram-Schmidt inside clusters), and the stored
+// reflectors applied back. Matrices between phases live in a per-workgroup
+// slab of global memory (L2 / MALL resident).
+#include "common.h"
+#include "env_dev.h"
+#include "kernels.h"
+
+namespace pm {
+
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 matrix-core product per real type. Operand layout (both
+// types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]. Output
+// register v of lane l holds D[row(l, v)][l % 16].
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+  typedef mf32x4 acc;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma<double> {
+  typedef mf64x4 acc;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+template <typename T>
+__device__ __forceinline__ void split(T x, typename RealOf<T>::type& re,
+                                      typename RealOf<T>::type& im) {
+  if constexpr (IsCplx<T>::value) {
+    re = x.re;
+    im = x.im;
+  } else {
+    re = x;
+    im = 0;
+  }
+}
+template <typename T>
+__device__ __forceinline__ T join(typename RealOf<T>::type re, typename RealOf<T>::type im) {
+  if constexpr (IsCplx<T>::value) return T(re, im);
+  else return re;
+}
+
+// ---------------------------------------------------------------------------
+// C (m x n, row stride ldc) = op(A) op(B) (+ C if acc), with
+// A[i][kk] = A[i*sai + kk*sak], B[kk][j] = B[kk*sbk + j*sbj]; CA / CB take
+// the complex conjugate of that operand. Waves take 32 x 32 output blocks
+// (2 x 2 MFMA tiles). herm: C is Hermitian; only the blocks on and below the
+// diagonal are formed and C[j][i] = conj(C[i][j]) is written for those
+// below it. Operands may be in global memory or LDS; out-of-range rows,
+// columns and k read as zero. The caller synchronises before reading C.
+// ---------------------------------------------------------------------------
+template <typename T, bool CA, bool CB>
+__device__ void mgemm(int m, int n, int k, const T* __restrict__ A, int sai, int sak,
+                      const T* __restrict__ B, int sbk, int sbj, T* __restrict__ C, int ldc,
+                      bool herm, bool acc) {
+  typedef typename RealOf<T>::type R;
+  typedef Mfma<R> F;
+  typedef typename F::acc V;
+  constexpr bool CX = IsCplx<T>::value;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = PEPS_NT >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nbi = (m + 31) >> 5, nbj = (n + 31) >> 5;
+  const int njobs = herm ? nbi * (nbi + 1) / 2 : nbi * nbj;
+  const R sa = CA ? R(-1) : R(1), sb = CB ? R(-1) : R(1);
+  for (int job = wv; job < njobs; job += nw) {
+    int bi, bj;
+    if (herm) {
+      bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
+      bj = job - bi * (bi + 1) / 2;
+    } else {
+      bi = job / nbj;
+      bj = job - bi * nbj;
+    }
+    const int i0 = bi * 32, j0 = bj * 32;
+    V cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cr[a][b][v] = 0;
+          ci[a][b][v] = 0;
+        }
+    if (acc) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = i0 + 16 * a + F::row(lane, v), j = j0 + 16 * b + li;
+            if (i < m && j < n) {
+              R re, im;
+              split(C[(size_t)i * ldc + j], re, im);
+              cr[a][b][v] = re;
+              ci[a][b][v] = im;
+            }
+          }
+    }
+    const bool ia0 = i0 + li < m, ia1 = i0 + 16 + li < m;
+    const bool jb0 = j0 + li < n, jb1 = j0 + 16 + li < n;
+    const T* pa0 = A + (size_t)(i0 + li) * sai;
+    const T* pa1 = A + (size_t)(i0 + 16 + li) * sai;
+    const T* pb0 = B + (size_t)(j0 + li) * sbj;
+    const T* pb1 = B + (size_t)(j0 + 16 + li) * sbj;
+    for (int k0 = 0; k0 < k; k0 += 16) {
+      R ar[4][2], ai[4][2], br[4][2], bim[4][2];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = k0 + 4 * s + lk;
+        const bool kin = kk < k;
+        T x0 = (kin && ia0) ? pa0[(size_t)kk * sak] : T(0);
+        T x1 = (kin && ia1) ? pa1[(size_t)kk * sak] : T(0);
+        T y0 = (kin && jb0) ? pb0[(size_t)kk * sbk] : T(0);
+        T y1 = (kin && jb1) ? pb1[(size_t)kk * sbk] : T(0);
+        split(x0, ar[s][0], ai[s][0]);
+        split(x1, ar[s][1], ai[s][1]);
+        split(y0, br[s][0], bim[s][0]);
+        split(y1, br[s][1], bim[s][1]);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = F::mac(ar[s][a], br[s][b], cr[a][b]);
+            if constexpr (CX) {
+              // (ar + i sa ai)(br + i sb bi)
+              const R ai_ = sa * ai[s][a], bi_ = sb * bim[s][b];
+              cr[a][b] = F::mac(-ai_, bi_, cr[a][b]);
+              ci[a][b] = F::mac(ar[s][a], bi_, ci[a][b]);
+              ci[a][b] = F::mac(ai_, br[s][b], ci[a][b]);
+            }
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * a + F::row(lane, v), j = j0 + 16 * b + li;
+          if (i < m && j < n) {
+            const T val = join<T>(cr[a][b][v], ci[a][b][v]);
+            C[(size_t)i * ldc + j] = val;
+            if (herm && bi != bj) C[(size_t)j * ldc + i] = conjx(val);
+          }
+        }
+  }
+}
+
+// Reduction over the workgroup without a trailing barrier: `red` holds two
+// slots of 16 values and consecutive reductions alternate between them, so
+// the barrier of one reduction orders the reads of the one before.
+template <typename T>
+__device__ __forceinline__ T blk_sum2(T v, T* red, int& slot) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  T* r = red + 16 * slot;
+  slot ^= 1;
+  if (l == 0) r[w] = v;
+  __syncthreads();
+  T s = r[0];
+  for (int i = 1; i < PEPS_NT / 64; ++i) s += r[i];
+  return s;
+}
+
+// packed lower triangle: element (i, j), j <= i
+__device__ __forceinline__ int pk(int i, int j) { return (i * (i + 1)) / 2 + j; }
+
+__host__ __device__ inline int dm_np(int bmax, int D) { return (bmax * D + 31) / 32 * 32; }
+__host__ __device__ inline int dm_rmax(int chi) { return chi + 1; }
+
+// Slab of one workgroup (elements of T unless noted):
+//   G   : Ly x NP x NP  left Gram environments G_0 .. G_{Ly-1}
+//   Pk, X, Z, T1, W, Hv : NP x NP each
+//   then reals: Yt (RMAX x NP), lu (RMAX x 6 x NP)
+__host__ __device__ inline size_t dm_slab_elems(int Ly, int bmax, int D, int chi, size_t tsize,
+                                                size_t rsize) {
+  const size_t np = dm_np(bmax, D);
+  const size_t rm = dm_rmax(chi);
+  const size_t t_el = ((size_t)Ly + 6) * np * np;
+  const size_t r_bytes = rm * np * 7 * rsize;
+  return t_el + (r_bytes + tsize - 1) / tsize + 64;
+}
+
+// LDS: max(E + A, packed rho / eigenvector block) + the small vectors
+__host__ __device__ inline size_t dm_lds_bytes(int bmax, int D, int chi, size_t tsize,
+                                               size_t rsize) {
+  const size_t np = dm_np(bmax, D);
+  size_t big = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
+  const size_t rho = np * (np + 1) / 2;
+  const size_t xr = np * (size_t)dm_rmax(chi);
+  if (rho > big) big = rho;
+  if (xr > big) big = xr;
+  big = (big + 1) / 2 * 2;
+  const size_t small_t = 3 * np + 32;          // tau, vb, wb, red
+  const size_t small_r = 3 * np + 2 * 64 + 8;  // d, e, e^2, lam, gap scratch
+  return big * tsize + small_t * tsize + small_r * rsize + 64;
+}
+
+template <typename T>
+struct DmSh {
+  typedef typename RealOf<T>::type R;
+  T *big, *tau, *vb, *wb, *red;
+  R *dd, *ee, *e2, *lam;
+  __device__ DmSh(unsigned char* lds, int bmax, int D, int chi) {
+    const size_t np = dm_np(bmax, D);
+    size_t bg = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
+    const size_t rho = np * (np + 1) / 2;
+    const size_t xr = np * (size_t)dm_rmax(chi);
+    if (rho > bg) bg = rho;
+    if (xr > bg) bg = xr;
+    bg = (bg + 1) / 2 * 2;
+    big = reinterpret_cast<T*>(lds);
+    tau = big + bg;
+    vb = tau + np;
+    wb = vb + np;
+    red = wb + np;
+    dd = reinterpret_cast<R*>(red + 32);
+    ee = dd + np;
+    e2 = ee + np;
+    lam = e2 + np;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Householder reduction of the Hermitian nz x nz matrix held as a packed
+// lower triangle (rho) to a real symmetric tridiagonal (dd, ee): reflector j
+// H_j = I - tau_j v_j v_j^H acts on rows j+1..nz-1, v_j[j+1] = 1, and maps
+// column j below the diagonal to (beta_j, 0, ...) with beta_j real, so
+// rho = Q T Q^H with Q = H_0 H_1 ... H_{nz-2}. v_j goes to Hv row j.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& slot) {
+  typedef typename RealOf<T>::type R;
+  const int tid = threadIdx.x, NT = PEPS_NT;
+  const int TPR = nz <= 128 ? 4 : 2;  // threads per row in the symv / update
+  const int rpp = NT / TPR;            // rows per pass
+  const int ri = tid / TPR, q = tid - ri * TPR;
+  // squares of column 0 below row 1
+  R s2 = 0;
+  for (int i = 2 + tid; i < nz; i += NT) s2 += abs2x(rho[pk(i, 0)]);
+  s2 = blk_sum2(s2, reinterpret_cast<R*>(sh.red), slot);
+  for (int j = 0; j + 1 < nz; ++j) {
+    const T alpha = rho[pk(j + 1, j)];
+    R ar, aim;
+    split(alpha, ar, aim);
+    T tau = T(0), sc = T(0);
+    R beta = ar;
+    if (!(s2 == R(0) && aim == R(0))) {
+      const R nrm = sqrt(ar * ar + aim * aim + s2);
+      beta = ar >= R(0) ? -nrm : nrm;
+      tau = join<T>((beta - ar) / beta, -aim / beta);
+      sc = recipx(alpha - T(beta));
+    }
+    if (tid == 0) {
+      sh.dd[j] = realx(rho[pk(j, j)]);
+      sh.ee[j] = beta;
+      sh.tau[j] = tau;
+    }
+    const bool refl = tau != T(0);
+    // v (rows j+1..nz-1) to LDS and to Hv row j
+    for (int i = j + 1 + tid; i < nz; i += NT) {
+      const T v = i == j + 1 ? T(1) : rho[pk(i, j)] * sc;
+      sh.vb[i] = v;
+      Hv[(size_t)j * ldh + i] = v;
+    }
+    __syncthreads();
+    if (!refl) {
+      // column j+1's squares below row j+2 for the next reflector
+      R t = 0;
+      for (int i = j + 3 + tid; i < nz; i += NT) t += abs2x(rho[pk(i, j + 1)]);
+      s2 = blk_sum2(t, reinterpret_cast<R*>(sh.red), slot);
+      continue;
+    }
+    // u = B v for the trailing block B (rows / columns j+1..), then
+    // w = tau u - (|tau|^2 / 2) (v^H u) v
+    T vhu = T(0);
+    T ui[2] = {T(0), T(0)};
+    for (int p = 0; p < 2; ++p) {
+      const int i = j + 1 + ri + p * rpp;
+      T u = T(0);
+      if (i < nz) {
+        for (int kk = j + 1 + q; kk < nz; kk += TPR)
+          u += (kk <= i ? rho[pk(i, kk)] : conjx(rho[pk(kk, i)])) * sh.vb[kk];
+      }
+      u = group_sum(u, TPR);
+      ui[p] = u;
+      if (i < nz && q == 0) vhu += conjx(sh.vb[i]) * u;
+    }
+    const R vhu_r = blk_sum2(realx(vhu), reinterpret_cast<R*>(sh.red), slot);
+    const R t2 = abs2x(tau) * R(0.5) * vhu_r;
+    for (int p = 0; p < 2; ++p) {
+      const int i = j + 1 + ri + p * rpp;
+      if (i < nz && q == 0) sh.wb[i] = tau * ui[p] - sh.vb[i] * t2;
+    }
+    __syncthreads();
+    // B -= v w^H + w v^H on the lower triangle; column j+1's new squares
+    // below row j+2 feed the next reflector
+    R t = 0;
+    for (int p = 0; p < 2; ++p) {
+      const int i = j + 1 + ri + p * rpp;
+      if (i < nz) {
+        const T vi = sh.vb[i], wi = sh.wb[i];
+        for (int kk = j + 1 + q; kk <= i; kk += TPR) {
+          const T nv = rho[pk(i, kk)] - vi * conjx(sh.wb[kk]) - wi * conjx(sh.vb[kk]);
+          rho[pk(i, kk)] = nv;
+          if (kk == j + 1 && i >= j + 3) t += abs2x(nv);
+        }
+      }
+    }
+    s2 = blk_sum2(t, reinterpret_cast<R*>(sh.red), slot);
+  }
+  if (tid == 0) {
+    sh.dd[nz - 1] = realx(rho[pk(nz - 1, nz - 1)]);
+    sh.ee[nz - 1] = 0;
+  }
+  __syncthreads();
+}
+
+// Eigenvalues below x of the symmetric tridiagonal (d, e^2): Sturm count.
+template <typename R>
+__device__ __forceinline__ int sturm(const R* d, const R* e2, int n, R x, R pivmin) {
+  int c = 0;
+  R qv = d[0] - x;
+  if (fabs((double)qv) < (double)pivmin) qv = -pivmin;
+  c += qv < R(0);
+  for (int i = 1; i < n; ++i) {
+    qv = (d[i] - x) - e2[i - 1] / qv;
+    if (fabs((double)qv) < (double)pivmin) qv = -pivmin;
+    c += qv < R(0);
+  }
+  return c;
+}
+
+// The rr largest eigenvalues of (dd, ee), descending, into lam[0..rr):
+// LPE lanes per eigenvalue evaluate Sturm counts at LPE-1 interior points
+// of its bracket and keep the sub-interval that holds it.
+template <typename R>
+__device__ void top_eigenvalues(const R* dd, const R* ee, R* e2, R* lam, int nz, int rr,
+                                R* red, int& slot, R& tnorm_out) {
+  const int tid = threadIdx.x, NT = PEPS_NT;
+  R lo = R(1e300 > 1e30 ? 0 : 0), hi = 0;
+  R gl = 0, gu = 0;
+  for (int i = tid; i < nz; i += NT) {
+    const R a = i > 0 ? fabs(ee[i - 1]) : R(0);
+    const R b = i + 1 < nz ? fabs(ee[i]) : R(0);
+    e2[i] = ee[i] * ee[i];
+    const R l0 = dd[i] - a - b, u0 = dd[i] + a + b;
+    if (i == tid) {
+      gl = l0;
+      gu = u0;
+    } else {
+      gl = l0 < gl ? l0 : gl;
+      gu = u0 > gu ? u0 : gu;
+    }
+  }
+  // block min / max through the sum slots: -max(-x)
+  R mn = tid < nz ? -gl : -R(1e30);
+  R mx = tid < nz ? gu : -R(1e30);
+  mn = wave_max(mn);
+  mx = wave_max(mx);
+  {
+    const int w = tid >> 6, l = tid & 63;
+    R* r = red + 16 * slot;
+    slot ^= 1;
+    if (l == 0) {
+      r[w] = mn;
+      r[8 + w] = mx;
+    }
+    __syncthreads();
+    mn = r[0];
+    mx = r[8];
+    for (int i = 1; i < NT / 64; ++i) {
+      mn = r[i] > mn ? r[i] : mn;
+      mx = r[8 + i] > mx ? r[8 + i] : mx;
+    }
+  }
+  gl = -mn;
+  gu = mx;
+  const R tnorm = fabs(gl) > fabs(gu) ? fabs(gl) : fabs(gu);
+  tnorm_out = tnorm;
+  const R epsr = Eps<R>::v;
+  const R pad = R(2) * epsr * tnorm * nz + (tnorm > R(0) ? R(0) : R(1));
+  gl -= pad;
+  gu += pad;
+  // pivmin: the smallest pivot magnitude kept in a Sturm count
+  R emax = 0;
+  for (int i = 0; i + 1 < nz; ++i) emax = e2[i] > emax ? e2[i] : emax;
+  const R pivmin = (std::is_same<R, double>::value ? R(2.2250738585072014e-308)
+                                                     : R(1.17549435e-38f)) *
+                   (emax > R(1) ? emax : R(1));
+  int LPE = 16;
+  while (LPE > 2 && rr * LPE > NT) LPE >>= 1;
+  const int qe = tid / LPE, p = tid - qe * LPE;
+  const int iters = std::is_same<R, double>::value ? (LPE >= 16 ? 15 : 20) : (LPE >= 16 ? 8 : 11);
+  lo = gl;
+  hi = gu;
+  const bool act = qe < rr;
+  const int m = nz - 1 - qe;  // ascending index of the wanted eigenvalue
+  for (int it = 0; it < iters; ++it) {
+    int pbest = 0;
+    if (act && p > 0) {
+      const R x = lo + (hi - lo) * (R)p / (R)LPE;
+      if (sturm(dd, e2, nz, x, pivmin) <= m) pbest = p;
+    }
+    // largest interior point that still has at most m eigenvalues below
+    int g = pbest;
+    for (int o = 1; o < LPE; o <<= 1) {
+      const int h = __shfl_xor(g, o, 64);
+      g = h > g ? h : g;
+    }
+    const R w = hi - lo;
+    const R nlo = lo + w * (R)g / (R)LPE;
+    const R nhi = (g + 1 == LPE) ? hi : lo + w * (R)(g + 1) / (R)LPE;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (act && p == 0) lam[qe] = R(0.5) * (lo + hi);
+  __syncthreads();
+}
+
+// Eigenvector of the tridiagonal for eigenvalue x by inverse iteration
+// (partial-pivoting LU of T - x I, three solves from a vector of ones),
+// normalised, into y[0..n). Serial in the calling lane; wk: 5 n reals.
+template <typename R>
+__device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* wk, R* y) {
+  R* u0 = wk;
+  R* u1 = wk + n;
+  R* u2 = wk + 2 * n;
+  R* ml = wk + 3 * n;
+  R* pv = wk + 4 * n;
+  const R tiny = Eps<R>::v * (tnorm > R(0) ? tnorm : R(1));
+  // factorise: rows i, i+1 with pivoting on the sub-diagonal
+  R c0 = dd[0] - x, c1 = n > 1 ? ee[0] : R(0), c2 = 0;
+  for (int i = 0; i + 1 < n; ++i) {
+    const R s0 = ee[i], s1 = dd[i + 1] - x, s2 = i + 2 < n ? ee[i + 1] : R(0);
+    if (fabs(s0) > fabs(c0)) {
+      const R mm = c0 / s0;
+      u0[i] = s0;
+      u1[i] = s1;
+      u2[i] = s2;
+      c0 = c1 - mm * s1;
+      c1 = c2 - mm * s2;
+      c2 = 0;
+      ml[i] = mm;
+      pv[i] = 1;
+    } else {
+      if (c0 == R(0)) c0 = tiny;
+      const R mm = s0 / c0;
+      u0[i] = c0;
+      u1[i] = c1;
+      u2[i] = c2;
+      c0 = s1 - mm * c1;
+      c1 = s2 - mm * c2;
+      c2 = 0;
+      ml[i] = mm;
+      pv[i] = 0;
+    }
+  }
+  if (c0 == R(0)) c0 = tiny;
+  u0[n - 1] = c0;
+  u1[n - 1] = 0;
+  u2[n - 1] = 0;
+  for (int i = 0; i < n; ++i) y[i] = R(1);
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 0; i + 1 < n; ++i) {
+      const R mm = ml[i];
+      if (pv[i] != R(0)) {
+        const R a = y[i], b = y[i + 1];
+        y[i] = b;
+        y[i + 1] = a - mm * b;
+      } else {
+        y[i + 1] -= mm * y[i];
+      }
+    }
+    R nrm = 0;
+    for (int i = n - 1; i >= 0; --i) {
+      R s = y[i];
+      if (i + 1 < n) s -= u1[i] * y[i + 1];
+      if (i + 2 < n) s -= u2[i] * y[i + 2];
+      s /= u0[i];
+      y[i] = s;
+      nrm = fabs(s) > nrm ? fabs(s) : nrm;
+    }
+    const R inv = nrm > R(0) ? R(1) / nrm : R(1);
+    for (int i = 0; i < n; ++i) y[i] *= inv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The r leading eigenvectors of the Hermitian nz x nz matrix rho (full, in
+// the slab, row stride NP): on exit Xe (LDS, nz x r, row stride r) holds
+// them as columns, lam[0..rr) the rr = min(r + 1, nz) largest eigenvalues.
+// rho is copied to LDS as a packed lower triangle (sh.big) first; Xe
+// overlays it after the reduction.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, typename RealOf<T>::type* Yt,
+                       typename RealOf<T>::type* lu, const DmSh<T>& sh, int& slot,
+                       typename RealOf<T>::type& tnorm) {
+  typedef typename RealOf<T>::type R;
+  const int tid = threadIdx.x, NT = PEPS_NT;
+  T* rho = sh.big;
+  const int tot = nz * (nz + 1) / 2;
+  for (int idx = tid; idx < tot; idx += NT) {
+    // invert idx = i (i + 1) / 2 + j
+    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while (pk(i + 1, 0) <= idx) ++i;
+    while (pk(i, 0) > idx) --i;
+    const int j = idx - pk(i, 0);
+    rho[idx] = rhoG[(size_t)i * np + j];
+  }
+  __syncthreads();
+  tridiag(rho, nz, Hv, np, sh, slot);
+  top_eigenvalues(sh.dd, sh.ee, sh.e2, sh.lam, nz, rr, reinterpret_cast<R*>(sh.red), slot, tnorm);
+  // eigenvectors of the tridiagonal, one lane each
+  if (tid < r) inv_iter_lane(sh.dd, sh.ee, nz, sh.lam[tid], tnorm, lu + (size_t)tid * 5 * np,
+                             Yt + (size_t)tid * np);
+  __syncthreads();
+  // Gram-Schmidt inside clusters of close eigenvalues (wave 0, in order)
+  if (tid < 64) {
+    const R ctol = R(1e-3) * tnorm;
+    for (int j = 0; j < r; ++j) {
+      R* yj = Yt + (size_t)j * np;
+      bool touched = false;
+      for (int i = 0; i < j; ++i) {
+        if (!(fabs(sh.lam[i] - sh.lam[j]) <= ctol)) continue;
+        const R* yi = Yt + (size_t)i * np;
+        R d = 0;
+        for (int e = tid; e < nz; e += 64) d += yi[e] * yj[e];
+        d = wave_sum(d);
+        for (int e = tid; e < nz; e += 64) yj[e] -= d * yi[e];
+        touched = true;
+      }
+      R s = 0;
+      for (int e = tid; e < nz; e += 64) s += yj[e] * yj[e];
+      s = wave_sum(s);
+      const R inv = s > R(0) ? R(1) / sqrt(s) : R(0);
+      for (int e = tid; e < nz; e += 64) yj[e] *= inv;
+      (void)touched;
+    }
+  }
+  __syncthreads();
+  // Xe = Q Y: reflectors applied last to first; column c owned by P lanes
+  // of one wave (no barrier: columns are independent)
+  T* Xe = sh.big;
+  for (int idx = tid; idx < nz * r; idx += NT) {
+    const int e = idx / r, c = idx - e * r;
+    Xe[idx] = T(Yt[(size_t)c * np + e]);
+  }
+  __syncthreads();
+  int P = 64;
+  while (P > 1 && r * P > NT) P >>= 1;
+  const int col = tid / P, part = tid - col * P;
+  if (col < r) {
+    for (int j = nz - 2; j >= 0; --j) {
+      const T tj = sh.tau[j];
+      if (tj == T(0)) continue;
+      const T* v = Hv + (size_t)j * np;
+      T s = T(0);
+      for (int e = j + 1 + part; e < nz; e += P) s += conjx(v[e]) * Xe[e * r + col];
+      s = group_sum(s, P);
+      s = s * tj;
+      for (int e = j + 1 + part; e < nz; e += P) Xe[e * r + col] -= v[e] * s;
+    }
+  }
+  __syncthreads();
+}
+
+// One row absorbed by the density-matrix truncation (see the file header).
+template <int M>
+__device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename ModeT<M>::T* theta,
+                              const uint8_t* s, bool bottom, int t, typename ModeT<M>::T* envs,
+                              double* lg, typename ModeT<M>::T* slab, const DmSh<typename ModeT<M>::T>& sh,
+                              int* flp, int& slot) {
+  typedef typename ModeT<M>::T T;
+  typedef typename RealOf<T>::type R;
+  const int tid = threadIdx.x, NT = PEPS_NT;
+  const int np = dm_np(L.bmax, L.D);
+  const size_t np2 = (size_t)np * np;
+  T* Gs = slab;
+  T* Pk = Gs + (size_t)L.Ly * np2;
+  T* X = Pk + np2;
+  T* Z = X + np2;
+  T* T1 = Z + np2;
+  T* W = T1 + np2;
+  T* Hv = W + np2;
+  R* Yt = reinterpret_cast<R*>(Hv + np2);
+  R* lu = Yt + (size_t)dm_rmax(L.chi) * np;
+  T* Ebuf = sh.big;
+  T* Abuf = Ebuf + L.bmax * L.D * L.bmax;
+  int& fl = *flp;
+  const size_t slot_elems = (size_t)L.Ly * L.site_box;
+  const int* edims = tab + L.off_env;
+  const int x = bottom ? L.Lx - 1 - t : t;
+  const int sp = bottom ? slot_bottom(L, x + 1) : slot_top(L, x - 1);
+  const int sn = bottom ? slot_bottom(L, x) : slot_top(L, x);
+  const T* Eprev = envs + (size_t)sp * slot_elems;
+  T* Enew = envs + (size_t)sn * slot_elems;
+
+  // ---- left to right: Gram environments ----
+  if (tid == 0) Gs[0] = T(1);  // G_0 = [1]
+  __syncthreads();
+  for (int y = 0; y < L.Ly - 1; ++y) {
+    const SiteView v = site_view(tab, L, x * L.Ly + y, bottom);
+    const int bl = edims[(sp * L.Ly + y) * 3 + 0];
+    const int br = edims[(sp * L.Ly + y) * 3 + 2];
+    const int Pl = bl * v.Dl, Pr = br * v.Dr;
+    load_lds(Ebuf, Eprev + (size_t)y * L.site_box, bl * v.Din * br);
+    load_lds(Abuf, site_tensor(theta, tab, L, s, x * L.Ly + y), v.Dl * v.Dr * v.Din * v.Dout);
+    __syncthreads();
+    const T* Gy = Gs + (size_t)y * np2;
+    T* Gn = Gs + (size_t)(y + 1) * np2;
+    const FastDiv fPr(Pr), fDl(v.Dl), fDr(v.Dr);
+    for (int k = 0; k < v.Dout; ++k) {
+      // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k]
+      for (int i = tid; i < Pl * Pr; i += NT) {
+        int row = i;
+        int col = divmod(row, fPr);
+        const int l = divmod(row, fDl);
+        const int aa = row;
+        const int r = divmod(col, fDr);
+        const int b = col;
+        T acc = 0;
+        for (int in = 0; in < v.Din; ++in)
+          acc += opnd<M>(Ebuf[(aa * v.Din + in) * br + b]) *
+                 opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]);
+        Pk[(size_t)(i / Pr) * np + (i - (i / Pr) * Pr)] = acc;
+      }
+      __syncthreads();
+      // X = G_y P_k (G_y Hermitian: read as conj(G_y)^T, rows coalesced)
+      mgemm<T, IsCplx<T>::value, false>(Pl, Pr, Pl, Gy, 1, np, Pk, np, 1, X, np, false, false);
+      __syncthreads();
+      // G_{y+1} (+)= P_k^H X
+      mgemm<T, IsCplx<T>::value, false>(Pr, Pr, Pl, Pk, 1, np, X, np, 1, Gn, np, true, k > 0);
+      __syncthreads();
+    }
+    // unit scale: the Gram only fixes directions
+    R mx = 0;
+    for (int i = tid; i < Pr; i += NT) {
+      const R a = absx(Gn[(size_t)i * np + i]);
+      mx = a > mx ? a : mx;
+    }
+    mx = block_max(mx, reinterpret_cast<R*>(sh.red + 16 * slot));
+    const int e = pow2_exponent((double)mx);
+    if (e != 0) {
+      const R f = (R)ldexp(1.0, -e);
+      for (int i = tid; i < Pr * Pr; i += NT) Gn[(size_t)(i / Pr) * np + (i % Pr)] *= f;
+    }
+    __syncthreads();
+  }
+
+  // ---- right to left: density matrices and their leading eigenvectors ----
+  int nbr = 1;
+  double logrow = 0.0;
+  if (tid == 0) W[0] = T(1);
+  __syncthreads();
+  for (int y = L.Ly - 1; y >= 0; --y) {
+    const int nsite = x * L.Ly + y;
+    const SiteView v = site_view(tab, L, nsite, bottom);
+    const int bl = edims[(sp * L.Ly + y) * 3 + 0];
+    const int br = edims[(sp * L.Ly + y) * 3 + 2];
+    const int Pl = bl * v.Dl;
+    const int zc = v.Dout * nbr;
+    load_lds(Ebuf, Eprev + (size_t)y * L.site_box, bl * v.Din * br);
+    load_lds(Abuf, site_tensor(theta, tab, L, s, nsite), v.Dl * v.Dr * v.Din * v.Dout);
+    __syncthreads();
+    // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]
+    for (int r = 0; r < v.Dr; ++r)
+      mgemm<T, false, false>(bl * v.Din, nbr, br, Ebuf, br, 1, W + (size_t)r * np, v.Dr * np, 1,
+                             T1 + r * nbr, v.Dr * nbr, false, false);
+    __syncthreads();
+    // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]
+    {
+      const int tot = Pl * zc;
+      const FastDiv fzc(zc), fDl(v.Dl), fnbr(nbr);
+      for (int i = tid; i < tot; i += NT) {
+        int row = i;
+        int col = divmod(row, fzc);
+        const int l = divmod(row, fDl);
+        const int aa = row;
+        const int c = divmod(col, fnbr);
+        const int k = col;
+        T acc = 0;
+        for (int in = 0; in < v.Din; ++in)
+          for (int r = 0; r < v.Dr; ++r)
+            acc += opnd<M>(T1[(size_t)(aa * v.Din + in) * (v.Dr * nbr) + r * nbr + c]) *
+                   opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]);
+        Z[(size_t)(aa * v.Dl + l) * np + k * nbr + c] = acc;
+      }
+    }
+    __syncthreads();
+    int rnew;
+    if (y > 0) {
+      const T* Gy = Gs + (size_t)y * np2;
+      // Y = G_y Z, rho = Z^H Y (Hermitian)
+      mgemm<T, IsCplx<T>::value, false>(Pl, zc, Pl, Gy, 1, np, Z, np, 1, X, np, false, false);
+      __syncthreads();
+      mgemm<T, IsCplx<T>::value, false>(zc, zc, Pl, Z, 1, np, X, np, 1, Pk, np, true, false);
+      __syncthreads();
+      // unit scale (eigenvectors only)
+      R mx = 0;
+      for (int i = tid; i < zc; i += NT) {
+        const R a = absx(Pk[(size_t)i * np + i]);
+        mx = a > mx ? a : mx;
+      }
+      mx = block_max(mx, reinterpret_cast<R*>(sh.red + 16 * slot));
+      const int es = pow2_exponent((double)mx);
+      const R fsc = (R)ldexp(1.0, -es);
+      // trace (for the truncated weight) at unit scale
+      double trc = 0;
+      for (int i = tid; i < zc; i += NT) trc += (double)realx(Pk[(size_t)i * np + i]) * (double)fsc;
+      if (es != 0)
+        for (int i = tid; i < zc * zc; i += NT) Pk[(size_t)(i / zc) * np + (i % zc)] *= fsc;
+      trc = block_sum(trc, reinterpret_cast<double*>(sh.red + 16 * slot));
+      __syncthreads();
+      rnew = edims[(sn * L.Ly + y) * 3 + 0];
+      const int rr = rnew + 1 < zc ? rnew + 1 : zc;
+      R tnorm;
+      dm_eig<T>(Pk, np, zc, rnew, rr, Hv, Yt, lu, sh, slot, tnorm);
+      // kept count and cut flags from the eigenvalues (lam = sigma^2)
+      __shared__ int s_keep;
+      if (tid == 0) {
+        int keep = rnew;
+        if (L.trunc_w > 0.0) {
+          double kept = 0;
+          for (int j = 0; j < rnew; ++j) kept += (double)(sh.lam[j] > R(0) ? sh.lam[j] : R(0));
+          const double lim = L.trunc_w * trc;
+          double tail = trc - kept;
+          if (tail < 0) tail = 0;
+          if (tail <= lim) {
+            for (int j = rnew - 1; j >= 1; --j) {
+              const double lj = sh.lam[j] > R(0) ? (double)sh.lam[j] : 0.0;
+              if (tail + lj > lim) break;
+              tail += lj;
+              keep = j;
+            }
+          }
+          const double marg = std::is_same<R, double>::value ? 1e-8 : 1e-4;
+          bool near = fabs(tail - lim) <= marg * lim;
+          if (keep > 1 && tail <= lim) {
+            const double lp = sh.lam[keep - 1] > R(0) ? (double)sh.lam[keep - 1] : 0.0;
+            near = near || fabs(tail + lp - lim) <= marg * lim;
+          }
+          if (near) fl |= 8;
+        }
+        if (keep < zc && keep < rr) {
+          const double sa = sqrt(fmax((double)sh.lam[keep - 1], 0.0));
+          const double sb = sqrt(fmax((double)sh.lam[keep], 0.0));
+          if (sa > 0.0 && (sa - sb) < 1e-8 * sa) fl |= 8;
+        }
+        s_keep = keep;
+      }
+      __syncthreads();
+      const int rkeep = s_keep;
+      // discarded columns of the kept block are zero
+      T* Xe = sh.big;
+      if (rkeep < rnew)
+        for (int i = tid; i < zc * rnew; i += NT)
+          if (i % rnew >= rkeep) Xe[i] = T(0);
+      __syncthreads();
+      // W_y = Z [v_0 .. v_{rnew-1}]
+      mgemm<T, false, false>(Pl, rnew, zc, Z, np, 1, Xe, rnew, 1, W, np, false, false);
+      // the new tensor B[j, e] = conj(v_j[e]) / max |v|
+      R bm = 0;
+      for (int i = tid; i < zc * rnew; i += NT) {
+        const R a = absx(Xe[i]);
+        bm = a > bm ? a : bm;
+      }
+      bm = block_max(bm, reinterpret_cast<R*>(sh.red + 16 * slot));
+      const R binv = bm > R(0) ? R(1) / bm : R(1);
+      if (!(bm > R(0)) || !isfinite((double)bm)) {
+        if (tid == 0) fl |= (bm == R(0)) ? 1 : 2;
+      } else {
+        logrow += log((double)bm);
+      }
+      T* dst = Enew + (size_t)y * L.site_box;
+      for (int i = tid; i < rnew * zc; i += NT) {
+        const int j = i / zc, e = i - j * zc;
+        dst[i] = conjx(Xe[e * rnew + j]) * binv;
+      }
+      __syncthreads();
+      // W carries the weight of the sites to its right: unit scale, the
+      // power of two into the log scale
+      R wm = 0;
+      for (int i = tid; i < Pl * rnew; i += NT) {
+        const R a = absx(W[(size_t)(i / rnew) * np + (i % rnew)]);
+        wm = a > wm ? a : wm;
+      }
+      wm = block_max(wm, reinterpret_cast<R*>(sh.red + 16 * slot));
+      const int ew = pow2_exponent((double)wm);
+      if (ew != 0) {
+        const R f = (R)ldexp(1.0, -ew);
+        for (int i = tid; i < Pl * rnew; i += NT) W[(size_t)(i / rnew) * np + (i % rnew)] *= f;
+      }
+      logrow += ew * 0.69314718055994530942;
+      __syncthreads();
+    } else {
+      rnew = 1;
+      // the leftmost tensor is Z itself (1 x zc)
+      R zm = 0;
+      for (int i = tid; i < zc; i += NT) {
+        const R a = absx(Z[i]);
+        zm = a > zm ? a : zm;
+      }
+      zm = block_max(zm, reinterpret_cast<R*>(sh.red + 16 * slot));
+      if (!(zm > R(0)) || !isfinite((double)zm)) {
+        if (tid == 0) fl |= (zm == R(0)) ? 1 : 2;
+        zm = R(1);
+      } else {
+        logrow += log((double)zm);
+      }
+      const R zinv = R(1) / zm;
+      T* dst = Enew + (size_t)y * L.site_box;
+      for (int i = tid; i < zc; i += NT) dst[i] = Z[i] * zinv;
+      __syncthreads();
+    }
+    nbr = rnew;
+  }
+  if (tid == 0) lg[sn] = lg[sp] + logrow;
+  __syncthreads();
+}
+
+// Persistent grid over (sample, direction) tasks.
+template <int M>
+__global__ void __launch_bounds__(512)
+k_env_dm(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
+         const uint8_t* __restrict__ samples, typename ModeT<M>::T* __restrict__ env,
+         double* __restrict__ logs, int* __restrict__ flags, int n, int ndir, int dir0,
+         typename ModeT<M>::T* __restrict__ slabs, size_t slab) {
+  typedef typename ModeT<M>::T T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const DmSh<T> sh(smem_raw, L.bmax, L.D, L.chi);
+  T* myslab = slabs + (size_t)blockIdx.x * slab;
+  __shared__ int fl;
+  const size_t slot_elems = (size_t)L.Ly * L.site_box;
+  for (int task = blockIdx.x; task < n * ndir; task += gridDim.x) {
+    const int smp = task / ndir;
+    const int dir = dir0 + (task - smp * ndir);
+    const bool bottom = dir == 1;
+    if (threadIdx.x == 0) fl = 0;
+    __syncthreads();
+    int slot = 0;
+    const uint8_t* s = samples + (size_t)smp * L.N;
+    T* envs = env + (size_t)smp * L.n_slots * slot_elems;
+    double* lg = logs + (size_t)smp * L.n_slots;
+    // the first row of the sweep read as an MPS (Ebuf and red of the
+    // canonical kernel's carve-up)
+    EnvSmem<T> es(sh.big, sh.red, L, false);
+    es.Ebuf = sh.big;
+    es.red = sh.red;
+    env_first_row<M>(L, tab, theta, s, bottom, envs, lg, es, &fl);
+    for (int t = 1; t <= L.Lx - 2; ++t)
+      dm_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, myslab, sh, &fl, slot);
+    if (threadIdx.x == 0 && fl && flags) atomicOr(flags + smp, fl);
+    __syncthreads();
+  }
+}
+
+// ---- host side ----
+static size_t dm_rsize(int mode) {
+  return (mode == MODE_F64 || mode == MODE_C128) ? 8 : 4;
+}
+
+size_t env_dm_slab_elems(const Lattice& L, int mode) {
+  return (dm_slab_elems(L.Ly, L.bmax, L.D, L.chi, mode_elem_bytes(mode), dm_rsize(mode)) + 63) /
+         64 * 64;
+}
+size_t env_dm_lds_bytes(const Lattice& L, int mode) {
+  return dm_lds_bytes(L.bmax, L.D, L.chi, mode_elem_bytes(mode), dm_rsize(mode));
+}
+// Resident workgroups of the persistent grid: the occupancy of the
+// kernel's instance times the compute units, at most one per task.
+template <int M>
+static int dm_blocks_m(const Lattice& L) {
+  int dev = 0, cus = 256, per = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  const size_t lds = env_dm_lds_bytes(L, M);
+  hipFuncSetAttribute((const void*)k_env_dm<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_env_dm<M>, 512, lds) ==
+          hipSuccess &&
+      nb > 0)
+    per = nb;
+  return per * cus;
+}
+int env_dm_grid(const Lattice& L, int mode, int tasks) {
+  int g = 0;
+  switch (mode) {
+    case MODE_F64: g = dm_blocks_m<MODE_F64>(L); break;
+    case MODE_F32: g = dm_blocks_m<MODE_F32>(L); break;
+    case MODE_BF16: g = dm_blocks_m<MODE_BF16>(L); break;
+    case MODE_C128: g = dm_blocks_m<MODE_C128>(L); break;
+    default: g = dm_blocks_m<MODE_C64>(L); break;
+  }
+  return tasks < g ? (tasks > 0 ? tasks : 1) : g;
+}
+
+template <int M>
+hipError_t launch_env_dm(const Lattice& L, const int* tab, const void* theta,
+                         const uint8_t* samples, void* env, double* logs, int* flags, int n,
+                         void* slabs, int grid, hipStream_t st, bool bottom_only) {
+  typedef typename ModeT<M>::T T;
+  const size_t lds = env_dm_lds_bytes(L, M);
+  hipError_t e = hipFuncSetAttribute((const void*)k_env_dm<M>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_env_dm<M>), dim3(grid), dim3(512), lds, st, L, tab, (const T*)theta,
+                     samples, (T*)env, logs, flags, n, bottom_only ? 1 : 2, bottom_only ? 1 : 0,
+                     (T*)slabs, env_dm_slab_elems(L, M));
+  return hipGetLastError();
+}
+
+#define INST(M)                                                                              \
+  template hipError_t launch_env_dm<M>(const Lattice&, const int*, const void*, const uint8_t*, \
+                                       void*, double*, int*, int, void*, int, hipStream_t, bool);
+INST(MODE_F64)
+INST(MODE_F32)
+INST(MODE_BF16)
+INST(MODE_C128)
+INST(MODE_C64)
+#undef INST
+
+}  // namespace pm

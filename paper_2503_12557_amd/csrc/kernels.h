@@ -52,6 +52,16 @@ hipError_t launch_env_sweep(const Lattice& L, const int* tab, const void* theta,
                             const uint8_t* samples, void* env, double* logs, void* rscr,
                             int* flags, int n, int jac_sweeps, void* gws, hipStream_t st,
                             bool bottom_only = false);
+// density-matrix environments on the matrix cores (env_dm.hip): one
+// persistent grid of `grid` workgroups, each with a slab of
+// env_dm_slab_elems elements of the compute type
+size_t env_dm_slab_elems(const Lattice& L, int mode);
+size_t env_dm_lds_bytes(const Lattice& L, int mode);
+int env_dm_grid(const Lattice& L, int mode, int tasks);
+template <int M>
+hipError_t launch_env_dm(const Lattice& L, const int* tab, const void* theta,
+                         const uint8_t* samples, void* env, double* logs, int* flags, int n,
+                         void* slabs, int grid, hipStream_t st, bool bottom_only = false);
 template <int M>
 hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, const double* logs,
                           int icut, double* logpsi, int* flags, int n, hipStream_t st);
