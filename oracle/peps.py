@@ -230,11 +230,14 @@ def compress_canonical(mps, chi: int, cutoff: float = 0.0):
     return out
 
 
-def compress_density_matrix(mps, chi: int):
+def compress_density_matrix(mps, chi: int, cutoff: float = 0.0):
     """The density-matrix MPS-MPO truncation (Sec. "On the boundary MPS
     method"): left Gram environments of the untruncated product, then from
     the right the reduced density matrix of each site is diagonalised and
     its chi dominant eigenvectors become the new right-isometric tensor.
+    The eigenvalues are the squared singular values of the canonical centre
+    matrix, so a maximal truncated weight (``kept_count``) applies to their
+    square roots.
     """
     n = len(mps)
     G = [None] * n
@@ -251,8 +254,10 @@ def compress_density_matrix(mps, chi: int):
         rho = Zm.T @ G[y].T @ Zm.conj()
         rho = 0.5 * (rho + rho.conj().T)
         w, V = np.linalg.eigh(rho)
-        r = min(chi, bl, k * r0)
-        order = np.argsort(w)[::-1][:r]
+        order = np.argsort(w)[::-1]
+        sv = np.sqrt(np.clip(w[order], 0.0, None))[:min(bl, k * r0)]
+        r = kept_count(sv, chi, cutoff)
+        order = order[:r]
         Bt = V[:, order].T.reshape(r, k, r0)
         out[y] = Bt
         W = np.einsum('akc,jkc->aj', Z, Bt.conj())
@@ -279,9 +284,7 @@ def normalize(mps):
 def _compressor(method: str, cutoff: float):
     if method == 'canonical':
         return lambda m, chi: compress_canonical(m, chi, cutoff)
-    if cutoff > 0.0:
-        raise ValueError('the truncated-weight cutoff is defined for the canonical method')
-    return compress_density_matrix
+    return lambda m, chi: compress_density_matrix(m, chi, cutoff)
 
 
 def top_environments(A, g: Geometry, chi: int, method: str = 'canonical', cutoff: float = 0.0):

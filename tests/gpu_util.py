@@ -7,10 +7,12 @@ from oracle import hamiltonian as OH
 from oracle import peps
 
 
-def oracle_eval(theta, Lx, Ly, D, chi, configs, model=None, want_O=False):
+def oracle_eval(theta, Lx, Ly, D, chi, configs, model=None, want_O=False, method="canonical",
+                cutoff=0.0):
     g = peps.Geometry(Lx, Ly, 2, D)
     ham = oracle_ham(model, Lx, Ly) if model else None
-    return peps.evaluate(theta, g, configs, chi, ham, want_O=want_O)
+    return peps.evaluate(theta, g, configs, chi, ham, want_O=want_O, method=method,
+                         cutoff=cutoff)
 
 
 def oracle_ham(model, Lx, Ly):

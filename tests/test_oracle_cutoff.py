@@ -72,3 +72,24 @@ def test_error_falls_with_the_cutoff():
         errs.append(np.abs(np.exp(lp - ref) - 1).max())
     assert errs[0] > 0.1 and errs[-1] < 1e-5
     assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+
+
+def test_density_matrix_cutoff_equals_canonical():
+    # the density-matrix truncation applies the same kept-count rule to the
+    # square roots of its eigenvalues: with a cutoff it must keep the same
+    # states as the canonical sweep (same bond dimensions, same amplitudes)
+    cases = [(4, 4, 2, 4, 5, 0.0, 1e-3), (5, 4, 3, 6, 7, 0.5, 1e-2), (4, 5, 3, 5, 9, 0.0, 1e-2)]
+    for Lx, Ly, D, chi, seed, mu, cut in cases:
+        g = peps.Geometry(Lx, Ly, 2, D)
+        th = synth.theta(Lx, Ly, 2, D, seed=seed, mu=mu)
+        cf = synth.sz0_configs(Lx * Ly, 3, seed=seed + 1)
+        a, _, _ = peps.evaluate(th, g, cf, chi, cutoff=cut)
+        b, _, _ = peps.evaluate(th, g, cf, chi, method='densmat', cutoff=cut)
+        c, _, _ = peps.evaluate(th, g, cf, chi)
+        assert np.abs(np.exp(a - b) - 1).max() < 1e-10
+        assert np.abs(np.exp(a - c) - 1).max() > 1e-6   # the cutoff changes the result
+        A = peps.project(peps.site_tensors(th, g), g, cf[0])
+        U1, _ = peps.top_environments(A, g, chi, 'canonical', cut)
+        U2, _ = peps.top_environments(A, g, chi, 'densmat', cut)
+        for x in range(1, Lx - 1):
+            assert [t.shape for t in U1[x]] == [t.shape for t in U2[x]]
