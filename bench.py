@@ -1,18 +1,21 @@
 """Throughput of the sampled finite-PEPS hot path on one MI355X.
 
-Workload (8x8 open lattice, d=2, D=4, chi=16, 4096 configurations, J1-J2
-Heisenberg with J2/J1 = 0.5, tensors i.i.d. N(0,1) from a fixed seed): one
-step evaluates ln Psi, the local energies E_loc and the log-derivatives O of
-every configuration of the batch (the samples are drawn once, before the
-timed region, by the library's Metropolis sampler when it is available).
-The timed precision defaults to FP32; the same batch is also evaluated in
-FP64 outside the timed region and the relative error of the batch-mean
-energy is reported.
+Timed workload (10x10 open lattice, d=2, D=5, chi=25, complex tensors with
+real and imaginary parts i.i.d. N(0,1) from seed 4, chiral spin-liquid
+Hamiltonian J1=1, J2=0.5, J_chi=0.2; 8192 configurations drawn once, before
+the timed region, by the library's exchange Metropolis sampler in
+complex128): one step evaluates ln Psi, the local energies E_loc and the
+log-derivatives O of one batch of configurations (consecutive steps cycle
+through the 8192) in complex64 with the density-matrix truncation on the
+matrix cores. The same 8192 configurations are evaluated in complex128
+outside the timed region, and the relative error of the mean energy on
+identical samples is reported, with per-configuration quantiles.
 
-Prints one JSON line. Extra fields: the FP64 throughput, the minSR step time,
-one step of the optimisation loop (sample + evaluate + minSR + update), the
-per-kernel split from HIP events, the roofline of the dominant kernel and
-the CPU oracle timed on a bounded sample.
+Prints one JSON line. Extra fields: complex128 throughput, the minSR step
+at n = 8192 (complex parameters, FP64 solve), the per-kernel split from HIP
+events, the roofline of the dominant kernel, the oracle timed on the host's
+cores on a bounded sample, the 8x8 D=4 chi=16 and 12x12 D=4 chi=16 Rydberg
+workloads in FP32 / BF16 against FP64, and the learned-proposal comparison.
 """
 from __future__ import annotations
 
@@ -27,104 +30,171 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {  # MI355X published peaks
+PEAK = {  # MI355X published peaks (dense)
+    "fp32_matrix_tflops": 157.3,
+    "fp64_matrix_tflops": 78.6,
     "fp32_vector_tflops": 157.3,
     "fp64_vector_tflops": 78.6,
     "hbm_gbs": 8000.0,
 }
 
 
-# ---------------------------------------------------------------------------
-# Algorithmic flop model of the environment build (the canonical two-sweep
-# truncation: left QR sweep, right SVD sweep), per sample and both sweeps.
-#   GEMM m x k x n: 2mnk;  Householder R of m x n (m >= n): 2mn^2 - 2n^3/3;
-#   SVD of an m x n block (m <= n) with its m right singular vectors:
-#   4 m^2 n + 8 m^3 (Golub and Van Loan's count for the R-SVD).
-# ---------------------------------------------------------------------------
 def _legs(Lx, Ly, D, x, y):
     return (1 if y == 0 else D, 1 if y == Ly - 1 else D, 1 if x == 0 else D,
             1 if x == Lx - 1 else D)
 
 
-def env_flops_per_sample(Lx, Ly, D, chi):
-    total = 0.0
+def env_bonds(Lx, Ly, D, chi):
+    """Bond dimensions of every boundary MPS (as the library's tables): for
+    each direction and absorbed row t, per site the (bl, br) of the previous
+    environment, the rank bound kk of the left sweep and the new bond r."""
+    out = []
     for direction in (0, 1):
-        # bonds of the first row MPS
-        bonds = [_legs(Lx, Ly, D, 0 if direction == 0 else Lx - 1, y)[1] for y in range(Ly)]
-        right = [1] + bonds[:-1]  # left bond of site y
-        left_b = right
-        right_b = bonds
+        x0 = 0 if direction == 0 else Lx - 1
+        right = [_legs(Lx, Ly, D, x0, y)[1] for y in range(Ly)]
+        left = [1] + right[:-1]
+        rows = []
         for t in range(1, Lx - 1):
             x = t if direction == 0 else Lx - 1 - t
-            kk = []
-            kp = 1
+            kk, kp = [], 1
             for y in range(Ly - 1):
                 Dl, Dr, Du, Dd = _legs(Lx, Ly, D, x, y)
-                Din, Dout = (Du, Dd) if direction == 0 else (Dd, Du)
-                Pl, Pr = left_b[y] * Dl, right_b[y] * Dr
-                total += Dout * 2.0 * Pl * Pr * Din            # P_k
-                if y > 0:
-                    total += Dout * 2.0 * kp * Pl * Pr          # R P_k
-                m, n = kp * Dout, Pr
-                if m >= n:
-                    total += 2.0 * m * n * n - 2.0 * n ** 3 / 3
-                else:
-                    total += 2.0 * n * m * m - 2.0 * m ** 3 / 3
-                kp = min(m, n)
+                Dout = Dd if direction == 0 else Du
+                kp = min(kp * Dout, right[y] * Dr)
                 kk.append(kp)
-            nbr = 1
-            new_left = [1] * Ly
-            new_right = [1] * Ly
+            new_l, new_r, nbr = [1] * Ly, [1] * Ly, 1
+            sites = []
             for y in range(Ly - 1, -1, -1):
                 Dl, Dr, Du, Dd = _legs(Lx, Ly, D, x, y)
                 Din, Dout = (Du, Dd) if direction == 0 else (Dd, Du)
-                bl, br = left_b[y], right_b[y]
-                Pl = bl * Dl
-                zc = Dout * nbr
-                total += 2.0 * bl * Din * nbr * br * Dr        # T1
-                total += 2.0 * Pl * zc * Din * Dr              # Z
-                if y > 0:
-                    kpr = kk[y - 1]
-                    total += 2.0 * kpr * Pl * zc               # C = R Z
-                    m = kpr
+                r = min(chi, kk[y - 1], Dout * nbr) if y > 0 else 1
+                sites.append(dict(y=y, bl=left[y], br=right[y], Dl=Dl, Dr=Dr, Din=Din,
+                                  Dout=Dout, nbr=nbr, r=r))
+                new_l[y], new_r[y], nbr = r, sites[-1]["nbr"], r
+            rows.append(sites[::-1])
+            left, right = new_l, new_r
+        out.append(rows)
+    return out
+
+
+def dm_env_flops_per_sample(Lx, Ly, D, chi, cplx):
+    """Algorithmic flops of the density-matrix environment build per sample
+    (both directions), split into matrix-core work (the Gram, density and
+    weight products) and the rest (projections, eigensolver). A real
+    m x n x k product counts 2mnk, a complex one 8mnk; a Hermitian result
+    counts its lower triangle; the Householder tridiagonalisation of an n x n
+    Hermitian matrix 16n^3/3 (complex) or 4n^3/3 (real), its back
+    transformation of r vectors 8 n^2 r (complex) or 2 n^2 r."""
+    cf = 4.0 if cplx else 1.0
+    mm = alu = 0.0
+    for rows in env_bonds(Lx, Ly, D, chi):
+        for sites in rows:
+            for st in sites[:-1]:   # left sweep
+                Pl, Pr = st["bl"] * st["Dl"], st["br"] * st["Dr"]
+                for _ in range(st["Dout"]):
+                    alu += cf * 2.0 * Pl * Pr * st["Din"]
+                    mm += cf * (2.0 * Pl * Pl * Pr + Pl * Pr * (Pr + 1.0))
+            for st in sites:        # right sweep
+                Pl = st["bl"] * st["Dl"]
+                zc = st["Dout"] * st["nbr"]
+                mm += cf * 2.0 * st["bl"] * st["Din"] * st["nbr"] * st["br"] * st["Dr"]
+                alu += cf * 2.0 * Pl * zc * st["Din"] * st["Dr"]
+                if st["y"] > 0:
+                    mm += cf * (2.0 * Pl * Pl * zc + Pl * zc * (zc + 1.0) + 2.0 * Pl * zc * st["r"])
+                    alu += (16.0 / 3.0 if cplx else 4.0 / 3.0) * zc ** 3
+                    alu += (8.0 if cplx else 2.0) * zc * zc * st["r"]
+    return mm, alu
+
+
+def canonical_env_flops_per_sample(Lx, Ly, D, chi):
+    """Algorithmic flops of the canonical (QR -> SVD) environment build per
+    sample and both sweeps, real tensors: GEMM 2mnk, Householder R of m x n
+    2mn^2 - 2n^3/3, SVD of m x n (m <= n) with its right vectors
+    4 m^2 n + 8 m^3."""
+    total = 0.0
+    for rows in env_bonds(Lx, Ly, D, chi):
+        for sites in rows:
+            kp = 1
+            kks = []
+            for st in sites[:-1]:
+                Pl, Pr = st["bl"] * st["Dl"], st["br"] * st["Dr"]
+                total += st["Dout"] * 2.0 * Pl * Pr * st["Din"]
+                if st["y"] > 0:
+                    total += st["Dout"] * 2.0 * kp * Pl * Pr
+                m, n = kp * st["Dout"], Pr
+                total += (2.0 * m * n * n - 2.0 * n ** 3 / 3) if m >= n else (2.0 * n * m * m - 2.0 * m ** 3 / 3)
+                kp = min(m, n)
+                kks.append(kp)
+            for st in sites:
+                Pl = st["bl"] * st["Dl"]
+                zc = st["Dout"] * st["nbr"]
+                total += 2.0 * st["bl"] * st["Din"] * st["nbr"] * st["br"] * st["Dr"]
+                total += 2.0 * Pl * zc * st["Din"] * st["Dr"]
+                if st["y"] > 0:
+                    m = kks[st["y"] - 1]
+                    total += 2.0 * m * Pl * zc
                     if m > zc:
                         total += 2.0 * m * zc * zc - 2.0 * zc ** 3 / 3
                         m = zc
-                    total += 4.0 * m * m * zc + 8.0 * m ** 3   # SVD
-                    r = min(chi, kpr, zc)
-                    total += 2.0 * Pl * zc * r                 # W
-                else:
-                    r = 1
-                new_left[y] = r
-                new_right[y] = nbr
-                nbr = r
-            left_b, right_b = new_left, new_right
+                    total += 4.0 * m * m * zc + 8.0 * m ** 3 + 2.0 * Pl * zc * st["r"]
     return total
 
 
-def kernel_source_hash():
-    """Hash of the sources the environment kernel is built from."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("common.h", "env_dev.h", "env.hip"):
-        with open(os.path.join(ROOT, "paper_2503_12557_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def env_site_bonds(Lx, Ly, D, chi):
+    """(left, right) bonds of every site of every environment: top[x] for
+    E^u[x] (x = 0..Lx-2), bottom[x] for E^l[x] (x = 1..Lx-1)."""
+    eb = env_bonds(Lx, Ly, D, chi)
+    top = {0: [(1 if y == 0 else D, 1 if y == Ly - 1 else D) for y in range(Ly)]}
+    bot = {Lx - 1: [(1 if y == 0 else D, 1 if y == Ly - 1 else D) for y in range(Ly)]}
+    for t in range(1, Lx - 1):
+        top[t] = [(st["r"], st["nbr"]) for st in eb[0][t - 1]]
+        bot[Lx - 1 - t] = [(st["r"], st["nbr"]) for st in eb[1][t - 1]]
+    return top, bot
 
 
-def env_traffic(dtype):
-    """HBM bytes per k_env_sweep launch from the committed rocprofv3 counter
-    runs (FETCH_SIZE + WRITE_SIZE, calibrated by a copy of known size), or
-    None when they were taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_env_sweep.json")
-    try:
-        with open(path) as fh:
-            rec = json.load(fh)
-    except OSError:
-        return None
-    if rec.get("source_hash") != kernel_source_hash() or rec.get("dtype") != dtype:
-        return None
-    return rec.get("bytes_per_launch")
+def strip2_step_flops(Lx, Ly, D, x, y, up, dn, cplx):
+    """Flops of one step of a two-row partial contraction at column y of rows
+    (x, x+1) with up environment bonds up[y] (or the trivial one), down
+    bonds dn[y]: the four products of the step (2mnk each, x4 complex)."""
+    cf = 4.0 if cplx else 1.0
+    ua, ub = up[y] if up else (1, 1)
+    ba, bb = dn[y] if dn else (1, 1)
+    uk = D if x > 0 else 1
+    Dl = 1 if y == 0 else D
+    Dr = 1 if y == Ly - 1 else D
+    Dd1 = D
+    Dd2 = D if x + 1 < Lx - 1 else 1
+    inner = Dl * Dl * ba
+    f = 2.0 * inner * uk * ub * ua
+    f += 2.0 * (Dl * ba * ub) * (Dr * Dd1) * (Dl * uk)
+    f += 2.0 * (ba * ub * Dr) * (Dr * Dd2) * (Dl * Dd1)
+    f += 2.0 * (ub * Dr * Dr) * bb * (ba * Dd2)
+    return cf * f
+
+
+def strip2_flops(Lx, Ly, D, chi, configs, cplx):
+    """Flops of the two-row strip kernel over a batch, from its step count:
+    per row pair the Ly right-partial steps, the Ly left-partial steps and
+    one window per move with a nonzero coefficient (anti-aligned vertical
+    pairs: one column, diagonal pairs: two), each step as strip2_step_flops."""
+    top, bot = env_site_bonds(Lx, Ly, D, chi)
+    total = 0.0
+    s = configs.reshape(len(configs), Lx, Ly)
+    n = len(configs)
+    for x in range(Lx - 1):
+        up = top[x - 1] if x > 0 else None
+        dn = bot[x + 2] if x + 2 <= Lx - 1 else None
+        step = [strip2_step_flops(Lx, Ly, D, x, y, up, dn, cplx) for y in range(Ly)]
+        a, b = s[:, x, :], s[:, x + 1, :]
+        vert = (a != b)
+        d1 = (a[:, :-1] != b[:, 1:])
+        d2 = (a[:, 1:] != b[:, :-1])
+        total += 2 * n * sum(step)
+        for y in range(Ly):
+            total += vert[:, y].sum() * step[y]
+        for y in range(Ly - 1):
+            total += (d1[:, y].sum() + d2[:, y].sum()) * (step[y] + step[y + 1])
+    return total
 
 
 def _sync():
@@ -132,37 +202,75 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def cpu_baseline(theta, Lx, Ly, D, chi, configs, seconds=12.0):
-    """The FP64 oracle on the host, one process and one BLAS thread, on the
-    first configurations of the batch until about `seconds` have passed."""
-    from threadpoolctl import threadpool_limits
+_T0 = time.perf_counter()
 
+
+def _log(msg):
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# The oracle on the host's cores: one worker process per core, one BLAS
+# thread each, configurations handed out one at a time until the time budget
+# is spent.
+# ---------------------------------------------------------------------------
+_ORC = {}
+
+
+def _orc_init(theta, Lx, Ly, D, chi, model):
+    from threadpoolctl import threadpool_limits
     from oracle import hamiltonian as OH
     from oracle import peps
+    _ORC["lim"] = threadpool_limits(limits=1)
     g = peps.Geometry(Lx, Ly, 2, D)
-    ham = OH.j1j2(Lx, Ly, 1.0, 0.5)
-    T = peps.site_tensors(theta, g)
+    name, kw = model
+    ham = {"j1j2": OH.j1j2, "chiral": OH.csl, "rydberg": OH.rydberg}[name](Lx, Ly, **kw)
+    _ORC.update(T=peps.site_tensors(theta, g), g=g, chi=chi, ham=ham, peps=peps)
+
+
+def _orc_one(cfg):
+    P = _ORC["peps"]
+    sc = P.SampleContraction(_ORC["T"], _ORC["g"], cfg, _ORC["chi"])
+    sc.local_energy(_ORC["ham"])
+    sc.logderiv_compact()
+    return 1
+
+
+def cpu_baseline(theta, Lx, Ly, D, chi, model, configs, seconds=20.0):
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(cores, 16))
+    ctxm = mp.get_context("fork")
     done = 0
-    with threadpool_limits(limits=1):
+    with ctxm.Pool(workers, initializer=_orc_init,
+                   initargs=(theta, Lx, Ly, D, chi, model)) as pool:
+        # warm the workers (imports, tensors) outside the timed region
+        pool.map(_orc_one, [configs[i % len(configs)] for i in range(workers)])
         t0 = time.perf_counter()
-        while done < len(configs):
-            sc = peps.SampleContraction(T, g, configs[done], chi)
-            sc.local_energy(ham)
-            sc.logderiv_compact()
+        it = pool.imap_unordered(_orc_one, [configs[i % len(configs)] for i in range(100000)])
+        for _ in it:
             done += 1
             if time.perf_counter() - t0 > seconds:
                 break
         dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} configurations of the same batch (psi + E_loc + O, FP64 numpy, "
-                      f"1 BLAS thread), {dt:.1f} s"}
+        pool.terminate()
+    return {"value": done / dt, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"{done} configurations of the timed batch (psi + E_loc + O, FP64 / "
+                      f"complex128 numpy oracle, canonical truncation, one BLAS thread per "
+                      f"worker, {workers} worker processes) in {dt:.1f} s"}
 
 
 def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     """Effective samples per second of the energy series: local exchange
     Metropolis against independence MH with the learned proposal (trained on
-    65536 configurations of the local sampler, 2000 Adam steps by default).
-    Sampling time only; E_loc of the recorded states is evaluated untimed."""
+    65536 configurations of the local sampler). Both arms start from
+    burned-in states: the IMH chains from the local sampler's states after
+    16 sweeps, the local chains run their own 16 burn-in sweeps, whose
+    separately timed cost is subtracted. E_loc of the recorded states is
+    evaluated untimed."""
     import torch
 
     from paper_2503_12557_amd import analysis
@@ -170,14 +278,18 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     N = Lx * Ly
     ctx = Context(Lx, Ly, D, chi, "f32")
     ctx.set_hamiltonian(ham)
-    chains, T = 256, 64
-    init, _ = ctx.sample(theta, "exchange", n_chains=chains, per_chain=1, burn_in=16, seed=21)
+    chains, T, burn = 256, 64, 16
+    init, _ = ctx.sample(theta, "exchange", n_chains=chains, per_chain=1, burn_in=burn, seed=21)
     _sync()
     t0 = time.perf_counter()
-    mh, acc_mh = ctx.sample(theta, "exchange", n_chains=chains, per_chain=T, burn_in=0,
+    ctx.sample(theta, "exchange", n_chains=chains, per_chain=1, burn_in=burn, seed=25)
+    _sync()
+    t_burn = (time.perf_counter() - t0) * burn / (burn + 1.0)
+    t0 = time.perf_counter()
+    mh, acc_mh = ctx.sample(theta, "exchange", n_chains=chains, per_chain=T, burn_in=burn,
                             seed=22)
     _sync()
-    t_mh = time.perf_counter() - t0
+    t_mh = time.perf_counter() - t0 - t_burn
     e_mh = ctx.evaluate(theta, mh, want_o=False)[1][:, 0].view(chains, T).cpu().numpy()
     t0 = time.perf_counter()
     data, _ = ctx.sample(theta, "exchange", n_chains=1024, per_chain=64, burn_in=16, seed=23)
@@ -198,8 +310,6 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     t_imh = time.perf_counter() - t0
     states = hist.permute(1, 0, 2).reshape(chains * T, N).contiguous()
     e_imh = ctx.evaluate(theta, states, want_o=False)[1][:, 0].view(chains, T).cpu().numpy()
-    # E_loc of unconverged random tensors is heavy-tailed: ESS from the
-    # rank-normalised series, the plain estimate reported beside it
     tau_mh, tau_imh = analysis.tau_int_ranked(e_mh), analysis.tau_int_ranked(e_imh)
     raw_mh, raw_imh = analysis.tau_int(e_mh), analysis.tau_int(e_imh)
     hist_np = hist.cpu().numpy()
@@ -207,13 +317,13 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     sweeps_moves = (2 * Ly - 1) * Lx
     return {
         "workload": f"{Lx}x{Ly} D={D} chi={chi} J1-J2 J2/J1=0.5, {chains} chains x {T} "
-                    "steps, energy series, stationary starts",
+                    f"steps, energy series, both arms after {burn} burn-in sweeps",
         "tau_int_estimator": "Sokal window on rank-normalised E_loc (normal scores of pooled "
                              "ranks); tau_int_plain: same window on raw E_loc",
         "local_mh": {"tau_int": tau_mh, "tau_int_plain": raw_mh, "ess": chains * T / tau_mh,
-                     "seconds": t_mh,
+                     "seconds": t_mh, "burn_in_seconds_subtracted": t_burn,
                      "ess_per_s": chains * T / tau_mh / t_mh,
-                     "acceptance_per_move": float(acc_mh.sum().item()) / (chains * T * sweeps_moves)},
+                     "acceptance_per_move": float(acc_mh.sum().item()) / (chains * (T + burn) * sweeps_moves)},
         "imh_learned": {"tau_int": tau_imh, "tau_int_plain": raw_imh,
                         "ess": chains * T / tau_imh, "seconds": t_imh,
                         "ess_per_s": chains * T / tau_imh / t_imh,
@@ -225,16 +335,72 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     }
 
 
+def _err_block(e_lo, e_hi, lp_lo, lp_hi):
+    """Relative error of the mean energy and per-configuration quantiles."""
+    import torch
+    rel = abs(e_lo.mean().item() - e_hi.mean().item()) / abs(e_hi.mean().item())
+    per = ((e_lo - e_hi).abs() / e_hi.abs().clamp_min(1.0)).cpu().numpy()
+    dpsi = (lp_lo[:, 0] - lp_hi[:, 0]).abs().cpu().numpy()
+    return rel, {"median": float(np.median(per)), "p90": float(np.quantile(per, 0.9)),
+                 "p99": float(np.quantile(per, 0.99)), "max": float(per.max())}, \
+        {"median": float(np.median(dpsi)), "p99": float(np.quantile(dpsi, 0.99))}
+
+
+def side_workload(Context, ham, Lx, Ly, D, chi, n, seed, mu, kind, dtypes, ref="f64",
+                  compression="canonical"):
+    """Throughput and energy error of reduced-precision modes on one of the
+    real-tensor workloads (samples from the library's FP64 sampler)."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    th = torch.from_numpy(synth.theta(Lx, Ly, 2, D, seed=seed, mu=mu)).to(dev)
+    c64 = Context(Lx, Ly, D, chi, ref)
+    c64.set_hamiltonian(ham)
+    chains = min(n, 1024)
+    t0 = time.perf_counter()
+    sm, _ = c64.sample(th, kind, n_chains=chains, per_chain=(n + chains - 1) // chains,
+                       burn_in=8, seed=seed + 10)
+    _sync()
+    t_s = time.perf_counter() - t0
+    sm = sm[:n].contiguous()
+    out = {"workload": f"{Lx}x{Ly} d=2 D={D} chi={chi}, N({mu},1) tensors seed {seed}, {n} "
+                       f"configurations ({kind} Metropolis, FP64, burn-in 8)",
+           "sampling_s": round(t_s, 2)}
+    res = {}
+    for dt in [ref] + list(dtypes):
+        ctx = c64 if dt == ref else Context(Lx, Ly, D, chi, dt)
+        if ctx is not c64:
+            ctx.set_hamiltonian(ham)
+        if compression != "canonical":
+            ctx.set_compression(compression)
+        o = ctx.evaluate(th, sm)
+        _sync()
+        t0 = time.perf_counter()
+        ctx.evaluate(th, sm, out=o)
+        _sync()
+        res[dt] = (o, time.perf_counter() - t0)
+    lp_hi, e_hi = res[ref][0][0], res[ref][0][1][:, 0].double()
+    out[f"{ref}_samples_per_s"] = round(n / res[ref][1], 2)
+    out["energy_mean_" + ref] = e_hi.mean().item()
+    for dt in dtypes:
+        o, t = res[dt]
+        rel, per, dpsi = _err_block(o[1][:, 0].double(), e_hi, o[0], lp_hi)
+        out[dt] = {"samples_per_s": round(n / t, 2), "energy_rel_err": rel,
+                   "eloc_rel_err_per_config": per, "ln_psi_abs_err_per_config": dpsi}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f64"])
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--batch", type=int, default=1024,
+                    help="configurations per step (steps cycle through the set)")
+    ap.add_argument("--configs", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sampler", default="auto", choices=["auto", "uniform", "metropolis"])
-    ap.add_argument("--no-ess", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side workloads and the learned-proposal comparison")
     ap.add_argument("--made-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -246,109 +412,104 @@ def main():
 
     import synth
     from paper_2503_12557_amd import Context, hamiltonians
-    from paper_2503_12557_amd.binding import PepsError
 
-    Lx, Ly, D, chi, n = 8, 8, 4, 16, args.n
     dev = torch.device("cuda:0")
-    theta_np = synth.theta(Lx, Ly, 2, D, seed=2, mu=0.0)
+    Lx, Ly, D, chi = 10, 10, 5, 25
+    model = ("chiral", dict(J1=1.0, J2=0.5, Jchi=0.2))
+    ham = hamiltonians.chiral(Lx, Ly, J1=1.0, J2=0.5, Jchi=0.2)
+    theta_np = synth.theta(Lx, Ly, 2, D, seed=4, cplx=True)
     theta = torch.from_numpy(theta_np).to(dev)
-    ham = hamiltonians.j1j2(Lx, Ly, 1.0, 0.5)
+    nconf = args.configs
 
-    ctx64 = Context(Lx, Ly, D, chi, "f64")
-    ctx64.set_hamiltonian(ham)
-    sampler_used = "uniform S_z=0 permutations (seed 1)"
-    samples = None
-    t_sample = None
-    if args.sampler in ("auto", "metropolis"):
-        try:
-            # the FP64 sampler: the batch does not move with FP32 rounding
-            ctx_s = ctx64
-            chains = min(n, 1024)
-            per = (n + chains - 1) // chains
-            t0 = time.perf_counter()
-            samples, acc = ctx_s.sample(theta, "exchange", n_chains=chains, per_chain=per,
-                                        burn_in=8, thin=1, seed=1)
-            _sync()
-            t_sample = time.perf_counter() - t0
-            sampler_used = (f"local exchange Metropolis (library sampler, FP64, {chains} chains x "
-                            f"{per}, burn-in 8 sweeps, seed 1)")
-        except PepsError:
-            if args.sampler == "metropolis":
-                raise
-            samples = None
-    if samples is None:
-        samples = torch.from_numpy(synth.sz0_configs(Lx * Ly, n, seed=1)).to(dev)
-    samples = samples[:n].contiguous()
+    ref = Context(Lx, Ly, D, chi, "c128")
+    ref.set_hamiltonian(ham)
+    ref.set_compression("densmat")
+    chains = min(nconf, 1024)
+    per = (nconf + chains - 1) // chains
+    t0 = time.perf_counter()
+    samples, acc = ref.sample(theta, "exchange", n_chains=chains, per_chain=per, burn_in=8,
+                              thin=1, seed=1)
+    _sync()
+    t_sample = time.perf_counter() - t0
+    samples = samples[:nconf].contiguous()
+    _log(f"sampled {nconf} configurations in {t_sample:.1f} s")
+    sampler_used = (f"local exchange Metropolis (library sampler, complex128, {chains} chains x "
+                    f"{per}, burn-in 8 sweeps, seed 1), {t_sample:.1f} s")
 
-    # FP64 reference pass (untimed) on the same batch
-    lp64, e64, O64, f64 = ctx64.evaluate(theta, samples)
+    # complex128 reference on the whole set (untimed; its rate reported)
+    out128 = ref.evaluate(theta, samples)
     _sync()
     t0 = time.perf_counter()
-    ctx64.evaluate(theta, samples)
+    ref.evaluate(theta, samples, out=out128)
     _sync()
-    t64 = time.perf_counter() - t0
+    t128 = time.perf_counter() - t0
+    _log(f"complex128 reference: {nconf / t128:.1f} samples/s")
 
-    # a plain elementwise kernel of known traffic (256 MiB read + 256 MiB
-    # written); its FETCH_SIZE / WRITE_SIZE under rocprofv3 --pmc calibrate
-    # the traffic counters
-    calib = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-    torch.mul(calib, 2.0)
-    del calib
-    ctx = ctx64 if args.dtype == "f64" else Context(Lx, Ly, D, chi, args.dtype)
-    if ctx is not ctx64:
-        ctx.set_hamiltonian(ham)
-    out = ctx.evaluate(theta, samples)
-    for _ in range(args.warmup):
-        ctx.evaluate(theta, samples, out=out)
+    ctx = Context(Lx, Ly, D, chi, "c64")
+    ctx.set_hamiltonian(ham)
+    ctx.set_compression("densmat")
+    full = ctx.evaluate(theta, samples)   # every configuration once, for the error
+    _sync()
+    B = min(args.batch, nconf)
+    chunks = [samples[i:i + B].contiguous() for i in range(0, nconf - B + 1, B)]
+    outs = [ctx.evaluate(theta, chunks[0]) for _ in range(2)]
+    for w in range(args.warmup):
+        ctx.evaluate(theta, chunks[w % len(chunks)], out=outs[w % 2])
     _sync()
     ctx.profile(True)
     ctx.profile_read(reset=True)
     _sync()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.evaluate(theta, samples, out=out)
+    for k in range(args.steps):
+        ctx.evaluate(theta, chunks[k % len(chunks)], out=outs[k % 2])
     _sync()
     dt = time.perf_counter() - t0
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
-    lp, el, O, fl = out
-    e_lo = el[:, 0].double().mean().item()
-    e_hi = e64[:, 0].mean().item()
-    rel_e = abs(e_lo - e_hi) / abs(e_hi)
-    # per-configuration errors: the batch mean of random tensors is carried
-    # by a few near-zero amplitudes with huge E_loc, so report quantiles too
-    per_e = ((el[:, 0].double() - e64[:, 0]).abs() / e64[:, 0].abs().clamp_min(1.0)).cpu().numpy()
-    per_psi = (lp[:, 0] - lp64[:, 0]).abs().cpu().numpy()
-    flags = int(torch.bitwise_or(fl, f64).max().item())
+    _log(f"timed {args.steps} steps: {B * args.steps / dt:.1f} samples/s")
 
-    # minSR step on the batch (FP64 solve), timed separately
-    ctx.minsr_step(O, samples, el, eps=1e-4, rcond=1e-12)
-    _sync()
-    t0 = time.perf_counter()
-    dth, diag = ctx.minsr_step(O, samples, el, eps=1e-4, rcond=1e-12)
-    _sync()
-    t_minsr = time.perf_counter() - t0
-
+    rel_e, per_e, per_psi = _err_block(full[1][:, 0].double(), out128[1][:, 0],
+                                       full[0], out128[0])
+    flags = int(torch.bitwise_or(full[3], out128[3]).max().item())
     ms_per_step = dt / args.steps * 1e3
-    value = n / (dt / args.steps)
+    value = B / (dt / args.steps)
+
     per_kernel = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                       "ms_avg": round(v[0] / v[1], 4) if v[1] else None}
                   for k, v in prof.items() if v[1]}
-    # dominant kernel and its roofline
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
-    env_avg_ms = per_kernel["env"]["ms_avg"]
-    # samples one launch processes: the batch is split into equal chunks
-    env_launches_per_step = per_kernel["env"]["launches"] / args.steps
-    samples_per_launch = n / env_launches_per_step
-    env_flops = env_flops_per_sample(Lx, Ly, D, chi) * samples_per_launch
-    peak = PEAK["fp64_vector_tflops"] if args.dtype == "f64" else PEAK["fp32_vector_tflops"]
-    achieved = env_flops / (env_avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_env_sweep", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-                "traffic": env_traffic(args.dtype),
-                "algorithmic_flops_per_launch": env_flops,
-                "samples_per_launch": samples_per_launch,
-                "avg_launch_ms": env_avg_ms, "dominant_kernel_by_time": dom}
+    # roofline of the dominant kernel: algorithmic flops of one launch over
+    # its average duration
+    steps_done = args.steps
+    mm_s, alu_s = dm_env_flops_per_sample(Lx, Ly, D, chi, True)
+    env_launch_samples = B / (per_kernel["env"]["launches"] / steps_done)
+    s2_batch = torch.cat([chunks[k % len(chunks)] for k in range(steps_done)]).cpu().numpy()
+    s2_flops_total = strip2_flops(Lx, Ly, D, chi, s2_batch, True)
+    rooflines = {
+        "env": {"kernel": "k_env_dm", "bound": "mfma",
+                "achieved": mm_s * env_launch_samples / (per_kernel["env"]["ms_avg"] * 1e-3) / 1e12,
+                "peak": PEAK["fp32_matrix_tflops"], "unit": "TFLOP/s",
+                "algorithmic_mfma_flops_per_sample": mm_s,
+                "algorithmic_alu_flops_per_sample": alu_s,
+                "samples_per_launch": env_launch_samples,
+                "avg_launch_ms": per_kernel["env"]["ms_avg"]},
+    }
+    if "strip2" in per_kernel:
+        s2 = per_kernel["strip2"]
+        rooflines["strip2"] = {
+            "kernel": "k_strip2", "bound": "alu",
+            "achieved": s2_flops_total / s2["launches"] / (s2["ms_avg"] * 1e-3) / 1e12,
+            "peak": PEAK["fp32_vector_tflops"], "unit": "TFLOP/s",
+            "algorithmic_flops_per_launch": s2_flops_total / s2["launches"],
+            "samples_per_launch": B * steps_done / s2["launches"],
+            "avg_launch_ms": s2["ms_avg"]}
+    for r in rooflines.values():
+        r["achieved"] = round(r["achieved"], 3)
+        r["frac"] = round(r["achieved"] / r["peak"], 5)
+    dom_key = dom if dom in rooflines else "env"
+    roofline = dict(rooflines[dom_key])
+    roofline["traffic"] = None
+    roofline["dominant_kernel_by_time"] = dom
 
     res = {
         "metric": "samples/s (psi+E_loc+O)",
@@ -361,124 +522,54 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
+        "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "8x8 open lattice d=2 D=4 chi=16, J1-J2 J2/J1=0.5, "
-                               f"{n} configurations, tensors N(0,1) seed 2",
-                   "samples": sampler_used, "global_batch": n},
-        "energy_rel_err_vs_f64": rel_e,
-        "eloc_rel_err_per_config": {"median": float(np.median(per_e)),
-                                    "p99": float(np.quantile(per_e, 0.99)),
-                                    "max": float(per_e.max())},
-        "ln_psi_abs_err_per_config": {"median": float(np.median(per_psi)),
-                                      "p99": float(np.quantile(per_psi, 0.99))},
-        "energy_mean_f64": e_hi,
-        "value_f64": round(n / t64, 2),
-        "minsr_step_ms": round(t_minsr * 1e3, 2),
-        "sampling_s": round(t_sample, 2) if t_sample is not None else None,
-        "minsr_diag": [float(v) for v in diag.cpu().numpy()],
+        "config": {"workload": "10x10 open lattice d=2 D=5 chi=25, complex tensors "
+                               "N(0,1)+iN(0,1) seed 4, chiral spin liquid J1=1 J2=0.5 "
+                               f"Jchi=0.2, {nconf} configurations",
+                   "samples": sampler_used, "global_batch": B, "configurations": nconf,
+                   "truncation": "density-matrix (Gram and density products on MFMA)"},
+        "energy_rel_err_vs_c128": rel_e,
+        "eloc_rel_err_per_config": per_e,
+        "ln_psi_abs_err_per_config": per_psi,
+        "energy_mean_c128": out128[1][:, 0].mean().item(),
+        "value_c128": round(nconf / t128, 2),
         "flags_or": flags,
         "per_kernel": per_kernel,
         "roofline": roofline,
+        "rooflines": rooflines,
     }
-    # one step of the optimisation loop on the same workload, in the bench's
-    # compute dtype: sample (1024 chains x 4, burn-in 8) + evaluate + minSR +
-    # update, from a copy of theta
-    th_opt = theta.clone()
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
+    # minSR step on all configurations (n = 8192, complex parameters, FP64
+    # Gram and solve) from the complex64 log-derivatives
+    O, el = full[2], full[1]
+    ctx.minsr_step(O, samples, el, eps=1e-4, rcond=1e-12)
     _sync()
     t0 = time.perf_counter()
-    ctx.vmc_step(th_opt, 0.05, n_chains=1024, per_chain=max(1, n // 1024), burn_in=8, seed=9)
+    dth, diag = ctx.minsr_step(O, samples, el, eps=1e-4, rcond=1e-12)
     _sync()
-    t_vmc = time.perf_counter() - t0
-    pv = ctx.profile_read(reset=True)
-    ctx.profile(False)
-    res["optimisation_step"] = {
-        "seconds": round(t_vmc, 3), "samples": 1024 * max(1, n // 1024),
-        "sampler": "local exchange Metropolis, 1024 chains, burn-in 8 sweeps",
-        "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pv.items() if v[1]}}
-    del th_opt
-    # the same evaluation with a maximal truncated weight of 1e-4 per bond
-    # (the paper's cutoff) inside chi = 16, and the relative contraction
-    # error Delta psi against the fixed chi = 16 amplitudes
-    ctx.set_truncation(1e-4)
-    outc = ctx.evaluate(theta, samples)
-    _sync()
-    t0 = time.perf_counter()
-    ctx.evaluate(theta, samples, out=outc)
-    _sync()
-    t_cut = time.perf_counter() - t0
-    ctx.set_truncation(0.0)
-    dpsi = (torch.exp(outc[0][:, 0] - lp[:, 0]) - 1).abs().cpu().numpy()
-    res["truncated_weight_1e-4"] = {
-        "samples_per_s": round(n / t_cut, 2),
-        "delta_psi_median": float(np.median(dpsi)), "delta_psi_p99": float(np.quantile(dpsi, 0.99)),
-        "energy_mean": float(outc[1][:, 0].double().mean().item())}
-    # direct sampler (independent draws, importance weights) on the same
-    # workload: 1024 draws, chi_d = D, in the bench's compute dtype
-    nd = min(n, 1024)
-    ctx.direct_sample(theta, 64, D, seed=12, want_logw=False)
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
-    _sync()
-    t0 = time.perf_counter()
-    sd, lpd, lwd, fld = ctx.direct_sample(theta, nd, D, seed=13)
-    _sync()
-    t_dir = time.perf_counter() - t0
-    pdir = ctx.profile_read(reset=True)
-    ctx.profile(False)
-    # the same draws reusing the double-layer environments just built
-    _sync()
-    t0 = time.perf_counter()
-    ctx.direct_sample(theta, nd, D, seed=13, refresh=False)
-    _sync()
-    t_reuse = time.perf_counter() - t0
-    wd = torch.exp(lwd - lwd.max())
-    ess = (wd.sum() ** 2 / (wd * wd).sum()).item()
-    # the reweighted energy of the direct draws (self-normalised importance
-    # sampling) beside the Metropolis batch mean
-    eld = ctx.local_energy(theta, sd)[:, 0].double()
-    e_dir = ((wd * eld).sum() / wd.sum()).item()
-    res["direct_sampler"] = {
-        "samples": nd, "chi_double": D, "seconds": round(t_dir, 3),
-        "samples_per_s": round(nd / t_dir, 2), "importance_ess": round(ess, 2),
-        "ess_per_s": round(ess / t_dir, 2), "flags_or": int(fld.max().item()),
-        "reweighted_energy": e_dir, "metropolis_energy_fp64": e_hi,
-        "seconds_reusing_double_layer": round(t_reuse, 3),
-        "samples_per_s_reusing_double_layer": round(nd / t_reuse, 2),
-        "ms_by_kernel_kind": {k: round(v[0], 2) for k, v in pdir.items() if v[1]}}
-    # strict local energy (every amplitude at the one cut) on the first 64
-    # configurations of the batch, in the bench's compute dtype
-    ks = min(n, 64)
-    sk = samples[:ks].contiguous()
-    es = ctx.local_energy_strict(theta, sk)
-    _sync()
-    t0 = time.perf_counter()
-    es = ctx.local_energy_strict(theta, sk)
-    _sync()
-    t_strict = time.perf_counter() - t0
-    res["strict_local_energy"] = {
-        "samples": ks, "seconds": round(t_strict, 4),
-        "samples_per_s": round(ks / t_strict, 2),
-        "mean_re": float(es[:, 0].mean().item()),
-        "strip_mean_re_same_samples": float(el[:ks, 0].double().mean().item())}
-    # energy error on the mu = 0.5 tensors (positive mean, less cancellation)
-    th5 = torch.from_numpy(synth.theta(Lx, Ly, 2, D, seed=3, mu=0.5)).to(dev)
-    ctx_s5 = Context(Lx, Ly, D, chi, "f32")
-    s5, _ = ctx_s5.sample(th5, "exchange", n_chains=1024, per_chain=1, burn_in=8, seed=5)
-    e5_hi = ctx64.evaluate(th5, s5, want_o=False)[1][:, 0].mean().item()
-    e5_lo = ctx.evaluate(th5, s5, want_o=False)[1][:, 0].double().mean().item()
-    res["energy_rel_err_vs_f64_mu0.5"] = abs(e5_lo - e5_hi) / abs(e5_hi)
-    res["energy_mean_f64_mu0.5"] = e5_hi
-    if not args.no_ess:
-        res["learned_proposal"] = ess_comparison(Context, theta, Lx, Ly, D, chi, ham,
+    res["minsr_step_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    _log(f"minSR n={nconf}: {res['minsr_step_ms']} ms")
+    res["minsr_n"] = nconf
+    res["minsr_diag"] = [float(v) for v in diag.cpu().numpy()]
+    del dth, O, full, out128
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        res["workload_8x8_D4_chi16"] = side_workload(
+            Context, hamiltonians.j1j2(8, 8, 1.0, 0.5), 8, 8, 4, 16, 4096, 2, 0.0, "exchange",
+            ["f32", "bf16"])
+        res["workload_12x12_D4_chi16_rydberg"] = side_workload(
+            Context, hamiltonians.rydberg(12, 12, Omega=1.0, Delta=3.0, V=1.7 ** 6), 12, 12, 4, 16,
+            4096, 5, 0.0, "flip", ["f32", "bf16"])
+        th2 = torch.from_numpy(synth.theta(8, 8, 2, 4, seed=2)).to(dev)
+        _log("side workloads done")
+        res["learned_proposal"] = ess_comparison(Context, th2, 8, 8, 4, 16,
+                                                 hamiltonians.j1j2(8, 8, 1.0, 0.5),
                                                  args.made_steps)
+    _log("extras done")
     if not args.no_cpu:
-        # a bounded sample of the batch: up to 512 configurations or ~15 s
-        k = min(n, 512)
-        res["cpu_baseline"] = cpu_baseline(theta_np, Lx, Ly, D, chi, samples[:k].cpu().numpy(),
-                                           seconds=15.0)
+        res["cpu_baseline"] = cpu_baseline(theta_np, Lx, Ly, D, chi, model,
+                                           samples[:256].cpu().numpy(), seconds=20.0)
     print(json.dumps(res))
 
 

@@ -55,6 +55,15 @@ typedef enum {
   PEPS_ERR_NONFINITE = 5     /* non-finite input (theta, E_loc) */
 } peps_status;
 
+/* Asynchrony. peps_amplitude, peps_local_energy, peps_logderiv,
+ * and peps_evaluate enqueue their work on the stream and
+ * return without waiting for the device: a non-finite theta is then not a
+ * return code but bit PEPS_FLAG_NONFINITE in every sample's flags (when
+ * flags are requested; the outputs are non-finite too). minsr_step checks
+ * E_loc on the host first (one synchronisation); the samplers, the
+ * optimisation step and the strict energy synchronise where they need a
+ * count or a decision from the device. */
+
 /* Compute precision of the contractions (Sec. "On Numerical Stability"
  * discusses reduced precision). Log scales, local energies and the minSR
  * solve are always FP64 (complex FP64 for complex parameters). */

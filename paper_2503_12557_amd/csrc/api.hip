@@ -461,7 +461,11 @@ peps_status peps_set_hamiltonian(peps_ctx* c, int n_terms, const int* term_nsite
 // ---------------------------------------------------------------------------
 // internal drivers
 // ---------------------------------------------------------------------------
-static peps_status prepare_theta(peps_ctx* c, const double* theta, hipStream_t st) {
+// theta in the compute type. sync: check it on the host (synchronises the
+// stream) and fail with PEPS_ERR_NONFINITE; otherwise the non-finite flag
+// stays on the device (c->bad) for launch_flag_bad.
+static peps_status prepare_theta(peps_ctx* c, const double* theta, hipStream_t st,
+                                 bool sync = true) {
   const int np = c->L.n_params;
   peps_status s = c->theta_c.ensure((size_t)np * c->tsize);
   if (s != PEPS_OK) return s;
@@ -470,6 +474,7 @@ static peps_status prepare_theta(peps_ctx* c, const double* theta, hipStream_t s
   HIPCHK(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
   HIPCHK(launch_convert_theta(c->g.dtype == PEPS_BF16 ? MODE_F32 : c->g.dtype, theta,
                               c->theta_c.p, np, (int*)c->bad.p, st));
+  if (!sync) return PEPS_OK;
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -657,25 +662,34 @@ static peps_status dispatch(peps_ctx* c, const double* theta, const uint8_t* sam
   hipStream_t st = (hipStream_t)stream;
   if (n == 0) return PEPS_OK;
   if (eloc && !c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
-  peps_status s = prepare_theta(c, theta, st);
+  // no host round trip: a non-finite theta is reported in the flags
+  peps_status s = prepare_theta(c, theta, st, false);
   if (s != PEPS_OK) return s;
   switch (c->g.dtype) {
     case PEPS_F64:
-      return evaluate_impl<MODE_F64>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
-                                     flags, st);
+      s = evaluate_impl<MODE_F64>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                  flags, st);
+      break;
     case PEPS_F32:
-      return evaluate_impl<MODE_F32>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
-                                     flags, st);
+      s = evaluate_impl<MODE_F32>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                  flags, st);
+      break;
     case PEPS_BF16:
-      return evaluate_impl<MODE_BF16>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
-                                      flags, st);
+      s = evaluate_impl<MODE_BF16>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                   flags, st);
+      break;
     case PEPS_C128:
-      return evaluate_impl<MODE_C128>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
-                                      flags, st);
+      s = evaluate_impl<MODE_C128>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                   flags, st);
+      break;
     default:
-      return evaluate_impl<MODE_C64>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
-                                     flags, st);
+      s = evaluate_impl<MODE_C64>(c, theta, samples, n, env_cache, env_given, logpsi, eloc, O,
+                                  flags, st);
+      break;
   }
+  if (s != PEPS_OK) return s;
+  if (flags) HIPCHK(launch_flag_bad(flags, n, (const int*)c->bad.p, st));
+  return PEPS_OK;
 }
 
 extern "C" {

@@ -141,6 +141,19 @@ __global__ void k_convert_theta(const double* __restrict__ src, T* __restrict__ 
   }
 }
 
+// every sample's flags get bit 1 (non-finite) when theta held a non-finite value
+__global__ void k_flag_bad(int* __restrict__ flags, int n, const int* __restrict__ bad) {
+  if (*bad == 0) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    flags[i] |= 2;
+}
+
+hipError_t launch_flag_bad(int* flags, int n, const int* bad, hipStream_t st) {
+  const int blocks = (n + 255) / 256 < 256 ? (n + 255) / 256 : 256;
+  hipLaunchKernelGGL(k_flag_bad, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, flags, n, bad);
+  return hipGetLastError();
+}
+
 // ---- host launchers ----
 size_t env_lds_bytes(int mode, const Lattice& L, bool gm) {
   const size_t es = mode_elem_bytes(mode);

@@ -67,6 +67,7 @@ hipError_t launch_overlap(const Lattice& L, const int* tab, const void* env, con
                           int icut, double* logpsi, int* flags, int n, hipStream_t st);
 hipError_t launch_convert_theta(int mode, const double* src, void* dst, int n, int* bad,
                                 hipStream_t st);
+hipError_t launch_flag_bad(int* flags, int n, const int* bad, hipStream_t st);
 
 template <int M>
 hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,

@@ -420,28 +420,33 @@ __global__ void k_sum_y(const S* __restrict__ y, int n, S* __restrict__ out) {
 }
 
 // certificate: no eigenvalue of T + eps I is dropped if trace(T) + eps <= eps / rcond
+// (a non-finite local energy, flagged by k_estats, fails it too: diag[3] = 2)
 __global__ void k_certify(int n, double eps, double rcond, double* __restrict__ ws,
-                          double* __restrict__ diag) {
+                          const int* __restrict__ bad, double* __restrict__ diag) {
   if (threadIdx.x != 0) return;
   const double bound = ws[2] + eps;
   const bool ok = (eps > 0.0) && (bound * rcond <= eps);
   ws[6] = ok ? 0.0 : 1.0;
   if (ws[4] != 0.0) ws[6] = 1.0;
+  if (*bad) ws[6] = 1.0;
   diag[0] = bound;
   diag[1] = eps;
   diag[2] = 0.0;
-  diag[3] = ws[6];
+  diag[3] = *bad ? 2.0 : ws[6];
   diag[4] = ws[0];
   diag[5] = ws[1];
   diag[6] = (double)n;
   diag[7] = ws[5];
 }
 
-__global__ void k_init_ws(double* ws) {
+// fresh state of a call: a kernel rather than a memset, so the whole step
+// can be recorded into a graph and the workspace can be shared memory
+__global__ void k_init_ws(double* ws, int* bad) {
   if (threadIdx.x == 0) {
     ws[4] = 0.0;
     ws[5] = 1e300;
     ws[6] = 0.0;
+    *bad = 0;
   }
 }
 
@@ -459,8 +464,7 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
   S* sy = y + n;
   double* ws = (double*)(sy + 1);
   int* bad = (int*)(ws + 16);
-  hipLaunchKernelGGL(k_init_ws, dim3(1), dim3(64), 0, st, ws);
-  hipMemsetAsync(bad, 0, sizeof(int), st);
+  hipLaunchKernelGGL(k_init_ws, dim3(1), dim3(64), 0, st, ws, bad);
   const int cb = (L.n_compact + 255) / 256;
   hipLaunchKernelGGL(k_colmean<TO>, dim3(cb), dim3(256), 0, st, L, tab, O, samples, n, mean);
   hipLaunchKernelGGL(k_proj_mean<TO>, dim3(n + 1), dim3(256), 0, st, L, tab, O, samples, n,
@@ -480,7 +484,8 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
       hipLaunchKernelGGL(k_chol_syrk<S>, dim3(nr, nr), dim3(256), 0, st, Tm, n, kb);
     }
   }
-  hipLaunchKernelGGL(k_certify, dim3(1), dim3(64), 0, st, n, eps, rcond, ws, diag);
+  hipLaunchKernelGGL(k_certify, dim3(1), dim3(64), 0, st, n, eps, rcond, ws, (const int*)bad,
+                     diag);
   hipLaunchKernelGGL(k_chol_solve<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, eloc,
                      (const double*)ws, y);
   hipLaunchKernelGGL(k_sum_y<S>, dim3(1), dim3(256), 0, st, (const S*)y, n, sy);

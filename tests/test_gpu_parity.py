@@ -182,3 +182,22 @@ def test_uniform_amplitude_gives_closed_form_energy(dev):
     e = el.cpu().numpy()
     assert np.abs(e[:, 0] - (n_nn + 0.5 * n_nnn) / 4).max() < 1e-10
     assert np.abs(e[:, 1]).max() == 0.0
+
+
+def test_nonfinite_theta_is_flagged_without_a_host_check(dev):
+    # the evaluation calls do not synchronise: a non-finite parameter shows
+    # up as the non-finite flag of every sample
+    Lx, Ly, D, chi = 3, 4, 2, 4
+    theta = synth.theta(Lx, Ly, 2, D, seed=9)
+    theta[7] = np.nan
+    cf = synth.sz0_configs(Lx * Ly, 5, seed=3)
+    ctx = _ctx(Lx, Ly, D, chi, "f64", J1J2)
+    th, sm = _to(dev, theta, cf)
+    lp, el, O, fl = ctx.evaluate(th, sm)
+    torch.cuda.synchronize()
+    assert ((fl.cpu().numpy() & 2) != 0).all()
+    theta[7] = 0.5
+    th, _ = _to(dev, theta, cf)
+    lp, el, O, fl = ctx.evaluate(th, sm)
+    torch.cuda.synchronize()
+    assert (fl.cpu().numpy() & 2).max() == 0
