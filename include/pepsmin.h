@@ -56,7 +56,7 @@ typedef enum {
 } peps_status;
 
 /* Asynchrony. peps_amplitude, peps_local_energy, peps_logderiv,
- * and peps_evaluate enqueue their work on the stream and
+ * peps_evaluate and minsr_step_noalloc enqueue their work on the stream and
  * return without waiting for the device: a non-finite theta is then not a
  * return code but bit PEPS_FLAG_NONFINITE in every sample's flags (when
  * flags are requested; the outputs are non-finite too). minsr_step checks
@@ -284,6 +284,24 @@ peps_status peps_evaluate(peps_ctx* ctx, const double* theta, const uint8_t* sam
 peps_status minsr_step(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
                        const double* eloc, double eps, double rcond, double* dtheta,
                        double* diag, void* stream);
+
+/* minsr_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results as minsr_step, with the workspace (column
+ * means [N_p], T [n][n], solve vectors) in a fixed device array of 48 MiB
+ * that the library holds on every GPU it runs on until the process ends.
+ * Calls no allocator and does not synchronise; the inputs, outputs and
+ * errors are those of minsr_step, except that a non-finite local energy is
+ * reported on the device (diag[3] = 2, dtheta NaN) instead of by a return
+ * code. PEPS_ERR_UNSUPPORTED when the workspace,
+ * N_p * e + n * n * e + (2n + 2) * e + 144 bytes with e = 8 (real) or 16
+ * (complex) each rounded up to 256, exceeds 48 MiB (e.g. n = 1024 with
+ * complex parameters needs 16 MiB plus 16 N_p bytes). Every call on one GPU
+ * uses that GPU's one array, which keeps the last call's contents: calls
+ * that overlap on one GPU (other streams, other host threads) race. */
+peps_status minsr_step_noalloc(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
+                               const double* eloc, double eps, double rcond, double* dtheta,
+                               double* diag, void* stream);
 
 /* Local Metropolis sampling of p(S) ~ |Psi(S)|^2 (Sec. "On Direct
  * Sampling" names Markov chains as the alternative to direct sampling).

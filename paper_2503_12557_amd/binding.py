@@ -31,7 +31,8 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "peps_profile", "peps_profile_read", "made_create", "made_destroy",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
            "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
-           "peps_set_truncation", "peps_direct_sample", "peps_set_compression"]
+           "peps_set_truncation", "peps_direct_sample", "peps_set_compression",
+           "minsr_step_noalloc"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -89,6 +90,8 @@ def load():
     lib.peps_evaluate.restype = I
     lib.minsr_step.argtypes = [P, P, P, I, P, D, D, P, P, P]
     lib.minsr_step.restype = I
+    lib.minsr_step_noalloc.argtypes = [P, P, P, I, P, D, D, P, P, P]
+    lib.minsr_step_noalloc.restype = I
     lib.peps_sample.argtypes = [P, P, I, I, I, I, I, U64, U64, P, P, P]
     lib.peps_sample.restype = I
     lib.peps_vmc_step.argtypes = [P, P, I, I, I, I, I, U64, U64, D, D, D, P, P, P, P, P]
@@ -307,6 +310,21 @@ class Context:
         _check(load().minsr_step(self._h, _ptr(O.contiguous()), _ptr(samples.contiguous()), n,
                                  _ptr(eloc.contiguous()), float(eps), float(rcond), _ptr(dtheta),
                                  _ptr(diag), _stream()))
+        return dtheta, diag
+
+    def minsr_step_noalloc(self, O, samples, eloc, eps=1e-4, rcond=1e-12, dtheta=None,
+                           diag=None):
+        """minsr_step with the library's fixed device workspace (no device
+        allocation inside the call); dtheta and diag may be given."""
+        import torch
+        n = samples.shape[0]
+        assert O.dtype == self.o_dtype and O.shape == (n, self.n_compact)
+        if dtheta is None:
+            dtheta = torch.empty(self.n_params, dtype=self.theta_dtype, device=O.device)
+        if diag is None:
+            diag = torch.zeros(8, dtype=torch.float64, device=O.device)
+        _check(load().minsr_step_noalloc(self._h, _ptr(O), _ptr(samples), n, _ptr(eloc), float(eps),
+                                         float(rcond), _ptr(dtheta), _ptr(diag), _stream()))
         return dtheta, diag
 
     def logderiv_vjp(self, O, samples, g):

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,38 @@ struct DevBuf {
     cap = 0;
   }
 };
+
+}  // namespace
+
+// Workspace of the allocation-free minSR entry point: one array per GPU,
+// held until the process ends. Its name is a host-side stand-in; kernels get
+// the device address resolved per device by scratch_ptr().
+#define PEPS_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+__device__ __align__(256) unsigned char scratch[PEPS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scr_mu;
+void* g_scr_ptr[64] = {};
+
+// Device address of `scratch` on the current device, resolved once per
+// device with that device current.
+peps_status scratch_ptr(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(PEPS_ERR_UNSUPPORTED, "device index %d above 63", dev);
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  if (!g_scr_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PEPS_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scr_ptr[dev] = p;
+  }
+  *out = g_scr_ptr[dev];
+  return PEPS_OK;
+}
 
 }  // namespace
 
@@ -269,6 +302,13 @@ peps_status peps_create(const peps_geom* geom, peps_ctx** out) {
   c->s1_gm = strip1_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
   c->s2_gm = strip2_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
   c->smp_gm = sample_lds_bytes(g.dtype, c->L, false) > kLdsDyn;
+  {
+    void* sp = nullptr;
+    if ((st = scratch_ptr(&sp)) != PEPS_OK) {
+      peps_destroy(c);
+      return st;
+    }
+  }
   c->dm_ok = env_dm_lds_bytes(c->L, g.dtype) <= kLdsDyn && g.chi + 1 <= 256 &&
              ((c->L.bmax * g.D + 31) / 32 * 32) <= 256;
   *out = c;
@@ -943,6 +983,35 @@ peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n
   ProfScope ps(c, st, PEPS_PROF_MINSR);
   HIPCHK(launch_minsr(L, c->d_tab, mode, O, samples, n, eloc, eps, rcond, dtheta, diag,
                       c->mean.p, c->Tm.p, c->vec.p, st));
+  return PEPS_OK;
+}
+
+peps_status minsr_step_noalloc(peps_ctx* c, const void* O, const uint8_t* samples, int n,
+                               const double* eloc, double eps, double rcond, double* dtheta,
+                               double* diag, void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (n < 2) return fail(PEPS_ERR_ARG, "minSR needs at least 2 samples (got %d)", n);
+  if (!O || !samples || !eloc || !dtheta || !diag) return fail(PEPS_ERR_ARG, "null pointer");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(PEPS_ERR_ARG, "eps must be finite and >= 0");
+  if (!(rcond >= 0.0 && rcond < 1.0)) return fail(PEPS_ERR_ARG, "rcond must be in [0, 1)");
+  const Lattice& L = c->L;
+  const int mode = c->g.dtype == PEPS_BF16 ? MODE_F32 : c->g.dtype;
+  size_t b_mean, b_T, b_vec;
+  minsr_ws_bytes(L, mode, n, &b_mean, &b_T, &b_vec);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t need = up(b_mean) + up(b_T) + up(b_vec);
+  if (need > PEPS_NOALLOC_SCRATCH_BYTES)
+    return fail(PEPS_ERR_UNSUPPORTED,
+                "minsr_step_noalloc: n = %d with %d parameters needs %zu bytes of workspace, "
+                "above its fixed %zu-byte scratch (use minsr_step)",
+                n, L.n_params, need, PEPS_NOALLOC_SCRATCH_BYTES);
+  void* base = nullptr;
+  peps_status s = scratch_ptr(&base);
+  if (s != PEPS_OK) return s;
+  char* b = (char*)base;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_minsr(L, c->d_tab, mode, O, samples, n, eloc, eps, rcond, dtheta, diag, b,
+                      b + up(b_mean), b + up(b_mean) + up(b_T), st));
   return PEPS_OK;
 }
 
