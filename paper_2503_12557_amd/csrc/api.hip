@@ -142,7 +142,7 @@ struct peps_ctx {
   std::vector<Ev> pending;
   double prof_ms[PEPS_PROF_KINDS] = {};
   long prof_n[PEPS_PROF_KINDS] = {};
-  size_t chunk_budget = (size_t)12 << 30;  // bytes of per-chunk scratch
+  size_t chunk_budget = (size_t)48 << 30;  // bytes of per-chunk scratch
 };
 
 // Bracket one launch with events when profiling is on.
@@ -537,7 +537,7 @@ static size_t per_sample_scratch(const peps_ctx* c, bool env_internal) {
   size_t g = 0;
   if (c->env_gm && !dm) g += 2 * env_slab_elems(L, c->g.dtype);
   if (c->s1_gm) g += (size_t)L.Lx * strip1_slab_elems(L);
-  if (c->s2_gm) g += (size_t)(L.Lx - 1) * strip2_slab_elems(L);
+  if (c->s2_gm) g += (size_t)(L.Lx - 1) * strip2_slab_elems(L, c->g.dtype);
   size_t e = env_internal ? env_tensor_elems_per_sample(L) : 0;
   return (r + s1 + s2 + g + e) * c->tsize + (env_internal ? L.n_slots * sizeof(double) : 0);
 }
@@ -609,7 +609,7 @@ static peps_status run_strips(peps_ctx* c, const uint8_t* sm, int m, const char*
     s = c->epart.ensure((size_t)m * nparts * 2 * sizeof(double));
     if (s != PEPS_OK) return s;
     if (c->s2_gm && H.n_strips) {
-      if ((s = c->gws_s2.ensure((size_t)m * (L.Lx - 1) * strip2_slab_elems(L) * c->tsize)) !=
+      if ((s = c->gws_s2.ensure((size_t)m * (L.Lx - 1) * strip2_slab_elems(L, c->g.dtype) * c->tsize)) !=
           PEPS_OK)
         return s;
       g2 = c->gws_s2.p;

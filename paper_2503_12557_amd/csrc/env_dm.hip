@@ -27,160 +27,9 @@
 #include "common.h"
 #include "env_dev.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace pm {
-
-typedef float mf32x4 __attribute__((ext_vector_type(4)));
-typedef double mf64x4 __attribute__((ext_vector_type(4)));
-
-// One 16x16x4 matrix-core product per real type. Operand layout (both
-// types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]. Output
-// register v of lane l holds D[row(l, v)][l % 16].
-template <typename R> struct Mfma;
-template <> struct Mfma<float> {
-  typedef mf32x4 acc;
-  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-template <> struct Mfma<double> {
-  typedef mf64x4 acc;
-  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
-};
-
-template <typename T>
-__device__ __forceinline__ void split(T x, typename RealOf<T>::type& re,
-                                      typename RealOf<T>::type& im) {
-  if constexpr (IsCplx<T>::value) {
-    re = x.re;
-    im = x.im;
-  } else {
-    re = x;
-    im = 0;
-  }
-}
-template <typename T>
-__device__ __forceinline__ T join(typename RealOf<T>::type re, typename RealOf<T>::type im) {
-  if constexpr (IsCplx<T>::value) return T(re, im);
-  else return re;
-}
-
-// ---------------------------------------------------------------------------
-// C (m x n, row stride ldc) = op(A) op(B) (+ C if acc), with
-// A[i][kk] = A[i*sai + kk*sak], B[kk][j] = B[kk*sbk + j*sbj]; CA / CB take
-// the complex conjugate of that operand. Waves take 32 x 32 output blocks
-// (2 x 2 MFMA tiles). herm: C is Hermitian; only the blocks on and below the
-// diagonal are formed and C[j][i] = conj(C[i][j]) is written for those
-// below it. Operands may be in global memory or LDS; out-of-range rows,
-// columns and k read as zero. The caller synchronises before reading C.
-// ---------------------------------------------------------------------------
-template <typename T, bool CA, bool CB>
-__device__ void mgemm(int m, int n, int k, const T* __restrict__ A, int sai, int sak,
-                      const T* __restrict__ B, int sbk, int sbj, T* __restrict__ C, int ldc,
-                      bool herm, bool acc) {
-  typedef typename RealOf<T>::type R;
-  typedef Mfma<R> F;
-  typedef typename F::acc V;
-  constexpr bool CX = IsCplx<T>::value;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = PEPS_NT >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int nbi = (m + 31) >> 5, nbj = (n + 31) >> 5;
-  const int njobs = herm ? nbi * (nbi + 1) / 2 : nbi * nbj;
-  const R sa = CA ? R(-1) : R(1), sb = CB ? R(-1) : R(1);
-  for (int job = wv; job < njobs; job += nw) {
-    int bi, bj;
-    if (herm) {
-      bi = 0;
-      while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
-      bj = job - bi * (bi + 1) / 2;
-    } else {
-      bi = job / nbj;
-      bj = job - bi * nbj;
-    }
-    const int i0 = bi * 32, j0 = bj * 32;
-    V cr[2][2], ci[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          cr[a][b][v] = 0;
-          ci[a][b][v] = 0;
-        }
-    if (acc) {
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = i0 + 16 * a + F::row(lane, v), j = j0 + 16 * b + li;
-            if (i < m && j < n) {
-              R re, im;
-              split(C[(size_t)i * ldc + j], re, im);
-              cr[a][b][v] = re;
-              ci[a][b][v] = im;
-            }
-          }
-    }
-    const bool ia0 = i0 + li < m, ia1 = i0 + 16 + li < m;
-    const bool jb0 = j0 + li < n, jb1 = j0 + 16 + li < n;
-    const T* pa0 = A + (size_t)(i0 + li) * sai;
-    const T* pa1 = A + (size_t)(i0 + 16 + li) * sai;
-    const T* pb0 = B + (size_t)(j0 + li) * sbj;
-    const T* pb1 = B + (size_t)(j0 + 16 + li) * sbj;
-    for (int k0 = 0; k0 < k; k0 += 16) {
-      R ar[4][2], ai[4][2], br[4][2], bim[4][2];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int kk = k0 + 4 * s + lk;
-        const bool kin = kk < k;
-        T x0 = (kin && ia0) ? pa0[(size_t)kk * sak] : T(0);
-        T x1 = (kin && ia1) ? pa1[(size_t)kk * sak] : T(0);
-        T y0 = (kin && jb0) ? pb0[(size_t)kk * sbk] : T(0);
-        T y1 = (kin && jb1) ? pb1[(size_t)kk * sbk] : T(0);
-        split(x0, ar[s][0], ai[s][0]);
-        split(x1, ar[s][1], ai[s][1]);
-        split(y0, br[s][0], bim[s][0]);
-        split(y1, br[s][1], bim[s][1]);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            cr[a][b] = F::mac(ar[s][a], br[s][b], cr[a][b]);
-            if constexpr (CX) {
-              // (ar + i sa ai)(br + i sb bi)
-              const R ai_ = sa * ai[s][a], bi_ = sb * bim[s][b];
-              cr[a][b] = F::mac(-ai_, bi_, cr[a][b]);
-              ci[a][b] = F::mac(ar[s][a], bi_, ci[a][b]);
-              ci[a][b] = F::mac(ai_, br[s][b], ci[a][b]);
-            }
-          }
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + 16 * a + F::row(lane, v), j = j0 + 16 * b + li;
-          if (i < m && j < n) {
-            const T val = join<T>(cr[a][b][v], ci[a][b][v]);
-            C[(size_t)i * ldc + j] = val;
-            if (herm && bi != bj) C[(size_t)j * ldc + i] = conjx(val);
-          }
-        }
-  }
-}
 
 // Reduction over the workgroup without a trailing barrier: `red` holds two
 // slots of 16 values and consecutive reductions alternate between them, so

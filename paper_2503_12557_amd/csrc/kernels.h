@@ -44,7 +44,7 @@ size_t strip2_lds_bytes(int mode, const Lattice& L, bool gm);
 size_t sample_lds_bytes(int mode, const Lattice& L, bool gm);
 size_t env_slab_elems(const Lattice& L, int mode);
 size_t strip1_slab_elems(const Lattice& L);
-size_t strip2_slab_elems(const Lattice& L);
+size_t strip2_slab_elems(const Lattice& L, int mode);
 size_t sample_slab_elems(const Lattice& L, int mode);
 
 template <int M>

@@ -220,11 +220,16 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
 // Lf | Lt | Lt2 (partials) | X1 = X3 | X2 (chunk intermediates) | Us | Bs
 // (environments) | A1s | A2s (site tensors): every operand of a step is
 // staged on chip, so its contractions read LDS only
-static size_t strip2_big(int bmax, int D) {
+// With the matrix-core steps (global working set, FP32 / FP64 / complex
+// modes) the intermediates hold the whole outer bond: B^2 D^3 each.
+__host__ __device__ inline bool strip2_mm(int mode, bool gm) { return gm && mode != MODE_BF16; }
+__host__ __device__ inline size_t strip2_xsz(int bmax, int D, bool mm) {
+  return mm ? (size_t)bmax * bmax * D * D * D : (size_t)S2G * bmax * D * D * D;
+}
+static size_t strip2_big(int bmax, int D, bool mm = false) {
   const size_t B2D2 = (size_t)bmax * bmax * D * D;
-  const size_t BD3 = (size_t)bmax * D * D * D;
   const size_t box = (size_t)bmax * D * bmax;
-  return 3 * B2D2 + 2 * S2G * BD3 + 2 * box + 2 * (size_t)D * D * D * D;
+  return 3 * B2D2 + 2 * strip2_xsz(bmax, D, mm) + 2 * box + 2 * (size_t)D * D * D * D;
 }
 size_t strip2_lds_elems(int bmax, int D) { return strip2_big(bmax, D) + 16; }
 
@@ -249,9 +254,11 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   T* Lt = Lf + box2;
   T* Lt2 = Lt + box2;
   // X3 of a chunk is formed after X1 is consumed and takes its place
+  constexpr bool MMP = GM && M != MODE_BF16;
+  const size_t xsz = strip2_xsz(B, D, MMP);
   T* X1 = Lt2 + box2;
-  T* X2 = X1 + S2G * bd3;
-  T* Us = X2 + S2G * bd3;
+  T* X2 = X1 + xsz;
+  T* Us = X2 + xsz;
   T* Bs = Us + box;
   T* A1s = Bs + box;
   T* A2s = A1s + D * D * D * D;
@@ -324,8 +331,12 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
     stage(y, pbit(s[n1]), pbit(s[n2]));
-    s2_step_right<M>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
-                     Bs, ba_(y), bb_(y), X1, X2, X1, rnxt);
+    if constexpr (MMP)
+      s2_step_right_mm<T>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2,
+                          Dd2, Bs, ba_(y), bb_(y), X1, X2, rnxt);
+    else
+      s2_step_right<M>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
+                       Bs, ba_(y), bb_(y), X1, X2, X1, rnxt);
     const int cnt = ua_(y) * Dl1 * Dl2 * ba_(y);
     const int e = pow2_exponent((double)block_absmax(rnxt, 1, cnt, cnt, red));
     scale_pow2(rnxt, cnt, e);
@@ -370,8 +381,12 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           const int p1 = in_move(mv, a1) ? 1 - pbit(s[a1]) : pbit(s[a1]);
           const int p2 = in_move(mv, a2) ? 1 - pbit(s[a2]) : pbit(s[a2]);
           stage(yy, p1, p2);
-          s2_step_left<M>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2,
-                          Dd2, Bs, ba_(yy), bb_(yy), X1, X2, X1, nxt);
+          if constexpr (MMP)
+            s2_step_left_mm<T>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
+                               Dr2, Dd2, Bs, ba_(yy), bb_(yy), X1, X2, nxt);
+          else
+            s2_step_left<M>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
+                            Dr2, Dd2, Bs, ba_(yy), bb_(yy), X1, X2, X1, nxt);
           scale_pow2(nxt, ub_(yy) * Dr1 * Dr2 * bb_(yy), dex[yy]);
           __syncthreads();
           cur = nxt;
@@ -395,8 +410,12 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     legs_of(tab, L, n1, Dl1, Dr1, Du1, Dd1);
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
     stage(y, pbit(s[n1]), pbit(s[n2]));
-    s2_step_left<M>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2, Bs,
-                    ba_(y), bb_(y), X1, X2, X1, Lt);
+    if constexpr (MMP)
+      s2_step_left_mm<T>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
+                         Bs, ba_(y), bb_(y), X1, X2, Lt);
+    else
+      s2_step_left<M>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2, Bs,
+                      ba_(y), bb_(y), X1, X2, X1, Lt);
     const int cnt = ub_(y) * Dr1 * Dr2 * bb_(y);
     {
       typedef typename RealOf<T>::type R;
@@ -598,7 +617,9 @@ size_t strip2_lds_bytes(int mode, const Lattice& L, bool gm) {
   return (gm ? 16 : strip2_lds_elems(L.bmax, L.D)) * mode_elem_bytes(mode);
 }
 size_t strip1_slab_elems(const Lattice& L) { return (strip1_big(L.bmax, L.D) + 15) / 16 * 16; }
-size_t strip2_slab_elems(const Lattice& L) { return (strip2_big(L.bmax, L.D) + 15) / 16 * 16; }
+size_t strip2_slab_elems(const Lattice& L, int mode) {
+  return (strip2_big(L.bmax, L.D, strip2_mm(mode, true)) + 15) / 16 * 16;
+}
 
 template <int M>
 hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
@@ -633,7 +654,7 @@ hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
   if (gm)
     hipLaunchKernelGGL((k_strip2<M, true>), dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
                        (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n,
-                       (T*)gws, strip2_slab_elems(L));
+                       (T*)gws, strip2_slab_elems(L, M));
   else
     hipLaunchKernelGGL((k_strip2<M, false>), dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
                        (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n,

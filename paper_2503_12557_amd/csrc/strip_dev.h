@@ -4,6 +4,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace pm {
 
@@ -458,6 +459,71 @@ __device__ __forceinline__ void s2_step_right(const T* Rp, const T* U, int ua, i
             Rout + a0 * (Dl1 * Dl2 * ba), ba, 1, false);
     __syncthreads();
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// Two-row steps on the matrix cores for the large shapes (working sets in a
+// global slab): each step is four products over the whole outer bond, the
+// intermediates X1 and X2 (B^2 D^3 elements each) in the slab, X3 reusing
+// X1. Same contractions and output layouts as s2_step_left / s2_step_right.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void s2_step_left_mm(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
+                                int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2,
+                                int Dd2, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout) {
+  const int inner = Dl1 * Dl2 * ba;
+  // X1[(m1,m2,c),(u,b)] = sum_a L[a,(m1,m2,c)] U[a,(u,b)]
+  mgemm_map<T, false, false>(inner, uk * ub, ua, Lp, IMap(1), IMap(inner), U, IMap(uk * ub),
+                             IMap(1), X1, IMap(uk * ub), IMap(1), false, false);
+  __syncthreads();
+  // X2[(m2,c,b),(r1,t)] = sum_{(m1,u)} X1[(m1,m2,c),(u,b)] A1[m1,r1,u,t]
+  mgemm_map<T, false, false>(Dl2 * ba * ub, Dr1 * Dd1, Dl1 * uk, X1, IMap(ub, uk * ub, 1),
+                             IMap(uk, Dl2 * ba * uk * ub, ub), A1, IMap(uk, Dr1 * uk * Dd1, Dd1),
+                             IMap(Dd1, uk * Dd1, 1), X2, IMap(Dr1 * Dd1), IMap(1), false, false);
+  __syncthreads();
+  // X3[(c,b,r1),(s,d)] = sum_{(m2,t)} X2[(m2,c,b),(r1,t)] A2[m2,s,t,d]  (into X1)
+  T* X3 = X1;
+  mgemm_map<T, false, false>(ba * ub * Dr1, Dr2 * Dd2, Dl2 * Dd1, X2, IMap(Dd1),
+                             IMap(Dd1, ba * ub * Dr1 * Dd1, 1), A2, IMap(Dd1, Dr2 * Dd1 * Dd2, Dd2),
+                             IMap(Dd2, Dd1 * Dd2, 1), X3, IMap(Dr2 * Dd2), IMap(1), false, false);
+  __syncthreads();
+  // L'[(b,r1,s),e] = sum_{(c,d)} X3[(c,b,r1),(s,d)] B[(c,d),e]
+  mgemm_map<T, false, false>(ub * Dr1 * Dr2, bb, ba * Dd2, X3, IMap(Dd2),
+                             IMap(Dd2, ub * Dr1 * Dr2 * Dd2, 1), Bt, IMap(bb), IMap(1), Lout,
+                             IMap(bb), IMap(1), false, false);
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void s2_step_right_mm(const T* Rp, const T* U, int ua, int uk, int ub, const T* A1,
+                                 int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2,
+                                 int Dd2, const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Rout) {
+  const int rw = Dr1 * Dr2 * bb;
+  // Y1[(a,u),(r1,s,e)] = sum_b U[(a,u),b] R[b,(r1,s,e)]
+  mgemm_map<T, false, false>(ua * uk, rw, ub, U, IMap(ub), IMap(1), Rp, IMap(rw), IMap(1), Y1,
+                             IMap(rw), IMap(1), false, false);
+  __syncthreads();
+  // Y2[(a,s,e),(m1,t)] = sum_{(u,r1)} Y1[(a,u),(r1,s,e)] A1[m1,r1,u,t]
+  mgemm_map<T, false, false>(ua * Dr2 * bb, Dl1 * Dd1, uk * Dr1, Y1, IMap(Dr2 * bb, uk * rw, 1),
+                             IMap(Dr1, rw, Dr2 * bb), A1, IMap(Dr1, Dd1, uk * Dd1),
+                             IMap(Dd1, Dr1 * uk * Dd1, 1), Y2, IMap(Dl1 * Dd1), IMap(1), false,
+                             false);
+  __syncthreads();
+  // Y3[(a,e,m1),(m2,d)] = sum_{(s,t)} Y2[(a,s,e),(m1,t)] A2[m2,s,t,d]  (into Y1)
+  T* Y3 = Y1;
+  mgemm_map<T, false, false>(ua * bb * Dl1, Dl2 * Dd2, Dr2 * Dd1, Y2,
+                             IMap(bb * Dl1, Dr2 * bb * Dl1 * Dd1, Dd1),
+                             IMap(Dd1, bb * Dl1 * Dd1, 1), A2, IMap(Dd2),
+                             IMap(Dd2, Dr2 * Dd1 * Dd2, 1), Y3, IMap(Dl2 * Dd2), IMap(1), false,
+                             false);
+  __syncthreads();
+  // R'[(a,m1,m2),c] = sum_{(d,e)} Y3[(a,e,m1),(m2,d)] B[c,(d,e)]
+  mgemm_map<T, false, false>(ua * Dl1 * Dl2, ba, Dd2 * bb, Y3,
+                             IMap(Dl1 * Dl2, bb * Dl1 * Dl2 * Dd2, Dd2),
+                             IMap(bb, 1, Dl1 * Dl2 * Dd2), Bt, IMap(1), IMap(Dd2 * bb), Rout,
+                             IMap(ba), IMap(1), false, false);
+  __syncthreads();
 }
 
 }  // namespace pm
