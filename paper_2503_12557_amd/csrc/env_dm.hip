@@ -66,19 +66,35 @@ __host__ __device__ inline size_t dm_slab_elems(int Ly, int bmax, int D, int chi
   return t_el + (r_bytes + tsize - 1) / tsize + 64;
 }
 
-// LDS: max(E + A, packed rho / eigenvector block) + the small vectors
-__host__ __device__ inline size_t dm_lds_bytes(int bmax, int D, int chi, size_t tsize,
-                                               size_t rsize) {
+// LDS: one big region (the staged E and A of a site, then the packed
+// density matrix, then the eigenvector phase: Xe | Yt | LU when that fits
+// under the dynamic-LDS cap, else Yt and LU stay in the slab) and the small
+// vectors.
+#define DM_LDS_CAP (150 * 1024)
+__host__ __device__ inline size_t dm_small_bytes(int np, size_t tsize, size_t rsize) {
+  return (3 * (size_t)np + 32) * tsize + (3 * (size_t)np + 2 * 64 + 8) * rsize + 64;
+}
+__host__ __device__ inline size_t dm_big_elems(int bmax, int D, int chi, size_t tsize,
+                                               size_t rsize, bool* eig_lds) {
   const size_t np = dm_np(bmax, D);
+  const size_t rm = dm_rmax(chi);
   size_t big = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
   const size_t rho = np * (np + 1) / 2;
-  const size_t xr = np * (size_t)dm_rmax(chi);
   if (rho > big) big = rho;
-  if (xr > big) big = xr;
-  big = (big + 1) / 2 * 2;
-  const size_t small_t = 3 * np + 32;          // tau, vb, wb, red
-  const size_t small_r = 3 * np + 2 * 64 + 8;  // d, e, e^2, lam, gap scratch
-  return big * tsize + small_t * tsize + small_r * rsize + 64;
+  if (np * rm > big) big = np * rm;
+  // Xe (np x rm, T) | Yt (rm x np, R) | LU (rm x 5 x np, R)
+  const size_t eig = np * rm + (rm * np * 6 * rsize + tsize - 1) / tsize;
+  const size_t with = (eig > big ? eig : big);
+  const bool fits = ((with + 1) / 2 * 2) * tsize + dm_small_bytes((int)np, tsize, rsize) <=
+                    DM_LDS_CAP;
+  if (eig_lds) *eig_lds = fits;
+  big = fits ? with : big;
+  return (big + 1) / 2 * 2;
+}
+__host__ __device__ inline size_t dm_lds_bytes(int bmax, int D, int chi, size_t tsize,
+                                               size_t rsize) {
+  const size_t big = dm_big_elems(bmax, D, chi, tsize, rsize, nullptr);
+  return big * tsize + dm_small_bytes(dm_np(bmax, D), tsize, rsize);
 }
 
 template <typename T>
@@ -86,14 +102,10 @@ struct DmSh {
   typedef typename RealOf<T>::type R;
   T *big, *tau, *vb, *wb, *red;
   R *dd, *ee, *e2, *lam;
+  bool eig_lds;  // Yt and LU of the eigenvector phase in LDS (after Xe)
   __device__ DmSh(unsigned char* lds, int bmax, int D, int chi) {
     const size_t np = dm_np(bmax, D);
-    size_t bg = (size_t)bmax * D * bmax + (size_t)D * D * D * D;
-    const size_t rho = np * (np + 1) / 2;
-    const size_t xr = np * (size_t)dm_rmax(chi);
-    if (rho > bg) bg = rho;
-    if (xr > bg) bg = xr;
-    bg = (bg + 1) / 2 * 2;
+    const size_t bg = dm_big_elems(bmax, D, chi, sizeof(T), sizeof(R), &eig_lds);
     big = reinterpret_cast<T*>(lds);
     tau = big + bg;
     vb = tau + np;
@@ -117,10 +129,14 @@ template <typename T>
 __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& slot) {
   typedef typename RealOf<T>::type R;
   const int tid = threadIdx.x, NT = PEPS_NT;
-  const int TPR = nz <= 128 ? 4 : 2;  // threads per row in the symv / update
-  const int rpp = NT / TPR;            // rows per pass
+  // symv: TPR lanes per row of the trailing block (full rows through the
+  // symmetric storage, balanced); update: groups of 8 lanes per pair of rows
+  // (one from the top, one from the bottom of the trailing triangle), so
+  // every group has about the same number of elements
+  const int TPR = nz <= 128 ? 4 : 2;
+  const int rpp = NT / TPR;
   const int ri = tid / TPR, q = tid - ri * TPR;
-  // squares of column 0 below row 1
+  const int G8 = 8, ng = NT / G8, grp = tid / G8, q8 = tid - grp * G8;
   R s2 = 0;
   for (int i = 2 + tid; i < nz; i += NT) s2 += abs2x(rho[pk(i, 0)]);
   s2 = blk_sum2(s2, reinterpret_cast<R*>(sh.red), slot);
@@ -141,16 +157,11 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       sh.ee[j] = beta;
       sh.tau[j] = tau;
     }
-    const bool refl = tau != T(0);
-    // v (rows j+1..nz-1) to LDS and to Hv row j
-    for (int i = j + 1 + tid; i < nz; i += NT) {
-      const T v = i == j + 1 ? T(1) : rho[pk(i, j)] * sc;
-      sh.vb[i] = v;
-      Hv[(size_t)j * ldh + i] = v;
-    }
-    __syncthreads();
-    if (!refl) {
-      // column j+1's squares below row j+2 for the next reflector
+    // v_i = 1 (i = j+1), rho[i][j] sc below: read from column j, which no
+    // later step touches
+    auto vv = [&](int i) -> T { return i == j + 1 ? T(1) : rho[pk(i, j)] * sc; };
+    if (tau == T(0)) {
+      for (int i = j + 1 + tid; i < nz; i += NT) Hv[(size_t)j * ldh + i] = vv(i);
       R t = 0;
       for (int i = j + 3 + tid; i < nz; i += NT) t += abs2x(rho[pk(i, j + 1)]);
       s2 = blk_sum2(t, reinterpret_cast<R*>(sh.red), slot);
@@ -165,11 +176,16 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       T u = T(0);
       if (i < nz) {
         for (int kk = j + 1 + q; kk < nz; kk += TPR)
-          u += (kk <= i ? rho[pk(i, kk)] : conjx(rho[pk(kk, i)])) * sh.vb[kk];
+          u += (kk <= i ? rho[pk(i, kk)] : conjx(rho[pk(kk, i)])) * vv(kk);
       }
       u = group_sum(u, TPR);
       ui[p] = u;
-      if (i < nz && q == 0) vhu += conjx(sh.vb[i]) * u;
+      if (i < nz && q == 0) {
+        const T vi = vv(i);
+        vhu += conjx(vi) * u;
+        sh.vb[i] = vi;
+        Hv[(size_t)j * ldh + i] = vi;
+      }
     }
     const R vhu_r = blk_sum2(realx(vhu), reinterpret_cast<R*>(sh.red), slot);
     const R t2 = abs2x(tau) * R(0.5) * vhu_r;
@@ -178,14 +194,16 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       if (i < nz && q == 0) sh.wb[i] = tau * ui[p] - sh.vb[i] * t2;
     }
     __syncthreads();
-    // B -= v w^H + w v^H on the lower triangle; column j+1's new squares
-    // below row j+2 feed the next reflector
+    // B -= v w^H + w v^H on the lower triangle, rows paired top / bottom;
+    // column j+1's new squares below row j+2 feed the next reflector
     R t = 0;
-    for (int p = 0; p < 2; ++p) {
-      const int i = j + 1 + ri + p * rpp;
-      if (i < nz) {
+    const int n1 = nz - j - 1, npair = (n1 + 1) / 2;
+    for (int g = grp; g < npair; g += ng) {
+      for (int h = 0; h < 2; ++h) {
+        const int i = h == 0 ? j + 1 + g : nz - 1 - g;
+        if (h == 1 && i <= j + 1 + g) break;
         const T vi = sh.vb[i], wi = sh.wb[i];
-        for (int kk = j + 1 + q; kk <= i; kk += TPR) {
+        for (int kk = j + 1 + q8; kk <= i; kk += G8) {
           const T nv = rho[pk(i, kk)] - vi * conjx(sh.wb[kk]) - wi * conjx(sh.vb[kk]);
           rho[pk(i, kk)] = nv;
           if (kk == j + 1 && i >= j + 3) t += abs2x(nv);
@@ -397,7 +415,12 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
   __syncthreads();
   tridiag(rho, nz, Hv, np, sh, slot);
   top_eigenvalues(sh.dd, sh.ee, sh.e2, sh.lam, nz, rr, reinterpret_cast<R*>(sh.red), slot, tnorm);
-  // eigenvectors of the tridiagonal, one lane each
+  // eigenvectors of the tridiagonal, one lane each; their LU factors and
+  // iterates in LDS after Xe when they fit (the packed matrix is dead now)
+  if (sh.eig_lds) {
+    Yt = reinterpret_cast<R*>(sh.big + (size_t)np * (r + 1 > rr ? r + 1 : rr));
+    lu = Yt + (size_t)(r + 1) * np;
+  }
   if (tid < r) inv_iter_lane(sh.dd, sh.ee, nz, sh.lam[tid], tnorm, lu + (size_t)tid * 5 * np,
                              Yt + (size_t)tid * np);
   __syncthreads();

@@ -149,11 +149,13 @@ def test_fp64_equals_library_canonical_path(dev):
 
 
 # Mean-0.5 tensors have one dominant boundary direction (sigma_1 >> sigma_chi);
-# the FP32 density matrix squares that ratio, so its error there is about ten
-# times the canonical FP32 path's (measured at 8x8 D=4 chi=16: E_loc 1.3e-4,
-# Psi 1.9e-5), hence 1e-3 rather than the canonical path's 1e-4.
+# the FP32 density matrix squares that ratio, so its error there is ten or
+# more times the canonical FP32 path's. At 8x8 D=4 chi=16 one of the eight
+# configurations is cancellation-limited: its E_loc error measured 1.3e-4 and
+# 1.2e-3 under two orders of the same FP32 reductions (Psi 2e-5 and 8e-6),
+# hence 3e-3 rather than the canonical path's 1e-4.
 @pytest.mark.parametrize("dtype,mu,bound", [("f32", 0.0, 1e-3), ("c64", 0.0, 1e-3),
-                                            ("f32", 0.5, 1e-3)])
+                                            ("f32", 0.5, 3e-3)])
 def test_reduced_precision_bounded(dev, dtype, mu, bound):
     cplx = dtype == "c64"
     Lx, Ly, D, chi = (6, 6, 3, 6) if mu == 0.0 else (8, 8, 4, 16)
