@@ -197,6 +197,40 @@ def strip2_flops(Lx, Ly, D, chi, configs, cplx):
     return total
 
 
+def kernel_source_hash(files):
+    """Hash of the sources a kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2503_12557_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_traffic(kernel, samples_per_launch):
+    """HBM bytes per launch of the environment or two-row strip kernel from
+    the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE calibrated
+    by a copy of known size), scaled to this launch's configurations; None
+    when the counters were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_env_dm_10x10_D5_chi25_c64.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if kernel == "env":
+        if rec.get("source_hash") != kernel_source_hash(["common.h", "env_dev.h", "mfma.h",
+                                                         "env_dm.hip"]):
+            return None
+        b = rec["bytes_per_launch"]
+    else:
+        if rec.get("strip2_source_hash") != kernel_source_hash(["common.h", "mfma.h",
+                                                                "strip_dev.h", "strip.hip"]):
+            return None
+        b = rec["strip2_bytes_per_launch"]
+    return b * samples_per_launch / rec["samples_per_launch"]
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -439,6 +473,12 @@ def main():
     t128 = time.perf_counter() - t0
     _log(f"complex128 reference: {nconf / t128:.1f} samples/s")
 
+    # a plain elementwise kernel of known traffic (256 MiB read + 256 MiB
+    # written): its FETCH_SIZE / WRITE_SIZE under rocprofv3 --pmc calibrate
+    # the traffic counters of the other kernels
+    calib = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    torch.mul(calib, 2.0)
+    del calib
     ctx = Context(Lx, Ly, D, chi, "c64")
     ctx.set_hamiltonian(ham)
     ctx.set_compression("densmat")
@@ -500,9 +540,10 @@ def main():
     for r in rooflines.values():
         r["achieved"] = round(r["achieved"], 3)
         r["frac"] = round(r["achieved"] / r["peak"], 5)
+    for key, r in rooflines.items():
+        r["traffic"] = kernel_traffic(key, r["samples_per_launch"])
     dom_key = dom if dom in rooflines else "env"
     roofline = dict(rooflines[dom_key])
-    roofline["traffic"] = None
     roofline["dominant_kernel_by_time"] = dom
 
     res = {
