@@ -162,3 +162,39 @@ def test_training_raises_imh_acceptance(dev):
           f"empirical trained {emp:.3f}")
     assert acc_exact[1] > acc_exact[0] + 0.1
     assert abs(emp - acc_exact[1]) < 0.03
+
+
+def _bf16_rne(a):
+    """bfloat16 rounding (round to nearest, ties to even) of FP32 values,
+    returned as FP64: the top 16 bits of the IEEE single after adding
+    0x7fff plus the lowest kept bit."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("N,H,n_up,B", [(16, 32, 8, 64), (64, 256, 32, 256)])
+def test_bf16_weights_match_oracle_on_rounded_weights(dev, N, H, n_up, B):
+    # with bf16 weights the kernels use the weights rounded to bfloat16 and
+    # accumulate in FP32; the oracle in FP64 on the same rounded weights
+    # must agree to FP32 accumulation (the gradient is taken at the rounded
+    # weights and applied to the FP32 master copy)
+    p = OM.init_params(N, H, seed=N + 1, scale=0.3)
+    x = synth.sz0_configs(N, B, seed=3)
+    m = _made(N, H, n_up, bf16=True)
+    pt = torch.tensor(p, dtype=torch.float32, device=dev)
+    xt = torch.from_numpy(x).to(dev)
+    loss, g = m.loss_grad(pt, xt)
+    lq = m.logq(pt, xt)
+    torch.cuda.synchronize()
+    p32 = pt.double().cpu().numpy()
+    W1, b1, W2, b2 = OM.unpack(p32, N, H)
+    pr = np.concatenate([_bf16_rne(W1).ravel(), b1.ravel(), _bf16_rne(W2).ravel(), b2.ravel()])
+    assert pr.shape == p32.shape and np.abs(pr - p32).max() > 0  # the rounding acts
+    ref_loss, ref_g = OM.loss_and_grad(pr, x, N, H, n_up)
+    ref_lq = OM.log_q(pr, x, N, H, n_up)
+    e_loss = abs(loss.item() - ref_loss) / abs(ref_loss)
+    e_g = np.abs(g.double().cpu().numpy() - ref_g).max() / np.abs(ref_g).max()
+    e_lq = np.abs(lq.cpu().numpy() - ref_lq).max() / np.abs(ref_lq).max()
+    print(f"bf16 MADE N={N}: loss {e_loss:.2e} grad {e_g:.2e} ln q {e_lq:.2e}")
+    assert e_loss <= 1e-5 and e_g <= 1e-5 and e_lq <= 1e-5
