@@ -303,20 +303,39 @@ peps_status minsr_step_noalloc(peps_ctx* ctx, const void* O, const uint8_t* samp
                                const double* eloc, double eps, double rcond, double* dtheta,
                                double* diag, void* stream);
 
-/* Local Metropolis sampling of p(S) ~ |Psi(S)|^2 (Sec. "On Direct
- * Sampling" names Markov chains as the alternative to direct sampling).
- * kind PEPS_SAMPLE_EXCHANGE: exchanges of anti-aligned nearest neighbours
- * (S^z conserved, chains start with floor(N/2) up spins); PEPS_SAMPLE_FLIP:
- * single-site flips. A move is accepted iff u < |Psi(S')/Psi(S)|^2 with the
- * ratio taken in the strip holding the move and u from Philox4x32-10 keyed
- * by seed (counter: move id, sweep + offset, chain, tag). Chain c writes
- * samples[c*per_chain + j] = its state after sweep burn_in + (j+1)*thin - 1.
- * accepted: int32 [n_chains] accepted-move counts (or NULL). At most 1024
- * sites (PEPS_ERR_UNSUPPORTED above). */
+/* Sampling of p(S) ~ |Psi(S)|^2 by Markov chains (Sec. "On Direct
+ * Sampling" names them as the alternative to direct sampling).
+ * kind PEPS_SAMPLE_EXCHANGE: local exchanges of anti-aligned nearest
+ * neighbours (S^z conserved, chains start with floor(N/2) up spins);
+ * PEPS_SAMPLE_FLIP: single-site flips. A move is accepted iff
+ * u < |Psi(S')/Psi(S)|^2 with the ratio taken in the strip holding the move
+ * and u from Philox4x32-10 keyed by seed (counter: move id, sweep + offset,
+ * chain, tag). A sweep visits every bond (site) once.
+ * kind PEPS_SAMPLE_IMH: independence Metropolis-Hastings with the learned
+ * proposal q of `proposal` (a made_ctx and its parameters): every step draws
+ * one S' ~ q per chain (made_sample, offset + step), evaluates
+ * ln Psi(S')_i* (peps_amplitude) and accepts iff
+ * ln u < 2 (ln|Psi(S')| - ln|Psi(S)|) + ln q(S) - ln q(S') (imh_step);
+ * chains start from proposal->init [n_chains][N] (device, e.g. local
+ * samples) or, if NULL, from a draw of q; a "sweep" is one step.
+ * Chain c writes samples[c*per_chain + j] = its state after sweep
+ * burn_in + (j+1)*thin - 1; logpsi (device FP64 [n][2] or NULL) receives
+ * (ln|Psi|, arg Psi) of every written sample (the local kinds evaluate it
+ * with peps_amplitude after the chains). accepted: int32 [n_chains]
+ * accepted-move counts (or NULL). proposal: required for IMH, ignored
+ * otherwise. At most 1024 sites for the local kinds (PEPS_ERR_UNSUPPORTED
+ * above). */
+typedef struct made_ctx made_ctx;
+typedef struct {
+  made_ctx* made;          /* the proposal network */
+  const float* params;     /* its FP32 parameters (device) */
+  const uint8_t* init;     /* initial states [n_chains][N] (device) or NULL */
+} peps_proposal;
+enum { PEPS_SAMPLE_IMH = 2 };
 peps_status peps_sample(peps_ctx* ctx, const double* theta, int kind, int n_chains,
-                        int per_chain, int burn_in, int thin, uint64_t seed,
-                        uint64_t offset, uint8_t* samples, int32_t* accepted,
-                        void* stream);
+                        int per_chain, int burn_in, int thin, uint64_t seed, uint64_t offset,
+                        const peps_proposal* proposal, uint8_t* samples, double* logpsi,
+                        int32_t* accepted, void* stream);
 
 /* One step of the optimisation loop (Eq. tdvp iterated, as in the
  * optimisations of Sec. "Results"): n = n_chains * per_chain samples from
@@ -370,7 +389,6 @@ peps_status peps_profile_read(peps_ctx* ctx, double* ms, long* counts, int reset
  * with bf16 != 0 the weights are rounded to bfloat16 where they enter a
  * product (FP32 accumulation). Configurations: uint8 [n][N] device.
  * ---------------------------------------------------------------------- */
-typedef struct made_ctx made_ctx;
 peps_status made_create(int N, int H, int n_up, int bf16, made_ctx** out);
 void made_destroy(made_ctx* m);
 size_t made_num_params(const made_ctx* m);
@@ -383,6 +401,18 @@ peps_status made_loss_grad(made_ctx* m, const float* params, const uint8_t* x, i
 peps_status made_adam_step(made_ctx* m, float* params, const float* grads, float* mom,
                            float* var, int t, double lr, double beta1, double beta2, double eps,
                            void* stream);
+/* `steps` Adam steps of mini-batch training on data (device uint8 [M][N]):
+ * step i takes the batch of `batch` rows at positions i*batch ..
+ * (i+1)*batch - 1 of a sequence of epochs, epoch e visiting row
+ * (a_e r + c_e) mod M at its position r, with (a_e, c_e) drawn from
+ * splitmix64 seeded by `seed` (a_e coprime with M: a permutation); then the
+ * loss and gradient of made_loss_grad and the Adam update of
+ * made_adam_step with step counter t0 + i + 1. losses: device FP64
+ * [steps], the batch loss of every step. Queued on the stream; the
+ * permutation table is copied from host memory the context keeps. */
+peps_status made_train(made_ctx* m, float* params, const uint8_t* data, int M, int steps,
+                       int batch, int t0, double lr, double beta1, double beta2, double eps,
+                       uint64_t seed, float* mom, float* var, double* losses, void* stream);
 /* Draw n configurations from q site by site (uniforms from Philox4x32-10,
  * counter (site, sample, offset, tag)) with their ln q (device FP64 [n]). */
 peps_status made_sample(made_ctx* m, const float* params, int n, uint64_t seed, uint64_t offset,
@@ -390,6 +420,19 @@ peps_status made_sample(made_ctx* m, const float* params, int n, uint64_t seed, 
 /* ln q of given configurations (device FP64 [n]). */
 peps_status made_logq(made_ctx* m, const float* params, const uint8_t* x, int n, double* logq,
                       void* stream);
+/* Integrated autocorrelation time and effective sample size of a scalar
+ * series observed on n_chains chains of length T (device FP64
+ * [n_chains][T], e.g. E_loc along each chain): rho(t) averaged over the
+ * chains, centred on the mean over all observations (chains that start
+ * stationary), tau(W) = 1 + 2 sum_{t=1..W} rho(t) with Sokal's automatic
+ * window (the smallest W >= c tau(W)); ranked != 0 first replaces the
+ * values by the normal scores Phi^-1((r - 3/8) / (S + 1/4)) of their pooled
+ * ranks (average ranks for ties, S = n_chains T), the rank-normalised form
+ * that heavy-tailed local energies need. out: device FP64 [2] = (tau_int,
+ * S / tau_int); work: device FP64 [S + T]. At most 2^24 observations
+ * (PEPS_ERR_UNSUPPORTED); ranked costs O(S^2) comparisons. */
+peps_status peps_tau_int(const double* series, int n_chains, int T, int ranked, double c,
+                         double* work, double* out, void* stream);
 /* One independence Metropolis-Hastings step for n_chains chains: chain c
  * moves to prop[c] iff ln u < 2 (ln|Psi(prop)| - ln|Psi(state)|)
  * + ln q(state) - ln q(prop), u from Philox (counter: chain, step, 0, tag).

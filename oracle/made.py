@@ -155,6 +155,18 @@ def integrated_autocorr(series, c=5.0):
     return max(tau, 1.0)
 
 
+def rank_normalise(series):
+    """Normal scores Phi^-1((r - 3/8) / (S + 1/4)) of the pooled ranks r of
+    a series (average ranks for ties, S values; Blom's offsets), the
+    rank-normalised series of Vehtari et al. (2021), for tau_int of
+    heavy-tailed local energies."""
+    from scipy.special import ndtri
+    from scipy.stats import rankdata
+    x = np.asarray(series, dtype=np.float64)
+    r = rankdata(x.ravel(), method="average").reshape(x.shape)
+    return ndtri((r - 0.375) / (x.size + 0.25))
+
+
 def enumerate_sector(N, n_up):
     """All configurations of N bits with exactly n_up zeros, as uint8 [M, N]."""
     out = []

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "PEPS_OK", 1: "PEPS_ERR_ARG", 2: "PEPS_ERR_UNSUPPORTED", 3: "
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "c128": 3, "c64": 4}
 COMPLEX = ("c128", "c64")
 FLAG_ZERO, FLAG_NONFINITE, FLAG_NOCONV, FLAG_DEGENERATE = 1, 2, 4, 8
-SAMPLE_EXCHANGE, SAMPLE_FLIP = 0, 1
+SAMPLE_EXCHANGE, SAMPLE_FLIP, SAMPLE_IMH = 0, 1, 2
 COMPRESS = {"canonical": 0, "densmat": 1}
 
 # every symbol the header declares
@@ -32,7 +32,7 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
            "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
            "peps_set_truncation", "peps_direct_sample", "peps_set_compression",
-           "minsr_step_noalloc"]
+           "minsr_step_noalloc", "made_train", "peps_tau_int"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -40,6 +40,10 @@ class PepsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+class Proposal(ctypes.Structure):
+    _fields_ = [("made", ctypes.c_void_p), ("params", ctypes.c_void_p), ("init", ctypes.c_void_p)]
 
 
 class Geom(ctypes.Structure):
@@ -92,7 +96,7 @@ def load():
     lib.minsr_step.restype = I
     lib.minsr_step_noalloc.argtypes = [P, P, P, I, P, D, D, P, P, P]
     lib.minsr_step_noalloc.restype = I
-    lib.peps_sample.argtypes = [P, P, I, I, I, I, I, U64, U64, P, P, P]
+    lib.peps_sample.argtypes = [P, P, I, I, I, I, I, U64, U64, P, P, P, P, P]
     lib.peps_sample.restype = I
     lib.peps_vmc_step.argtypes = [P, P, I, I, I, I, I, U64, U64, D, D, D, P, P, P, P, P]
     lib.peps_vmc_step.restype = I
@@ -110,6 +114,10 @@ def load():
     lib.made_loss_grad.restype = I
     lib.made_adam_step.argtypes = [P, P, P, P, P, I, D, D, D, D, P]
     lib.made_adam_step.restype = I
+    lib.made_train.argtypes = [P, P, P, I, I, I, I, D, D, D, D, U64, P, P, P, P]
+    lib.made_train.restype = I
+    lib.peps_tau_int.argtypes = [P, I, I, I, D, P, P, P]
+    lib.peps_tau_int.restype = I
     lib.made_sample.argtypes = [P, P, I, U64, U64, P, P, P]
     lib.made_sample.restype = I
     lib.made_logq.argtypes = [P, P, P, I, P, P]
@@ -351,17 +359,29 @@ class Context:
         return {k: (ms[i], cnt[i]) for i, k in enumerate(PROF_KINDS)}
 
     def sample(self, theta, kind="exchange", n_chains=256, per_chain=4, burn_in=32, thin=1,
-               seed=0, offset=0):
+               seed=0, offset=0, proposal=None, want_logpsi=False):
+        """Markov chains of |Psi|^2: kind "exchange" / "flip" (local moves) or
+        "imh" (independence MH with proposal = (Made, params, init or None)).
+        Returns (samples, accepted) or (samples, accepted, logpsi)."""
         import torch
         theta = self._theta(theta)
         n = n_chains * per_chain
-        samples = torch.empty(n, self.Lx * self.Ly, dtype=torch.uint8, device=theta.device)
-        acc = torch.zeros(n_chains, dtype=torch.int32, device=theta.device)
-        k = SAMPLE_EXCHANGE if kind == "exchange" else SAMPLE_FLIP
+        dev = theta.device
+        samples = torch.empty(n, self.Lx * self.Ly, dtype=torch.uint8, device=dev)
+        acc = torch.zeros(n_chains, dtype=torch.int32, device=dev)
+        lp = torch.empty(n, 2, dtype=torch.float64, device=dev) if want_logpsi else None
+        k = {"exchange": SAMPLE_EXCHANGE, "flip": SAMPLE_FLIP, "imh": SAMPLE_IMH}[kind]
+        pr = None
+        if kind == "imh":
+            made, params, init = proposal
+            pr = Proposal(made._h.value, params.data_ptr(),
+                          init.contiguous().data_ptr() if init is not None else None)
+            self._keep = (params, init)
         _check(load().peps_sample(self._h, _ptr(theta.contiguous()), k, n_chains, per_chain,
-                                  burn_in, thin, seed, offset, _ptr(samples), _ptr(acc),
-                                  _stream()))
-        return samples, acc
+                                  burn_in, thin, seed, offset,
+                                  ctypes.byref(pr) if pr is not None else None, _ptr(samples),
+                                  _ptr(lp), _ptr(acc), _stream()))
+        return (samples, acc, lp) if want_logpsi else (samples, acc)
 
     def vmc_step(self, theta, tau, kind="exchange", n_chains=256, per_chain=4, burn_in=32,
                  thin=1, seed=0, offset=0, eps=1e-4, rcond=1e-12):
@@ -451,25 +471,17 @@ class Made:
         return lq
 
     def train(self, params, data, steps, batch=1024, lr=1e-3, seed=0):
-        """Adam on mean -ln q over shuffled mini-batches of `data` (uint8
-        [M][N] on the device); returns the per-step losses (device tensor)."""
+        """Adam on mean -ln q over permuted mini-batches of `data` (uint8
+        [M][N] on the device), all steps in one library call (made_train);
+        returns the per-step losses (device tensor)."""
         import torch
-        g = torch.Generator(device="cpu").manual_seed(seed)
         m = torch.zeros_like(params)
         v = torch.zeros_like(params)
-        grads = torch.empty_like(params)
         losses = torch.empty(steps, dtype=torch.float64, device=params.device)
-        M = data.shape[0]
-        perm = torch.randperm(M, generator=g).to(params.device)
-        pos = 0
-        for t in range(1, steps + 1):
-            if pos + batch > M:
-                perm = torch.randperm(M, generator=g).to(params.device)
-                pos = 0
-            xb = data.index_select(0, perm[pos:pos + batch]).contiguous()
-            pos += batch
-            self.loss_grad(params, xb, grads, losses[t - 1:t])
-            self.adam(params, grads, m, v, t, lr)
+        data = data.contiguous()
+        _check(load().made_train(self._h, _ptr(params), _ptr(data), data.shape[0], steps, batch, 0,
+                                 lr, 0.9, 0.999, 1e-8, int(seed), _ptr(m), _ptr(v), _ptr(losses),
+                                 _stream()))
         return losses
 
 
@@ -481,29 +493,17 @@ def imh_step(state, state_lp, state_lq, prop, prop_lp, prop_lq, seed, step, acce
 
 
 def run_imh(ctx, theta, made, params, n_chains, n_steps, seed=0, record=None, init=None):
-    """Independence MH chains driven by the learned proposal: every step draws
-    one proposal per chain from q, evaluates ln|Psi| of the proposals with
-    peps_amplitude and accepts with the PEPS as the arbiter. Chains start from
-    `init` (uint8 [n_chains][N] on the device, e.g. local-Metropolis samples)
-    or from a draw of q. Returns the final states, the visited states per
-    step ([n_steps][n_chains][N] if record) and the acceptance counts."""
-    import torch
-    dev = theta.device
-    if init is None:
-        state, st_lq = made.sample(params, n_chains, seed=seed, offset=0)
-    else:
-        state = init.clone().contiguous()
-        st_lq = made.logq(params, state)
-    st_lp, _ = ctx.amplitude(theta, state)
-    acc = torch.zeros(n_chains, dtype=torch.int32, device=dev)
-    hist = [] if record else None
-    for t in range(1, n_steps + 1):
-        prop, pr_lq = made.sample(params, n_chains, seed=seed, offset=t)
-        pr_lp, _ = ctx.amplitude(theta, prop)
-        imh_step(state, st_lp, st_lq, prop, pr_lp, pr_lq, seed, t, acc)
-        if record:
-            hist.append(state.clone())
-    return state, (torch.stack(hist) if record else None), acc
+    """Independence MH chains driven by the learned proposal, in one library
+    call (peps_sample with kind "imh"): every step draws one proposal per
+    chain from q, evaluates its ln|Psi| and accepts with the PEPS as the
+    arbiter. Chains start from `init` (uint8 [n_chains][N] on the device,
+    e.g. local-Metropolis samples) or from a draw of q. Returns the final
+    states, the visited states per step ([n_steps][n_chains][N] if record)
+    and the acceptance counts."""
+    s, acc = ctx.sample(theta, "imh", n_chains=n_chains, per_chain=n_steps, burn_in=0, thin=1,
+                        seed=seed, offset=0, proposal=(made, params, init))
+    hist = s.view(n_chains, n_steps, -1).permute(1, 0, 2)
+    return hist[-1].contiguous(), (hist.contiguous() if record else None), acc
 
 
 def _autograd_function():

@@ -134,6 +134,8 @@ struct peps_ctx {
   int compress = 0;
   bool dm_ok = false;
   DevBuf gws_dm;
+  // independence MH chains: states, proposals, their ln Psi and ln q
+  DevBuf imh_st, imh_pr, imh_stlp, imh_stlq, imh_prlp, imh_prlq;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
   int jac_sweeps = 40;
   // optional per-kernel timing with HIP events on the launch stream
@@ -143,6 +145,15 @@ struct peps_ctx {
   double prof_ms[PEPS_PROF_KINDS] = {};
   long prof_n[PEPS_PROF_KINDS] = {};
   size_t chunk_budget = (size_t)48 << 30;  // bytes of per-chunk scratch
+};
+
+struct made_ctx {
+  int N, H, n_up, bf16;
+  DevBuf a, lg, dlg, da, logq;
+  // training: the gathered batch, the gradient and the per-epoch
+  // permutations (a, c)
+  DevBuf xb, gr, ptab;
+  std::vector<unsigned long long> hptab;
 };
 
 // Bracket one launch with events when profiling is on.
@@ -326,7 +337,9 @@ void peps_destroy(peps_ctx* c) {
                     &c->gws_smp, &c->vmc_O,      &c->vmc_dth,    &c->vmc_lp,
                     &c->str_idx, &c->str_batch,  &c->str_coef,   &c->str_lp, &c->str_fl,
                     &c->dir_th2, &c->dir_zero,   &c->dir_env2,   &c->dir_lp2, &c->dir_slab,
-                    &c->dir_lp,  &c->dir_fl,    &c->gws_dm};
+                    &c->dir_lp,  &c->dir_fl,    &c->gws_dm,
+                    &c->imh_st,  &c->imh_pr,    &c->imh_stlp,   &c->imh_stlq, &c->imh_prlp,
+                    &c->imh_prlq};
   if (c->dbl) peps_destroy(c->dbl);
   for (DevBuf* b : bufs) b->release();
   delete c;
@@ -1061,20 +1074,77 @@ peps_status peps_profile_read(peps_ctx* c, double* ms, long* counts, int reset) 
   return PEPS_OK;
 }
 
+static peps_status sample_imh(peps_ctx* c, const double* theta, int n_chains, int per_chain,
+                              int burn_in, int thin, uint64_t seed, uint64_t offset,
+                              const peps_proposal* pr, uint8_t* samples, double* logpsi,
+                              int32_t* accepted, hipStream_t st) {
+  const Lattice& L = c->L;
+  if (!pr || !pr->made || !pr->params) return fail(PEPS_ERR_ARG, "IMH needs a proposal");
+  if (pr->made->N != L.N)
+    return fail(PEPS_ERR_ARG, "proposal over %d sites, lattice has %d", pr->made->N, L.N);
+  const size_t nc = (size_t)n_chains;
+  peps_status s;
+  if ((s = c->imh_st.ensure(nc * L.N)) != PEPS_OK) return s;
+  if ((s = c->imh_pr.ensure(nc * L.N)) != PEPS_OK) return s;
+  if ((s = c->imh_stlp.ensure(nc * 2 * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->imh_prlp.ensure(nc * 2 * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->imh_stlq.ensure(nc * sizeof(double))) != PEPS_OK) return s;
+  if ((s = c->imh_prlq.ensure(nc * sizeof(double))) != PEPS_OK) return s;
+  uint8_t* state = (uint8_t*)c->imh_st.p;
+  uint8_t* prop = (uint8_t*)c->imh_pr.p;
+  double* st_lp = (double*)c->imh_stlp.p;
+  double* st_lq = (double*)c->imh_stlq.p;
+  double* pr_lp = (double*)c->imh_prlp.p;
+  double* pr_lq = (double*)c->imh_prlq.p;
+  if (pr->init) {
+    HIPCHK(hipMemcpyAsync(state, pr->init, nc * L.N, hipMemcpyDeviceToDevice, st));
+    if ((s = made_logq(pr->made, pr->params, state, n_chains, st_lq, st)) != PEPS_OK) return s;
+  } else {
+    if ((s = made_sample(pr->made, pr->params, n_chains, seed, offset, state, st_lq, st)) !=
+        PEPS_OK)
+      return s;
+  }
+  if ((s = peps_amplitude(c, theta, state, n_chains, nullptr, st_lp, nullptr, st)) != PEPS_OK)
+    return s;
+  const long long total = (long long)burn_in + (long long)per_chain * thin;
+  int j = 0;
+  for (long long t = 1; t <= total; ++t) {
+    if ((s = made_sample(pr->made, pr->params, n_chains, seed, offset + (uint64_t)t, prop, pr_lq,
+                         st)) != PEPS_OK)
+      return s;
+    if ((s = peps_amplitude(c, theta, prop, n_chains, nullptr, pr_lp, nullptr, st)) != PEPS_OK)
+      return s;
+    if ((s = imh_step(n_chains, L.N, state, st_lp, st_lq, prop, pr_lp, pr_lq, seed,
+                      offset + (uint64_t)t, accepted, st)) != PEPS_OK)
+      return s;
+    if (t > burn_in && (t - burn_in) % thin == 0 && j < per_chain) {
+      HIPCHK(launch_imh_record(n_chains, L.N, state, st_lp, per_chain, j, samples, logpsi, st));
+      ++j;
+    }
+  }
+  return PEPS_OK;
+}
+
 peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains, int per_chain,
-                        int burn_in, int thin, uint64_t seed, uint64_t offset, uint8_t* samples,
+                        int burn_in, int thin, uint64_t seed, uint64_t offset,
+                        const peps_proposal* proposal, uint8_t* samples, double* logpsi,
                         int32_t* accepted, void* stream) {
   if (!c) return fail(PEPS_ERR_ARG, "null context");
   if (!theta || !samples) return fail(PEPS_ERR_ARG, "null theta or samples");
-  if (kind != PEPS_SAMPLE_EXCHANGE && kind != PEPS_SAMPLE_FLIP)
+  if (kind != PEPS_SAMPLE_EXCHANGE && kind != PEPS_SAMPLE_FLIP && kind != PEPS_SAMPLE_IMH)
     return fail(PEPS_ERR_ARG, "unknown sampler kind %d", kind);
   if (n_chains < 1 || per_chain < 1 || burn_in < 0 || thin < 1)
     return fail(PEPS_ERR_ARG, "need n_chains >= 1, per_chain >= 1, burn_in >= 0, thin >= 1");
   if ((long long)burn_in + (long long)per_chain * thin > (1LL << 30))
     return fail(PEPS_ERR_ARG, "too many sweeps");
+  hipStream_t st = (hipStream_t)stream;
+  if (kind == PEPS_SAMPLE_IMH) {
+    if (accepted) HIPCHK(hipMemsetAsync(accepted, 0, (size_t)n_chains * sizeof(int32_t), st));
+    return sample_imh(c, theta, n_chains, per_chain, burn_in, thin, seed, offset, proposal,
+                      samples, logpsi, accepted, st);
+  }
   const Lattice& L = c->L;
   if (L.N > 1024) return fail(PEPS_ERR_UNSUPPORTED, "sampler holds at most 1024 sites");
-  hipStream_t st = (hipStream_t)stream;
   peps_status s = prepare_theta(c, theta, st);
   if (s != PEPS_OK) return s;
   const size_t BD = (size_t)L.bmax * L.D;
@@ -1091,20 +1161,24 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
     if ((s = c->gws_smp.ensure(nc * sample_slab_elems(L, c->g.dtype) * c->tsize)) != PEPS_OK) return s;
     gws = c->gws_smp.p;
   }
-  ProfScope ps(c, st, PEPS_PROF_SAMPLE);
+  {
+    ProfScope ps(c, st, PEPS_PROF_SAMPLE);
 #define MET(MODE)                                                                               \
   HIPCHK(launch_metropolis<MODE>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain, burn_in, \
                                  thin, seed, offset, samples, accepted, c->env_int.p,           \
                                  (double*)c->eloc_tmp.p, c->rscr.p, c->rt1.p, c->rt2.p,         \
                                  c->jac_sweeps, gws, st))
-  switch (c->g.dtype) {
-    case PEPS_F64: MET(MODE_F64); break;
-    case PEPS_F32: MET(MODE_F32); break;
-    case PEPS_BF16: MET(MODE_BF16); break;
-    case PEPS_C128: MET(MODE_C128); break;
-    default: MET(MODE_C64);
-  }
+    switch (c->g.dtype) {
+      case PEPS_F64: MET(MODE_F64); break;
+      case PEPS_F32: MET(MODE_F32); break;
+      case PEPS_BF16: MET(MODE_BF16); break;
+      case PEPS_C128: MET(MODE_C128); break;
+      default: MET(MODE_C64);
+    }
 #undef MET
+  }
+  if (logpsi)
+    return peps_amplitude(c, theta, samples, n_chains * per_chain, nullptr, logpsi, nullptr, st);
   return PEPS_OK;
 }
 
@@ -1127,8 +1201,8 @@ peps_status peps_vmc_step(peps_ctx* c, double* theta, int kind, int n_chains, in
   if (s != PEPS_OK) return s;
   if ((s = c->vmc_dth.ensure(nth * sizeof(double))) != PEPS_OK) return s;
   if ((s = c->vmc_lp.ensure((size_t)n * 2 * sizeof(double))) != PEPS_OK) return s;
-  s = peps_sample(c, theta, kind, n_chains, per_chain, burn_in, thin, seed, offset, samples,
-                  nullptr, stream);
+  s = peps_sample(c, theta, kind, n_chains, per_chain, burn_in, thin, seed, offset, nullptr,
+                  samples, nullptr, nullptr, stream);
   if (s != PEPS_OK) return s;
   s = peps_evaluate(c, theta, samples, n, (double*)c->vmc_lp.p, eloc, c->vmc_O.p, flags, stream);
   if (s != PEPS_OK) return s;
@@ -1147,10 +1221,6 @@ peps_status peps_vmc_step(peps_ctx* c, double* theta, int kind, int n_chains, in
 // ---------------------------------------------------------------------------
 // learned proposal
 // ---------------------------------------------------------------------------
-struct made_ctx {
-  int N, H, n_up, bf16;
-  DevBuf a, lg, dlg, da, logq;
-};
 
 peps_status made_create(int N, int H, int n_up, int bf16, made_ctx** out) {
   if (!out) return fail(PEPS_ERR_ARG, "null output pointer");
@@ -1174,6 +1244,9 @@ void made_destroy(made_ctx* m) {
   m->dlg.release();
   m->da.release();
   m->logq.release();
+  m->xb.release();
+  m->gr.release();
+  m->ptab.release();
   delete m;
 }
 
@@ -1219,6 +1292,80 @@ peps_status made_adam_step(made_ctx* m, float* params, const float* grads, float
     return fail(PEPS_ERR_ARG, "bad Adam hyper-parameters");
   HIPCHK(launch_made_adam((int)made_num_params(m), params, grads, mom, var, t, (float)lr,
                           (float)beta1, (float)beta2, (float)eps, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
+static unsigned long long splitmix64(unsigned long long& x) {
+  unsigned long long z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+peps_status made_train(made_ctx* m, float* params, const uint8_t* data, int M, int steps,
+                       int batch, int t0, double lr, double beta1, double beta2, double eps,
+                       uint64_t seed, float* mom, float* var, double* losses, void* stream) {
+  if (!m || !params || !data || !mom || !var || !losses) return fail(PEPS_ERR_ARG, "null pointer");
+  if (M < 1 || steps < 0 || batch < 1 || t0 < 0)
+    return fail(PEPS_ERR_ARG, "need M >= 1, steps >= 0, batch >= 1, t0 >= 0");
+  if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(PEPS_ERR_ARG, "bad Adam hyper-parameters");
+  if (steps == 0) return PEPS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  peps_status s = made_ws(m, batch, true);
+  if (s != PEPS_OK) return s;
+  if ((s = m->xb.ensure((size_t)batch * m->N)) != PEPS_OK) return s;
+  // one permutation r -> (a r + c) mod M per epoch, a coprime with M
+  const long long total = (long long)steps * batch;
+  const long long epochs = total / M + 2;
+  m->hptab.assign(2 * (size_t)epochs, 0ull);
+  unsigned long long sm = seed;
+  for (long long e = 0; e < epochs; ++e) {
+    unsigned long long a = M > 1 ? splitmix64(sm) % (unsigned long long)M : 1ull;
+    if (a == 0) a = 1;
+    auto gcd = [](unsigned long long x, unsigned long long y) {
+      while (y) {
+        const unsigned long long t = x % y;
+        x = y;
+        y = t;
+      }
+      return x;
+    };
+    while (gcd(a, (unsigned long long)M) != 1ull) a = a + 1 < (unsigned long long)M ? a + 1 : 1;
+    m->hptab[2 * e] = a;
+    m->hptab[2 * e + 1] = splitmix64(sm) % (unsigned long long)M;
+  }
+  if ((s = m->ptab.ensure(m->hptab.size() * sizeof(unsigned long long))) != PEPS_OK) return s;
+  HIPCHK(hipMemcpyAsync(m->ptab.p, m->hptab.data(), m->hptab.size() * sizeof(unsigned long long),
+                        hipMemcpyHostToDevice, st));
+  const int np = (int)made_num_params(m);
+  if ((s = m->gr.ensure((size_t)np * sizeof(float))) != PEPS_OK) return s;
+  float* grads = (float*)m->gr.p;
+  uint8_t* xb = (uint8_t*)m->xb.p;
+  for (int i = 0; i < steps; ++i) {
+    HIPCHK(launch_made_gather(data, M, m->N, batch, (long long)i * batch,
+                              (const unsigned long long*)m->ptab.p, xb, st));
+    HIPCHK(launch_made_forward(m->N, m->H, m->n_up, m->bf16, params, xb, batch, (float*)m->a.p,
+                               (float*)m->lg.p, st));
+    HIPCHK(launch_made_head(m->N, m->H, m->n_up, xb, batch, (const float*)m->lg.p,
+                            (float*)m->dlg.p, (double*)m->logq.p, st));
+    HIPCHK(launch_made_backward(m->N, m->H, m->n_up, m->bf16, params, xb, batch,
+                                (const float*)m->a.p, (const float*)m->dlg.p, (float*)m->da.p,
+                                grads, (const double*)m->logq.p, losses + i, st));
+    HIPCHK(launch_made_adam(np, params, grads, mom, var, t0 + i + 1, (float)lr, (float)beta1,
+                            (float)beta2, (float)eps, st));
+  }
+  return PEPS_OK;
+}
+
+peps_status peps_tau_int(const double* series, int n_chains, int T, int ranked, double c,
+                         double* work, double* out, void* stream) {
+  if (!series || !work || !out) return fail(PEPS_ERR_ARG, "null pointer");
+  if (n_chains < 1 || T < 1) return fail(PEPS_ERR_ARG, "need n_chains >= 1 and T >= 1");
+  if (!(c > 0.0)) return fail(PEPS_ERR_ARG, "window constant must be positive");
+  if ((long long)n_chains * T > (1LL << 24))
+    return fail(PEPS_ERR_UNSUPPORTED, "at most 2^24 observations");
+  HIPCHK(launch_tau_int(series, n_chains, T, ranked, c, work, out, (hipStream_t)stream));
   return PEPS_OK;
 }
 

@@ -130,6 +130,12 @@ hipError_t launch_made_backward(int N, int H, int n_up, int bf16, const float* P
                                 const uint8_t* x, int B, const float* a, const float* dlg,
                                 float* da, float* G, const double* logq, double* loss,
                                 hipStream_t st);
+hipError_t launch_made_gather(const uint8_t* data, int M, int N, int B, long long base,
+                              const unsigned long long* tab, uint8_t* out, hipStream_t st);
+hipError_t launch_imh_record(int n_chains, int N, const uint8_t* state, const double* st_lp,
+                             int per_chain, int j, uint8_t* out, double* out_lp, hipStream_t st);
+hipError_t launch_tau_int(const double* series, int nc, int T, int ranked, double c,
+                          double* work, double* out, hipStream_t st);
 hipError_t launch_made_adam(int n, float* P, const float* G, float* m, float* v, int t, float lr,
                             float b1, float b2, float eps, hipStream_t st);
 hipError_t launch_made_sample(int N, int H, int n_up, int bf16, const float* P, int n,

@@ -12,6 +12,7 @@
 // forced sites add nothing to log q or to the loss.
 #include "common.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace pm {
 
@@ -22,19 +23,26 @@ __device__ __forceinline__ bool mask_in(int k, int n, int N) { return (k % (N - 
 __device__ __forceinline__ bool mask_out(int n, int k, int N) { return n + 1 > (k % (N - 1)) + 1; }
 __device__ __forceinline__ float wround(float w, int bf16) { return bf16 ? bf16_round(w) : w; }
 
-// Tiled FP32 GEMM C[i][j] = sum_k A(i,k) B(k,j): 64 x 64 tiles, 16-deep
-// k chunks in LDS, 4 x 4 outputs per thread; A, B and the epilogue are
+// Tiled GEMM C[i][j] = sum_k A(i,k) B(k,j) on the FP32 matrix cores: 64 x 64
+// tiles, 16-deep k chunks staged in LDS, each of the four waves a 32 x 32
+// sub-tile of 2 x 2 MFMA 16x16x4 tiles (FP32 products, FP32 accumulation;
+// bf16-rounded weights are exact FP32 values). A, B and the epilogue are
 // functors so the masks, the ReLU and the biases are applied on the fly.
 template <class LA, class LB, class EP>
 __global__ void __launch_bounds__(256) k_gemm(int M, int Nn, int K, LA la, LB lb, EP ep) {
   __shared__ float As[16][68], Bs[16][68];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-  float acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = (wv >> 1) * 32, wj = (wv & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef Mfma<float> F;
+  F::acc acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.f;
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int e = tid; e < 16 * 64; e += 256) {
       const int kk = e >> 6, r = e & 63;
@@ -44,27 +52,26 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int Nn, int K, LA la, LB lb
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[kk][tr * 4 + i];
-        b[i] = Bs[kk][tc * 4 + i];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    for (int s = 0; s < 4; ++s) {
+      const int kk = 4 * s + lk;
+      const float a0 = As[kk][wi + li], a1 = As[kk][wi + 16 + li];
+      const float b0 = Bs[kk][wj + li], b1 = Bs[kk][wj + 16 + li];
+      acc[0][0] = F::mac(a0, b0, acc[0][0]);
+      acc[0][1] = F::mac(a0, b1, acc[0][1]);
+      acc[1][0] = F::mac(a1, b0, acc[1][0]);
+      acc[1][1] = F::mac(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = i0 + tr * 4 + i, c = j0 + tc * 4 + j;
-      if (r < M && c < Nn) ep(r, c, acc[i][j]);
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = i0 + wi + 16 * a + F::row(lane, v), c = j0 + wj + 16 * b + li;
+        if (r < M && c < Nn) ep(r, c, acc[a][b][v]);
+      }
 }
 
 struct MadeP {
@@ -299,6 +306,150 @@ __global__ void k_imh(int n_chains, int N, uint8_t* __restrict__ state,
     st_lq[c] = pr_lq[c];
     if (accepted) accepted[c] += 1;
   }
+}
+
+// Mini-batch gather: row b of the batch is data row (a_e r + c_e) mod M for
+// position g = base + b of the epoch sequence, e = g / M, r = g mod M; a_e is
+// coprime with M, so each epoch visits every row once in a permuted order.
+__global__ void k_gather_batch(const uint8_t* __restrict__ data, int M, int N, int B, long long base,
+                               const unsigned long long* __restrict__ tab,
+                               uint8_t* __restrict__ out) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const long long g = base + b;
+  const long long e = g / M, r = g - e * M;
+  const unsigned long long a = tab[2 * e], c = tab[2 * e + 1];
+  const long long row = (long long)((a * (unsigned long long)r + c) % (unsigned long long)M);
+  for (int n = threadIdx.x; n < N; n += blockDim.x)
+    out[(size_t)b * N + n] = data[(size_t)row * N + n];
+}
+
+hipError_t launch_made_gather(const uint8_t* data, int M, int N, int B, long long base,
+                              const unsigned long long* tab, uint8_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_batch, dim3(B), dim3(64), 0, st, data, M, N, B, base, tab, out);
+  return hipGetLastError();
+}
+
+// Chain c's state (and ln Psi) into row c * per_chain + j of the output.
+__global__ void k_imh_record(int n_chains, int N, const uint8_t* __restrict__ state,
+                             const double* __restrict__ st_lp, int per_chain, int j,
+                             uint8_t* __restrict__ out, double* __restrict__ out_lp) {
+  const int c = blockIdx.x;
+  if (c >= n_chains) return;
+  const size_t row = (size_t)c * per_chain + j;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) out[row * N + i] = state[(size_t)c * N + i];
+  if (out_lp && threadIdx.x == 0) {
+    out_lp[2 * row] = st_lp[2 * c];
+    out_lp[2 * row + 1] = st_lp[2 * c + 1];
+  }
+}
+
+hipError_t launch_imh_record(int n_chains, int N, const uint8_t* state, const double* st_lp,
+                             int per_chain, int j, uint8_t* out, double* out_lp, hipStream_t st) {
+  hipLaunchKernelGGL(k_imh_record, dim3(n_chains), dim3(64), 0, st, n_chains, N, state, st_lp,
+                     per_chain, j, out, out_lp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Integrated autocorrelation time of a scalar series on n_chains chains of
+// length T (Sokal's automatic window, c), the autocorrelation averaged over
+// chains and centred on the mean over all chains (the chains start
+// stationary). ranked: the series is first replaced by the normal scores
+// Phi^-1((r - 3/8) / (S + 1/4)) of its pooled ranks r (average rank for
+// ties; Blom's offsets), as in the rank-normalised effective sample size of
+// Vehtari et al. (2021). One workgroup; work: S + T doubles.
+// ---------------------------------------------------------------------------
+// Phi^-1(p) for 0 < p < 1: Acklam's rational approximation (relative error
+// below 1.2e-9) refined by one Halley step on Phi(x) = erfc(-x / sqrt 2) / 2.
+__device__ double inv_normal_cdf(double p) {
+  const double a[6] = {-3.969683028665376e+01, 2.209460984245205e+02, -2.759285104469687e+02,
+                       1.383577518672690e+02, -3.066479806614716e+01, 2.506628277459239e+00};
+  const double b[5] = {-5.447609879822406e+01, 1.615858368580409e+02, -1.556989798598866e+02,
+                       6.680131188771972e+01, -1.328068155288572e+01};
+  const double c[6] = {-7.784894002430293e-03, -3.223964580411365e-01, -2.400758277161838e+00,
+                       -2.549732539343734e+00, 4.374664141464968e+00, 2.938163982698783e+00};
+  const double d[4] = {7.784695709041462e-03, 3.224671290700398e-01, 2.445134137142996e+00,
+                       3.754408661907416e+00};
+  const double plow = 0.02425;
+  double x;
+  if (p < plow) {
+    const double q = sqrt(-2.0 * log(p));
+    x = (((((c[0] * q + c[1]) * q + c[2]) * q + c[3]) * q + c[4]) * q + c[5]) /
+        ((((d[0] * q + d[1]) * q + d[2]) * q + d[3]) * q + 1.0);
+  } else if (p <= 1.0 - plow) {
+    const double q = p - 0.5, r = q * q;
+    x = (((((a[0] * r + a[1]) * r + a[2]) * r + a[3]) * r + a[4]) * r + a[5]) * q /
+        (((((b[0] * r + b[1]) * r + b[2]) * r + b[3]) * r + b[4]) * r + 1.0);
+  } else {
+    const double q = sqrt(-2.0 * log(1.0 - p));
+    x = -(((((c[0] * q + c[1]) * q + c[2]) * q + c[3]) * q + c[4]) * q + c[5]) /
+        ((((d[0] * q + d[1]) * q + d[2]) * q + d[3]) * q + 1.0);
+  }
+  const double e = 0.5 * erfc(-x * 0.70710678118654752440) - p;
+  const double u = e * 2.50662827463100050242 * exp(0.5 * x * x);
+  return x - u / (1.0 + 0.5 * x * u);
+}
+
+__global__ void __launch_bounds__(1024) k_tau_int(const double* __restrict__ series, int nc, int T,
+                                                  int ranked, double cwin,
+                                                  double* __restrict__ work,
+                                                  double* __restrict__ out) {
+  __shared__ double red[16];
+  __shared__ double sv[2];
+  const int S = nc * T, tid = threadIdx.x, NT = blockDim.x;
+  const double* x = series;
+  double* z = work;
+  double* ac = work + S;
+  if (ranked) {
+    for (int i = tid; i < S; i += NT) {
+      const double xi = series[i];
+      long long less = 0, eq = 0;
+      for (int j = 0; j < S; ++j) {
+        const double xj = series[j];
+        less += xj < xi;
+        eq += xj == xi;
+      }
+      const double r = (double)less + 0.5 * (double)(eq + 1);
+      z[i] = inv_normal_cdf((r - 0.375) / ((double)S + 0.25));
+    }
+    __syncthreads();
+    x = z;
+  }
+  double sm = 0;
+  for (int i = tid; i < S; i += NT) sm += x[i];
+  sm = block_sum(sm, red);
+  const double mu = sm / S;
+  for (int t = tid; t < T; t += NT) {
+    double a = 0;
+    for (int cc = 0; cc < nc; ++cc) {
+      const double* row = x + (size_t)cc * T;
+      for (int i = 0; i + t < T; ++i) a += (row[i] - mu) * (row[i + t] - mu);
+    }
+    ac[t] = a / ((double)nc * (double)(T - t));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tau = 1.0;
+    if (ac[0] > 0.0 && T >= 2) {
+      double s = 0.0;
+      for (int W = 1; W < T; ++W) {
+        s += ac[W] / ac[0];
+        tau = 1.0 + 2.0 * s;
+        if (W >= cwin * tau) break;
+      }
+    }
+    if (tau < 1.0) tau = 1.0;
+    sv[0] = tau;
+    out[0] = tau;
+    out[1] = (double)S / tau;
+  }
+}
+
+hipError_t launch_tau_int(const double* series, int nc, int T, int ranked, double c,
+                          double* work, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_tau_int, dim3(1), dim3(1024), 0, st, series, nc, T, ranked, c, work, out);
+  return hipGetLastError();
 }
 
 static MadeP made_params(int N, int H, int n_up, int bf16, const float* P) {

@@ -198,3 +198,131 @@ def test_bf16_weights_match_oracle_on_rounded_weights(dev, N, H, n_up, B):
     e_lq = np.abs(lq.cpu().numpy() - ref_lq).max() / np.abs(ref_lq).max()
     print(f"bf16 MADE N={N}: loss {e_loss:.2e} grad {e_g:.2e} ln q {e_lq:.2e}")
     assert e_loss <= 1e-5 and e_g <= 1e-5 and e_lq <= 1e-5
+
+
+def _splitmix64_stream(seed):
+    """splitmix64 (Steele, Lea and Flood; Vigna's constants) from its
+    definition: state += golden gamma, then two xor-shift-multiply rounds."""
+    M64 = (1 << 64) - 1
+    x = seed & M64
+    while True:
+        x = (x + 0x9E3779B97F4A7C15) & M64
+        z = x
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        yield z ^ (z >> 31)
+
+
+def _epoch_rows(M, steps, batch, seed):
+    """Rows of every batch under the documented made_train order: epoch e
+    visits row (a_e r + c_e) mod M at its position r, a_e coprime with M."""
+    from math import gcd
+    g = _splitmix64_stream(seed)
+    epochs = steps * batch // M + 2
+    tab = []
+    for _ in range(epochs):
+        a = next(g) % M if M > 1 else 1
+        a = a or 1
+        while gcd(a, M) != 1:
+            a = a + 1 if a + 1 < M else 1
+        tab.append((a, next(g) % M))
+    rows = []
+    for i in range(steps):
+        pos = np.arange(i * batch, (i + 1) * batch)
+        e, r = pos // M, pos % M
+        rows.append(np.array([(tab[ee][0] * rr + tab[ee][1]) % M for ee, rr in zip(e, r)]))
+    return rows
+
+
+def test_made_train_equals_oracle_loop(dev):
+    # the library's training loop (one call, five Adam steps over permuted
+    # batches that cross an epoch boundary) against the oracle's loss,
+    # gradient and Adam on the same batches
+    N, H, n_up, M, B, steps, seed = 16, 32, 8, 200, 64, 5, 12345
+    data = synth.sz0_configs(N, M, seed=9)
+    p0 = OM.init_params(N, H, seed=4, scale=0.3)
+    m = _made(N, H, n_up)
+    pt = torch.tensor(p0, dtype=torch.float32, device=dev)
+    losses = m.train(pt, torch.from_numpy(data).to(dev), steps=steps, batch=B, lr=1e-2, seed=seed)
+    torch.cuda.synchronize()
+    f = lambda z: float(np.float32(z))
+    p = torch.tensor(p0, dtype=torch.float32).double().numpy()
+    mo = np.zeros_like(p)
+    v = np.zeros_like(p)
+    ref_l = []
+    for i, rows in enumerate(_epoch_rows(M, steps, B, seed)):
+        assert len(set(rows.tolist())) == B or i * B // M != ((i + 1) * B - 1) // M
+        loss, g = OM.loss_and_grad(p, data[rows], N, H, n_up)
+        ref_l.append(loss)
+        p, mo, v = OM.adam(p, g, mo, v, i + 1, lr=f(1e-2), b1=f(0.9), b2=f(0.999), eps=f(1e-8))
+    got = pt.double().cpu().numpy()
+    print("made_train: param err %.2e loss err %.2e" % (
+        np.abs(got - p).max() / np.abs(p).max(),
+        np.abs(losses.cpu().numpy() - ref_l).max() / np.abs(ref_l).max()))
+    assert np.abs(losses.cpu().numpy() - np.array(ref_l)).max() <= 1e-5 * np.abs(ref_l).max()
+    assert np.abs(got - p).max() <= 1e-4 * np.abs(p).max()
+
+
+def test_tau_int_kernel_matches_oracle(dev):
+    # the library's tau_int (peps_tau_int) against the oracle's direct sums,
+    # plain and on the oracle's rank-normalised series; ties in the data
+    # (sticky chains repeat values) exercise the average ranks
+    from paper_2503_12557_amd import analysis
+    rng = np.random.default_rng(3)
+    C, T, a = 32, 300, 0.6
+    x = np.zeros((C, T))
+    e = rng.standard_normal((C, T))
+    for t in range(1, T):
+        x[:, t] = a * x[:, t - 1] + e[:, t]
+    p = 0.67
+    y = np.empty((256, 64))
+    y[:, 0] = rng.standard_cauchy(256)
+    for t in range(1, 64):
+        keep = rng.random(256) < p
+        y[:, t] = np.where(keep, y[:, t - 1], rng.standard_cauchy(256))
+    for s in (x, y):
+        got, ref = analysis.tau_int(s), OM.integrated_autocorr(s)
+        assert abs(got - ref) <= 1e-9 * ref
+        got_r, ref_r = analysis.tau_int_ranked(s), OM.integrated_autocorr(OM.rank_normalise(s))
+        print(f"tau_int {got:.6f} / {ref:.6f}; ranked {got_r:.6f} / {ref_r:.6f}")
+        assert abs(got_r - ref_r) <= 1e-9 * ref_r
+
+
+def test_imh_sampler_kind_equals_its_building_blocks(dev):
+    # peps_sample with the IMH kind against the same chain assembled from
+    # made_sample, peps_amplitude and imh_step: identical states, ln Psi and
+    # acceptance counts; the local kinds' ln Psi output equals peps_amplitude
+    from paper_2503_12557_amd import Context
+    from paper_2503_12557_amd.binding import imh_step
+    Lx, Ly, D, chi = 3, 4, 2, 4
+    N = Lx * Ly
+    theta = synth.theta(Lx, Ly, 2, D, seed=8)
+    th = torch.from_numpy(theta).to(dev)
+    ctx = Context(Lx, Ly, D, chi, "f64")
+    m = _made(N, 32, N // 2)
+    pt = torch.tensor(OM.init_params(N, 32, seed=3, scale=0.5), dtype=torch.float32, device=dev)
+    init, _, lp_init = ctx.sample(th, "exchange", n_chains=64, per_chain=1, burn_in=10, seed=5,
+                                  want_logpsi=True)
+    ref_lp, _ = ctx.amplitude(th, init)
+    torch.cuda.synchronize()
+    assert torch.equal(lp_init, ref_lp)
+    s, acc, lp = ctx.sample(th, "imh", n_chains=64, per_chain=3, burn_in=2, thin=2, seed=9,
+                            offset=4, proposal=(m, pt, init), want_logpsi=True)
+    # the same chain by hand
+    state = init.clone()
+    st_lq = m.logq(pt, state)
+    st_lp, _ = ctx.amplitude(th, state)
+    acc2 = torch.zeros(64, dtype=torch.int32, device=dev)
+    rec, rec_lp = [], []
+    for t in range(1, 2 + 3 * 2 + 1):
+        prop, pr_lq = m.sample(pt, 64, seed=9, offset=4 + t)
+        pr_lp, _ = ctx.amplitude(th, prop)
+        imh_step(state, st_lp, st_lq, prop, pr_lp, pr_lq, 9, 4 + t, acc2)
+        if t > 2 and (t - 2) % 2 == 0:
+            rec.append(state.clone())
+            rec_lp.append(st_lp.clone())
+    torch.cuda.synchronize()
+    want = torch.stack(rec, 1).reshape(64 * 3, N)
+    want_lp = torch.stack(rec_lp, 1).reshape(64 * 3, 2)
+    assert torch.equal(s, want) and torch.equal(lp, want_lp) and torch.equal(acc, acc2)
+    assert acc.sum().item() > 0
