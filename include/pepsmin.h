@@ -157,8 +157,11 @@ peps_status peps_set_hamiltonian(peps_ctx* ctx, int n_terms, const int* term_nsi
  * log importance weight ln|Psi(S)_i*|^2 - ln p(S) (the amplitude of
  * peps_amplitude), which corrects the sampler's bias by reweighting; flags:
  * int32 [n] or NULL (1: both q zero at some site, 2: non-finite value, and
- * the amplitude's flags). Needs D^2 <= 16 and max(chi_double, D^2) * D^2 <=
- * 256 (PEPS_ERR_UNSUPPORTED otherwise). The workspace (double-layer context,
+ * the amplitude's flags). Needs D^2 <= 16, max(chi_double, D^2) * D^2 <=
+ * 256 and the row kernel's staged column, (max(chi, D)^2 D + 2 D^4 +
+ * max(chi_double, D^2)^2 D^2) elements of the compute type, within 150 KiB
+ * of LDS (e.g. FP64 at D = 4 allows chi <= 60 with chi_double = 4); any of
+ * these fails with PEPS_ERR_UNSUPPORTED before anything is queued. The workspace (double-layer context,
  * per-sample slabs of O(Ly chi^2 D^2 chi_double) elements) is grown on
  * demand; returns with the work queued on the stream. */
 peps_status peps_direct_sample(peps_ctx* ctx, const double* theta, int n, int chi_double,

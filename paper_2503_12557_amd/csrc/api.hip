@@ -833,6 +833,16 @@ peps_status peps_direct_sample(peps_ctx* c, const double* theta, int n, int chi_
   hipStream_t st = (hipStream_t)stream;
   const Lattice& L = c->L;
   peps_status s;
+  {
+    // the row kernel stages E, two site tensors and D^l of a column in LDS:
+    // reject shapes that do not fit before anything is queued
+    const size_t D2 = (size_t)L.D * L.D, bm2 = std::max<size_t>((size_t)chi_double, D2);
+    const size_t lds = ((size_t)L.bmax * L.D * L.bmax + 2 * D2 * D2 + bm2 * D2 * bm2) * c->tsize;
+    if (lds > kLdsDyn)
+      return fail(PEPS_ERR_UNSUPPORTED,
+                  "direct sampler: %zu bytes of LDS per row workgroup (chi = %d, D = %d, "
+                  "chi_double = %d) above %zu", lds, L.chi, L.D, chi_double, kLdsDyn);
+  }
   if (!c->dbl || c->dbl_chi != chi_double) {
     if (c->dbl) peps_destroy(c->dbl);
     c->dbl = nullptr;

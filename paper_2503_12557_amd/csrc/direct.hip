@@ -488,8 +488,9 @@ hipError_t launch_direct_row(const Lattice& L, const int* tab, const void* theta
   const size_t D4 = (size_t)L.D * L.D * L.D * L.D;
   const size_t lds = ((size_t)L.bmax * L.D * L.bmax + 2 * D4 +
                       (size_t)L2.bmax * L.D * L.D * L2.bmax) * sizeof(T);
-  hipFuncSetAttribute((const void*)k_direct_row<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_direct_row<M>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_direct_row<M>, dim3(n), dim3(256), lds, st, L, tab, (const T*)theta,
                      (const T*)env, L2, tab2, (const T*)env2, samples, logp, flags, n, i, k0, k1,
                      offset, (T*)slab, direct_slab_elems(L, L2));

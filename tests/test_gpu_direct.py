@@ -98,6 +98,17 @@ def test_direct_sample_argument_errors(dev):
     th2 = torch.from_numpy(synth.theta(3, 3, 2, 2, seed=1)).to(dev)
     with pytest.raises(PepsError):
         _ctx(3, 3, 2, 4, "f64").direct_sample(th2, 4, 0, seed=1)
+    # a column that does not fit in LDS (FP64, D = 4, chi = 64: 164 KiB) is
+    # rejected before any work is queued, and the context stays usable
+    th4 = torch.from_numpy(synth.theta(3, 3, 2, 4, seed=1)).to(dev)
+    big = _ctx(3, 3, 4, 64, "f64")
+    with pytest.raises(PepsError) as ex:
+        big.direct_sample(th4, 4, 4, seed=1)
+    assert ex.value.status == 2
+    small = _ctx(3, 3, 4, 60, "f64")
+    s, lp, lw, fl = small.direct_sample(th4, 4, 4, seed=1)
+    torch.cuda.synchronize()
+    assert torch.isfinite(lp).all()
 
 
 def test_reweighted_energy_is_unbiased_under_a_truncated_double_layer(dev):
