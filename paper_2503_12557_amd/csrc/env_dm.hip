@@ -85,8 +85,9 @@ __host__ __device__ inline size_t dm_big_elems(int bmax, int D, int chi, size_t 
   // Xe (np x rm, T) | Yt (rm x np, R) | LU (rm x 5 x np, R)
   const size_t eig = np * rm + (rm * np * 6 * rsize + tsize - 1) / tsize;
   const size_t with = (eig > big ? eig : big);
-  const bool fits = ((with + 1) / 2 * 2) * tsize + dm_small_bytes((int)np, tsize, rsize) <=
-                    DM_LDS_CAP;
+  // FP32 modes run two workgroups per CU: each keeps below half the LDS
+  const size_t cap = rsize == 4 ? DM_LDS_CAP / 2 : DM_LDS_CAP;
+  const bool fits = ((with + 1) / 2 * 2) * tsize + dm_small_bytes((int)np, tsize, rsize) <= cap;
   if (eig_lds) *eig_lds = fits;
   big = fits ? with : big;
   return (big + 1) / 2 * 2;
@@ -157,16 +158,19 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       sh.ee[j] = beta;
       sh.tau[j] = tau;
     }
-    // v_i = 1 (i = j+1), rho[i][j] sc below: read from column j, which no
-    // later step touches
-    auto vv = [&](int i) -> T { return i == j + 1 ? T(1) : rho[pk(i, j)] * sc; };
+    // v_i = 1 (i = j+1), rho[i][j] sc below, once into LDS and Hv row j
+    for (int i = j + 1 + tid; i < nz; i += NT) {
+      const T v = i == j + 1 ? T(1) : rho[pk(i, j)] * sc;
+      sh.vb[i] = v;
+      Hv[(size_t)j * ldh + i] = v;
+    }
     if (tau == T(0)) {
-      for (int i = j + 1 + tid; i < nz; i += NT) Hv[(size_t)j * ldh + i] = vv(i);
       R t = 0;
       for (int i = j + 3 + tid; i < nz; i += NT) t += abs2x(rho[pk(i, j + 1)]);
       s2 = blk_sum2(t, reinterpret_cast<R*>(sh.red), slot);
       continue;
     }
+    __syncthreads();
     // u = B v for the trailing block B (rows / columns j+1..), then
     // w = tau u - (|tau|^2 / 2) (v^H u) v
     T vhu = T(0);
@@ -175,17 +179,14 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       const int i = j + 1 + ri + p * rpp;
       T u = T(0);
       if (i < nz) {
-        for (int kk = j + 1 + q; kk < nz; kk += TPR)
-          u += (kk <= i ? rho[pk(i, kk)] : conjx(rho[pk(kk, i)])) * vv(kk);
+        // row part (k <= i) then the column part through the symmetry
+        int kk = j + 1 + q;
+        for (; kk <= i; kk += TPR) u += rho[pk(i, kk)] * sh.vb[kk];
+        for (; kk < nz; kk += TPR) u += conjx(rho[pk(kk, i)]) * sh.vb[kk];
       }
       u = group_sum(u, TPR);
       ui[p] = u;
-      if (i < nz && q == 0) {
-        const T vi = vv(i);
-        vhu += conjx(vi) * u;
-        sh.vb[i] = vi;
-        Hv[(size_t)j * ldh + i] = vi;
-      }
+      if (i < nz && q == 0) vhu += conjx(sh.vb[i]) * u;
     }
     const R vhu_r = blk_sum2(realx(vhu), reinterpret_cast<R*>(sh.red), slot);
     const R t2 = abs2x(tau) * R(0.5) * vhu_r;
@@ -729,8 +730,11 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
 }
 
 // Persistent grid over (sample, direction) tasks.
+// FP32 modes: two workgroups per CU (four waves per SIMD: registers capped at
+// 128 per lane) so
+// one workgroup's eigensolver overlaps the other's matrix-core products
 template <int M>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, (M == MODE_F32 || M == MODE_BF16 || M == MODE_C64) ? 4 : 2)
 k_env_dm(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, typename ModeT<M>::T* __restrict__ env,
          double* __restrict__ logs, int* __restrict__ flags, int n, int ndir, int dir0,

@@ -126,10 +126,13 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
     const T* pa1 = A + (ia1 ? ai(i0 + 16 + li) : 0);
     const T* pb0 = B + (jb0 ? bj(j0 + li) : 0);
     const T* pb1 = B + (jb1 ? bj(j0 + 16 + li) : 0);
-    for (int k0 = 0; k0 < k; k0 += 16) {
-      R ar[4][2], aim[4][2], br[4][2], bim[4][2];
+    // k-steps of 4 loaded ahead of their products: four for real operands,
+    // two for complex ones (register budget)
+    constexpr int KS = CX ? 2 : 4;
+    for (int k0 = 0; k0 < k; k0 += 4 * KS) {
+      R ar[KS][2], aim[KS][2], br[KS][2], bim[KS][2];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < KS; ++s) {
         const int kk = k0 + 4 * s + lk;
         const bool kin = kk < k;
         const int oa = kin ? ak(kk) : 0, ob = kin ? bk(kk) : 0;
@@ -143,7 +146,7 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
         split(y1, br[s][1], bim[s][1]);
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < KS; ++s) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
