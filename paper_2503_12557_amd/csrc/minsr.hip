@@ -13,6 +13,7 @@
 // dtheta = Obar^H y; the scalar type S is double or cplx<double>.
 #include "common.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace pm {
 
@@ -115,91 +116,271 @@ __global__ void k_estats(const double* __restrict__ eloc, int n, double* __restr
   }
 }
 
-// Masked Gram G[s,s'] = sum_k O_sk conj(O_s'k) over compact columns, 64 x 64
-// tiles of the lower triangle, 4 x 4 outputs per thread; written with the
-// centring and eps already applied:
-// T = (G - a_s - conj(a_s') + |m|^2)/n + eps delta.
-#define GT 64
-#define GK 16
+// ---- FP64 matrix-core tiles of the Hermitian products --------------------
+// A workgroup of four waves forms one 64 x 64 tile of C = A B^H, where the
+// rows of A and B are samples (the Gram) or rows of the Cholesky panel (the
+// trailing update); each wave owns a 32 x 32 block of 2 x 2 MFMA tiles.
+// Operands pass through LDS in chunks of HKC columns stored k-major,
+// [k][row], the layout in which 16 consecutive lanes read 16 rows of one k.
+// A complex product takes three real ones: with B' = conj(B),
+// P1 = Re A Re B', P2 = Im A Im B', P3 = (Re A + Im A)(Re B' + Im B'),
+// Re C = P1 - P2 and Im C = P3 - P1 - P2.
+#define HT 64
+#define HKC 16
+#define HLS (HT + 2)
+
+template <bool CX> struct HStage {
+  static constexpr int NP = CX ? 3 : 1;
+  double a[NP][HKC][HLS];
+  double b[NP][HKC][HLS];
+};
+
+// Partial products of one wave: p[component][row tile][column tile]
+template <bool CX> struct HPart {
+  static constexpr int NP = CX ? 3 : 1;
+  mf64x4 p[NP][2][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) p[c][i][j] = mf64x4{0.0, 0.0, 0.0, 0.0};
+  }
+};
+
+// element (k, r) of the staged A (isb = false) or of conj(B) (isb = true)
+template <bool CX>
+__device__ __forceinline__ void hput(HStage<CX>& sh, bool isb, int k, int r, double re,
+                                     double im) {
+  double (*d)[HKC][HLS] = isb ? sh.b : sh.a;
+  d[0][k][r] = re;
+  if constexpr (CX) {
+    if (isb) im = -im;
+    d[1][k][r] = im;
+    d[2][k][r] = re + im;
+  }
+}
+
+// accumulate kc4 (a multiple of 4) staged columns into the wave's partials
+template <bool CX>
+__device__ __forceinline__ void hchunk(const HStage<CX>& sh, HPart<CX>& acc, int kc4, int lane,
+                                       int wr, int wc) {
+  constexpr int NP = HStage<CX>::NP;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int kq = 0; kq < kc4; kq += 4) {
+    double av[NP][2], bv[NP][2];
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[c][t] = sh.a[c][kq + lk][32 * wr + 16 * t + lr];
+        bv[c][t] = sh.b[c][kq + lk][32 * wc + 16 * t + lr];
+      }
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc.p[c][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c][i], bv[c][j],
+                                                                acc.p[c][i][j], 0, 0, 0);
+  }
+}
+
+// value v (0..3) of tile (i, j) of the wave's partials as the scalar S
+template <typename S, bool CX>
+__device__ __forceinline__ S hval(const HPart<CX>& acc, int i, int j, int v) {
+  if constexpr (CX) {
+    const double p1 = acc.p[0][i][j][v], p2 = acc.p[1][i][j][v], p3 = acc.p[2][i][j][v];
+    return S(p1 - p2, p3 - p1 - p2);
+  } else {
+    return acc.p[0][i][j][v];
+  }
+}
+
+// lower-triangle tile t -> (bi, bj), bj <= bi; blocks are dealt out so that
+// each XCD (blocks b, b + 8, ...) takes a contiguous range of tiles, which
+// share operand rows in its L2
+__device__ __forceinline__ bool tri_tile(int ntiles, int& bi, int& bj) {
+  const int per = gridDim.x >> 3;
+  const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (t >= ntiles) return false;
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  bi = i;
+  bj = t - i * (i + 1) / 2;
+  return true;
+}
+
+static unsigned tri_grid(int nt) {
+  const unsigned ntiles = (unsigned)nt * (unsigned)(nt + 1) / 2;
+  return (ntiles + 7u) & ~7u;
+}
+
+// Masked Gram G[s,s'] = sum_k O_sk conj(O_s'k) over compact columns: the
+// parameters of site (x, y) are shared by two samples only when their
+// physical indices there agree, so each site's columns are accumulated
+// apart and added where the two bits agree (the bits of the tile's 64 rows
+// at every site are packed into one 64-bit word per site in LDS). Chunks of
+// HKC columns of one site are double-buffered in LDS, holding (Re, Im) of A
+// and of conj(B); the next chunk is loaded into registers before the
+// current one is multiplied, so one barrier per chunk remains. Written with
+// the centring and eps already applied:
+// T = (G - a_s - conj(a_s') + |m|^2)/n + eps delta, both triangles.
+template <bool CX> struct GStage {
+  static constexpr int NC = CX ? 2 : 1;
+  double v[2][2][NC][HKC][HLS];  // [buffer][A, conj B][Re, Im][k][row]
+};
+
 template <typename TO>
 __global__ void __launch_bounds__(256)
 k_gram(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
        const uint8_t* __restrict__ samples, int n, const typename SolveT<TO>::type* __restrict__ a,
-       double eps, typename SolveT<TO>::type* __restrict__ Tm) {
+       double eps, typename SolveT<TO>::type* __restrict__ Tm, int ntiles) {
   typedef typename SolveT<TO>::type S;
-  const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bj > bi) return;
-  __shared__ S As[GK][GT + 1], Bs[GK][GT + 1];
-  __shared__ uint8_t Pa[GK][GT], Pb[GK][GT];
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  S acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  const int s0 = bi * GT, t0 = bj * GT;
-  for (int k0 = 0; k0 < L.n_compact; k0 += GK) {
-    for (int e = tid; e < GK * GT; e += 256) {
-      const int kk = e / GT, r = e - kk * GT;  // r fastest: samples
-      const int jc = k0 + kk;
-      const int sa = s0 + r, sb = t0 + r;
-      S va = 0.0, vb = 0.0;
-      uint8_t pa = 0, pb = 0;
-      if (jc < L.n_compact) {
-        const int site = tab[L.off_csite + jc];
-        if (sa < n) {
-          va = to_s(O[(size_t)sa * L.n_compact + jc]);
-          pa = pbit(samples[(size_t)sa * L.N + site]);
-        }
-        if (sb < n) {
-          vb = conjx(to_s(O[(size_t)sb * L.n_compact + jc]));
-          pb = pbit(samples[(size_t)sb * L.N + site]);
-        }
-      }
-      As[kk][r] = va;
-      Bs[kk][r] = vb;
-      Pa[kk][r] = pa;
-      Pb[kk][r] = pb;
+  constexpr bool CX = IsCplx<TO>::value;
+  constexpr int NP = CX ? 3 : 1, NE = HT * HKC / 256;
+  __shared__ GStage<CX> sh;
+  extern __shared__ unsigned long long bits[];  // [site][A rows, B rows]
+  int bi, bj;
+  if (!tri_tile(ntiles, bi, bj)) return;
+  const int s0 = bi * HT, t0 = bj * HT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const size_t nc = (size_t)L.n_compact;
+  // physical bits of the 64 A rows and 64 B rows at every site
+  for (int site = w; site < L.N; site += 4) {
+    const int ra = s0 + lane, rb = t0 + lane;
+    const int ba = ra < n ? pbit(samples[(size_t)ra * L.N + site]) : 0;
+    const int bb = rb < n ? pbit(samples[(size_t)rb * L.N + site]) : 0;
+    const unsigned long long ma = __ballot(ba), mb = __ballot(bb);
+    if (lane == 0) {
+      bits[2 * site] = ma;
+      bits[2 * site + 1] = mb;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < GK; ++kk) {
-      S av[4], bv[4];
-      uint8_t ap[4], bp[4];
+  }
+  // chunk loader: element u of this thread is (row e / HKC, column e % HKC)
+  TO ra[NE], rb[NE];
+  auto load = [&](int site, int k0) {
+    const int c0 = tab[L.off_compact + site], kc = min(HKC, tab[L.off_block + site] - k0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        av[i] = As[kk][tr * 4 + i];
-        ap[i] = Pa[kk][tr * 4 + i];
-        bv[i] = Bs[kk][tc * 4 + i];
-        bp[i] = Pb[kk][tc * 4 + i];
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + 256 * u, r = e / HKC, k = e - r * HKC;
+      const size_t col = (size_t)c0 + k0 + k;
+      ra[u] = (k < kc && s0 + r < n) ? O[(size_t)(s0 + r) * nc + col] : TO(0);
+      rb[u] = (k < kc && t0 + r < n) ? O[(size_t)(t0 + r) * nc + col] : TO(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + 256 * u, r = e / HKC, k = e - r * HKC;
+      double re, im;
+      split(to_s(ra[u]), re, im);
+      sh.v[buf][0][0][k][r] = re;
+      if constexpr (CX) sh.v[buf][0][1][k][r] = im;
+      split(to_s(rb[u]), re, im);
+      sh.v[buf][1][0][k][r] = re;
+      if constexpr (CX) sh.v[buf][1][1][k][r] = -im;
+    }
+  };
+  mf64x4 tot[2][2][CX ? 2 : 1];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int c = 0; c < (CX ? 2 : 1); ++c) tot[i][j][c] = mf64x4{0.0, 0.0, 0.0, 0.0};
+  HPart<CX> cur;
+  cur.zero();
+  int site = 0, k0 = 0;
+  load(0, 0);
+  store(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int buf = 0;; buf ^= 1) {
+    const int nbk = tab[L.off_block + site];
+    const int kc4 = (min(HKC, nbk - k0) + 3) & ~3;
+    // the chunk after this one
+    int nsite = site, nk0 = k0 + HKC;
+    if (nk0 >= nbk) {
+      ++nsite;
+      nk0 = 0;
+    }
+    const bool more = nsite < L.N;
+    if (more) load(nsite, nk0);
+    for (int kq = 0; kq < kc4; kq += 4) {
+      double av[NP][2], bv[NP][2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[0][t] = sh.v[buf][0][0][kq + lk][32 * wr + 16 * t + lr];
+        bv[0][t] = sh.v[buf][1][0][kq + lk][32 * wc + 16 * t + lr];
+        if constexpr (CX) {
+          av[1][t] = sh.v[buf][0][1][kq + lk][32 * wr + 16 * t + lr];
+          bv[1][t] = sh.v[buf][1][1][kq + lk][32 * wc + 16 * t + lr];
+          av[2][t] = av[0][t] + av[1][t];
+          bv[2][t] = bv[0][t] + bv[1][t];
+        }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int c = 0; c < NP; ++c)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if constexpr (IsCplx<S>::value) {
-            if (ap[i] == bp[j]) acc[i][j] += av[i] * bv[j];
-          } else {
-            acc[i][j] += (ap[i] == bp[j]) ? av[i] * bv[j] : 0.0;
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cur.p[c][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c][i], bv[c][j],
+                                                                  cur.p[c][i][j], 0, 0, 0);
+    }
+    if (nsite != site) {
+      // add this site's products where the two samples share its parameters
+      const unsigned long long ma = bits[2 * site], mb = bits[2 * site + 1];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = 32 * wc + 16 * j + lr;
+          const int pb = (int)((mb >> col) & 1ull);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 32 * wr + 16 * i + 4 * v + lk;
+            if ((int)((ma >> row) & 1ull) == pb) {
+              double gr, gi;
+              split(hval<S, CX>(cur, i, j, v), gr, gi);
+              tot[i][j][0][v] += gr;
+              if constexpr (CX) tot[i][j][1][v] += gi;
+            }
           }
+        }
+      cur.zero();
     }
+    if (!more) break;
+    store(buf ^ 1);
     __syncthreads();
+    site = nsite;
+    k0 = nk0;
   }
   const S m2 = a[n];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int s = s0 + tr * 4 + i, t = t0 + tc * 4 + j;
-      if (s < n && t < n && t <= s) {
-        S v = (acc[i][j] - a[s] - conjx(a[t]) + m2) / (double)n;
-        if (s == t) {
-          v += S(eps);
-          if constexpr (IsCplx<S>::value) v.im = 0.0;  // Hermitian diagonal
+    for (int j = 0; j < 2; ++j) {
+      const int t = t0 + 32 * wc + 16 * j + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = s0 + 32 * wr + 16 * i + 4 * v + lk;
+        if (s < n && t < n && t <= s) {
+          S g;
+          if constexpr (CX) g = S(tot[i][j][0][v], tot[i][j][1][v]);
+          else g = tot[i][j][0][v];
+          S val = (g - a[s] - conjx(a[t]) + m2) / (double)n;
+          if (s == t) {
+            val += S(eps);
+            if constexpr (IsCplx<S>::value) val.im = 0.0;  // Hermitian diagonal
+          }
+          Tm[(size_t)s * n + t] = val;
+          Tm[(size_t)t * n + s] = conjx(val);
         }
-        Tm[(size_t)s * n + t] = v;
-        Tm[(size_t)t * n + s] = conjx(v);
       }
     }
 }
@@ -261,9 +442,14 @@ __global__ void __launch_bounds__(256) k_chol_diag(S* __restrict__ A, int n, int
   }
 }
 
-// rows below the diagonal block: X L_kk^H = A_ik  (one thread per row)
+// rows below the diagonal block: X L_kk^H = A_ik. NQ lanes share a row
+// (4 real, 8 complex), lane q holding the columns j = NQ u + q; column j is
+// finished by its owner and passed to the other lanes of the row.
+template <typename S> constexpr int trsm_lanes() { return IsCplx<S>::value ? 8 : 4; }
+
 template <typename S>
 __global__ void __launch_bounds__(256) k_chol_trsm(S* __restrict__ A, int n, int kb) {
+  constexpr int NQ = trsm_lanes<S>(), NU = CB / NQ;
   __shared__ S Lk[CB][CB + 1];
   const int k0 = kb * CB;
   const int nb = (n - k0) < CB ? (n - k0) : CB;
@@ -272,111 +458,197 @@ __global__ void __launch_bounds__(256) k_chol_trsm(S* __restrict__ A, int n, int
     Lk[i][j] = conjx(A[(size_t)(k0 + i) * n + k0 + j]);
   }
   __syncthreads();
-  const int row = k0 + nb + blockIdx.x * 256 + threadIdx.x;
-  if (row >= n) return;
-  S x[CB];
-  S* a = A + (size_t)row * n + k0;
+  const int tid = threadIdx.x, q = tid % NQ, lane = tid & 63;
+  const int row = k0 + nb + blockIdx.x * (256 / NQ) + tid / NQ;
+  const bool live = row < n;
+  S* a = A + (size_t)(live ? row : 0) * n + k0;
+  S x[NU];
 #pragma unroll
-  for (int j = 0; j < CB; ++j) x[j] = (j < nb) ? a[j] : S(0.0);
-#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int j = NQ * u + q;
+    x[u] = (live && j < nb) ? a[j] : S(0.0);
+  }
+#pragma clang loop unroll(full)
   for (int j = 0; j < CB; ++j) {
     if (j < nb) {
-      S v = x[j];
+      S xj = x[j / NQ] * (1.0 / realx(Lk[j][j]));
+      if (q == j % NQ) x[j / NQ] = xj;
+      const int src = (lane & ~(NQ - 1)) | (j % NQ);
+      if constexpr (IsCplx<S>::value) xj = S(__shfl(xj.re, src, 64), __shfl(xj.im, src, 64));
+      else xj = __shfl(xj, src, 64);
 #pragma unroll
-      for (int i = 0; i < CB; ++i)
-        if (i < j) v -= x[i] * Lk[j][i];
-      if constexpr (IsCplx<S>::value) x[j] = v * (1.0 / realx(Lk[j][j]));
-      else x[j] = v / Lk[j][j];
+      for (int u = j / NQ; u < NU; ++u) {
+        const int i = NQ * u + q;
+        if (i > j && i < nb) x[u] -= xj * Lk[i][j];
+      }
     }
   }
+  if (!live) return;
 #pragma unroll
-  for (int j = 0; j < CB; ++j)
-    if (j < nb) a[j] = x[j];
+  for (int u = 0; u < NU; ++u) {
+    const int j = NQ * u + q;
+    if (j < nb) a[j] = x[u];
+  }
 }
 
-// trailing update A_ij -= L_ik conj(L_jk) for the lower triangle, 64 x 64 tiles
+// trailing update A_ij -= L_ik L_jk^H of the lower triangle on the matrix
+// cores, 64 x 64 tiles (rows i, j beyond block kb; k over block kb)
 template <typename S>
-__global__ void __launch_bounds__(256) k_chol_syrk(S* __restrict__ A, int n, int kb) {
+__global__ void __launch_bounds__(256) k_chol_syrk(S* __restrict__ A, int n, int kb,
+                                                   int ntiles) {
+  constexpr bool CX = IsCplx<S>::value;
+  __shared__ HStage<CX> sh;
+  int bi, bj;
+  if (!tri_tile(ntiles, bi, bj)) return;
   const int k0 = kb * CB;
   const int base = k0 + CB;
-  const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bj > bi) return;
-  const int i0 = base + bi * GT, j0 = base + bj * GT;
-  __shared__ S As[CB][GT + 1], Bs[CB][GT + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < CB * GT; e += 256) {
-    const int r = e / CB, kk = e - r * CB;
-    As[kk][r] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + k0 + kk] : S(0.0);
-    Bs[kk][r] = (j0 + r < n) ? conjx(A[(size_t)(j0 + r) * n + k0 + kk]) : S(0.0);
-  }
-  __syncthreads();
-  const int tr = tid / 16, tc = tid % 16;
-  S acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int kk = 0; kk < CB; ++kk) {
-    S av[4], bv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      av[i] = As[kk][tr * 4 + i];
-      bv[i] = Bs[kk][tc * 4 + i];
+  const int i0 = base + bi * HT, j0 = base + bj * HT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  HPart<CX> acc;
+  acc.zero();
+  for (int kk = 0; kk < CB; kk += HKC) {
+    if (kk > 0) __syncthreads();
+    for (int e = tid; e < HT * HKC; e += 256) {
+      const int r = e / HKC, k = e - r * HKC;
+      double re = 0.0, im = 0.0, re2 = 0.0, im2 = 0.0;
+      if (i0 + r < n) split(A[(size_t)(i0 + r) * n + k0 + kk + k], re, im);
+      if (j0 + r < n) split(A[(size_t)(j0 + r) * n + k0 + kk + k], re2, im2);
+      hput<CX>(sh, false, k, r, re, im);
+      hput<CX>(sh, true, k, r, re2, im2);
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    __syncthreads();
+    hchunk<CX>(sh, acc, HKC, lane, wr, wc);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = i0 + tr * 4 + i, c = j0 + tc * 4 + j;
-      if (r < n && c < n && c <= r) A[(size_t)r * n + c] -= acc[i][j];
+    for (int j = 0; j < 2; ++j) {
+      const int c = j0 + 32 * wc + 16 * j + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = i0 + 32 * wr + 16 * i + 4 * v + (lane >> 4);
+        if (r < n && c < n && c <= r) A[(size_t)r * n + c] -= hval<S, CX>(acc, i, j, v);
+      }
     }
 }
 
-// y = L^-H L^-1 ebar in one block: ebar = (E - <E>)/sqrt(n) (Re E for real
-// parameters)
+// ebar = (E - <E>)/sqrt(n) (Re E for real parameters) into y
 template <typename S>
-__global__ void __launch_bounds__(256) k_chol_solve(const S* __restrict__ Lm, int n,
-                                                    const double* __restrict__ eloc,
-                                                    const double* __restrict__ ws,
-                                                    S* __restrict__ y) {
-  const int tid = threadIdx.x;
+__global__ void k_ebar(const double* __restrict__ eloc, int n, const double* __restrict__ ws,
+                       S* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
   const double isn = 1.0 / sqrt((double)n);
-  for (int i = tid; i < n; i += 256) {
-    if constexpr (IsCplx<S>::value)
-      y[i] = S((eloc[2 * i] - ws[0]) * isn, (eloc[2 * i + 1] - ws[8]) * isn);
-    else
-      y[i] = (eloc[2 * i] - ws[0]) * isn;
+  if constexpr (IsCplx<S>::value)
+    y[i] = S((eloc[2 * i] - ws[0]) * isn, (eloc[2 * i + 1] - ws[8]) * isn);
+  else
+    y[i] = (eloc[2 * i] - ws[0]) * isn;
+}
+
+// Blocked triangular solves of y = L^-H L^-1 y over 64-row blocks, one
+// launch per block. Forward (L z = b): workgroup g subtracts the solved
+// block ub from the rows of block ub + 1 + g; workgroup 0, which holds
+// block ub + 1 = sb, then solves it in one wave (lane i owns row i; the
+// diagonal block sits transposed in LDS so that a column is a contiguous
+// read). ub < 0: no update.
+template <typename S>
+__global__ void __launch_bounds__(256) k_trsv_fwd(const S* __restrict__ Lm, int n, int ub,
+                                                  int sb, S* __restrict__ y) {
+  __shared__ S Lt[CB][CB + 1];
+  __shared__ S xs[CB], zs[CB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int rb = (ub >= 0 ? ub + 1 : sb) + blockIdx.x;  // row block of this workgroup
+  const int r0 = rb * CB;
+  if (ub >= 0) {
+    const int k0 = ub * CB;
+    if (tid < CB) xs[tid] = y[k0 + tid];  // block ub is full: only the last can be short
+    __syncthreads();
+    const int r = tid >> 2, q = tid & 3, row = r0 + r;
+    S acc = S(0.0);
+    if (row < n) {
+      const S* l = Lm + (size_t)row * n + k0 + 16 * q;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc += l[j] * xs[16 * q + j];
+    }
+    acc += shfl_xor_x(acc, 1);
+    acc += shfl_xor_x(acc, 2);
+    if (q == 0 && row < n) {
+      const S v = y[row] - acc;
+      y[row] = v;
+      zs[r] = v;
+    }
+  } else if (tid < CB) {
+    zs[tid] = (r0 + tid < n) ? y[r0 + tid] : S(0.0);
+  }
+  if (blockIdx.x != 0 || sb < 0) return;
+  const int k1 = sb * CB, nb = (n - k1) < CB ? (n - k1) : CB;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e - i * nb;
+    if (j <= i) Lt[j][i] = Lm[(size_t)(k1 + i) * n + k1 + j];
   }
   __syncthreads();
-  // forward: L z = ebar
-  for (int j = 0; j < n; ++j) {
-    __shared__ S yj;
-    if (tid == 0) {
-      if constexpr (IsCplx<S>::value) yj = y[j] * (1.0 / realx(Lm[(size_t)j * n + j]));
-      else yj = y[j] / Lm[(size_t)j * n + j];
-      y[j] = yj;
-    }
-    __syncthreads();
-    for (int i = j + 1 + tid; i < n; i += 256) y[i] -= Lm[(size_t)i * n + j] * yj;
-    __syncthreads();
+  if (tid >= 64) return;
+  S b = zs[lane];
+  for (int j = 0; j < nb; ++j) {
+    S bj;
+    if constexpr (IsCplx<S>::value) bj = S(__shfl(b.re, j, 64), __shfl(b.im, j, 64));
+    else bj = __shfl(b, j, 64);
+    const S xj = bj * (1.0 / realx(Lt[j][j]));
+    if (lane == j) b = xj;
+    else if (lane > j && lane < nb) b -= Lt[j][lane] * xj;
   }
-  // backward: L^H y = z
-  for (int j = n - 1; j >= 0; --j) {
-    __shared__ S yj;
-    if (tid == 0) {
-      if constexpr (IsCplx<S>::value) yj = y[j] * (1.0 / realx(Lm[(size_t)j * n + j]));
-      else yj = y[j] / Lm[(size_t)j * n + j];
-      y[j] = yj;
+  if (lane < nb) y[k1 + lane] = b;
+}
+
+// Backward (L^H x = z): workgroup g subtracts the solved block ub from the
+// rows of block g (g < ub); the last workgroup, which holds block sb =
+// ub - 1, then solves it in one wave. ub = number of blocks: no update,
+// one workgroup solving block sb.
+template <typename S>
+__global__ void __launch_bounds__(256) k_trsv_bwd(const S* __restrict__ Lm, int n, int ub,
+                                                  int sb, int nblk, S* __restrict__ y) {
+  __shared__ S Lr[CB][CB + 1];
+  __shared__ S xs[CB], part[4][CB], zs[CB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int rb = (ub < nblk) ? (int)blockIdx.x : sb;
+  const int r0 = rb * CB;
+  if (ub < nblk) {
+    const int k0 = ub * CB, nbu = (n - k0) < CB ? (n - k0) : CB;
+    if (tid < CB) xs[tid] = (tid < nbu) ? y[k0 + tid] : S(0.0);
+    __syncthreads();
+    const int r = lane, q = tid >> 6;
+    S acc = S(0.0);
+#pragma unroll 4
+    for (int j = 16 * q; j < 16 * q + 16; ++j)
+      if (j < nbu) acc += conjx(Lm[(size_t)(k0 + j) * n + r0 + r]) * xs[j];
+    part[q][r] = acc;
+    __syncthreads();
+    if (tid < CB) {
+      const S v = y[r0 + tid] - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
+      y[r0 + tid] = v;
+      zs[tid] = v;
     }
-    __syncthreads();
-    for (int i = tid; i < j; i += 256) y[i] -= conjx(Lm[(size_t)j * n + i]) * yj;
-    __syncthreads();
+  } else if (tid < CB) {
+    zs[tid] = (r0 + tid < n) ? y[r0 + tid] : S(0.0);
   }
+  if (rb != sb) return;
+  const int k1 = sb * CB, nb = (n - k1) < CB ? (n - k1) : CB;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int j = e / nb, i = e - j * nb;
+    if (i <= j) Lr[j][i] = Lm[(size_t)(k1 + j) * n + k1 + i];
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  S b = zs[lane];
+  for (int j = nb - 1; j >= 0; --j) {
+    S bj;
+    if constexpr (IsCplx<S>::value) bj = S(__shfl(b.re, j, 64), __shfl(b.im, j, 64));
+    else bj = __shfl(b, j, 64);
+    const S xj = bj * (1.0 / realx(Lr[j][j]));
+    if (lane == j) b = xj;
+    else if (lane < j) b -= conjx(Lr[j][lane]) * xj;
+  }
+  if (lane < nb) y[k1 + lane] = b;
 }
 
 // dtheta_k = (sum_s conj(O_sk) y_s - conj(m_k) sum_s y_s)/sqrt(n);
@@ -470,24 +742,35 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
   hipLaunchKernelGGL(k_proj_mean<TO>, dim3(n + 1), dim3(256), 0, st, L, tab, O, samples, n,
                      (const S*)mean, a);
   hipLaunchKernelGGL(k_estats<IsCplx<S>::value>, dim3(1), dim3(256), 0, st, eloc, n, ws, bad);
-  const int nt = (n + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gram<TO>, dim3(nt, nt), dim3(256), 0, st, L, tab, O, samples, n,
-                     (const S*)a, eps, Tm);
+  const int nt = (n + HT - 1) / HT;
+  hipLaunchKernelGGL(k_gram<TO>, dim3(tri_grid(nt)), dim3(256), 2 * L.N * sizeof(uint64_t), st,
+                     L, tab, O, samples, n, (const S*)a, eps, Tm, nt * (nt + 1) / 2);
   hipLaunchKernelGGL(k_trace<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, eps, ws);
   const int nkb = (n + CB - 1) / CB;
   for (int kb = 0; kb < nkb; ++kb) {
     hipLaunchKernelGGL(k_chol_diag<S>, dim3(1), dim3(256), 0, st, Tm, n, kb, ws);
     const int rest = n - (kb + 1) * CB;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_trsm<S>, dim3((rest + 255) / 256), dim3(256), 0, st, Tm, n, kb);
-      const int nr = (rest + GT - 1) / GT;
-      hipLaunchKernelGGL(k_chol_syrk<S>, dim3(nr, nr), dim3(256), 0, st, Tm, n, kb);
+      hipLaunchKernelGGL(k_chol_trsm<S>, dim3((rest + 256 / trsm_lanes<S>() - 1) / (256 / trsm_lanes<S>())),
+                         dim3(256), 0, st, Tm, n, kb);
+      const int nr = (rest + HT - 1) / HT;
+      hipLaunchKernelGGL(k_chol_syrk<S>, dim3(tri_grid(nr)), dim3(256), 0, st, Tm, n, kb,
+                         nr * (nr + 1) / 2);
     }
   }
   hipLaunchKernelGGL(k_certify, dim3(1), dim3(64), 0, st, n, eps, rcond, ws, (const int*)bad,
                      diag);
-  hipLaunchKernelGGL(k_chol_solve<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, eloc,
+  hipLaunchKernelGGL(k_ebar<S>, dim3((n + 255) / 256), dim3(256), 0, st, eloc, n,
                      (const double*)ws, y);
+  hipLaunchKernelGGL(k_trsv_fwd<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, -1, 0, y);
+  for (int kb = 0; kb + 1 < nkb; ++kb)
+    hipLaunchKernelGGL(k_trsv_fwd<S>, dim3(nkb - 1 - kb), dim3(256), 0, st, (const S*)Tm, n, kb,
+                       kb + 1, y);
+  hipLaunchKernelGGL(k_trsv_bwd<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, nkb, nkb - 1,
+                     nkb, y);
+  for (int kb = nkb - 1; kb >= 1; --kb)
+    hipLaunchKernelGGL(k_trsv_bwd<S>, dim3(kb), dim3(256), 0, st, (const S*)Tm, n, kb, kb - 1,
+                       nkb, y);
   hipLaunchKernelGGL(k_sum_y<S>, dim3(1), dim3(256), 0, st, (const S*)y, n, sy);
   hipLaunchKernelGGL(k_dtheta<TO>, dim3(cb), dim3(256), 0, st, L, tab, O, samples, n,
                      (const S*)y, (const S*)mean, (const S*)sy, (const double*)ws, dtheta);
