@@ -271,32 +271,51 @@ peps_status peps_evaluate(peps_ctx* ctx, const double* theta, const uint8_t* sam
  *   T = Obar Obar^T (n x n, FP64),
  *   dtheta = Obar^T (T + eps I)^+ ebar,
  * where eigenvalues of T + eps I at or below rcond * (largest) are dropped
- * from the pseudo-inverse. The solve is a Cholesky factorisation of
- * T + eps I, which equals the pseudo-inverse whenever no eigenvalue is
- * dropped; that holds when trace(T) + eps <= eps / rcond, which is checked on
- * the device. If the check fails diag[3] is set to 1 and dtheta is filled
- * with NaN. Real modes use the real part of eloc and give dtheta FP64
- * [N_p]. Complex modes use the Hermitian forms T = Obar Obar^H,
+ * from the pseudo-inverse. The solver is chosen by peps_set_minsr_solver:
+ *   PEPS_MINSR_CHOLESKY (default): a Cholesky factorisation of T + eps I,
+ *     which equals the pseudo-inverse whenever no eigenvalue is dropped;
+ *     that holds when trace(T) + eps <= eps / rcond, which is checked on
+ *     the device. If the check fails diag[3] is set to 1 and dtheta is
+ *     filled with NaN.
+ *   PEPS_MINSR_EIGH: the eigendecomposition of T + eps I (the paper's
+ *     solve): Householder tridiagonalisation, bisection, inverse iteration;
+ *     n <= 3072 (PEPS_ERR_UNSUPPORTED above).
+ *   PEPS_MINSR_AUTO: Cholesky, and the eigendecomposition when the
+ *     certificate fails (n <= 3072; above that as CHOLESKY). Its kernels are
+ *     queued every call and return at once when the certificate holds (a
+ *     few microseconds each, three per sample row).
+ * Real modes use the real part of eloc and give dtheta FP64 [N_p]. Complex
+ * modes use the Hermitian forms T = Obar Obar^H,
  * dtheta = Obar^H (T + eps I)^+ ebar with complex ebar, and give dtheta as
  * interleaved FP64 pairs [N_p][2]. dtheta is the direction of Eq. tdvp:
- * theta moves as theta - tau * dtheta.
+ * theta moves as theta - tau * dtheta. A non-finite local energy is
+ * reported on the device (diag[3] = 2, dtheta NaN); the call does not
+ * synchronise.
  * diag (device, FP64 [8]): [0] trace(T)+eps (bound on the largest
- * eigenvalue), [1] eps, [2] number of dropped eigenvalues (0), [3] 1 if the
- * certificate failed, [4] Re <E>, [5] mean |E - <E>|^2 (real modes: of
- * Re E), [6] n, [7] smallest Cholesky pivot. */
+ * eigenvalue), [1] eps, [2] number of dropped eigenvalues (0 unless the
+ * eigendecomposition ran), [3] 1 if no valid step was formed (certificate
+ * failed with no eigendecomposition), 2 for a non-finite local energy, 0
+ * otherwise, [4] Re <E>, [5] mean |E - <E>|^2 (real modes: of Re E), [6] n,
+ * [7] smallest Cholesky pivot (1e300 when no factorisation ran). */
 peps_status minsr_step(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
                        const double* eloc, double eps, double rcond, double* dtheta,
                        double* diag, void* stream);
 
+/* Solver of minsr_step (and of the step inside peps_vmc_step); the
+ * eigendecomposition allocates n^2 FP64 of workspace on first use. */
+#define PEPS_MINSR_CHOLESKY 0
+#define PEPS_MINSR_EIGH 1
+#define PEPS_MINSR_AUTO 2
+peps_status peps_set_minsr_solver(peps_ctx* ctx, int solver);
+
 /* minsr_step for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation):
- * the same kernels and results as minsr_step, with the workspace (column
+ * the same kernels and results as minsr_step with the Cholesky solver
+ * (PEPS_ERR_UNSUPPORTED when another solver is set), with the workspace (column
  * means [N_p], T [n][n], solve vectors) in a fixed device array of 48 MiB
  * that the library holds on every GPU it runs on until the process ends.
  * Calls no allocator and does not synchronise; the inputs, outputs and
- * errors are those of minsr_step, except that a non-finite local energy is
- * reported on the device (diag[3] = 2, dtheta NaN) instead of by a return
- * code. PEPS_ERR_UNSUPPORTED when the workspace,
+ * errors are those of minsr_step. PEPS_ERR_UNSUPPORTED when the workspace,
  * N_p * e + n * n * e + (2n + 2) * e + 144 bytes with e = 8 (real) or 16
  * (complex) each rounded up to 256, exceeds 48 MiB (e.g. n = 1024 with
  * complex parameters needs 16 MiB plus 16 N_p bytes). Every call on one GPU

@@ -23,6 +23,7 @@ COMPLEX = ("c128", "c64")
 FLAG_ZERO, FLAG_NONFINITE, FLAG_NOCONV, FLAG_DEGENERATE = 1, 2, 4, 8
 SAMPLE_EXCHANGE, SAMPLE_FLIP, SAMPLE_IMH = 0, 1, 2
 COMPRESS = {"canonical": 0, "densmat": 1}
+MINSR_SOLVER = {"cholesky": 0, "eigh": 1, "auto": 2}
 
 # every symbol the header declares
 EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
@@ -32,6 +33,7 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "made_num_params", "made_loss_grad", "made_adam_step", "made_sample", "made_logq",
            "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
            "peps_set_truncation", "peps_direct_sample", "peps_set_compression",
+           "peps_set_minsr_solver",
            "minsr_step_noalloc", "made_train", "peps_tau_int"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
@@ -85,6 +87,8 @@ def load():
     lib.peps_set_truncation.restype = I
     lib.peps_set_compression.argtypes = [P, I]
     lib.peps_set_compression.restype = I
+    lib.peps_set_minsr_solver.argtypes = [P, I]
+    lib.peps_set_minsr_solver.restype = I
     lib.peps_direct_sample.argtypes = [P, P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P, P, P,
                                        P, P]
     lib.peps_direct_sample.restype = I
@@ -272,6 +276,13 @@ class Context:
         cores)."""
         _check(load().peps_set_compression(self._h, COMPRESS[method]))
         self.compression = method
+
+    def set_minsr_solver(self, solver):
+        """Solver of minsr_step: "cholesky" (certified, NaN when the
+        certificate fails), "eigh" (eigendecomposition, n <= 3072) or
+        "auto" (Cholesky, eigendecomposition after a failed certificate)."""
+        _check(load().peps_set_minsr_solver(self._h, MINSR_SOLVER[solver]))
+        self.minsr_solver = solver
 
     def local_energy_strict(self, theta, samples, flags=None):
         """E_loc with every amplitude from the full contraction at the one

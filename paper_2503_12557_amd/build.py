@@ -13,7 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpepsmin.so")
-SOURCES = ["env.hip", "env_dm.hip", "strip.hip", "minsr.hip", "sample.hip", "made.hip", "direct.hip",
+SOURCES = ["env.hip", "env_dm.hip", "strip.hip", "minsr.hip", "eigh.hip", "sample.hip", "made.hip",
+           "direct.hip",
            "api.hip"]
 ARCH = "gfx950"
 

@@ -134,6 +134,10 @@ struct peps_ctx {
   int compress = 0;
   bool dm_ok = false;
   DevBuf gws_dm;
+  // minSR solve: certified Cholesky, eigendecomposition, or Cholesky with the
+  // eigendecomposition after a failed certificate; its workspace
+  int minsr_solver = PEPS_MINSR_CHOLESKY;
+  DevBuf eig_ws;
   // independence MH chains: states, proposals, their ln Psi and ln q
   DevBuf imh_st, imh_pr, imh_stlp, imh_stlq, imh_prlp, imh_prlq;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
@@ -917,6 +921,14 @@ peps_status peps_set_compression(peps_ctx* c, int method) {
   return PEPS_OK;
 }
 
+peps_status peps_set_minsr_solver(peps_ctx* c, int solver) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (solver != PEPS_MINSR_CHOLESKY && solver != PEPS_MINSR_EIGH && solver != PEPS_MINSR_AUTO)
+    return fail(PEPS_ERR_ARG, "unknown minSR solver %d", solver);
+  c->minsr_solver = solver;
+  return PEPS_OK;
+}
+
 peps_status peps_local_energy_strict(peps_ctx* c, const double* theta, const uint8_t* samples,
                                      int n, double* eloc, int32_t* flags, void* stream) {
   peps_status s = check_common(c, theta, samples, n);
@@ -994,18 +1006,19 @@ peps_status minsr_step(peps_ctx* c, const void* O, const uint8_t* samples, int n
   if (s != PEPS_OK) return s;
   s = c->vec.ensure(b_vec);
   if (s != PEPS_OK) return s;
-  // reject non-finite E before any work
-  {
-    std::vector<double> h(2 * (size_t)n);
-    HIPCHK(hipMemcpyAsync(h.data(), eloc, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
-                          st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (double v : h)
-      if (!std::isfinite(v)) return fail(PEPS_ERR_NONFINITE, "eloc contains non-finite values");
+  const int solver = c->minsr_solver;
+  if (solver == PEPS_MINSR_EIGH && n > MINSR_EIG_MAX)
+    return fail(PEPS_ERR_UNSUPPORTED, "the eigendecomposition solve takes n <= %d (got %d)",
+                MINSR_EIG_MAX, n);
+  void* eig = nullptr;
+  if (solver != PEPS_MINSR_CHOLESKY && n <= MINSR_EIG_MAX) {
+    s = c->eig_ws.ensure(eigh_ws_bytes(n, is_complex(c->g.dtype)));
+    if (s != PEPS_OK) return s;
+    eig = c->eig_ws.p;
   }
   ProfScope ps(c, st, PEPS_PROF_MINSR);
   HIPCHK(launch_minsr(L, c->d_tab, mode, O, samples, n, eloc, eps, rcond, dtheta, diag,
-                      c->mean.p, c->Tm.p, c->vec.p, st));
+                      c->mean.p, c->Tm.p, c->vec.p, solver, eig, st));
   return PEPS_OK;
 }
 
@@ -1017,6 +1030,10 @@ peps_status minsr_step_noalloc(peps_ctx* c, const void* O, const uint8_t* sample
   if (!O || !samples || !eloc || !dtheta || !diag) return fail(PEPS_ERR_ARG, "null pointer");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(PEPS_ERR_ARG, "eps must be finite and >= 0");
   if (!(rcond >= 0.0 && rcond < 1.0)) return fail(PEPS_ERR_ARG, "rcond must be in [0, 1)");
+  if (c->minsr_solver != PEPS_MINSR_CHOLESKY)
+    return fail(PEPS_ERR_UNSUPPORTED,
+                "minsr_step_noalloc runs the certified Cholesky solve only (solver %d set)",
+                c->minsr_solver);
   const Lattice& L = c->L;
   const int mode = c->g.dtype == PEPS_BF16 ? MODE_F32 : c->g.dtype;
   size_t b_mean, b_T, b_vec;
@@ -1034,7 +1051,7 @@ peps_status minsr_step_noalloc(peps_ctx* c, const void* O, const uint8_t* sample
   char* b = (char*)base;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(launch_minsr(L, c->d_tab, mode, O, samples, n, eloc, eps, rcond, dtheta, diag, b,
-                      b + up(b_mean), b + up(b_mean) + up(b_T), st));
+                      b + up(b_mean), b + up(b_mean) + up(b_T), PEPS_MINSR_CHOLESKY, nullptr, st));
   return PEPS_OK;
 }
 

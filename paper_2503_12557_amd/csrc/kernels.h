@@ -152,11 +152,22 @@ hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
 // minSR
 // mode: MODE_F64 / MODE_F32 (FP64 solve of real parameters) or MODE_C128 /
 // MODE_C64 (complex FP64 solve); workspaces sized by minsr_ws_bytes.
+// solver: certified Cholesky, eigendecomposition, or Cholesky with the
+// eigendecomposition after a failed certificate (n <= MINSR_EIG_MAX for the
+// latter two; eig_ws of eigh_ws_bytes(n, complex) bytes, else unused).
+#define MINSR_CHOLESKY 0
+#define MINSR_EIGH 1
+#define MINSR_AUTO 2
+#define MINSR_EIG_MAX 3072
 void minsr_ws_bytes(const Lattice& L, int mode, int n, size_t* mean, size_t* T, size_t* vec);
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,
                         double rcond, double* dtheta, double* diag, void* ws_mean, void* ws_T,
-                        void* ws_vec, hipStream_t st);
+                        void* ws_vec, int solver, void* eig_ws, hipStream_t st);
+// eigendecomposition solve of T y = ebar in place of y (runs when *on)
+size_t eigh_ws_bytes(int n, bool cplx);
+hipError_t launch_eigh_solve(bool cplx, void* Tm, int n, double rcond, const int* on, double* ws,
+                             double* diag, void* y, void* eig_ws, hipStream_t st);
 // theta[i] -= tau * dtheta[i] for i < m, skipped when diag[3] (failed
 // pseudo-inverse certificate) is set
 hipError_t launch_theta_update(double* theta, const double* dtheta, const double* diag,

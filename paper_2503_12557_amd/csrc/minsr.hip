@@ -238,10 +238,12 @@ template <typename TO>
 __global__ void __launch_bounds__(256)
 k_gram(Lattice L, const int* __restrict__ tab, const TO* __restrict__ O,
        const uint8_t* __restrict__ samples, int n, const typename SolveT<TO>::type* __restrict__ a,
-       double eps, typename SolveT<TO>::type* __restrict__ Tm, int ntiles) {
+       double eps, typename SolveT<TO>::type* __restrict__ Tm, int ntiles,
+       const int* __restrict__ run_if) {
   typedef typename SolveT<TO>::type S;
   constexpr bool CX = IsCplx<TO>::value;
   constexpr int NP = CX ? 3 : 1, NE = HT * HKC / 256;
+  if (run_if && !*run_if) return;
   __shared__ GStage<CX> sh;
   extern __shared__ unsigned long long bits[];  // [site][A rows, B rows]
   int bi, bj;
@@ -535,7 +537,8 @@ __global__ void __launch_bounds__(256) k_chol_syrk(S* __restrict__ A, int n, int
 // ebar = (E - <E>)/sqrt(n) (Re E for real parameters) into y
 template <typename S>
 __global__ void k_ebar(const double* __restrict__ eloc, int n, const double* __restrict__ ws,
-                       S* __restrict__ y) {
+                       S* __restrict__ y, const int* __restrict__ run_if) {
+  if (run_if && !*run_if) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double isn = 1.0 / sqrt((double)n);
@@ -692,9 +695,13 @@ __global__ void k_sum_y(const S* __restrict__ y, int n, S* __restrict__ out) {
 }
 
 // certificate: no eigenvalue of T + eps I is dropped if trace(T) + eps <= eps / rcond
-// (a non-finite local energy, flagged by k_estats, fails it too: diag[3] = 2)
+// (a non-finite local energy, flagged by k_estats, fails it too: diag[3] = 2).
+// on = 1 runs the eigendecomposition solve: always with the eigh solver,
+// after a failed certificate with the automatic one (never for a
+// non-finite energy).
 __global__ void k_certify(int n, double eps, double rcond, double* __restrict__ ws,
-                          const int* __restrict__ bad, double* __restrict__ diag) {
+                          const int* __restrict__ bad, double* __restrict__ diag, int solver,
+                          int* __restrict__ on) {
   if (threadIdx.x != 0) return;
   const double bound = ws[2] + eps;
   const bool ok = (eps > 0.0) && (bound * rcond <= eps);
@@ -709,6 +716,7 @@ __global__ void k_certify(int n, double eps, double rcond, double* __restrict__ 
   diag[5] = ws[1];
   diag[6] = (double)n;
   diag[7] = ws[5];
+  *on = (*bad == 0) && (solver == MINSR_EIGH || (solver == MINSR_AUTO && ws[6] != 0.0));
 }
 
 // fresh state of a call: a kernel rather than a memset, so the whole step
@@ -718,24 +726,26 @@ __global__ void k_init_ws(double* ws, int* bad) {
     ws[4] = 0.0;
     ws[5] = 1e300;
     ws[6] = 0.0;
-    *bad = 0;
+    bad[0] = 0;
+    bad[1] = 0;
   }
 }
 
 template <typename TO>
 static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, const uint8_t* samples,
                              int n, const double* eloc, double eps, double rcond, double* dtheta,
-                             double* diag, void* mean_v, void* Tm_v, void* vec_v,
-                             hipStream_t st) {
+                             double* diag, void* mean_v, void* Tm_v, void* vec_v, int solver,
+                             void* eig_ws, hipStream_t st) {
   typedef typename SolveT<TO>::type S;
   S* mean = (S*)mean_v;
   S* Tm = (S*)Tm_v;
-  // vec layout: a[n+1] | y[n] | sum y | ws[16] (FP64) | bad (int)
+  // vec layout: a[n+1] | y[n] | sum y | ws[16] (FP64) | bad, on (int)
   S* a = (S*)vec_v;
   S* y = a + n + 1;
   S* sy = y + n;
   double* ws = (double*)(sy + 1);
   int* bad = (int*)(ws + 16);
+  int* on = bad + 1;
   hipLaunchKernelGGL(k_init_ws, dim3(1), dim3(64), 0, st, ws, bad);
   const int cb = (L.n_compact + 255) / 256;
   hipLaunchKernelGGL(k_colmean<TO>, dim3(cb), dim3(256), 0, st, L, tab, O, samples, n, mean);
@@ -744,33 +754,52 @@ static hipError_t minsr_impl(const Lattice& L, const int* tab, const TO* O, cons
   hipLaunchKernelGGL(k_estats<IsCplx<S>::value>, dim3(1), dim3(256), 0, st, eloc, n, ws, bad);
   const int nt = (n + HT - 1) / HT;
   hipLaunchKernelGGL(k_gram<TO>, dim3(tri_grid(nt)), dim3(256), 2 * L.N * sizeof(uint64_t), st,
-                     L, tab, O, samples, n, (const S*)a, eps, Tm, nt * (nt + 1) / 2);
+                     L, tab, O, samples, n, (const S*)a, eps, Tm, nt * (nt + 1) / 2,
+                     (const int*)nullptr);
   hipLaunchKernelGGL(k_trace<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, eps, ws);
   const int nkb = (n + CB - 1) / CB;
-  for (int kb = 0; kb < nkb; ++kb) {
-    hipLaunchKernelGGL(k_chol_diag<S>, dim3(1), dim3(256), 0, st, Tm, n, kb, ws);
-    const int rest = n - (kb + 1) * CB;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_trsm<S>, dim3((rest + 256 / trsm_lanes<S>() - 1) / (256 / trsm_lanes<S>())),
-                         dim3(256), 0, st, Tm, n, kb);
-      const int nr = (rest + HT - 1) / HT;
-      hipLaunchKernelGGL(k_chol_syrk<S>, dim3(tri_grid(nr)), dim3(256), 0, st, Tm, n, kb,
-                         nr * (nr + 1) / 2);
+  if (solver != MINSR_EIGH) {
+    for (int kb = 0; kb < nkb; ++kb) {
+      hipLaunchKernelGGL(k_chol_diag<S>, dim3(1), dim3(256), 0, st, Tm, n, kb, ws);
+      const int rest = n - (kb + 1) * CB;
+      if (rest > 0) {
+        hipLaunchKernelGGL(k_chol_trsm<S>,
+                           dim3((rest + 256 / trsm_lanes<S>() - 1) / (256 / trsm_lanes<S>())),
+                           dim3(256), 0, st, Tm, n, kb);
+        const int nr = (rest + HT - 1) / HT;
+        hipLaunchKernelGGL(k_chol_syrk<S>, dim3(tri_grid(nr)), dim3(256), 0, st, Tm, n, kb,
+                           nr * (nr + 1) / 2);
+      }
     }
   }
   hipLaunchKernelGGL(k_certify, dim3(1), dim3(64), 0, st, n, eps, rcond, ws, (const int*)bad,
-                     diag);
+                     diag, solver, on);
   hipLaunchKernelGGL(k_ebar<S>, dim3((n + 255) / 256), dim3(256), 0, st, eloc, n,
-                     (const double*)ws, y);
-  hipLaunchKernelGGL(k_trsv_fwd<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, -1, 0, y);
-  for (int kb = 0; kb + 1 < nkb; ++kb)
-    hipLaunchKernelGGL(k_trsv_fwd<S>, dim3(nkb - 1 - kb), dim3(256), 0, st, (const S*)Tm, n, kb,
-                       kb + 1, y);
-  hipLaunchKernelGGL(k_trsv_bwd<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, nkb, nkb - 1,
-                     nkb, y);
-  for (int kb = nkb - 1; kb >= 1; --kb)
-    hipLaunchKernelGGL(k_trsv_bwd<S>, dim3(kb), dim3(256), 0, st, (const S*)Tm, n, kb, kb - 1,
+                     (const double*)ws, y, (const int*)nullptr);
+  if (solver != MINSR_EIGH) {
+    hipLaunchKernelGGL(k_trsv_fwd<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, -1, 0, y);
+    for (int kb = 0; kb + 1 < nkb; ++kb)
+      hipLaunchKernelGGL(k_trsv_fwd<S>, dim3(nkb - 1 - kb), dim3(256), 0, st, (const S*)Tm, n,
+                         kb, kb + 1, y);
+    hipLaunchKernelGGL(k_trsv_bwd<S>, dim3(1), dim3(256), 0, st, (const S*)Tm, n, nkb, nkb - 1,
                        nkb, y);
+    for (int kb = nkb - 1; kb >= 1; --kb)
+      hipLaunchKernelGGL(k_trsv_bwd<S>, dim3(kb), dim3(256), 0, st, (const S*)Tm, n, kb, kb - 1,
+                         nkb, y);
+  }
+  if (solver != MINSR_CHOLESKY && n <= MINSR_EIG_MAX) {
+    if (solver == MINSR_AUTO) {
+      // the factorisation overwrote T and y: form both again if the path runs
+      hipLaunchKernelGGL(k_gram<TO>, dim3(tri_grid(nt)), dim3(256), 2 * L.N * sizeof(uint64_t),
+                         st, L, tab, O, samples, n, (const S*)a, eps, Tm, nt * (nt + 1) / 2,
+                         (const int*)on);
+      hipLaunchKernelGGL(k_ebar<S>, dim3((n + 255) / 256), dim3(256), 0, st, eloc, n,
+                         (const double*)ws, y, (const int*)on);
+    }
+    const hipError_t e = launch_eigh_solve(IsCplx<S>::value, Tm, n, rcond, on, ws, diag, y,
+                                           eig_ws, st);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_sum_y<S>, dim3(1), dim3(256), 0, st, (const S*)y, n, sy);
   hipLaunchKernelGGL(k_dtheta<TO>, dim3(cb), dim3(256), 0, st, L, tab, O, samples, n,
                      (const S*)y, (const S*)mean, (const S*)sy, (const double*)ws, dtheta);
@@ -841,20 +870,20 @@ hipError_t launch_theta_update(double* theta, const double* dtheta, const double
 hipError_t launch_minsr(const Lattice& L, const int* tab, int mode, const void* O,
                         const uint8_t* samples, int n, const double* eloc, double eps,
                         double rcond, double* dtheta, double* diag, void* ws_mean, void* ws_T,
-                        void* ws_vec, hipStream_t st) {
+                        void* ws_vec, int solver, void* eig_ws, hipStream_t st) {
   switch (mode) {
     case MODE_F64:
       return minsr_impl<double>(L, tab, (const double*)O, samples, n, eloc, eps, rcond, dtheta,
-                                diag, ws_mean, ws_T, ws_vec, st);
+                                diag, ws_mean, ws_T, ws_vec, solver, eig_ws, st);
     case MODE_C128:
       return minsr_impl<cplx<double>>(L, tab, (const cplx<double>*)O, samples, n, eloc, eps,
-                                      rcond, dtheta, diag, ws_mean, ws_T, ws_vec, st);
+                                      rcond, dtheta, diag, ws_mean, ws_T, ws_vec, solver, eig_ws, st);
     case MODE_C64:
       return minsr_impl<cplx<float>>(L, tab, (const cplx<float>*)O, samples, n, eloc, eps, rcond,
-                                     dtheta, diag, ws_mean, ws_T, ws_vec, st);
+                                     dtheta, diag, ws_mean, ws_T, ws_vec, solver, eig_ws, st);
     default:
       return minsr_impl<float>(L, tab, (const float*)O, samples, n, eloc, eps, rcond, dtheta,
-                               diag, ws_mean, ws_T, ws_vec, st);
+                               diag, ws_mean, ws_T, ws_vec, solver, eig_ws, st);
   }
 }
 

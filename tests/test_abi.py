@@ -55,6 +55,7 @@ def test_null_context_is_rejected():
 def test_null_arguments_of_the_newer_entry_points():
     binding, lib = _lib()
     assert lib.peps_set_compression(None, 1) == 1
+    assert lib.peps_set_minsr_solver(None, 1) == 1
     assert lib.minsr_step_noalloc(None, None, None, 4, None, 1e-4, 1e-12, None, None, None) == 1
     assert lib.peps_sample(None, None, 2, 4, 1, 0, 1, 0, 0, None, None, None, None, None) == 1
     assert lib.made_train(None, None, None, 8, 1, 4, 0, 1e-3, 0.9, 0.999, 1e-8, 0, None, None,
