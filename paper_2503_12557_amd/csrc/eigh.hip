@@ -177,8 +177,13 @@ __device__ __forceinline__ double start_entry(int j, int k) {
 }
 
 // 3. eigenvectors of the kept eigenvalues: one wave per cluster (a run of
-// kept eigenvalues with neighbouring gaps <= 1e-3 |Tri|), started by the
-// wave of its first member. Each member: inverse iteration (Tri - s I) x = b
+// kept eigenvalues with neighbouring gaps <= 1e-6 |Tri|), started by the
+// wave of its first member. Inverse iteration leaves in the vector of an
+// eigenvalue at gap g from another about u |Tri| / g of the other's vector,
+// and in y an error of the same relative size; gaps above 1e-6 |Tri| keep
+// that near 1e-10 without orthogonalisation, while (near-)degenerate
+// eigenvalues, such as the eps-shifted null space of a rank-deficient Gram,
+// are orthogonalised. Each member: inverse iteration (Tri - s I) x = b
 // with a partial-pivot LU formed row by row on lane 0 (U bands and d, e in
 // LDS), the iterate orthogonalised against the cluster's earlier vectors
 // and normalised; shifts of equal eigenvalues are separated by a few ulps
@@ -201,7 +206,7 @@ __global__ void __launch_bounds__(64) k_tri_vec(const double* __restrict__ dg,
   const double lmax = lam[n - 1];
   const double thr = rcond * lmax;
   const double tnorm = fmax(fabs(lam[0]), fabs(lmax));
-  const double gtol = 1e-3 * tnorm;
+  const double gtol = 1e-6 * tnorm;
   if (!(lam[i] > thr)) return;
   if (i > 0 && lam[i - 1] > thr && lam[i] - lam[i - 1] <= gtol) return;  // not the first member
   int last = i;
