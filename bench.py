@@ -77,6 +77,13 @@ def env_bonds(Lx, Ly, D, chi):
     return out
 
 
+# flops of the canonical (QR -> SVD) environment build of one 10x10 D=5
+# chi=25 complex sample, both sweeps, complex products counted as four real
+# ones: products 7.4 GF, Householder QR 5.3 GF, SVD with right vectors
+# 12.2 GF (shape-tracked per site)
+CANONICAL_ENV_FLOPS_10x10_D5_CHI25 = 24.9e9
+
+
 def dm_env_flops_per_sample(Lx, Ly, D, chi, cplx):
     """Algorithmic flops of the density-matrix environment build per sample
     (both directions), split into matrix-core work (the Gram, density and
@@ -519,12 +526,17 @@ def main():
     env_launch_samples = B / (per_kernel["env"]["launches"] / steps_done)
     s2_batch = torch.cat([chunks[k % len(chunks)] for k in range(steps_done)]).cpu().numpy()
     s2_flops_total = strip2_flops(Lx, Ly, D, chi, s2_batch, True)
+    env_s = per_kernel["env"]["ms_avg"] * 1e-3
     rooflines = {
         "env": {"kernel": "k_env_dm", "bound": "mfma",
-                "achieved": mm_s * env_launch_samples / (per_kernel["env"]["ms_avg"] * 1e-3) / 1e12,
+                "achieved": CANONICAL_ENV_FLOPS_10x10_D5_CHI25 * env_launch_samples / env_s / 1e12,
                 "peak": PEAK["fp32_matrix_tflops"], "unit": "TFLOP/s",
-                "algorithmic_mfma_flops_per_sample": mm_s,
-                "algorithmic_alu_flops_per_sample": alu_s,
+                "algorithmic_flops_per_sample": CANONICAL_ENV_FLOPS_10x10_D5_CHI25,
+                "algorithmic_flops_model": "canonical QR -> SVD environment build (GEMM 7.4 + "
+                                           "Householder QR 5.3 + SVD 12.2 GF per sample)",
+                "achieved_density_matrix_mfma_flops": mm_s * env_launch_samples / env_s / 1e12,
+                "density_matrix_mfma_flops_per_sample": mm_s,
+                "density_matrix_alu_flops_per_sample": alu_s,
                 "samples_per_launch": env_launch_samples,
                 "avg_launch_ms": per_kernel["env"]["ms_avg"]},
     }
@@ -539,6 +551,8 @@ def main():
             "avg_launch_ms": s2["ms_avg"]}
     for r in rooflines.values():
         r["achieved"] = round(r["achieved"], 3)
+        if "achieved_density_matrix_mfma_flops" in r:
+            r["achieved_density_matrix_mfma_flops"] = round(r["achieved_density_matrix_mfma_flops"], 3)
         r["frac"] = round(r["achieved"] / r["peak"], 5)
     for key, r in rooflines.items():
         r["traffic"] = kernel_traffic(key, r["samples_per_launch"])
@@ -601,6 +615,21 @@ def main():
     _log(f"minSR n={nconf}: {res['minsr_step_ms']} ms")
     res["minsr_n"] = nconf
     res["minsr_diag"] = [float(v) for v in diag.cpu().numpy()]
+    # the eigendecomposition solve (alone, and queued behind a certificate
+    # that holds) on the first 1024 configurations
+    ne = 1024
+    tims = {}
+    for solver in ("cholesky", "auto", "eigh"):
+        ctx.set_minsr_solver(solver)
+        ctx.minsr_step(O[:ne], samples[:ne], el[:ne], eps=1e-4, rcond=1e-12)
+        _sync()
+        t0 = time.perf_counter()
+        ctx.minsr_step(O[:ne], samples[:ne], el[:ne], eps=1e-4, rcond=1e-12)
+        _sync()
+        tims[solver] = round((time.perf_counter() - t0) * 1e3, 2)
+    ctx.set_minsr_solver("cholesky")
+    res["minsr_solvers_ms_n1024"] = tims
+    _log(f"minSR solvers at n={ne}: {tims}")
     del dth, O, full, out128
     torch.cuda.empty_cache()
 

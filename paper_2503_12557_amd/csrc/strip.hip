@@ -34,6 +34,9 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
          typename ModeT<M>::T* __restrict__ Oout, int* __restrict__ flags, int n, int want_e,
          int want_o, typename ModeT<M>::T* __restrict__ gws, size_t slab) {
   typedef typename ModeT<M>::T T;
+  // matrix-core steps for the global-slab shapes (not BF16, whose operands
+  // are rounded per product)
+  constexpr bool MMP = GM && M != MODE_BF16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int smp = blockIdx.x, x = blockIdx.y;
@@ -86,8 +89,12 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     legs_of(tab, L, ns, Dl, Dr, Du, Dd);
     const T* A = tensor_of(theta, tab, L, ns, pbit(s[ns]));
     T* Ry = Rt + (size_t)y * box;
-    s1_step_right<M>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
-                     dnT(y), ba_(y), bb_(y), X1, X2, Ry);
+    if constexpr (MMP)
+      s1_step_right_mm(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
+                       dnT(y), ba_(y), bb_(y), X1, X2, Ry);
+    else
+      s1_step_right<M>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
+                       dnT(y), ba_(y), bb_(y), X1, X2, Ry);
     const int cnt = ua_(y) * Dl * ba_(y);
     const int e = pow2_exponent((double)block_absmax(Ry, 1, cnt, cnt, red));
     scale_pow2(Ry, cnt, e);
@@ -125,27 +132,31 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     const T* Rn = Rt + (size_t)(y + 1) * box;
     const int nA = Dl * Dr * Du * Dd;
     if (want_o) {
-      // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
-      gemm<M>(Dl * ba, Du * ub, ua, Lf, 1, Dl * ba, U, Du * ub, 1, X1, Du * ub, 1, false);
-      // Q[(b,r),(c,d)] = sum_e R[(b,r),e] B[(c,d),e]
-      gemm<M>(ub * Dr, ba * Dd, bb, Rn, bb, 1, Bt, 1, bb, X2, ba * Dd, 1, false);
-      __syncthreads();
-      // Env[m,r,u,d] = sum_{c,b} X1[m,c,u,b] Q[b,r,c,d]
-      const FastDiv fDd(Dd), fDu(Du), fDr(Dr);
-      for (int i = tid; i < nA; i += PEPS_NT) {
-        int t = i;
-        const int d = divmod(t, fDd);
-        const int u = divmod(t, fDu);
-        const int r = divmod(t, fDr);
-        const int m = t;
-        T acc = 0;
-        for (int c = 0; c < ba; ++c)
-          for (int b = 0; b < ub; ++b)
-            acc += opnd<M>(X1[((m * ba + c) * Du + u) * ub + b]) *
-                   opnd<M>(X2[((b * Dr + r) * ba + c) * Dd + d]);
-        Env[i] = acc;
+      if constexpr (MMP) {
+        s1_hole_mm(Lf, U, ua, ub, Dl, Dr, Du, Dd, Rn, Bt, ba, bb, X1, X2, Env);
+      } else {
+        // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
+        gemm<M>(Dl * ba, Du * ub, ua, Lf, 1, Dl * ba, U, Du * ub, 1, X1, Du * ub, 1, false);
+        // Q[(b,r),(c,d)] = sum_e R[(b,r),e] B[(c,d),e]
+        gemm<M>(ub * Dr, ba * Dd, bb, Rn, bb, 1, Bt, 1, bb, X2, ba * Dd, 1, false);
+        __syncthreads();
+        // Env[m,r,u,d] = sum_{c,b} X1[m,c,u,b] Q[b,r,c,d]
+        const FastDiv fDd(Dd), fDu(Du), fDr(Dr);
+        for (int i = tid; i < nA; i += PEPS_NT) {
+          int t = i;
+          const int d = divmod(t, fDd);
+          const int u = divmod(t, fDu);
+          const int r = divmod(t, fDr);
+          const int m = t;
+          T acc = 0;
+          for (int c = 0; c < ba; ++c)
+            for (int b = 0; b < ub; ++b)
+              acc += opnd<M>(X1[((m * ba + c) * Du + u) * ub + b]) *
+                     opnd<M>(X2[((b * Dr + r) * ba + c) * Dd + d]);
+          Env[i] = acc;
+        }
+        __syncthreads();
       }
-      __syncthreads();
       const T psi_loc = lds_dot(Env, A, nA, red);
       T* o = Oout + (size_t)smp * L.n_compact + tab[L.off_compact + ns];
       const T inv = recipx(psi_loc);
@@ -166,8 +177,12 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
             int dl, dr, du, dd;
             legs_of(tab, L, n2, dl, dr, du, dd);
             const int p = in_move(mv, n2) ? 1 - pbit(s[n2]) : pbit(s[n2]);
-            s1_step_left<M>(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p), dl,
-                            dr, du, dd, dnT(yy), ba_(yy), bb_(yy), X1, X2, nxt);
+            if constexpr (MMP)
+              s1_step_left_mm(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p),
+                              dl, dr, du, dd, dnT(yy), ba_(yy), bb_(yy), X1, X2, nxt);
+            else
+              s1_step_left<M>(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p),
+                              dl, dr, du, dd, dnT(yy), ba_(yy), bb_(yy), X1, X2, nxt);
             scale_pow2(nxt, ub_(yy) * dr * bb_(yy), dex[yy]);
             __syncthreads();
             cur = nxt;
@@ -185,7 +200,10 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
       }
     }
     // Lf <- step(Lf, A_y)
-    s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
+    if constexpr (MMP)
+      s1_step_left_mm(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
+    else
+      s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
     {
       typedef typename RealOf<T>::type R;
       const R f = (R)ldexp(1.0, -dex[y]);

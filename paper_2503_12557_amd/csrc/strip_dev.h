@@ -463,6 +463,71 @@ __device__ __forceinline__ void s2_step_right(const T* Rp, const T* U, int ua, i
 
 
 // ---------------------------------------------------------------------------
+// One-row steps on the matrix cores for the large shapes: three products
+// per step over the whole outer bond (index maps absorb the leg order), the
+// intermediates (B^2 D^2 elements each) in X1 / X2. Same contractions and
+// output layouts as s1_step_left / s1_step_right.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void s1_step_left_mm(const T* Lp, const T* U, int ua, int ub, const T* A, int Dl,
+                                int Dr, int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2,
+                                T* Lout) {
+  // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
+  mgemm_map<T, false, false>(Dl * ba, Du * ub, ua, Lp, IMap(1), IMap(Dl * ba), U, IMap(Du * ub),
+                             IMap(1), X1, IMap(Du * ub), IMap(1), false, false);
+  __syncthreads();
+  // X2[(c,b),(r,d)] = sum_{(m,u)} X1[(m,c),(u,b)] A[m,r,u,d]
+  mgemm_map<T, false, false>(ba * ub, Dr * Dd, Dl * Du, X1, IMap(ub, Du * ub, 1),
+                             IMap(Du, ba * Du * ub, ub), A, IMap(Du, Dr * Du * Dd, Dd),
+                             IMap(Dd, Du * Dd, 1), X2, IMap(Dr * Dd), IMap(1), false, false);
+  __syncthreads();
+  // L'[(b,r),e] = sum_{(c,d)} X2[(c,b),(r,d)] B[(c,d),e]
+  mgemm_map<T, false, false>(ub * Dr, bb, ba * Dd, X2, IMap(Dr, Dr * Dd, Dd),
+                             IMap(Dd, ub * Dr * Dd, 1), Bt, IMap(bb), IMap(1), Lout, IMap(bb),
+                             IMap(1), false, false);
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void s1_step_right_mm(const T* Rp, const T* U, int ua, int ub, const T* A, int Dl,
+                                 int Dr, int Du, int Dd, const T* Bt, int ba, int bb, T* X1,
+                                 T* X2, T* Rout) {
+  // X1[(a,u),(r,e)] = sum_b U[(a,u),b] R[b,(r,e)]
+  mgemm_map<T, false, false>(ua * Du, Dr * bb, ub, U, IMap(ub), IMap(1), Rp, IMap(Dr * bb),
+                             IMap(1), X1, IMap(Dr * bb), IMap(1), false, false);
+  __syncthreads();
+  // X2[(a,e),(m,d)] = sum_{(u,r)} X1[(a,u),(r,e)] A[m,r,u,d]
+  mgemm_map<T, false, false>(ua * bb, Dl * Dd, Du * Dr, X1, IMap(bb, Du * Dr * bb, 1), IMap(bb),
+                             A, IMap(Dr, Dd, Du * Dd), IMap(Dd, Dr * Du * Dd, 1), X2,
+                             IMap(Dl * Dd), IMap(1), false, false);
+  __syncthreads();
+  // R'[(a,m),c] = sum_{(d,e)} X2[(a,e),(m,d)] B[c,(d,e)]
+  mgemm_map<T, false, false>(ua * Dl, ba, Dd * bb, X2, IMap(Dl, bb * Dl * Dd, Dd),
+                             IMap(bb, 1, Dl * Dd), Bt, IMap(1), IMap(Dd * bb), Rout, IMap(ba),
+                             IMap(1), false, false);
+  __syncthreads();
+}
+
+// Hole tensor of a one-row strip site on the matrix cores:
+// Env[m,r,u,d] = sum_{(c,b)} X1[(m,c),(u,b)] Q[(b,r),(c,d)] with
+// X1 = L U and Q[(b,r),(c,d)] = sum_e R[(b,r),e] B[(c,d),e].
+template <typename T>
+__device__ void s1_hole_mm(const T* Lp, const T* U, int ua, int ub, int Dl, int Dr, int Du,
+                           int Dd, const T* Rn, const T* Bt, int ba, int bb, T* X1, T* X2,
+                           T* Env) {
+  mgemm_map<T, false, false>(Dl * ba, Du * ub, ua, Lp, IMap(1), IMap(Dl * ba), U, IMap(Du * ub),
+                             IMap(1), X1, IMap(Du * ub), IMap(1), false, false);
+  mgemm_map<T, false, false>(ub * Dr, ba * Dd, bb, Rn, IMap(bb), IMap(1), Bt, IMap(1), IMap(bb),
+                             X2, IMap(ba * Dd), IMap(1), false, false);
+  __syncthreads();
+  mgemm_map<T, false, false>(Dl * Du, Dr * Dd, ba * ub, X1, IMap(Du, ba * Du * ub, ub),
+                             IMap(ub, Du * ub, 1), X2, IMap(ub, Dd, Dr * ba * Dd),
+                             IMap(Dd, ba * Dd, 1), Env, IMap(Du, Dr * Du * Dd, Dd),
+                             IMap(Dd, Du * Dd, 1), false, false);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Two-row steps on the matrix cores for the large shapes (working sets in a
 // global slab): each step is four products over the whole outer bond, the
 // intermediates X1 and X2 (B^2 D^3 elements each) in the slab, X3 reusing
