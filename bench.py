@@ -637,6 +637,9 @@ def main():
         res["workload_8x8_D4_chi16"] = side_workload(
             Context, hamiltonians.j1j2(8, 8, 1.0, 0.5), 8, 8, 4, 16, 4096, 2, 0.0, "exchange",
             ["f32", "bf16"])
+        res["workload_8x8_D4_chi16_mu05"] = side_workload(
+            Context, hamiltonians.j1j2(8, 8, 1.0, 0.5), 8, 8, 4, 16, 4096, 3, 0.5, "exchange",
+            ["f32", "bf16"])
         res["workload_12x12_D4_chi16_rydberg"] = side_workload(
             Context, hamiltonians.rydberg(12, 12, Omega=1.0, Delta=3.0, V=1.7 ** 6), 12, 12, 4, 16,
             4096, 5, 0.0, "flip", ["f32", "bf16"])
