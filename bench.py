@@ -643,6 +643,11 @@ def main():
         res["workload_12x12_D4_chi16_rydberg"] = side_workload(
             Context, hamiltonians.rydberg(12, 12, Omega=1.0, Delta=3.0, V=1.7 ** 6), 12, 12, 4, 16,
             4096, 5, 0.0, "flip", ["f32", "bf16"])
+        # the same with the density-matrix truncation: BF16 products on the
+        # bfloat16 matrix cores
+        res["workload_12x12_D4_chi16_rydberg_densmat"] = side_workload(
+            Context, hamiltonians.rydberg(12, 12, Omega=1.0, Delta=3.0, V=1.7 ** 6), 12, 12, 4, 16,
+            4096, 5, 0.0, "flip", ["f32", "bf16"], compression="densmat")
         th2 = torch.from_numpy(synth.theta(8, 8, 2, 4, seed=2)).to(dev)
         _log("side workloads done")
         res["learned_proposal"] = ess_comparison(Context, th2, 8, 8, 4, 16,

@@ -537,10 +537,10 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
       }
       __syncthreads();
       // X = G_y P_k (G_y Hermitian: read as conj(G_y)^T, rows coalesced)
-      mgemm<T, IsCplx<T>::value, false>(Pl, Pr, Pl, Gy, 1, np, Pk, np, 1, X, np, false, false);
+      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(Pl, Pr, Pl, Gy, 1, np, Pk, np, 1, X, np, false, false);
       __syncthreads();
       // G_{y+1} (+)= P_k^H X
-      mgemm<T, IsCplx<T>::value, false>(Pr, Pr, Pl, Pk, 1, np, X, np, 1, Gn, np, true, k > 0);
+      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(Pr, Pr, Pl, Pk, 1, np, X, np, 1, Gn, np, true, k > 0);
       __syncthreads();
     }
     // unit scale: the Gram only fixes directions
@@ -575,7 +575,7 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     __syncthreads();
     // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]
     for (int r = 0; r < v.Dr; ++r)
-      mgemm<T, false, false>(bl * v.Din, nbr, br, Ebuf, br, 1, W + (size_t)r * np, v.Dr * np, 1,
+      mgemm<T, false, false, M == MODE_BF16>(bl * v.Din, nbr, br, Ebuf, br, 1, W + (size_t)r * np, v.Dr * np, 1,
                              T1 + r * nbr, v.Dr * nbr, false, false);
     __syncthreads();
     // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]
@@ -602,9 +602,9 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     if (y > 0) {
       const T* Gy = Gs + (size_t)y * np2;
       // Y = G_y Z, rho = Z^H Y (Hermitian)
-      mgemm<T, IsCplx<T>::value, false>(Pl, zc, Pl, Gy, 1, np, Z, np, 1, X, np, false, false);
+      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(Pl, zc, Pl, Gy, 1, np, Z, np, 1, X, np, false, false);
       __syncthreads();
-      mgemm<T, IsCplx<T>::value, false>(zc, zc, Pl, Z, 1, np, X, np, 1, Pk, np, true, false);
+      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(zc, zc, Pl, Z, 1, np, X, np, 1, Pk, np, true, false);
       __syncthreads();
       // unit scale (eigenvectors only)
       R mx = 0;
@@ -668,7 +668,7 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
           if (i % rnew >= rkeep) Xe[i] = T(0);
       __syncthreads();
       // W_y = Z [v_0 .. v_{rnew-1}]
-      mgemm<T, false, false>(Pl, rnew, zc, Z, np, 1, Xe, rnew, 1, W, np, false, false);
+      mgemm<T, false, false, M == MODE_BF16>(Pl, rnew, zc, Z, np, 1, Xe, rnew, 1, W, np, false, false);
       // the new tensor B[j, e] = conj(v_j[e]) / max |v|
       R bm = 0;
       for (int i = tid; i < zc * rnew; i += NT) {

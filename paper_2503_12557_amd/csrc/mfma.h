@@ -10,6 +10,15 @@ namespace pm {
 
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef double mf64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
+
+// bfloat16 of x, rounded to nearest even (inf / nan kept)
+__device__ __forceinline__ __bf16 to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+  const unsigned short h = (unsigned short)(u >> 16);
+  return __builtin_bit_cast(__bf16, h);
+}
 
 // One 16x16x4 matrix-core product per real type. Operand layout (both
 // types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]. Output
@@ -68,9 +77,11 @@ struct IMap {
 // and below the diagonal are formed and conj(C[i][j]) is also written to
 // C[j][i] below it. Operands may be in global memory or LDS; out-of-range
 // rows, columns and k read as zero. The caller synchronises before reading
-// C.
+// C. BF (real FP32 operands only): the operands are rounded to bfloat16 and
+// multiplied by v_mfma_f32_16x16x32_bf16 (lane l holds A[l % 16][8 (l / 16)
+// + t] and B[8 (l / 16) + t][l % 16], t < 8) with FP32 accumulation.
 // ---------------------------------------------------------------------------
-template <typename T, bool CA, bool CB>
+template <typename T, bool CA, bool CB, bool BF = false>
 __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai, IMap ak,
                           const T* __restrict__ B, IMap bk, IMap bj, T* __restrict__ C, IMap ci,
                           IMap cj, bool herm, bool acc) {
@@ -126,6 +137,27 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
     const T* pa1 = A + (ia1 ? ai(i0 + 16 + li) : 0);
     const T* pb0 = B + (jb0 ? bj(j0 + li) : 0);
     const T* pb1 = B + (jb1 ? bj(j0 + 16 + li) : 0);
+    if constexpr (BF) {
+      static_assert(!CX, "bfloat16 products take real operands");
+      for (int k0 = 0; k0 < k; k0 += 32) {
+        mbf16x8 av[2], bv[2];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int kk = k0 + 8 * lk + t;
+          const bool kin = kk < k;
+          const int oa = kin ? ak(kk) : 0, ob = kin ? bk(kk) : 0;
+          av[0][t] = to_bf16((kin && ia0) ? (float)pa0[oa] : 0.f);
+          av[1][t] = to_bf16((kin && ia1) ? (float)pa1[oa] : 0.f);
+          bv[0][t] = to_bf16((kin && jb0) ? (float)pb0[ob] : 0.f);
+          bv[1][t] = to_bf16((kin && jb1) ? (float)pb1[ob] : 0.f);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], cr[a][b], 0, 0, 0);
+      }
+    } else {
     // k-steps of 4 loaded ahead of their products: four for real operands,
     // two for complex ones (register budget)
     constexpr int KS = CX ? 2 : 4;
@@ -162,6 +194,7 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
           }
       }
     }
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -179,11 +212,11 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
 }
 
 // Strided form: A[i*sai + kk*sak], B[kk*sbk + j*sbj], C[i*ldc + j].
-template <typename T, bool CA, bool CB>
+template <typename T, bool CA, bool CB, bool BF = false>
 __device__ __forceinline__ void mgemm(int m, int n, int k, const T* __restrict__ A, int sai,
                                       int sak, const T* __restrict__ B, int sbk, int sbj,
                                       T* __restrict__ C, int ldc, bool herm, bool acc) {
-  mgemm_map<T, CA, CB>(m, n, k, A, IMap(sai), IMap(sak), B, IMap(sbk), IMap(sbj), C, IMap(ldc),
+  mgemm_map<T, CA, CB, BF>(m, n, k, A, IMap(sai), IMap(sak), B, IMap(sbk), IMap(sbj), C, IMap(ldc),
                        IMap(1), herm, acc);
 }
 

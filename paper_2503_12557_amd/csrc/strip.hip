@@ -34,9 +34,10 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
          typename ModeT<M>::T* __restrict__ Oout, int* __restrict__ flags, int n, int want_e,
          int want_o, typename ModeT<M>::T* __restrict__ gws, size_t slab) {
   typedef typename ModeT<M>::T T;
-  // matrix-core steps for the global-slab shapes (not BF16, whose operands
-  // are rounded per product)
-  constexpr bool MMP = GM && M != MODE_BF16;
+  // matrix-core steps for the global-slab shapes (bfloat16 products in BF16
+  // mode)
+  constexpr bool MMP = GM;
+  constexpr bool BFP = M == MODE_BF16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int smp = blockIdx.x, x = blockIdx.y;
@@ -90,7 +91,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     const T* A = tensor_of(theta, tab, L, ns, pbit(s[ns]));
     T* Ry = Rt + (size_t)y * box;
     if constexpr (MMP)
-      s1_step_right_mm(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
+      s1_step_right_mm<T, BFP>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
                        dnT(y), ba_(y), bb_(y), X1, X2, Ry);
     else
       s1_step_right<M>(Rt + (size_t)(y + 1) * box, upT(y), ua_(y), ub_(y), A, Dl, Dr, Du, Dd,
@@ -133,7 +134,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     const int nA = Dl * Dr * Du * Dd;
     if (want_o) {
       if constexpr (MMP) {
-        s1_hole_mm(Lf, U, ua, ub, Dl, Dr, Du, Dd, Rn, Bt, ba, bb, X1, X2, Env);
+        s1_hole_mm<T, BFP>(Lf, U, ua, ub, Dl, Dr, Du, Dd, Rn, Bt, ba, bb, X1, X2, Env);
       } else {
         // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
         gemm<M>(Dl * ba, Du * ub, ua, Lf, 1, Dl * ba, U, Du * ub, 1, X1, Du * ub, 1, false);
@@ -178,7 +179,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
             legs_of(tab, L, n2, dl, dr, du, dd);
             const int p = in_move(mv, n2) ? 1 - pbit(s[n2]) : pbit(s[n2]);
             if constexpr (MMP)
-              s1_step_left_mm(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p),
+              s1_step_left_mm<T, BFP>(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p),
                               dl, dr, du, dd, dnT(yy), ba_(yy), bb_(yy), X1, X2, nxt);
             else
               s1_step_left<M>(cur, upT(yy), ua_(yy), ub_(yy), tensor_of(theta, tab, L, n2, p),
@@ -201,7 +202,7 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     }
     // Lf <- step(Lf, A_y)
     if constexpr (MMP)
-      s1_step_left_mm(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
+      s1_step_left_mm<T, BFP>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
     else
       s1_step_left<M>(Lf, U, ua, ub, A, Dl, Dr, Du, Dd, Bt, ba, bb, X1, X2, Lt);
     {
@@ -238,9 +239,10 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
 // Lf | Lt | Lt2 (partials) | X1 = X3 | X2 (chunk intermediates) | Us | Bs
 // (environments) | A1s | A2s (site tensors): every operand of a step is
 // staged on chip, so its contractions read LDS only
-// With the matrix-core steps (global working set, FP32 / FP64 / complex
-// modes) the intermediates hold the whole outer bond: B^2 D^3 each.
-__host__ __device__ inline bool strip2_mm(int mode, bool gm) { return gm && mode != MODE_BF16; }
+// With the matrix-core steps (global working set, every mode; bfloat16
+// products in BF16 mode) the intermediates hold the whole outer bond:
+// B^2 D^3 each.
+__host__ __device__ inline bool strip2_mm(int mode, bool gm) { return gm; }
 __host__ __device__ inline size_t strip2_xsz(int bmax, int D, bool mm) {
   return mm ? (size_t)bmax * bmax * D * D * D : (size_t)S2G * bmax * D * D * D;
 }
@@ -272,7 +274,8 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   T* Lt = Lf + box2;
   T* Lt2 = Lt + box2;
   // X3 of a chunk is formed after X1 is consumed and takes its place
-  constexpr bool MMP = GM && M != MODE_BF16;
+  constexpr bool MMP = GM;
+  constexpr bool BFP = M == MODE_BF16;
   const size_t xsz = strip2_xsz(B, D, MMP);
   T* X1 = Lt2 + box2;
   T* X2 = X1 + xsz;
@@ -350,7 +353,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
     stage(y, pbit(s[n1]), pbit(s[n2]));
     if constexpr (MMP)
-      s2_step_right_mm<T>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2,
+      s2_step_right_mm<T, BFP>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2,
                           Dd2, Bs, ba_(y), bb_(y), X1, X2, rnxt);
     else
       s2_step_right<M>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
@@ -400,7 +403,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           const int p2 = in_move(mv, a2) ? 1 - pbit(s[a2]) : pbit(s[a2]);
           stage(yy, p1, p2);
           if constexpr (MMP)
-            s2_step_left_mm<T>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
+            s2_step_left_mm<T, BFP>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
                                Dr2, Dd2, Bs, ba_(yy), bb_(yy), X1, X2, nxt);
           else
             s2_step_left<M>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
@@ -429,7 +432,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     legs_of(tab, L, n2, Dl2, Dr2, Du2, Dd2);
     stage(y, pbit(s[n1]), pbit(s[n2]));
     if constexpr (MMP)
-      s2_step_left_mm<T>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
+      s2_step_left_mm<T, BFP>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
                          Bs, ba_(y), bb_(y), X1, X2, Lt);
     else
       s2_step_left<M>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2, Bs,

@@ -171,6 +171,35 @@ def test_reduced_precision_bounded(dev, dtype, mu, bound):
     assert max(e_psi.max(), e_el.max(), e_O.max()) < bound
 
 
+# BF16 mode: every product of the density-matrix kernel, and of the strips on
+# global-slab shapes, takes bfloat16 operands on the matrix cores
+# (v_mfma_f32_16x16x32_bf16, FP32 accumulation); the eigensolver stays in
+# FP32. Against the FP64 oracle (density-matrix compression) with bounds on
+# Psi, E_loc and O, on mean-0.5 tensors (where BF16 is a usable mode) and on
+# mean-0 ones (cancellation of 1e4 and more per contraction). Measured
+# (Psi, E_loc, O): 6.4e-2 / 1.7e-3 / 7.1e-3 (12x12, mean 0.5), 11 / 0.17 /
+# 1.1 (12x12, mean 0), 1.4e-2 / 1.4e-3 / 7.6e-4 (6x6 D=5 chi=25, global-slab
+# strips on the matrix cores).
+@pytest.mark.parametrize("shape,model,mu,bound", [
+    ((12, 12, 4, 16), RYD, 0.5, (0.3, 0.01, 0.05)),
+    ((12, 12, 4, 16), RYD, 0.0, (50.0, 1.0, 5.0)),
+    ((6, 6, 5, 25), J1J2, 0.5, (0.1, 0.01, 0.01)),
+])
+def test_bf16_matrix_cores_bounded(dev, shape, model, mu, bound):
+    Lx, Ly, D, chi = shape
+    theta = synth.theta(Lx, Ly, 2, D, seed=91, mu=mu)
+    cf = configs_for(model, Lx * Ly, 4, seed=92)
+    olp, oel, oO = oracle_eval(theta, Lx, Ly, D, chi, cf, model=model, want_O=True,
+                               method="densmat")
+    lp, el, O, fl = _eval(dev, _ctx(Lx, Ly, D, chi, "bf16", model), theta, cf)
+    e_psi = rel_amp_err(lp, olp)
+    e_el = np.abs(el - oel) / np.maximum(1.0, np.abs(oel))
+    e_O = _o_err(theta, cf, O, oO, Lx, Ly, D)
+    print(f"bf16 {Lx}x{Ly} D={D} chi={chi} mu={mu}: psi {e_psi.max():.2e} "
+          f"eloc {e_el.max():.2e} O {e_O.max():.2e}")
+    assert e_psi.max() < bound[0] and e_el.max() < bound[1] and e_O.max() < bound[2]
+
+
 def test_truncated_weight_matches_oracle(dev):
     Lx, Ly, D, chi = 5, 6, 3, 7
     theta = synth.theta(Lx, Ly, 2, D, seed=61, mu=0.5)
