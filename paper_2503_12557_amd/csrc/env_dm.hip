@@ -56,7 +56,8 @@ __host__ __device__ inline int dm_rmax(int chi) { return chi + 1; }
 // Slab of one workgroup (elements of T unless noted):
 //   G   : Ly x NP x NP  left Gram environments G_0 .. G_{Ly-1}
 //   Pk, X, Z, T1, W, Hv : NP x NP each
-//   then reals: Yt (RMAX x NP), lu (RMAX x 6 x NP)
+//   then reals: Yt (RMAX x NP), lu (RMAX x 6 x NP): the iterates and U bands
+//   of the eigenvector phase when they do not fit in LDS
 __host__ __device__ inline size_t dm_slab_elems(int Ly, int bmax, int D, int chi, size_t tsize,
                                                 size_t rsize) {
   const size_t np = dm_np(bmax, D);
@@ -67,9 +68,9 @@ __host__ __device__ inline size_t dm_slab_elems(int Ly, int bmax, int D, int chi
 }
 
 // LDS: one big region (the staged E and A of a site, then the packed
-// density matrix, then the eigenvector phase: Xe | Yt | LU when that fits
-// under the dynamic-LDS cap, else Yt and LU stay in the slab) and the small
-// vectors.
+// density matrix, then the eigenvector phase: the U bands of the inverse
+// iterations under Xe, then their iterates Y, when that fits under the
+// dynamic-LDS cap, else U and Y stay in the slab) and the small vectors.
 #define DM_LDS_CAP (150 * 1024)
 __host__ __device__ inline size_t dm_small_bytes(int np, size_t tsize, size_t rsize) {
   return (3 * (size_t)np + 32) * tsize + (3 * (size_t)np + 2 * 64 + 8) * rsize + 64;
@@ -82,8 +83,9 @@ __host__ __device__ inline size_t dm_big_elems(int bmax, int D, int chi, size_t 
   const size_t rho = np * (np + 1) / 2;
   if (rho > big) big = rho;
   if (np * rm > big) big = np * rm;
-  // Xe (np x rm, T) | Yt (rm x np, R) | LU (rm x 5 x np, R)
-  const size_t eig = np * rm + (rm * np * 6 * rsize + tsize - 1) / tsize;
+  // U bands (3 np rm, R) under Xe (np rm, T), then Y (np rm, R)
+  const size_t xe_b = np * rm * tsize, u_b = 3 * np * rm * rsize;
+  const size_t eig = ((xe_b > u_b ? xe_b : u_b) + np * rm * rsize + tsize - 1) / tsize;
   const size_t with = (eig > big ? eig : big);
   // FP32 modes run two workgroups per CU: each keeps below half the LDS
   const size_t cap = rsize == 4 ? DM_LDS_CAP / 2 : DM_LDS_CAP;
@@ -103,7 +105,7 @@ struct DmSh {
   typedef typename RealOf<T>::type R;
   T *big, *tau, *vb, *wb, *red;
   R *dd, *ee, *e2, *lam;
-  bool eig_lds;  // Yt and LU of the eigenvector phase in LDS (after Xe)
+  bool eig_lds;  // U bands and iterates of the eigenvector phase in LDS
   __device__ DmSh(unsigned char* lds, int bmax, int D, int chi) {
     const size_t np = dm_np(bmax, D);
     const size_t bg = dm_big_elems(bmax, D, chi, sizeof(T), sizeof(R), &eig_lds);
@@ -322,71 +324,70 @@ __device__ void top_eigenvalues(const R* dd, const R* ee, R* e2, R* lam, int nz,
   __syncthreads();
 }
 
-// Eigenvector of the tridiagonal for eigenvalue x by inverse iteration
-// (partial-pivoting LU of T - x I, three solves from a vector of ones),
-// normalised, into y[0..n). Serial in the calling lane; wk: 5 n reals.
+// Eigenvector of the tridiagonal for eigenvalue x by inverse iteration:
+// three solves of (T - x I) y = b from b = ones, each forming the
+// partial-pivoting LU of T - x I row by row with b eliminated alongside (the
+// three bands of U kept for the back substitution), y scaled by its largest
+// entry after each solve. Serial in the calling lane; the bands u (3 n) and
+// y (n) are interleaved across lanes with stride ld (element i of this lane
+// at [i * ld]), so the lanes' accesses of one step are consecutive.
 template <typename R>
-__device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* wk, R* y) {
-  R* u0 = wk;
-  R* u1 = wk + n;
-  R* u2 = wk + 2 * n;
-  R* ml = wk + 3 * n;
-  R* pv = wk + 4 * n;
+__device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* u, R* y,
+                              int ld) {
+  R* u0 = u;
+  R* u1 = u + (size_t)n * ld;
+  R* u2 = u + (size_t)2 * n * ld;
   const R tiny = Eps<R>::v * (tnorm > R(0) ? tnorm : R(1));
-  // factorise: rows i, i+1 with pivoting on the sub-diagonal
-  R c0 = dd[0] - x, c1 = n > 1 ? ee[0] : R(0), c2 = 0;
-  for (int i = 0; i + 1 < n; ++i) {
-    const R s0 = ee[i], s1 = dd[i + 1] - x, s2 = i + 2 < n ? ee[i + 1] : R(0);
-    if (fabs(s0) > fabs(c0)) {
-      const R mm = c0 / s0;
-      u0[i] = s0;
-      u1[i] = s1;
-      u2[i] = s2;
-      c0 = c1 - mm * s1;
-      c1 = c2 - mm * s2;
-      c2 = 0;
-      ml[i] = mm;
-      pv[i] = 1;
-    } else {
-      if (c0 == R(0)) c0 = tiny;
-      const R mm = s0 / c0;
-      u0[i] = c0;
-      u1[i] = c1;
-      u2[i] = c2;
-      c0 = s1 - mm * c1;
-      c1 = s2 - mm * c2;
-      c2 = 0;
-      ml[i] = mm;
-      pv[i] = 0;
-    }
-  }
-  if (c0 == R(0)) c0 = tiny;
-  u0[n - 1] = c0;
-  u1[n - 1] = 0;
-  u2[n - 1] = 0;
-  for (int i = 0; i < n; ++i) y[i] = R(1);
+  for (int i = 0; i < n; ++i) y[(size_t)i * ld] = R(1);
   for (int it = 0; it < 3; ++it) {
+    // rows i, i+1 with pivoting on the sub-diagonal; (c0, c1) the current
+    // row's entries at columns i, i+1 and r0 its right-hand side
+    R c0 = dd[0] - x, c1 = n > 1 ? ee[0] : R(0), r0 = y[0];
     for (int i = 0; i + 1 < n; ++i) {
-      const R mm = ml[i];
-      if (pv[i] != R(0)) {
-        const R a = y[i], b = y[i + 1];
-        y[i] = b;
-        y[i + 1] = a - mm * b;
+      const R s0 = ee[i], s1 = dd[i + 1] - x, s2 = i + 2 < n ? ee[i + 1] : R(0);
+      const R rn = y[(size_t)(i + 1) * ld];
+      const size_t o = (size_t)i * ld;
+      if (fabs(s0) > fabs(c0)) {
+        const R mm = c0 / s0;
+        u0[o] = s0;
+        u1[o] = s1;
+        u2[o] = s2;
+        y[o] = rn;
+        c0 = c1 - mm * s1;
+        c1 = -(mm * s2);
+        r0 = r0 - mm * rn;
       } else {
-        y[i + 1] -= mm * y[i];
+        if (c0 == R(0)) c0 = tiny;
+        const R mm = s0 / c0;
+        u0[o] = c0;
+        u1[o] = c1;
+        u2[o] = R(0);
+        y[o] = r0;
+        c0 = s1 - mm * c1;
+        c1 = s2;
+        r0 = rn - mm * r0;
       }
     }
-    R nrm = 0;
+    if (c0 == R(0)) c0 = tiny;
+    const size_t ol = (size_t)(n - 1) * ld;
+    u0[ol] = c0;
+    u1[ol] = R(0);
+    u2[ol] = R(0);
+    y[ol] = r0;
+    R nrm = 0, y1 = 0, y2 = 0;
     for (int i = n - 1; i >= 0; --i) {
-      R s = y[i];
-      if (i + 1 < n) s -= u1[i] * y[i + 1];
-      if (i + 2 < n) s -= u2[i] * y[i + 2];
-      s /= u0[i];
-      y[i] = s;
+      const size_t o = (size_t)i * ld;
+      R s = y[o];
+      if (i + 1 < n) s -= u1[o] * y1;
+      if (i + 2 < n) s -= u2[o] * y2;
+      s /= u0[o];
+      y[o] = s;
+      y2 = y1;
+      y1 = s;
       nrm = fabs(s) > nrm ? fabs(s) : nrm;
     }
     const R inv = nrm > R(0) ? R(1) / nrm : R(1);
-    for (int i = 0; i < n; ++i) y[i] *= inv;
+    for (int i = 0; i < n; ++i) y[(size_t)i * ld] *= inv;
   }
 }
 
@@ -416,46 +417,43 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
   __syncthreads();
   tridiag(rho, nz, Hv, np, sh, slot);
   top_eigenvalues(sh.dd, sh.ee, sh.e2, sh.lam, nz, rr, reinterpret_cast<R*>(sh.red), slot, tnorm);
-  // eigenvectors of the tridiagonal, one lane each; their LU factors and
-  // iterates in LDS after Xe when they fit (the packed matrix is dead now)
+  // eigenvectors of the tridiagonal, one lane each, vector c's element e at
+  // Y[e * r + c]; in LDS when they fit (the packed matrix is dead now): the
+  // U bands over the area Xe takes later, Y after both
+  R* U = lu;
+  R* Y = Yt;
   if (sh.eig_lds) {
-    Yt = reinterpret_cast<R*>(sh.big + (size_t)np * (r + 1 > rr ? r + 1 : rr));
-    lu = Yt + (size_t)(r + 1) * np;
+    const size_t xe_b = (size_t)nz * r * sizeof(T), u_b = (size_t)3 * nz * r * sizeof(R);
+    U = reinterpret_cast<R*>(sh.big);
+    Y = reinterpret_cast<R*>(reinterpret_cast<char*>(sh.big) + (xe_b > u_b ? xe_b : u_b));
   }
-  if (tid < r) inv_iter_lane(sh.dd, sh.ee, nz, sh.lam[tid], tnorm, lu + (size_t)tid * 5 * np,
-                             Yt + (size_t)tid * np);
+  if (tid < r) inv_iter_lane(sh.dd, sh.ee, nz, sh.lam[tid], tnorm, U + tid, Y + tid, r);
   __syncthreads();
   // Gram-Schmidt inside clusters of close eigenvalues (wave 0, in order)
   if (tid < 64) {
     const R ctol = R(1e-3) * tnorm;
     for (int j = 0; j < r; ++j) {
-      R* yj = Yt + (size_t)j * np;
-      bool touched = false;
+      R* yj = Y + j;
       for (int i = 0; i < j; ++i) {
         if (!(fabs(sh.lam[i] - sh.lam[j]) <= ctol)) continue;
-        const R* yi = Yt + (size_t)i * np;
+        const R* yi = Y + i;
         R d = 0;
-        for (int e = tid; e < nz; e += 64) d += yi[e] * yj[e];
+        for (int e = tid; e < nz; e += 64) d += yi[(size_t)e * r] * yj[(size_t)e * r];
         d = wave_sum(d);
-        for (int e = tid; e < nz; e += 64) yj[e] -= d * yi[e];
-        touched = true;
+        for (int e = tid; e < nz; e += 64) yj[(size_t)e * r] -= d * yi[(size_t)e * r];
       }
       R s = 0;
-      for (int e = tid; e < nz; e += 64) s += yj[e] * yj[e];
+      for (int e = tid; e < nz; e += 64) s += yj[(size_t)e * r] * yj[(size_t)e * r];
       s = wave_sum(s);
       const R inv = s > R(0) ? R(1) / sqrt(s) : R(0);
-      for (int e = tid; e < nz; e += 64) yj[e] *= inv;
-      (void)touched;
+      for (int e = tid; e < nz; e += 64) yj[(size_t)e * r] *= inv;
     }
   }
   __syncthreads();
   // Xe = Q Y: reflectors applied last to first; column c owned by P lanes
   // of one wave (no barrier: columns are independent)
   T* Xe = sh.big;
-  for (int idx = tid; idx < nz * r; idx += NT) {
-    const int e = idx / r, c = idx - e * r;
-    Xe[idx] = T(Yt[(size_t)c * np + e]);
-  }
+  for (int idx = tid; idx < nz * r; idx += NT) Xe[idx] = T(Y[idx]);
   __syncthreads();
   int P = 64;
   while (P > 1 && r * P > NT) P >>= 1;
