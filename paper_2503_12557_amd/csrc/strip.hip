@@ -26,8 +26,17 @@ static size_t strip1_big(int bmax, int D) {
 static size_t strip1_small(int D) { return (size_t)D * D * D * D + 16; }
 size_t strip1_lds_elems(int bmax, int D) { return strip1_big(bmax, D) + strip1_small(D); }
 
+// Global-slab shapes in the FP32 modes trade registers for occupancy (the
+// steps are bound by operand latency): one-row strips in workgroups of 256
+// threads at most 168 VGPRs (three to a CU), two-row strips in 512 threads
+// at most 128 VGPRs (two to a CU); measured best of the two forms for each.
+#define STRIP_SMALL(M, GM) ((GM) && ((M) == MODE_F32 || (M) == MODE_BF16 || (M) == MODE_C64))
+#define STRIP1_THREADS(M, GM) (STRIP_SMALL(M, GM) ? 256 : PEPS_BLOCK_MAX)
+#define STRIP1_WAVES(M, GM) (STRIP_SMALL(M, GM) ? 3 : 1)
+#define STRIP2_WAVES(M, GM) (STRIP_SMALL(M, GM) ? 4 : 1)
+
 template <int M, bool GM>
-__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
+__global__ void __launch_bounds__(STRIP1_THREADS(M, GM), STRIP1_WAVES(M, GM))
 k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
@@ -254,7 +263,7 @@ static size_t strip2_big(int bmax, int D, bool mm = false) {
 size_t strip2_lds_elems(int bmax, int D) { return strip2_big(bmax, D) + 16; }
 
 template <int M, bool GM>
-__global__ void __launch_bounds__(PEPS_BLOCK_MAX)
+__global__ void __launch_bounds__(PEPS_BLOCK_MAX, STRIP2_WAVES(M, GM))
 k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
@@ -653,8 +662,9 @@ hipError_t launch_strip1(const Lattice& L, const int* tab, const void* theta,
   const void* fn = gm ? (const void*)k_strip1<M, true> : (const void*)k_strip1<M, false>;
   hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (gm)
-    hipLaunchKernelGGL((k_strip1<M, true>), dim3(n, L.Lx), dim3(512), lds, st, L, tab,
-                       (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O, flags, n,
+    hipLaunchKernelGGL((k_strip1<M, true>), dim3(n, L.Lx), dim3(STRIP1_THREADS(M, true)), lds, st,
+                       L, tab, (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, (T*)O,
+                       flags, n,
                        want_e ? 1 : 0, want_o ? 1 : 0, (T*)gws, strip1_slab_elems(L));
   else
     hipLaunchKernelGGL((k_strip1<M, false>), dim3(n, L.Lx), dim3(512), lds, st, L, tab,
