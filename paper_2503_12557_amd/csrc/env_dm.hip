@@ -458,16 +458,49 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
   int P = 64;
   while (P > 1 && r * P > NT) P >>= 1;
   const int col = tid / P, part = tid - col * P;
-  if (col < r) {
+  constexpr int VPL = 8;  // reflector entries a lane holds when they fit
+  if (col < r && (nz + P - 1) / P <= VPL) {
+    // the next reflector's entries are loaded while the current one is
+    // applied, so the slab's latency is off the dependent chain
+    T vc[VPL], vn[VPL];
+    auto load = [&](int j, T* dst) {
+      const T* v = Hv + (size_t)j * np;
+#pragma unroll
+      for (int u = 0; u < VPL; ++u) {
+        const int e = j + 1 + part + u * P;
+        dst[u] = e < nz ? v[e] : T(0);
+      }
+    };
+    load(nz - 2, vc);
+    for (int j = nz - 2; j >= 0; --j) {
+      if (j > 0) load(j - 1, vn);
+      const T tj = sh.tau[j];
+      if (tj != T(0)) {
+        T sdot = T(0);
+#pragma unroll
+        for (int u = 0; u < VPL; ++u) {
+          const int e = j + 1 + part + u * P;
+          if (e < nz) sdot += conjx(vc[u]) * Xe[e * r + col];
+        }
+        sdot = group_sum(sdot, P) * tj;
+#pragma unroll
+        for (int u = 0; u < VPL; ++u) {
+          const int e = j + 1 + part + u * P;
+          if (e < nz) Xe[e * r + col] -= vc[u] * sdot;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < VPL; ++u) vc[u] = vn[u];
+    }
+  } else if (col < r) {
     for (int j = nz - 2; j >= 0; --j) {
       const T tj = sh.tau[j];
       if (tj == T(0)) continue;
       const T* v = Hv + (size_t)j * np;
-      T s = T(0);
-      for (int e = j + 1 + part; e < nz; e += P) s += conjx(v[e]) * Xe[e * r + col];
-      s = group_sum(s, P);
-      s = s * tj;
-      for (int e = j + 1 + part; e < nz; e += P) Xe[e * r + col] -= v[e] * s;
+      T sdot = T(0);
+      for (int e = j + 1 + part; e < nz; e += P) sdot += conjx(v[e]) * Xe[e * r + col];
+      sdot = group_sum(sdot, P) * tj;
+      for (int e = j + 1 + part; e < nz; e += P) Xe[e * r + col] -= v[e] * sdot;
     }
   }
   __syncthreads();
