@@ -88,12 +88,16 @@ def _trivial(Ly, dt):
     return [np.ones((1, 1, 1), dtype=dt) for _ in range(Ly)]
 
 
-def _sweep(T, g, s, chi, kind, key, chain, sweep_ctr, cutoff=0.0):
-    """One sweep in place on s; returns the number of accepted moves."""
+def _sweep(T, g, s, chi, kind, key, chain, sweep_ctr, cutoff=0.0, method='canonical'):
+    """One sweep in place on s; returns the number of accepted moves.
+    method: the boundary-MPS truncation ('canonical' QR -> SVD or the
+    'densmat' density-matrix algorithm), used for every environment."""
     Lx, Ly = g.Lx, g.Ly
     A = peps.project(T, g, s)
     dt = A[(0, 0)].dtype
-    B, _ = peps.bottom_environments(A, g, chi, 'canonical', cutoff)
+    B, _ = peps.bottom_environments(A, g, chi, method, cutoff)
+    compress = (peps.compress_canonical if method == 'canonical'
+                else peps.compress_density_matrix)
     acc = 0
     U = None
 
@@ -153,8 +157,7 @@ def _sweep(T, g, s, chi, kind, key, chain, sweep_ctr, cutoff=0.0):
             if x == 0:
                 U, _ = peps.normalize(peps.top_row_mps(Acur, g, 0))
             else:
-                U, _ = peps.normalize(peps.compress_canonical(
-                    peps.absorb(U, Acur, g, x, True), chi, cutoff))
+                U, _ = peps.normalize(compress(peps.absorb(U, Acur, g, x, True), chi, cutoff))
     return acc
 
 
@@ -171,10 +174,11 @@ def _close2(st, L, y0, cols):
 
 
 def metropolis(theta, g, chi, kind, n_chains, per_chain, burn_in, thin, seed,
-               offset=0, cutoff=0.0):
+               offset=0, cutoff=0.0, method='canonical'):
     """Samples [n_chains * per_chain, N] (chain-major) and accepted counts.
     cutoff: maximal truncated weight of every boundary-MPS truncation
-    (``peps.kept_count``), 0 for a fixed chi.
+    (``peps.kept_count``), 0 for a fixed chi; method: the truncation
+    algorithm ('canonical' or 'densmat').
 
     Sample j of a chain is the state after sweep burn_in + (j+1)*thin - 1.
     """
@@ -187,7 +191,7 @@ def metropolis(theta, g, chi, kind, n_chains, per_chain, burn_in, thin, seed,
         s = initial_state(g.N, c, seed, kind)
         j = 0
         for sw in range(total):
-            acc[c] += _sweep(T, g, s, chi, kind, key, c, sw + offset, cutoff)
+            acc[c] += _sweep(T, g, s, chi, kind, key, c, sw + offset, cutoff, method)
             if sw >= burn_in and (sw - burn_in) % thin == thin - 1:
                 out[c * per_chain + j] = s
                 j += 1

@@ -141,6 +141,7 @@ struct peps_ctx {
   // independence MH chains: states, proposals, their ln Psi and ln q
   DevBuf imh_st, imh_pr, imh_stlp, imh_stlq, imh_prlp, imh_prlq;
   DevBuf gws_env, gws_s1, gws_s2, gws_smp;
+  DevBuf smp_state;  // chain states and acceptance counts between the sampler's phases
   int jac_sweeps = 40;
   // optional per-kernel timing with HIP events on the launch stream
   bool prof = false;
@@ -343,7 +344,7 @@ void peps_destroy(peps_ctx* c) {
                     &c->dir_th2, &c->dir_zero,   &c->dir_env2,   &c->dir_lp2, &c->dir_slab,
                     &c->dir_lp,  &c->dir_fl,    &c->gws_dm,
                     &c->imh_st,  &c->imh_pr,    &c->imh_stlp,   &c->imh_stlq, &c->imh_prlp,
-                    &c->imh_prlq};
+                    &c->imh_prlq, &c->eig_ws,   &c->smp_state};
   if (c->dbl) peps_destroy(c->dbl);
   for (DevBuf* b : bufs) b->release();
   delete c;
@@ -1188,13 +1189,21 @@ peps_status peps_sample(peps_ctx* c, const double* theta, int kind, int n_chains
     if ((s = c->gws_smp.ensure(nc * sample_slab_elems(L, c->g.dtype) * c->tsize)) != PEPS_OK) return s;
     gws = c->gws_smp.p;
   }
+  if ((s = c->smp_state.ensure(sample_state_bytes(L, n_chains))) != PEPS_OK) return s;
+  // the density-matrix truncation for the chains' environments when chosen
+  void* dm_slabs = nullptr;
+  if (c->compress == PEPS_COMPRESS_DENSMAT) {
+    const int mode = c->g.dtype;
+    if ((s = c->gws_dm.ensure(nc * env_dm_slab_elems(L, mode) * c->tsize)) != PEPS_OK) return s;
+    dm_slabs = c->gws_dm.p;
+  }
   {
     ProfScope ps(c, st, PEPS_PROF_SAMPLE);
 #define MET(MODE)                                                                               \
   HIPCHK(launch_metropolis<MODE>(L, c->d_tab, c->theta_c.p, kind, n_chains, per_chain, burn_in, \
                                  thin, seed, offset, samples, accepted, c->env_int.p,           \
                                  (double*)c->eloc_tmp.p, c->rscr.p, c->rt1.p, c->rt2.p,         \
-                                 c->jac_sweeps, gws, st))
+                                 c->jac_sweeps, gws, c->smp_state.p, dm_slabs, st))
     switch (c->g.dtype) {
       case PEPS_F64: MET(MODE_F64); break;
       case PEPS_F32: MET(MODE_F32); break;

@@ -799,6 +799,41 @@ k_env_dm(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   }
 }
 
+// The sampler's environment phase with the density-matrix truncation: one
+// workgroup per chain (grid = chains); row < 0 rebuilds the bottom
+// environments of the chain's state, row >= 0 absorbs that row into the top
+// environment (row 0: the first row read as an MPS).
+template <int M>
+__global__ void __launch_bounds__(512, (M == MODE_F32 || M == MODE_BF16 || M == MODE_C64) ? 4 : 2)
+k_smp_env_dm(Lattice L, const int* __restrict__ tab,
+             const typename ModeT<M>::T* __restrict__ theta, int n_chains, int row,
+             const uint8_t* __restrict__ state, typename ModeT<M>::T* __restrict__ env,
+             double* __restrict__ logs, typename ModeT<M>::T* __restrict__ slabs, size_t slab) {
+  typedef typename ModeT<M>::T T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int chain = blockIdx.x;
+  if (chain >= n_chains) return;
+  const DmSh<T> sh(smem_raw, L.bmax, L.D, L.chi);
+  T* myslab = slabs + (size_t)chain * slab;
+  __shared__ int fl;
+  if (threadIdx.x == 0) fl = 0;
+  __syncthreads();
+  int slot = 0;
+  const bool bottom = row < 0;
+  const uint8_t* s = state + (size_t)chain * L.N;
+  T* envs = env + (size_t)chain * L.n_slots * ((size_t)L.Ly * L.site_box);
+  double* lg = logs + (size_t)chain * L.n_slots;
+  if (row <= 0) {
+    EnvSmem<T> es(sh.big, sh.red, L, false);
+    es.Ebuf = sh.big;
+    es.red = sh.red;
+    env_first_row<M>(L, tab, theta, s, bottom, envs, lg, es, &fl);
+  }
+  const int t0 = bottom ? 1 : row, t1 = bottom ? L.Lx - 2 : row;
+  for (int t = t0 > 1 ? t0 : 1; t <= t1; ++t)
+    dm_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, myslab, sh, &fl, slot);
+}
+
 // ---- host side ----
 static size_t dm_rsize(int mode) {
   return (mode == MODE_F64 || mode == MODE_C128) ? 8 : 4;
@@ -867,5 +902,37 @@ INST(MODE_BF16)
 INST(MODE_C128)
 INST(MODE_C64)
 #undef INST
+
+template <int M>
+static hipError_t smp_env_dm_m(const Lattice& L, const int* tab, const void* theta, int n_chains,
+                               int row, const uint8_t* state, void* env, double* logs,
+                               void* slabs, hipStream_t st) {
+  typedef typename ModeT<M>::T T;
+  const size_t lds = env_dm_lds_bytes(L, M);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_smp_env_dm<M>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_smp_env_dm<M>, dim3(n_chains), dim3(512), lds, st, L, tab,
+                     (const T*)theta, n_chains, row, state, (T*)env, logs, (T*)slabs,
+                     env_dm_slab_elems(L, M));
+  return hipGetLastError();
+}
+
+hipError_t launch_smp_env_dm(const Lattice& L, const int* tab, int mode, const void* theta,
+                             int n_chains, int row, const uint8_t* state, void* env, double* logs,
+                             void* slabs, hipStream_t st) {
+  switch (mode) {
+    case MODE_F64:
+      return smp_env_dm_m<MODE_F64>(L, tab, theta, n_chains, row, state, env, logs, slabs, st);
+    case MODE_F32:
+      return smp_env_dm_m<MODE_F32>(L, tab, theta, n_chains, row, state, env, logs, slabs, st);
+    case MODE_BF16:
+      return smp_env_dm_m<MODE_BF16>(L, tab, theta, n_chains, row, state, env, logs, slabs, st);
+    case MODE_C128:
+      return smp_env_dm_m<MODE_C128>(L, tab, theta, n_chains, row, state, env, logs, slabs, st);
+    default:
+      return smp_env_dm_m<MODE_C64>(L, tab, theta, n_chains, row, state, env, logs, slabs, st);
+  }
+}
 
 }  // namespace pm

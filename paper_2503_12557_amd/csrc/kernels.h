@@ -112,14 +112,21 @@ hipError_t launch_direct_row(const Lattice& L, const int* tab, const void* theta
 hipError_t launch_direct_logw(int n, const double* lpsi, const double* logp, const int* afl,
                               double* logw, int* flags, hipStream_t st);
 
-// Metropolis sampler
+// Metropolis sampler; state: sample_state_bytes of chain states and counts;
+// dm_slabs (chains x env_dm_slab_elems) selects the density-matrix
+// truncation for the environments, nullptr the canonical one
 size_t sample_lds_elems(int bmax, int D, int mode);
+size_t sample_state_bytes(const Lattice& L, int n_chains);
 template <int M>
 hipError_t launch_metropolis(const Lattice& L, const int* tab, const void* theta, int kind,
                              int n_chains, int per_chain, int burn_in, int thin, uint64_t seed,
                              uint64_t offset, uint8_t* samples, int* accepted, void* envscr,
                              double* logscr, void* rscr, void* rt1, void* rt2, int jac_sweeps,
-                             void* gws, hipStream_t st);
+                             void* gws, void* state, void* dm_slabs, hipStream_t st);
+// the sampler's environment phase by the density-matrix truncation
+hipError_t launch_smp_env_dm(const Lattice& L, const int* tab, int mode, const void* theta,
+                             int n_chains, int row, const uint8_t* state, void* env, double* logs,
+                             void* slabs, hipStream_t st);
 
 // learned proposal
 hipError_t launch_made_forward(int N, int H, int n_up, int bf16, const float* P,

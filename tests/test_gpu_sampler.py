@@ -37,6 +37,27 @@ def test_chains_identical_to_oracle(dev, Lx, Ly, D, chi, kind):
     assert np.array_equal(acc.cpu().numpy(), ref_acc)
 
 
+@pytest.mark.parametrize("Lx,Ly,D,chi,kind,dtype", [(5, 4, 3, 3, "exchange", "f64"),
+                                                    (4, 4, 2, 3, "flip", "f64"),
+                                                    (4, 5, 2, 3, "exchange", "c128")])
+def test_density_matrix_chains_identical_to_oracle(dev, Lx, Ly, D, chi, kind, dtype):
+    # environments of the chains by the density-matrix truncation (the
+    # context's compression) against the oracle sampler with the same one
+    from paper_2503_12557_amd import Context
+    cplx = dtype == "c128"
+    theta = synth.theta(Lx, Ly, 2, D, seed=40 + D, cplx=cplx)
+    ctx = Context(Lx, Ly, D, chi, dtype)
+    ctx.set_compression("densmat")
+    th = torch.from_numpy(theta).to(dev)
+    sm, acc = ctx.sample(th, kind, n_chains=5, per_chain=3, burn_in=2, thin=2, seed=99, offset=1)
+    torch.cuda.synchronize()
+    g = peps.Geometry(Lx, Ly, 2, D)
+    ref, ref_acc = sampler.metropolis(theta, g, chi, kind, 5, 3, 2, 2, seed=99, offset=1,
+                                      method="densmat")
+    assert np.array_equal(sm.cpu().numpy(), ref)
+    assert np.array_equal(acc.cpu().numpy(), ref_acc)
+
+
 def test_exchange_conserves_sz(dev):
     from paper_2503_12557_amd import Context
     Lx, Ly, D, chi = 6, 6, 3, 6
