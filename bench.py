@@ -304,14 +304,16 @@ def cpu_baseline(theta, Lx, Ly, D, chi, model, configs, seconds=20.0):
                       f"worker, {workers} worker processes) in {dt:.1f} s"}
 
 
-def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
+def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps, model="J1-J2 J2/J1=0.5",
+                   chains=256, T=64, burn=16, data_chains=1024, data_per=64, data_burn=16,
+                   compression="canonical"):
     """Effective samples per second of the energy series: local exchange
     Metropolis against independence MH with the learned proposal (trained on
-    65536 configurations of the local sampler). Both arms start from
-    burned-in states: the IMH chains from the local sampler's states after
-    16 sweeps, the local chains run their own 16 burn-in sweeps, whose
-    separately timed cost is subtracted. E_loc of the recorded states is
-    evaluated untimed."""
+    data_chains x data_per configurations of the local sampler). Both arms
+    start from burned-in states: the IMH chains from the local sampler's
+    states after `burn` sweeps, the local chains run their own `burn`
+    burn-in sweeps, whose separately timed cost is subtracted. E_loc of the
+    recorded states is evaluated untimed."""
     import torch
 
     from paper_2503_12557_amd import analysis
@@ -319,7 +321,8 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     N = Lx * Ly
     ctx = Context(Lx, Ly, D, chi, "f32")
     ctx.set_hamiltonian(ham)
-    chains, T, burn = 256, 64, 16
+    if compression != "canonical":
+        ctx.set_compression(compression)
     init, _ = ctx.sample(theta, "exchange", n_chains=chains, per_chain=1, burn_in=burn, seed=21)
     _sync()
     t0 = time.perf_counter()
@@ -331,11 +334,15 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
                             seed=22)
     _sync()
     t_mh = time.perf_counter() - t0 - t_burn
+    _log(f"local chains: {t_mh:.1f} s")
     e_mh = ctx.evaluate(theta, mh, want_o=False)[1][:, 0].view(chains, T).cpu().numpy()
+    _log("local chains evaluated")
     t0 = time.perf_counter()
-    data, _ = ctx.sample(theta, "exchange", n_chains=1024, per_chain=64, burn_in=16, seed=23)
+    data, _ = ctx.sample(theta, "exchange", n_chains=data_chains, per_chain=data_per,
+                         burn_in=data_burn, seed=23)
     _sync()
     t_data = time.perf_counter() - t0
+    _log(f"{data.shape[0]} training configurations: {t_data:.1f} s")
     made = Made(N, 256, N // 2, bf16=True)
     params = torch.tensor(0.01 * np.random.default_rng(7).standard_normal(made.n_params),
                           dtype=torch.float32, device=theta.device)
@@ -349,6 +356,7 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
                            record=True, init=init)
     _sync()
     t_imh = time.perf_counter() - t0
+    _log(f"independence chains: {t_imh:.1f} s")
     states = hist.permute(1, 0, 2).reshape(chains * T, N).contiguous()
     e_imh = ctx.evaluate(theta, states, want_o=False)[1][:, 0].view(chains, T).cpu().numpy()
     tau_mh, tau_imh = analysis.tau_int_ranked(e_mh), analysis.tau_int_ranked(e_imh)
@@ -357,8 +365,9 @@ def ess_comparison(Context, theta, Lx, Ly, D, chi, ham, made_steps):
     repeat = float((hist_np[1:] == hist_np[:-1]).all(axis=2).mean())
     sweeps_moves = (2 * Ly - 1) * Lx
     return {
-        "workload": f"{Lx}x{Ly} D={D} chi={chi} J1-J2 J2/J1=0.5, {chains} chains x {T} "
-                    f"steps, energy series, both arms after {burn} burn-in sweeps",
+        "workload": f"{Lx}x{Ly} D={D} chi={chi} {model}, {chains} chains x {T} "
+                    f"steps, energy series, both arms after {burn} burn-in sweeps, FP32, "
+                    f"{compression} truncation",
         "tau_int_estimator": "Sokal window on rank-normalised E_loc (normal scores of pooled "
                              "ranks); tau_int_plain: same window on raw E_loc",
         "local_mh": {"tau_int": tau_mh, "tau_int_plain": raw_mh, "ess": chains * T / tau_mh,
@@ -443,6 +452,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the side workloads and the learned-proposal comparison")
     ap.add_argument("--made-steps", type=int, default=2000)
+    ap.add_argument("--proposal-16x16", action="store_true",
+                    help="only the learned-proposal comparison on the 16x16 D=6 chi=36 "
+                         "Heisenberg lattice (minutes; reduced chain and training sizes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -455,6 +467,18 @@ def main():
     from paper_2503_12557_amd import Context, hamiltonians
 
     dev = torch.device("cuda:0")
+    if args.proposal_16x16:
+        # 16x16 D=6 chi=36 Heisenberg, real N(0,1) tensors seed 6: the
+        # density-matrix sampler needs about 2.5 s per sweep of 256 chains
+        # here, so the arms take 256 chains x 32 steps and the proposal
+        # trains on 512 chains x 16 configurations
+        th5 = torch.from_numpy(synth.theta(16, 16, 2, 6, seed=6)).to(dev)
+        out = ess_comparison(Context, th5, 16, 16, 6, 36, hamiltonians.j1j2(16, 16, 1.0, 0.0),
+                             args.made_steps, model="Heisenberg", chains=256, T=32, burn=8,
+                             data_chains=512, data_per=16, data_burn=8, compression="densmat")
+        print(json.dumps({"metric": "ESS/s of the energy series (learned proposal vs local MH)",
+                          "learned_proposal_16x16_D6_chi36": out}))
+        return
     Lx, Ly, D, chi = 10, 10, 5, 25
     model = ("chiral", dict(J1=1.0, J2=0.5, Jchi=0.2))
     ham = hamiltonians.chiral(Lx, Ly, J1=1.0, J2=0.5, Jchi=0.2)
@@ -465,12 +489,20 @@ def main():
     ref = Context(Lx, Ly, D, chi, "c128")
     ref.set_hamiltonian(ham)
     ref.set_compression("densmat")
-    # the timed set: uniform S_z = 0 configurations (the library's local
-    # sampler costs about 10 ms per chain sweep at this shape, so a fully
-    # Metropolis-drawn set of 8192 would take minutes); a Metropolis subset
-    # is drawn and evaluated separately below
-    samples = torch.from_numpy(synth.sz0_configs(Lx * Ly, nconf, seed=1)).to(dev)
-    sampler_used = "uniform S_z=0 configurations (seed 1)"
+    # the timed set: configurations drawn by the library's exchange
+    # Metropolis sampler in complex128 (density-matrix environments), up to
+    # 1024 chains, one sweep between samples after 8 burn-in sweeps
+    chains = min(1024, nconf)
+    per_chain = max(1, nconf // chains)
+    nconf = chains * per_chain
+    t0 = time.perf_counter()
+    samples, _acc = ref.sample(theta, "exchange", n_chains=chains, per_chain=per_chain, burn_in=8,
+                               thin=1, seed=1)
+    _sync()
+    t_smp = time.perf_counter() - t0
+    sampler_used = (f"exchange Metropolis, complex128, {chains} chains x {per_chain} samples, "
+                    f"burn-in 8, one sweep between samples (seed 1)")
+    _log(f"sampled {nconf} configurations in {t_smp:.1f} s")
     # complex128 reference on the whole set (untimed; its rate reported)
     out128 = ref.evaluate(theta, samples)
     _sync()
@@ -578,6 +610,7 @@ def main():
                                f"Jchi=0.2, {nconf} configurations",
                    "samples": sampler_used, "global_batch": B, "configurations": nconf,
                    "truncation": "density-matrix (Gram and density products on MFMA)"},
+        "sampling_s_c128": round(t_smp, 2),
         "energy_rel_err_vs_c128": rel_e,
         "eloc_rel_err_per_config": per_e,
         "ln_psi_abs_err_per_config": per_psi,
@@ -588,21 +621,6 @@ def main():
         "roofline": roofline,
         "rooflines": rooflines,
     }
-    # energy error on configurations drawn by the library's exchange sampler
-    # (complex64, 256 chains, 3 burn-in sweeps), evaluated in both precisions
-    t0 = time.perf_counter()
-    ms, _ = ctx.sample(theta, "exchange", n_chains=256, per_chain=1, burn_in=3, seed=1)
-    _sync()
-    t_ms = time.perf_counter() - t0
-    a = ctx.evaluate(theta, ms, want_o=False)
-    b = ref.evaluate(theta, ms, want_o=False)
-    rel_m, per_m, psi_m = _err_block(a[1][:, 0].double(), b[1][:, 0], a[0], b[0])
-    res["metropolis_subset"] = {
-        "samples": 256, "sampler": "exchange Metropolis, complex64, 256 chains, burn-in 3",
-        "sampling_s": round(t_ms, 2), "energy_rel_err_vs_c128": rel_m,
-        "eloc_rel_err_per_config": per_m, "ln_psi_abs_err_per_config": psi_m,
-        "energy_mean_c128": b[1][:, 0].mean().item()}
-    _log(f"Metropolis subset: {t_ms:.1f} s sampling, energy error {rel_m:.2e}")
     # minSR step on all configurations (n = 8192, complex parameters, FP64
     # Gram and solve) from the complex64 log-derivatives
     O, el = full[2], full[1]
