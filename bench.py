@@ -648,6 +648,18 @@ def main():
     ctx.set_minsr_solver("cholesky")
     res["minsr_solvers_ms_n1024"] = tims
     _log(f"minSR solvers at n={ne}: {tims}")
+    # one optimisation step end to end (complex64, density-matrix
+    # environments): 1024 chains x 1 sample after 8 burn-in sweeps, the
+    # evaluation, minSR and the update of theta
+    th_step = theta.clone()
+    t0 = time.perf_counter()
+    ctx.vmc_step(th_step, 1e-3, "exchange", n_chains=1024, per_chain=1, burn_in=8, seed=3)
+    _sync()
+    res["vmc_step_s"] = {"seconds": round(time.perf_counter() - t0, 3),
+                         "config": "complex64, 1024 chains x 1 sample, 8 burn-in sweeps, "
+                                   "evaluation, minSR (n = 1024) and theta update"}
+    _log(f"optimisation step: {res['vmc_step_s']['seconds']} s")
+    del th_step
     del dth, O, full, out128
     torch.cuda.empty_cache()
 

@@ -250,11 +250,14 @@ peps_status peps_local_energy_strict(peps_ctx* ctx, const double* theta,
 peps_status peps_logderiv(peps_ctx* ctx, const double* theta, const uint8_t* samples,
                           int n, const void* env_cache, void* O, void* stream);
 
-/* Vector-Jacobian product of ln Psi over a batch (the backward pass of the
- * log-amplitude): grad_theta[k] = sum_s g[s] O_k(S_s) with O from
- * peps_logderiv (compact, compute precision) expanded with zeros where
- * p != s_xy. g: FP64 [n]; grad_theta: FP64 [N_p], overwritten.
- * Real modes only (PEPS_ERR_UNSUPPORTED for complex parameters). */
+/* Vector-Jacobian product of ln|Psi| over a batch (the backward pass of the
+ * log-amplitude, Sec. "Finite PEPS and Sampling": dPsi/dT as a hole
+ * network): grad_theta[k] = sum_s g[s] O_k(S_s) with O from peps_logderiv
+ * (compact, compute precision) expanded with zeros where p != s_xy.
+ * g: FP64 [n]; grad_theta: FP64 [N_p], overwritten. Complex parameters:
+ * grad_theta is FP64 pairs [N_p][2] holding d/dRe theta_k + i d/dIm theta_k
+ * of sum_s g[s] ln|Psi(S_s)|, which is sum_s g[s] conj(O_k(S_s)) since
+ * ln|Psi| = Re ln Psi and ln Psi is holomorphic in theta. */
 peps_status peps_logderiv_vjp(peps_ctx* ctx, const void* O, const uint8_t* samples, int n,
                               const double* g, double* grad_theta, void* stream);
 

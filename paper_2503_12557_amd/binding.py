@@ -347,8 +347,9 @@ class Context:
         return dtheta, diag
 
     def logderiv_vjp(self, O, samples, g):
+        """sum_s g_s dln|Psi(S_s)|/dtheta (complex parameters: d/dRe + i d/dIm)."""
         import torch
-        out = torch.empty(self.n_params, dtype=torch.float64, device=O.device)
+        out = torch.empty(self.n_params, dtype=self.theta_dtype, device=O.device)
         _check(load().peps_logderiv_vjp(self._h, _ptr(O.contiguous()), _ptr(samples.contiguous()),
                                         samples.shape[0], _ptr(g.contiguous()), _ptr(out),
                                         _stream()))
@@ -526,7 +527,8 @@ def _autograd_function():
         Forward: peps_amplitude (ln|Psi| at the middle cut). Backward: the
         environments are rebuilt (not stored) and the one-row hole networks
         give O_k = d ln Psi_row(x)(S)/d theta_k (peps_logderiv); the gradient
-        is sum_s g_s Re O_s (peps_logderiv_vjp). In the exact-contraction
+        is sum_s g_s O_s for real parameters and sum_s g_s conj(O_s) (PyTorch's
+        d/dRe + i d/dIm) for complex ones (peps_logderiv_vjp). In the exact-contraction
         regime this is the exact derivative of the forward value; below the
         exact Schmidt rank it is the strip derivative (the cut of the
         forward value and the strip of row x are different approximations).

@@ -1061,15 +1061,15 @@ peps_status peps_logderiv_vjp(peps_ctx* c, const void* O, const uint8_t* samples
   if (!c) return fail(PEPS_ERR_ARG, "null context");
   if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
   if (!grad_theta || (n > 0 && (!O || !samples || !g))) return fail(PEPS_ERR_ARG, "null pointer");
-  if (is_complex(c->g.dtype))
-    return fail(PEPS_ERR_UNSUPPORTED, "the vector-Jacobian product is for real parameters");
   hipStream_t st = (hipStream_t)stream;
+  const bool cx = is_complex(c->g.dtype);
   if (n == 0) {
-    HIPCHK(hipMemsetAsync(grad_theta, 0, (size_t)c->L.n_params * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(grad_theta, 0, (size_t)c->L.n_params * (cx ? 2 : 1) * sizeof(double),
+                          st));
     return PEPS_OK;
   }
-  HIPCHK(launch_vjp(c->L, c->d_tab, c->g.dtype == PEPS_F64 ? MODE_F64 : MODE_F32, O, samples, n,
-                    g, grad_theta, st));
+  const int mode = c->g.dtype == PEPS_BF16 ? MODE_F32 : c->g.dtype;
+  HIPCHK(launch_vjp(c->L, c->d_tab, mode, O, samples, n, g, grad_theta, st));
   return PEPS_OK;
 }
 

@@ -835,6 +835,29 @@ __global__ void k_vjp(Lattice L, const int* __restrict__ tab, const TO* __restri
   out[off + blk + j] = acc1;
 }
 
+// Complex parameters: the gradient of sum_s g_s ln|Psi(S_s)| with respect to
+// (Re theta_k, Im theta_k) as the pair d/dRe + i d/dIm = sum_s g_s conj(O_sk)
+// (ln|Psi| = Re ln Psi and ln Psi is holomorphic with derivative O_k).
+template <typename R>
+__global__ void k_vjp_c(Lattice L, const int* __restrict__ tab, const cplx<R>* __restrict__ O,
+                        const uint8_t* __restrict__ samples, int n, const double* __restrict__ g,
+                        double* __restrict__ out) {
+  const int jc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jc >= L.n_compact) return;
+  const int site = tab[L.off_csite + jc];
+  const int j = jc - tab[L.off_compact + site];
+  const int off = tab[L.off_param + site], blk = tab[L.off_block + site];
+  cplx<double> acc0(0.0, 0.0), acc1(0.0, 0.0);
+  for (int s = 0; s < n; ++s) {
+    const cplx<R> o = O[(size_t)s * L.n_compact + jc];
+    const cplx<double> v((double)o.re * g[s], -(double)o.im * g[s]);
+    if (pbit(samples[(size_t)s * L.N + site])) acc1 += v;
+    else acc0 += v;
+  }
+  put(out, off + j, acc0);
+  put(out, off + blk + j, acc1);
+}
+
 hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
                       const uint8_t* samples, int n, const double* g, double* out,
                       hipStream_t st) {
@@ -842,6 +865,12 @@ hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
   if (mode == MODE_F64)
     hipLaunchKernelGGL(k_vjp<double>, dim3(cb), dim3(256), 0, st, L, tab, (const double*)O,
                        samples, n, g, out);
+  else if (mode == MODE_C128)
+    hipLaunchKernelGGL(k_vjp_c<double>, dim3(cb), dim3(256), 0, st, L, tab,
+                       (const cplx<double>*)O, samples, n, g, out);
+  else if (mode == MODE_C64)
+    hipLaunchKernelGGL(k_vjp_c<float>, dim3(cb), dim3(256), 0, st, L, tab,
+                       (const cplx<float>*)O, samples, n, g, out);
   else
     hipLaunchKernelGGL(k_vjp<float>, dim3(cb), dim3(256), 0, st, L, tab, (const float*)O,
                        samples, n, g, out);

@@ -154,10 +154,34 @@ def test_complex_minsr_matches_oracle(dev, dtype, n, eps):
     assert err <= tol
 
 
-def test_complex_vjp_is_rejected(dev):
-    from paper_2503_12557_amd.binding import PepsError
-    ctx = _ctx(3, 3, 2, 4, "c128")
-    O = torch.zeros(2, ctx.n_compact, dtype=torch.complex128, device=dev)
-    sm = torch.zeros(2, 9, dtype=torch.uint8, device=dev)
-    with pytest.raises(PepsError):
-        ctx.logderiv_vjp(O, sm, torch.ones(2, dtype=torch.float64, device=dev))
+def test_complex_vjp_matches_finite_differences(dev):
+    # exact contraction (3x3, D=2, chi=4): the autograd gradient of
+    # sum_s g_s ln|Psi(S_s)| w.r.t. complex parameters (PyTorch's
+    # d/dRe + i d/dIm) against central differences of the oracle's ln|Psi|
+    Lx, Ly, D, chi = 3, 3, 2, 4
+    theta = synth.theta(Lx, Ly, 2, D, seed=12, cplx=True)
+    cf = synth.sz0_configs(Lx * Ly - 1, 6, seed=13)
+    cf = np.concatenate([cf, np.zeros((6, 1), dtype=np.uint8)], axis=1)
+    g = np.random.default_rng(14).standard_normal(6)
+    ctx = _ctx(Lx, Ly, D, chi, "c128")
+    th = torch.from_numpy(theta).to(dev).requires_grad_(True)
+    sm = torch.from_numpy(cf).to(dev)
+    lp = ctx.log_abs_psi(th, sm)
+    (lp * torch.from_numpy(g).to(dev)).sum().backward()
+    grad = th.grad.cpu().numpy()
+
+    def f(t):
+        lpo = oracle_eval(t, Lx, Ly, D, chi, cf)[0]
+        return float(np.sum(g * np.real(lpo)))
+
+    rng = np.random.default_rng(15)
+    idx = rng.choice(theta.size, 12, replace=False)
+    h = 1e-6
+    for k in idx:
+        for unit in (1.0, 1j):
+            tp, tm = theta.copy(), theta.copy()
+            tp[k] += h * unit
+            tm[k] -= h * unit
+            fd = (f(tp) - f(tm)) / (2 * h)
+            got = grad[k].real if unit == 1.0 else grad[k].imag
+            assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (k, unit, got, fd)
