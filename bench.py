@@ -396,6 +396,42 @@ def _err_block(e_lo, e_hi, lp_lo, lp_hi):
         {"median": float(np.median(dpsi)), "p99": float(np.quantile(dpsi, 0.99))}
 
 
+def cutoff_workload(Context, hamiltonians):
+    """Throughput of the density-matrix environments with a maximal truncated
+    weight per bond (kept bonds carried through the contractions) against
+    fixed chi: 10x10 D=5 chi=25 J1-J2, real N(0.5,1) tensors (seed 4), FP32,
+    1024 uniform S_z = 0 configurations; ln Psi change against fixed chi."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    th = torch.from_numpy(synth.theta(10, 10, 2, 5, seed=4, mu=0.5)).to(dev)
+    sm = torch.from_numpy(synth.sz0_configs(100, 1024, seed=5)).to(dev)
+    out, base = {}, None
+    for cut in (0.0, 1e-4):
+        ctx = Context(10, 10, 5, 25, "f32")
+        ctx.set_hamiltonian(hamiltonians.j1j2(10, 10, 1.0, 0.5))
+        ctx.set_compression("densmat")
+        if cut:
+            ctx.set_truncation(cut)
+        o = ctx.evaluate(th, sm)
+        _sync()
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        t0 = time.perf_counter()
+        ctx.evaluate(th, sm, out=o)
+        _sync()
+        dt = time.perf_counter() - t0
+        pr = ctx.profile_read(reset=True)
+        lp = o[0][:, 0].double().cpu().numpy()
+        base = lp if base is None else base
+        out[f"cutoff_{cut:g}"] = {"samples_per_s": round(1024 / dt, 1),
+                                  "env_ms": round(pr["env"][0], 2),
+                                  "ln_psi_change_median": float(np.median(np.abs(lp - base)))}
+    out["workload"] = ("10x10 D=5 chi=25 J1-J2, real N(0.5,1) tensors seed 4, FP32, density-matrix "
+                       "truncation, 1024 uniform S_z=0 configurations")
+    return out
+
+
 def side_workload(Context, ham, Lx, Ly, D, chi, n, seed, mu, kind, dtypes, ref="f64",
                   compression="canonical"):
     """Throughput and energy error of reduced-precision modes on one of the
@@ -678,6 +714,7 @@ def main():
         res["workload_12x12_D4_chi16_rydberg_densmat"] = side_workload(
             Context, hamiltonians.rydberg(12, 12, Omega=1.0, Delta=3.0, V=1.7 ** 6), 12, 12, 4, 16,
             4096, 5, 0.0, "flip", ["f32", "bf16"], compression="densmat")
+        res["truncated_weight_10x10_D5_chi25"] = cutoff_workload(Context, hamiltonians)
         th2 = torch.from_numpy(synth.theta(8, 8, 2, 4, seed=2)).to(dev)
         _log("side workloads done")
         res["learned_proposal"] = ess_comparison(Context, th2, 8, 8, 4, 16,

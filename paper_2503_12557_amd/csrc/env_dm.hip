@@ -506,12 +506,37 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
   __syncthreads();
 }
 
+// Stored bonds of environment slot sp (left bond of every site, then 1):
+// the kept bonds of an environment read over its chi-wide layout.
+__device__ __forceinline__ void dm_first_bonds(const Lattice& L, const int* tab, int sp, int* kb) {
+  const int* ed = tab + L.off_env;
+  for (int y = threadIdx.x; y <= L.Ly; y += PEPS_NT) kb[y] = y < L.Ly ? ed[(sp * L.Ly + y) * 3] : 1;
+  __syncthreads();
+}
+
+// The leading [bl][din][br] block of a boundary tensor stored as
+// [.][din][brs] (kept bonds of a truncated-weight cut inside the chi-wide
+// layout), packed.
+template <typename T>
+__device__ __forceinline__ void load_block(T* dst, const T* src, int bl, int din, int br,
+                                           int brs) {
+  const int cnt = bl * din * br;
+  for (int i = threadIdx.x; i < cnt; i += PEPS_NT) {
+    const int ai = i / br, b = i - ai * br;
+    dst[i] = src[(size_t)ai * brs + b];
+  }
+}
+
 // One row absorbed by the density-matrix truncation (see the file header).
+// kprev[y] / kprev[y+1]: the kept left / right bond of site y of the
+// previous environment (kprev[Ly] = 1); the bonds kept here go to knew.
+// Every contraction runs over the kept bonds only; the tensors are stored
+// in the chi-wide layout with zeros beyond them.
 template <int M>
 __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename ModeT<M>::T* theta,
                               const uint8_t* s, bool bottom, int t, typename ModeT<M>::T* envs,
                               double* lg, typename ModeT<M>::T* slab, const DmSh<typename ModeT<M>::T>& sh,
-                              int* flp, int& slot) {
+                              int* flp, int& slot, const int* kprev, int* knew) {
   typedef typename ModeT<M>::T T;
   typedef typename RealOf<T>::type R;
   const int tid = threadIdx.x, NT = PEPS_NT;
@@ -542,10 +567,10 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
   __syncthreads();
   for (int y = 0; y < L.Ly - 1; ++y) {
     const SiteView v = site_view(tab, L, x * L.Ly + y, bottom);
-    const int bl = edims[(sp * L.Ly + y) * 3 + 0];
-    const int br = edims[(sp * L.Ly + y) * 3 + 2];
+    const int bl = kprev[y], br = kprev[y + 1];
+    const int brs = edims[(sp * L.Ly + y) * 3 + 2];
     const int Pl = bl * v.Dl, Pr = br * v.Dr;
-    load_lds(Ebuf, Eprev + (size_t)y * L.site_box, bl * v.Din * br);
+    load_block(Ebuf, Eprev + (size_t)y * L.site_box, bl, v.Din, br, brs);
     load_lds(Abuf, site_tensor(theta, tab, L, s, x * L.Ly + y), v.Dl * v.Dr * v.Din * v.Dout);
     __syncthreads();
     const T* Gy = Gs + (size_t)y * np2;
@@ -597,11 +622,14 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
   for (int y = L.Ly - 1; y >= 0; --y) {
     const int nsite = x * L.Ly + y;
     const SiteView v = site_view(tab, L, nsite, bottom);
-    const int bl = edims[(sp * L.Ly + y) * 3 + 0];
-    const int br = edims[(sp * L.Ly + y) * 3 + 2];
+    const int bl = kprev[y], br = kprev[y + 1];
+    const int brs = edims[(sp * L.Ly + y) * 3 + 2];
     const int Pl = bl * v.Dl;
     const int zc = v.Dout * nbr;
-    load_lds(Ebuf, Eprev + (size_t)y * L.site_box, bl * v.Din * br);
+    // the new tensor's stored (chi-wide) left and right bonds
+    const int rs = edims[(sn * L.Ly + y) * 3 + 0];
+    const int nbrs = edims[(sn * L.Ly + y) * 3 + 2];
+    load_block(Ebuf, Eprev + (size_t)y * L.site_box, bl, v.Din, br, brs);
     load_lds(Abuf, site_tensor(theta, tab, L, s, nsite), v.Dl * v.Dr * v.Din * v.Dout);
     __syncthreads();
     // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]
@@ -630,6 +658,7 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     }
     __syncthreads();
     int rnew;
+    int rkeep_row = 1;
     if (y > 0) {
       const T* Gy = Gs + (size_t)y * np2;
       // Y = G_y Z, rho = Z^H Y (Hermitian)
@@ -653,7 +682,7 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
         for (int i = tid; i < zc * zc; i += NT) Pk[(size_t)(i / zc) * np + (i % zc)] *= fsc;
       trc = block_sum(trc, reinterpret_cast<double*>(sh.red + 16 * slot));
       __syncthreads();
-      rnew = edims[(sn * L.Ly + y) * 3 + 0];
+      rnew = rs < zc ? rs : zc;
       const int rr = rnew + 1 < zc ? rnew + 1 : zc;
       R tnorm;
       dm_eig<T>(Pk, np, zc, rnew, rr, Hv, Yt, lu, sh, slot, tnorm);
@@ -692,6 +721,7 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
       }
       __syncthreads();
       const int rkeep = s_keep;
+      rkeep_row = rkeep;
       // discarded columns of the kept block are zero
       T* Xe = sh.big;
       if (rkeep < rnew)
@@ -714,10 +744,12 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
         logrow += log((double)bm);
       }
       T* dst = Enew + (size_t)y * L.site_box;
-      for (int i = tid; i < rnew * zc; i += NT) {
-        const int j = i / zc, e = i - j * zc;
-        dst[i] = conjx(Xe[e * rnew + j]) * binv;
+      const int kc = v.Dout * nbrs;
+      for (int i = tid; i < rs * kc; i += NT) {
+        const int j = i / kc, rem = i - j * kc, k = rem / nbrs, c = rem - k * nbrs;
+        dst[i] = (j < rkeep && c < nbr) ? conjx(Xe[(k * nbr + c) * rnew + j]) * binv : T(0);
       }
+      if (tid == 0) knew[y] = rkeep;
       __syncthreads();
       // W carries the weight of the sites to its right: unit scale, the
       // power of two into the log scale
@@ -751,10 +783,17 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
       }
       const R zinv = R(1) / zm;
       T* dst = Enew + (size_t)y * L.site_box;
-      for (int i = tid; i < zc; i += NT) dst[i] = Z[i] * zinv;
+      for (int i = tid; i < v.Dout * nbrs; i += NT) {
+        const int k = i / nbrs, c = i - k * nbrs;
+        dst[i] = c < nbr ? Z[k * nbr + c] * zinv : T(0);
+      }
+      if (tid == 0) {
+        knew[0] = 1;
+        knew[L.Ly] = 1;
+      }
       __syncthreads();
     }
-    nbr = rnew;
+    nbr = y > 0 ? rkeep_row : 1;
   }
   if (tid == 0) lg[sn] = lg[sp] + logrow;
   __syncthreads();
@@ -792,8 +831,12 @@ k_env_dm(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     es.Ebuf = sh.big;
     es.red = sh.red;
     env_first_row<M>(L, tab, theta, s, bottom, envs, lg, es, &fl);
+    // kept bonds of the environment absorbed next (the first row's: exact)
+    __shared__ int kb[2][33];
+    dm_first_bonds(L, tab, bottom ? slot_bottom(L, L.Lx - 1) : slot_top(L, 0), kb[0]);
     for (int t = 1; t <= L.Lx - 2; ++t)
-      dm_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, myslab, sh, &fl, slot);
+      dm_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, myslab, sh, &fl, slot,
+                       kb[(t - 1) & 1], kb[t & 1]);
     if (threadIdx.x == 0 && fl && flags) atomicOr(flags + smp, fl);
     __syncthreads();
   }
@@ -830,8 +873,15 @@ k_smp_env_dm(Lattice L, const int* __restrict__ tab,
     env_first_row<M>(L, tab, theta, s, bottom, envs, lg, es, &fl);
   }
   const int t0 = bottom ? 1 : row, t1 = bottom ? L.Lx - 2 : row;
-  for (int t = t0 > 1 ? t0 : 1; t <= t1; ++t)
-    dm_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, myslab, sh, &fl, slot);
+  // kept bonds carried within this launch; a top row absorbed alone reads
+  // the previous row's tensors over their stored (chi-wide, zero-padded)
+  // bonds
+  __shared__ int kb[2][33];
+  const int tf = t0 > 1 ? t0 : 1;
+  dm_first_bonds(L, tab, bottom ? slot_bottom(L, L.Lx - 1) : slot_top(L, tf - 1), kb[0]);
+  for (int t = tf; t <= t1; ++t)
+    dm_absorb_row<M>(L, tab, theta, s, bottom, t, envs, lg, myslab, sh, &fl, slot,
+                     kb[(t - tf) & 1], kb[(t - tf + 1) & 1]);
 }
 
 // ---- host side ----
