@@ -637,25 +637,12 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
       mgemm<T, false, false, M == MODE_BF16>(bl * v.Din, nbr, br, Ebuf, br, 1, W + (size_t)r * np, v.Dr * np, 1,
                              T1 + r * nbr, v.Dr * nbr, false, false);
     __syncthreads();
-    // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]
-    {
-      const int tot = Pl * zc;
-      const FastDiv fzc(zc), fDl(v.Dl), fnbr(nbr);
-      for (int i = tid; i < tot; i += NT) {
-        int row = i;
-        int col = divmod(row, fzc);
-        const int l = divmod(row, fDl);
-        const int aa = row;
-        const int c = divmod(col, fnbr);
-        const int k = col;
-        T acc = 0;
-        for (int in = 0; in < v.Din; ++in)
-          for (int r = 0; r < v.Dr; ++r)
-            acc += opnd<M>(T1[(size_t)(aa * v.Din + in) * (v.Dr * nbr) + r * nbr + c]) *
-                   opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]);
-        Z[(size_t)(aa * v.Dl + l) * np + k * nbr + c] = acc;
-      }
-    }
+    // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]: one product
+    // with rows (a,c), columns (l,k) and contracted (in,r)
+    mgemm_map<T, false, false, M == MODE_BF16>(
+        bl * nbr, v.Dl * v.Dout, v.Din * v.Dr, T1, IMap(nbr, v.Din * v.Dr * nbr, 1), IMap(nbr),
+        Abuf, IMap(v.Dr, v.s_in, v.s_r), IMap(v.Dout, v.s_l, v.s_out), Z,
+        IMap(nbr, v.Dl * np, 1), IMap(v.Dout, np, nbr), false, false);
     __syncthreads();
     int rnew;
     int rkeep_row = 1;
