@@ -632,10 +632,11 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     load_block(Ebuf, Eprev + (size_t)y * L.site_box, bl, v.Din, br, brs);
     load_lds(Abuf, site_tensor(theta, tab, L, s, nsite), v.Dl * v.Dr * v.Din * v.Dout);
     __syncthreads();
-    // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]
-    for (int r = 0; r < v.Dr; ++r)
-      mgemm<T, false, false, M == MODE_BF16>(bl * v.Din, nbr, br, Ebuf, br, 1, W + (size_t)r * np, v.Dr * np, 1,
-                             T1 + r * nbr, v.Dr * nbr, false, false);
+    // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]: one product with
+    // columns (r,c)
+    mgemm_map<T, false, false, M == MODE_BF16>(
+        bl * v.Din, v.Dr * nbr, br, Ebuf, IMap(br), IMap(1), W, IMap(v.Dr * np),
+        IMap(nbr, np, 1), T1, IMap(v.Dr * nbr), IMap(1), false, false);
     __syncthreads();
     // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]: one product
     // with rows (a,c), columns (l,k) and contracted (in,r)
