@@ -30,6 +30,10 @@ def flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # keep the compiler from emitting packed FP32 arithmetic
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # inline every device helper into its kernel: past the default
+            # basic-block budget the inliner emits calls, and a helper called
+            # out of line addresses its LDS operands through flat pointers
+            "-mllvm", "-amdgpu-inline-max-bb=20000",
             "-Wno-unused-result", "-Wno-unused-value", "-I", os.path.join(HERE, "..", "include")]
 
 

@@ -55,16 +55,21 @@ __host__ __device__ inline int dm_rmax(int chi) { return chi + 1; }
 
 // Slab of one workgroup (elements of T unless noted):
 //   G   : Ly x NP x NP  left Gram environments G_0 .. G_{Ly-1}
-//   Pk, X, Z, T1, W, Hv : NP x NP each
-//   then reals: Yt (RMAX x NP), lu (RMAX x 6 x NP): the iterates and U bands
-//   of the eigenvector phase when they do not fit in LDS
+//   then the right sweep's Pk, X, Z, T1, W, Hv (NP x NP each) and reals Yt
+//   (RMAX x NP), lu (RMAX x 6 x NP): the iterates and U bands of the
+//   eigenvector phase when they do not fit in LDS; the left sweep's two
+//   intermediates W1, W2 (B^2 D^3 each) overlay the same region
+__host__ __device__ inline size_t dm_wsz(int bmax, int D) {
+  return (size_t)bmax * bmax * D * D * D;
+}
 __host__ __device__ inline size_t dm_slab_elems(int Ly, int bmax, int D, int chi, size_t tsize,
                                                 size_t rsize) {
   const size_t np = dm_np(bmax, D);
   const size_t rm = dm_rmax(chi);
-  const size_t t_el = ((size_t)Ly + 6) * np * np;
   const size_t r_bytes = rm * np * 7 * rsize;
-  return t_el + (r_bytes + tsize - 1) / tsize + 64;
+  const size_t right = 6 * np * np + (r_bytes + tsize - 1) / tsize;
+  const size_t left = 2 * dm_wsz(bmax, D);
+  return (size_t)Ly * np * np + (right > left ? right : left) + 64;
 }
 
 // LDS: one big region (the staged E and A of a site, then the packed
@@ -222,16 +227,29 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
   __syncthreads();
 }
 
+// a / b on the serial chains of the eigenvector phase (Sturm counts,
+// inverse iteration): FP32 takes the hardware reciprocal (1 ulp) times a,
+// FP64 the correctly rounded quotient. Both recurrences only need the
+// quotient to a few ulp: a Sturm count changes only for shifts within
+// rounding of an eigenvalue, and inverse iteration converges from any
+// nearby solve.
+template <typename R>
+__device__ __forceinline__ R quot(R a, R b) { return a / b; }
+template <>
+__device__ __forceinline__ float quot<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
 // Eigenvalues below x of the symmetric tridiagonal (d, e^2): Sturm count.
 template <typename R>
 __device__ __forceinline__ int sturm(const R* d, const R* e2, int n, R x, R pivmin) {
   int c = 0;
   R qv = d[0] - x;
-  if (fabs((double)qv) < (double)pivmin) qv = -pivmin;
+  if (fabs(qv) < pivmin) qv = -pivmin;
   c += qv < R(0);
   for (int i = 1; i < n; ++i) {
-    qv = (d[i] - x) - e2[i - 1] / qv;
-    if (fabs((double)qv) < (double)pivmin) qv = -pivmin;
+    qv = (d[i] - x) - quot(e2[i - 1], qv);
+    if (fabs(qv) < pivmin) qv = -pivmin;
     c += qv < R(0);
   }
   return c;
@@ -348,7 +366,7 @@ __device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* 
       const R rn = y[(size_t)(i + 1) * ld];
       const size_t o = (size_t)i * ld;
       if (fabs(s0) > fabs(c0)) {
-        const R mm = c0 / s0;
+        const R mm = quot(c0, s0);
         u0[o] = s0;
         u1[o] = s1;
         u2[o] = s2;
@@ -358,7 +376,7 @@ __device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* 
         r0 = r0 - mm * rn;
       } else {
         if (c0 == R(0)) c0 = tiny;
-        const R mm = s0 / c0;
+        const R mm = quot(s0, c0);
         u0[o] = c0;
         u1[o] = c1;
         u2[o] = R(0);
@@ -380,7 +398,7 @@ __device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* 
       R s = y[o];
       if (i + 1 < n) s -= u1[o] * y1;
       if (i + 2 < n) s -= u2[o] * y2;
-      s /= u0[o];
+      s = quot(s, u0[o]);
       y[o] = s;
       y2 = y1;
       y1 = s;
@@ -551,6 +569,9 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
   T* Hv = W + np2;
   R* Yt = reinterpret_cast<R*>(Hv + np2);
   R* lu = Yt + (size_t)dm_rmax(L.chi) * np;
+  T* W1 = Pk;
+  T* W2 = W1 + dm_wsz(L.bmax, L.D);
+  constexpr bool CX = IsCplx<T>::value, BFM = M == MODE_BF16;
   T* Ebuf = sh.big;
   T* Abuf = Ebuf + L.bmax * L.D * L.bmax;
   int& fl = *flp;
@@ -575,30 +596,34 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     __syncthreads();
     const T* Gy = Gs + (size_t)y * np2;
     T* Gn = Gs + (size_t)(y + 1) * np2;
-    const FastDiv fPr(Pr), fDl(v.Dl), fDr(v.Dr);
-    for (int k = 0; k < v.Dout; ++k) {
-      // P_k[(a,l),(b,r)] = sum_in E[a,in,b] A[l,r,in,k]
-      for (int i = tid; i < Pl * Pr; i += NT) {
-        int row = i;
-        int col = divmod(row, fPr);
-        const int l = divmod(row, fDl);
-        const int aa = row;
-        const int r = divmod(col, fDr);
-        const int b = col;
-        T acc = 0;
-        for (int in = 0; in < v.Din; ++in)
-          acc += opnd<M>(Ebuf[(aa * v.Din + in) * br + b]) *
-                 opnd<M>(Abuf[l * v.s_l + r * v.s_r + in * v.s_in + k * v.s_out]);
-        Pk[(size_t)(i / Pr) * np + (i - (i / Pr) * Pr)] = acc;
-      }
-      __syncthreads();
-      // X = G_y P_k (G_y Hermitian: read as conj(G_y)^T, rows coalesced)
-      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(Pl, Pr, Pl, Gy, 1, np, Pk, np, 1, X, np, false, false);
-      __syncthreads();
-      // G_{y+1} (+)= P_k^H X
-      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(Pr, Pr, Pl, Pk, 1, np, X, np, 1, Gn, np, true, k > 0);
-      __syncthreads();
-    }
+    // G_{y+1} = sum_k P_k^H G_y P_k contracted one tensor at a time (no P_k
+    // is formed): E, A, conj(A), conj(E), each step one matrix-core product
+    // W1[(a,l,l'),(in,b)] = sum_a' G[(a,l),(a',l')] E[a',in,b]
+    const int n1 = v.Din * br;
+    mgemm_map<T, false, false, BFM>(Pl * v.Dl, n1, bl, Gy, IMap(v.Dl, np, 1), IMap(v.Dl), Ebuf,
+                                    IMap(n1), IMap(1), W1, IMap(n1), IMap(1), false, false);
+    __syncthreads();
+    // W2[(a,l,b),(r,k)] = sum_{(l',in)} W1[(a,l,l'),(in,b)] A[l',r,in,k]
+    const int n2 = v.Dr * v.Dout;
+    mgemm_map<T, false, false, BFM>(Pl * br, n2, v.Dl * v.Din, W1, IMap(br, v.Dl * n1, 1),
+                                    IMap(v.Din, n1, br), Abuf, IMap(v.Din, v.s_l, v.s_in),
+                                    IMap(v.Dout, v.s_r, v.s_out), W2, IMap(n2), IMap(1), false,
+                                    false);
+    __syncthreads();
+    // W3[(a,b,r'),(in',r)] = sum_{(l,k)} W2[(a,l,b),(r',k)] conj(A[l,r,in',k])
+    // (into W1)
+    const int n3 = v.Din * v.Dr;
+    mgemm_map<T, false, CX, BFM>(bl * br * v.Dr, n3, v.Dl * v.Dout, W2,
+                                 IMap(br * v.Dr, v.Dl * br * n2, v.Dout), IMap(v.Dout, br * n2, 1),
+                                 Abuf, IMap(v.Dout, v.s_l, v.s_out), IMap(v.Dr, v.s_in, v.s_r), W1,
+                                 IMap(n3), IMap(1), false, false);
+    __syncthreads();
+    // G_{y+1}[(b,r),(b',r')] = sum_{(a,in')} W3[(a,b',r'),(in',r)] conj(E[a,in',b]),
+    // rows (b',r',r) of the product scattered to their places in G_{y+1}
+    mgemm_map<T, false, CX, BFM>(br * v.Dr * v.Dr, br, bl * v.Din, W1, IMap(v.Dr, n3, 1),
+                                 IMap(v.Din, br * v.Dr * n3, v.Dr), Ebuf, IMap(br), IMap(1), Gn,
+                                 IMap(v.Dr, 1, np), IMap(v.Dr * np), false, false);
+    __syncthreads();
     // unit scale: the Gram only fixes directions
     R mx = 0;
     for (int i = tid; i < Pr; i += NT) {

@@ -469,7 +469,7 @@ __device__ __forceinline__ void s2_step_right(const T* Rp, const T* U, int ua, i
 // output layouts as s1_step_left / s1_step_right.
 // ---------------------------------------------------------------------------
 template <typename T, bool BF = false>
-__device__ void s1_step_left_mm(const T* Lp, const T* U, int ua, int ub, const T* A, int Dl,
+__device__ __forceinline__ void s1_step_left_mm(const T* Lp, const T* U, int ua, int ub, const T* A, int Dl,
                                 int Dr, int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2,
                                 T* Lout) {
   // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
@@ -534,7 +534,7 @@ __device__ void s1_hole_mm(const T* Lp, const T* U, int ua, int ub, int Dl, int 
 // X1. Same contractions and output layouts as s2_step_left / s2_step_right.
 // ---------------------------------------------------------------------------
 template <typename T, bool BF = false>
-__device__ void s2_step_left_mm(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
+__device__ __forceinline__ void s2_step_left_mm(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
                                 int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2,
                                 int Dd2, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout) {
   const int inner = Dl1 * Dl2 * ba;
