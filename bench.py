@@ -86,8 +86,8 @@ CANONICAL_ENV_FLOPS_10x10_D5_CHI25 = 24.9e9
 
 def dm_env_flops_per_sample(Lx, Ly, D, chi, cplx):
     """Algorithmic flops of the density-matrix environment build per sample
-    (both directions), split into matrix-core work (the Gram, density and
-    weight products) and the rest (projections, eigensolver). A real
+    (both directions), split into matrix-core work (the Gram, projection,
+    density and weight products) and the rest (eigensolver). A real
     m x n x k product counts 2mnk, a complex one 8mnk; a Hermitian result
     counts its lower triangle; the Householder tridiagonalisation of an n x n
     Hermitian matrix 16n^3/3 (complex) or 4n^3/3 (real), its back
@@ -96,16 +96,18 @@ def dm_env_flops_per_sample(Lx, Ly, D, chi, cplx):
     mm = alu = 0.0
     for rows in env_bonds(Lx, Ly, D, chi):
         for sites in rows:
-            for st in sites[:-1]:   # left sweep
-                Pl, Pr = st["bl"] * st["Dl"], st["br"] * st["Dr"]
-                for _ in range(st["Dout"]):
-                    alu += cf * 2.0 * Pl * Pr * st["Din"]
-                    mm += cf * (2.0 * Pl * Pl * Pr + Pl * Pr * (Pr + 1.0))
+            for st in sites[:-1]:   # left sweep: G E, then A, conj(A), conj(E)
+                bl, br, Dl, Dr = st["bl"], st["br"], st["Dl"], st["Dr"]
+                Din, Dout = st["Din"], st["Dout"]
+                mm += cf * 2.0 * (bl * Dl * Dl * Din * br * bl
+                                  + bl * Dl * br * Dr * Dout * Dl * Din
+                                  + bl * br * Dr * Din * Dr * Dl * Dout
+                                  + br * Dr * Dr * br * bl * Din)
             for st in sites:        # right sweep
                 Pl = st["bl"] * st["Dl"]
                 zc = st["Dout"] * st["nbr"]
                 mm += cf * 2.0 * st["bl"] * st["Din"] * st["nbr"] * st["br"] * st["Dr"]
-                alu += cf * 2.0 * Pl * zc * st["Din"] * st["Dr"]
+                mm += cf * 2.0 * Pl * zc * st["Din"] * st["Dr"]
                 if st["y"] > 0:
                     mm += cf * (2.0 * Pl * Pl * zc + Pl * zc * (zc + 1.0) + 2.0 * Pl * zc * st["r"])
                     alu += (16.0 / 3.0 if cplx else 4.0 / 3.0) * zc ** 3
