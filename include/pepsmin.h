@@ -238,6 +238,39 @@ peps_status peps_local_energy_strict(peps_ctx* ctx, const double* theta,
                                      const uint8_t* samples, int n, double* eloc,
                                      int32_t* flags, void* stream);
 
+/* Rotated-basis estimator (Sec. "On reusing environments and the convenient
+ * treatment of long-range interactions"; App. "Sampling-based PEPS schemes
+ * can yield a variational upper bound on the energy"): the terms of a
+ * Hamiltonian split into sets that are each diagonal in one product basis
+ * (a long-range Heisenberg model: the X X, Y Y and Z Z terms). For a set
+ * diagonal in the eigenbasis of sigma^b, the PEPS U_b^(x N) Psi is sampled
+ * and the set's diagonal form evaluated on its configurations; the sum over
+ * the sets estimates <H> with no amplitude ratio.
+ *
+ * peps_rotate_basis writes the parameters of U_b^(x N) Psi: every site
+ * tensor's physical index multiplied by U_b, T'[s] = sum_p U_b[s,p] T[p],
+ * with U_x the Hadamard matrix (U_x X U_x^dagger = Z) and U_y = H S^dagger,
+ * S = diag(1, i) (U_y Y U_y^dagger = Z); PEPS_BASIS_Z copies. theta and
+ * theta_out: FP64 device arrays in the context's parameter layout ([N_p], or
+ * [N_p][2] for complex contexts); they may be the same array. PEPS_BASIS_Y
+ * needs a complex context (PEPS_ERR_UNSUPPORTED otherwise: the rotated
+ * tensors are complex); another basis value is PEPS_ERR_ARG. Queued on
+ * stream. */
+#define PEPS_BASIS_Z 0
+#define PEPS_BASIS_X 1
+#define PEPS_BASIS_Y 2
+peps_status peps_rotate_basis(peps_ctx* ctx, const double* theta, int basis, double* theta_out,
+                              void* stream);
+
+/* The diagonal part of the context's Hamiltonian on each configuration:
+ * eloc[n][2] (re, im) FP64 device array, sum_t <S|h_t|S> + the long-range
+ * pairs + the on-site table, no amplitude. With a Hamiltonian whose terms are
+ * all diagonal (a set of the rotated-basis estimator in its rotated form)
+ * this is the set's local energy. Needs a Hamiltonian (PEPS_ERR_ARG
+ * otherwise). Queued on stream. */
+peps_status peps_energy_diag(peps_ctx* ctx, const uint8_t* samples, int n, double* eloc,
+                             void* stream);
+
 /* Log-derivatives O_k(S) = d ln Psi_row(x)(S) / d theta_k for every
  * parameter k of a site (x, y) with physical index s_xy (the hole network
  * of row x between E^u[x-1] and E^l[x+1], divided by that strip's

@@ -24,6 +24,7 @@ FLAG_ZERO, FLAG_NONFINITE, FLAG_NOCONV, FLAG_DEGENERATE = 1, 2, 4, 8
 SAMPLE_EXCHANGE, SAMPLE_FLIP, SAMPLE_IMH = 0, 1, 2
 COMPRESS = {"canonical": 0, "densmat": 1}
 MINSR_SOLVER = {"cholesky": 0, "eigh": 1, "auto": 2}
+BASIS = {"z": 0, "x": 1, "y": 2}
 
 # every symbol the header declares
 EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
@@ -34,7 +35,8 @@ EXPORTS = ["peps_create", "peps_destroy", "peps_last_error", "peps_num_params",
            "imh_step", "peps_logderiv_vjp", "peps_vmc_step", "peps_local_energy_strict",
            "peps_set_truncation", "peps_direct_sample", "peps_set_compression",
            "peps_set_minsr_solver",
-           "minsr_step_noalloc", "made_train", "peps_tau_int"]
+           "minsr_step_noalloc", "made_train", "peps_tau_int", "peps_rotate_basis",
+           "peps_energy_diag"]
 PROF_KINDS = ["env", "overlap", "strip1", "strip2", "esum", "minsr", "sample", "unused"]
 
 
@@ -130,6 +132,10 @@ def load():
     lib.imh_step.restype = I
     lib.peps_logderiv_vjp.argtypes = [P, P, P, I, P, P, P]
     lib.peps_logderiv_vjp.restype = I
+    lib.peps_rotate_basis.argtypes = [P, P, I, P, P]
+    lib.peps_rotate_basis.restype = I
+    lib.peps_energy_diag.argtypes = [P, P, I, P, P]
+    lib.peps_energy_diag.restype = I
     _lib = lib
     return lib
 
@@ -294,6 +300,50 @@ class Context:
         _check(load().peps_local_energy_strict(self._h, _ptr(theta), _ptr(samples), n,
                                                _ptr(eloc), _ptr(flags), _stream()))
         return eloc
+
+    def rotate_basis(self, theta, basis):
+        """Parameters of U_b^(x N) Psi (basis "x": Hadamard, "y": H S^dagger,
+        complex contexts only; "z" copies), same layout as theta."""
+        import torch
+        theta = self._theta(theta)
+        out = torch.empty_like(theta)
+        _check(load().peps_rotate_basis(self._h, _ptr(theta), BASIS[basis], _ptr(out), _stream()))
+        return out
+
+    def energy_diag(self, samples):
+        """Diagonal part of the context's Hamiltonian per configuration,
+        [n, 2] (re, im); no amplitude is computed."""
+        import torch
+        assert samples.dtype == torch_uint8() and samples.is_cuda
+        assert samples.dim() == 2 and samples.shape[1] == self.Lx * self.Ly
+        samples = samples.contiguous()
+        n = samples.shape[0]
+        eloc = torch.empty(n, 2, dtype=torch.float64, device=samples.device)
+        _check(load().peps_energy_diag(self._h, _ptr(samples), n, _ptr(eloc), _stream()))
+        return eloc
+
+    def rotated_energy(self, theta, sets, n_chains=256, per_chain=8, burn_in=32, seed=0):
+        """Rotated-basis estimate of <H> (Sec. "On reusing environments and
+        the convenient treatment of long-range interactions"): for every
+        (basis, diagonal term set) of ``sets`` the rotated PEPS is sampled
+        with single-spin flips and the set's diagonal energy averaged.
+        Replaces the context's Hamiltonian. Returns {basis: (mean, standard
+        error over chains)} and their sum under "total"."""
+        import torch
+        out, tot, var = {}, 0.0, 0.0
+        for b, ham in sets.items():
+            th = self.rotate_basis(theta, b)
+            self.set_hamiltonian(ham)
+            smp, _ = self.sample(th, "flip", n_chains=n_chains, per_chain=per_chain,
+                                 burn_in=burn_in, seed=seed)
+            e = self.energy_diag(smp)[:, 0].reshape(n_chains, per_chain).mean(dim=1)
+            mean = float(e.mean())
+            err = float(e.std() / n_chains ** 0.5) if n_chains > 1 else float("nan")
+            out[b] = (mean, err)
+            tot += mean
+            var += err * err
+        out["total"] = (tot, var ** 0.5)
+        return out
 
     def logderiv(self, theta, samples, env_cache=None):
         import torch

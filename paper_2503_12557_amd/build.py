@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpepsmin.so")
 SOURCES = ["env.hip", "env_dm.hip", "strip.hip", "minsr.hip", "eigh.hip", "sample.hip", "made.hip",
-           "direct.hip",
+           "direct.hip", "rotate.hip",
            "api.hip"]
 ARCH = "gfx950"
 

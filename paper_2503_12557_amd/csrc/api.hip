@@ -1073,6 +1073,38 @@ peps_status peps_logderiv_vjp(peps_ctx* c, const void* O, const uint8_t* samples
   return PEPS_OK;
 }
 
+peps_status peps_rotate_basis(peps_ctx* c, const double* theta, int basis, double* theta_out,
+                              void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (!theta || !theta_out) return fail(PEPS_ERR_ARG, "null pointer");
+  if (basis < PEPS_BASIS_Z || basis > PEPS_BASIS_Y)
+    return fail(PEPS_ERR_ARG, "basis %d (0 = Z, 1 = X, 2 = Y)", basis);
+  const bool cx = is_complex(c->g.dtype);
+  if (basis == PEPS_BASIS_Y && !cx)
+    return fail(PEPS_ERR_UNSUPPORTED, "the Y rotation gives complex tensors: use a complex context");
+  hipStream_t st = (hipStream_t)stream;
+  if (basis == PEPS_BASIS_Z) {
+    if (theta_out != theta)
+      HIPCHK(hipMemcpyAsync(theta_out, theta, (size_t)c->L.n_params * (cx ? 2 : 1) * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    return PEPS_OK;
+  }
+  HIPCHK(launch_rotate_basis(c->L, c->d_tab, basis == PEPS_BASIS_X ? ROT_X : ROT_Y, cx, theta,
+                             theta_out, st));
+  return PEPS_OK;
+}
+
+peps_status peps_energy_diag(peps_ctx* c, const uint8_t* samples, int n, double* eloc,
+                             void* stream) {
+  if (!c) return fail(PEPS_ERR_ARG, "null context");
+  if (n < 0) return fail(PEPS_ERR_ARG, "negative sample count");
+  if (n > 0 && (!samples || !eloc)) return fail(PEPS_ERR_ARG, "null pointer");
+  if (!c->has_ham) return fail(PEPS_ERR_ARG, "no Hamiltonian set");
+  if (n == 0) return PEPS_OK;
+  HIPCHK(launch_energy_diag_sum(c->L, c->H, samples, nullptr, 0, eloc, n, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
 peps_status peps_profile(peps_ctx* c, int enable) {
   if (!c) return fail(PEPS_ERR_ARG, "null context");
   c->prof = enable != 0;

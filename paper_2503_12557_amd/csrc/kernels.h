@@ -152,6 +152,14 @@ hipError_t launch_imh(int n_chains, int N, uint8_t* state, double* st_lp, double
                       const uint8_t* prop, const double* pr_lp, const double* pr_lq, uint64_t seed,
                       uint64_t step, int* accepted, hipStream_t st);
 
+// global basis rotation of FP64 parameters (real, or interleaved complex):
+// ROT_X multiplies every physical index by the Hadamard matrix, ROT_Y by
+// H S^dagger (complex parameters only); in and out may alias
+#define ROT_X 1
+#define ROT_Y 2
+hipError_t launch_rotate_basis(const Lattice& L, const int* tab, int basis, bool cplx,
+                               const double* in, double* out, hipStream_t st);
+
 hipError_t launch_vjp(const Lattice& L, const int* tab, int mode, const void* O,
                       const uint8_t* samples, int n, const double* g, double* out,
                       hipStream_t st);

@@ -12,7 +12,11 @@ Models (arXiv 2503.12557):
     i*lam*(P - P^-1) equals 2*lam times that four-triangle sum (Sec.
     "Chiral spin liquid");
   * Rydberg array Omega/2 sum sigma^x - Delta sum n + sum_{i<j} V/r^6 n n
-    (Sec. "Rydberg atom arrays and long-range interactions").
+    (Sec. "Rydberg atom arrays and long-range interactions");
+  * long-range Heisenberg sum_{i<j} J / r^alpha S_i . S_j (plus a uniform
+    field h . S) as the three sets of the rotated-basis estimator, each in
+    its diagonal form (Sec. "On reusing environments and the convenient
+    treatment of long-range interactions").
 """
 from __future__ import annotations
 
@@ -126,3 +130,26 @@ def rydberg(Lx, Ly, Omega=1.0, Delta=1.0, V=1.7 ** 6):
             b.pair_ij.append((i, j))
             b.pair_v.append(V / float(r2) ** 3)
     return b.done()
+
+
+def long_range_heisenberg_sets(Lx, Ly, J=1.0, alpha=3.0, field=(0.0, 0.0, 0.0)):
+    """The X X, Y Y and Z Z parts of sum_{i<j} J / r_ij^alpha S_i . S_j +
+    sum_n (h_x S^x_n + h_y S^y_n + h_z S^z_n), each rotated to the Z basis
+    (J / r^alpha S^z S^z per pair, h_b S^z per site): keys "x", "y", "z" for
+    the rotations of peps_rotate_basis."""
+    N = Lx * Ly
+    sz = 0.5 * np.diag([1.0, -1.0]).astype(complex)
+    zz = np.kron(sz, sz)
+    out = {}
+    for b, h in zip("xyz", field):
+        bld = _Builder(N)
+        for i in range(N):
+            xi, yi = divmod(i, Ly)
+            for j in range(i + 1, N):
+                xj, yj = divmod(j, Ly)
+                r = float(np.hypot(xi - xj, yi - yj))
+                bld.term((i, j), (J / r ** alpha) * zz)
+            if h:
+                bld.term((i,), h * sz)
+        out[b] = bld.done()
+    return out

@@ -61,3 +61,5 @@ def test_null_arguments_of_the_newer_entry_points():
     assert lib.made_train(None, None, None, 8, 1, 4, 0, 1e-3, 0.9, 0.999, 1e-8, 0, None, None,
                           None, None) == 1
     assert lib.peps_tau_int(None, 4, 8, 0, 5.0, None, None, None) == 1
+    assert lib.peps_rotate_basis(None, None, 1, None, None) == 1
+    assert lib.peps_energy_diag(None, None, 4, None, None) == 1
