@@ -476,17 +476,25 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
   int P = 64;
   while (P > 1 && r * P > NT) P >>= 1;
   const int col = tid / P, part = tid - col * P;
-  constexpr int VPL = 8;  // reflector entries a lane holds when they fit
+  constexpr int VPL = 8;  // column entries a lane holds when they fit
   if (col < r && (nz + P - 1) / P <= VPL) {
-    // the next reflector's entries are loaded while the current one is
-    // applied, so the slab's latency is off the dependent chain
-    T vc[VPL], vn[VPL];
+    // lane `part` keeps rows part + u P of its column in registers for the
+    // whole transformation; reflector j touches the rows below j (the
+    // others read as zero), and the next reflector's entries are loaded
+    // while the current one is applied, so the slab's latency is off the
+    // dependent chain
+    T xe[VPL], vc[VPL], vn[VPL];
+#pragma unroll
+    for (int u = 0; u < VPL; ++u) {
+      const int e = part + u * P;
+      xe[u] = e < nz ? Xe[e * r + col] : T(0);
+    }
     auto load = [&](int j, T* dst) {
       const T* v = Hv + (size_t)j * np;
 #pragma unroll
       for (int u = 0; u < VPL; ++u) {
-        const int e = j + 1 + part + u * P;
-        dst[u] = e < nz ? v[e] : T(0);
+        const int e = part + u * P;
+        dst[u] = (e > j && e < nz) ? v[e] : T(0);
       }
     };
     load(nz - 2, vc);
@@ -496,19 +504,18 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
       if (tj != T(0)) {
         T sdot = T(0);
 #pragma unroll
-        for (int u = 0; u < VPL; ++u) {
-          const int e = j + 1 + part + u * P;
-          if (e < nz) sdot += conjx(vc[u]) * Xe[e * r + col];
-        }
+        for (int u = 0; u < VPL; ++u) sdot += conjx(vc[u]) * xe[u];
         sdot = group_sum(sdot, P) * tj;
 #pragma unroll
-        for (int u = 0; u < VPL; ++u) {
-          const int e = j + 1 + part + u * P;
-          if (e < nz) Xe[e * r + col] -= vc[u] * sdot;
-        }
+        for (int u = 0; u < VPL; ++u) xe[u] -= vc[u] * sdot;
       }
 #pragma unroll
       for (int u = 0; u < VPL; ++u) vc[u] = vn[u];
+    }
+#pragma unroll
+    for (int u = 0; u < VPL; ++u) {
+      const int e = part + u * P;
+      if (e < nz) Xe[e * r + col] = xe[u];
     }
   } else if (col < r) {
     for (int j = nz - 2; j >= 0; --j) {
