@@ -126,6 +126,39 @@ struct DmSh {
   }
 };
 
+// Multiply-adds as fused FMAs (four per complex product): u + a b,
+// u + conj(a) b and u - a conj(b).
+__device__ __forceinline__ float fmac(float u, float a, float b) { return fmaf(a, b, u); }
+__device__ __forceinline__ double fmac(double u, double a, double b) { return fma(a, b, u); }
+template <typename R>
+__device__ __forceinline__ cplx<R> fmac(cplx<R> u, cplx<R> a, cplx<R> b) {
+  u.re = fma(a.re, b.re, u.re);
+  u.re = fma(-a.im, b.im, u.re);
+  u.im = fma(a.re, b.im, u.im);
+  u.im = fma(a.im, b.re, u.im);
+  return u;
+}
+__device__ __forceinline__ float fmac_ca(float u, float a, float b) { return fmaf(a, b, u); }
+__device__ __forceinline__ double fmac_ca(double u, double a, double b) { return fma(a, b, u); }
+template <typename R>
+__device__ __forceinline__ cplx<R> fmac_ca(cplx<R> u, cplx<R> a, cplx<R> b) {
+  u.re = fma(a.re, b.re, u.re);
+  u.re = fma(a.im, b.im, u.re);
+  u.im = fma(a.re, b.im, u.im);
+  u.im = fma(-a.im, b.re, u.im);
+  return u;
+}
+__device__ __forceinline__ float fnmac_cb(float u, float a, float b) { return fmaf(-a, b, u); }
+__device__ __forceinline__ double fnmac_cb(double u, double a, double b) { return fma(-a, b, u); }
+template <typename R>
+__device__ __forceinline__ cplx<R> fnmac_cb(cplx<R> u, cplx<R> a, cplx<R> b) {
+  u.re = fma(-a.re, b.re, u.re);
+  u.re = fma(-a.im, b.im, u.re);
+  u.im = fma(-a.im, b.re, u.im);
+  u.im = fma(a.re, b.im, u.im);
+  return u;
+}
+
 // ---------------------------------------------------------------------------
 // Householder reduction of the Hermitian nz x nz matrix held as a packed
 // lower triangle (rho) to a real symmetric tridiagonal (dd, ee): reflector j
@@ -186,10 +219,17 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       const int i = j + 1 + ri + p * rpp;
       T u = T(0);
       if (i < nz) {
-        // row part (k <= i) then the column part through the symmetry
+        // row part (k <= i) then the column part through the symmetry, the
+        // packed index of (kk, i) stepped by kk TPR + TPR (TPR + 1) / 2
         int kk = j + 1 + q;
-        for (; kk <= i; kk += TPR) u += rho[pk(i, kk)] * sh.vb[kk];
-        for (; kk < nz; kk += TPR) u += conjx(rho[pk(kk, i)]) * sh.vb[kk];
+        const T* rr = rho + pk(i, 0);
+        for (; kk <= i; kk += TPR) u = fmac(u, rr[kk], sh.vb[kk]);
+        int a = pk(kk, i);
+        const int step0 = TPR * (TPR + 1) / 2;
+        for (; kk < nz; kk += TPR) {
+          u = fmac_ca(u, rho[a], sh.vb[kk]);
+          a += TPR * kk + step0;
+        }
       }
       u = group_sum(u, TPR);
       ui[p] = u;
@@ -211,9 +251,10 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
         const int i = h == 0 ? j + 1 + g : nz - 1 - g;
         if (h == 1 && i <= j + 1 + g) break;
         const T vi = sh.vb[i], wi = sh.wb[i];
+        T* rr = rho + pk(i, 0);
         for (int kk = j + 1 + q8; kk <= i; kk += G8) {
-          const T nv = rho[pk(i, kk)] - vi * conjx(sh.wb[kk]) - wi * conjx(sh.vb[kk]);
-          rho[pk(i, kk)] = nv;
+          const T nv = fnmac_cb(fnmac_cb(rr[kk], vi, sh.wb[kk]), wi, sh.vb[kk]);
+          rr[kk] = nv;
           if (kk == j + 1 && i >= j + 3) t += abs2x(nv);
         }
       }
