@@ -15,9 +15,11 @@
 // centre matrix, and the kept eigenvectors its dominant right singular
 // vectors, so the truncated state equals the canonical QR -> SVD sweep's.
 //
-// The products G_y P_k, P_k^H X, G_y Z and Z^H Y run as MFMA tiles
-// (v_mfma_f32_16x16x4_f32 for FP32 / complex64, v_mfma_f64_16x16x4_f64 for
-// FP64 / complex128; a complex product is four real ones). The Hermitian
+// The Gram is contracted one tensor at a time (G_y with E, A, conj(A),
+// conj(E); no P_k is formed), and it, Z_y, G_y Z_y, rho_y and W_y run as
+// MFMA products (v_mfma_f32_16x16x4_f32 for FP32 / complex64,
+// v_mfma_f64_16x16x4_f64 for FP64 / complex128, bfloat16 operands in BF16
+// mode; a complex product is four real ones). The Hermitian
 // eigenproblem of rho_y is solved by Householder tridiagonalisation (rho in
 // LDS as a packed lower triangle), multisection bisection on Sturm counts
 // for the leading eigenvalues, inverse iteration with partial-pivoting LU
