@@ -272,15 +272,22 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
 
 // a / b on the serial chains of the eigenvector phase (Sturm counts,
 // inverse iteration): FP32 takes the hardware reciprocal (1 ulp) times a,
-// FP64 the correctly rounded quotient. Both recurrences only need the
-// quotient to a few ulp: a Sturm count changes only for shifts within
-// rounding of an eigenvalue, and inverse iteration converges from any
-// nearby solve.
+// FP64 the hardware reciprocal refined by one Newton step, r (2 - b r),
+// which squares its relative error, times a (a few ulp). Both recurrences
+// only need the quotient to a few ulp: a Sturm count changes only for
+// shifts within rounding of an eigenvalue, and inverse iteration converges
+// from any nearby solve.
 template <typename R>
-__device__ __forceinline__ R quot(R a, R b) { return a / b; }
+__device__ __forceinline__ R quot(R a, R b);
 template <>
 __device__ __forceinline__ float quot<float>(float a, float b) {
   return a * __builtin_amdgcn_rcpf(b);
+}
+template <>
+__device__ __forceinline__ double quot<double>(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return a * r;
 }
 
 // Eigenvalues below x of the symmetric tridiagonal (d, e^2): Sturm count.
