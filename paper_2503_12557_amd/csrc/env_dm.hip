@@ -657,12 +657,12 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     // is formed): E, A, conj(A), conj(E), each step one matrix-core product
     // W1[(a,l,l'),(in,b)] = sum_a' G[(a,l),(a',l')] E[a',in,b]
     const int n1 = v.Din * br;
-    mgemm_map<T, false, false, BFM>(Pl * v.Dl, n1, bl, Gy, IMap(v.Dl, np, 1), IMap(v.Dl), Ebuf,
+    mgemm_map<T, false, false, BFM, CX>(Pl * v.Dl, n1, bl, Gy, IMap(v.Dl, np, 1), IMap(v.Dl), Ebuf,
                                     IMap(n1), IMap(1), W1, IMap(n1), IMap(1), false, false);
     __syncthreads();
     // W2[(a,l,b),(r,k)] = sum_{(l',in)} W1[(a,l,l'),(in,b)] A[l',r,in,k]
     const int n2 = v.Dr * v.Dout;
-    mgemm_map<T, false, false, BFM>(Pl * br, n2, v.Dl * v.Din, W1, IMap(br, v.Dl * n1, 1),
+    mgemm_map<T, false, false, BFM, CX>(Pl * br, n2, v.Dl * v.Din, W1, IMap(br, v.Dl * n1, 1),
                                     IMap(v.Din, n1, br), Abuf, IMap(v.Din, v.s_l, v.s_in),
                                     IMap(v.Dout, v.s_r, v.s_out), W2, IMap(n2), IMap(1), false,
                                     false);
@@ -670,14 +670,14 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     // W3[(a,b,r'),(in',r)] = sum_{(l,k)} W2[(a,l,b),(r',k)] conj(A[l,r,in',k])
     // (into W1)
     const int n3 = v.Din * v.Dr;
-    mgemm_map<T, false, CX, BFM>(bl * br * v.Dr, n3, v.Dl * v.Dout, W2,
+    mgemm_map<T, false, CX, BFM, CX>(bl * br * v.Dr, n3, v.Dl * v.Dout, W2,
                                  IMap(br * v.Dr, v.Dl * br * n2, v.Dout), IMap(v.Dout, br * n2, 1),
                                  Abuf, IMap(v.Dout, v.s_l, v.s_out), IMap(v.Dr, v.s_in, v.s_r), W1,
                                  IMap(n3), IMap(1), false, false);
     __syncthreads();
     // G_{y+1}[(b,r),(b',r')] = sum_{(a,in')} W3[(a,b',r'),(in',r)] conj(E[a,in',b]),
     // rows (b',r',r) of the product scattered to their places in G_{y+1}
-    mgemm_map<T, false, CX, BFM>(br * v.Dr * v.Dr, br, bl * v.Din, W1, IMap(v.Dr, n3, 1),
+    mgemm_map<T, false, CX, BFM, CX>(br * v.Dr * v.Dr, br, bl * v.Din, W1, IMap(v.Dr, n3, 1),
                                  IMap(v.Din, br * v.Dr * n3, v.Dr), Ebuf, IMap(br), IMap(1), Gn,
                                  IMap(v.Dr, 1, np), IMap(v.Dr * np), false, false);
     __syncthreads();
@@ -716,13 +716,13 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     __syncthreads();
     // T1[(a,in),(r,c)] = sum_b E[(a,in), b] W[(b,r), c]: one product with
     // columns (r,c)
-    mgemm_map<T, false, false, M == MODE_BF16>(
+    mgemm_map<T, false, false, M == MODE_BF16, IsCplx<T>::value>(
         bl * v.Din, v.Dr * nbr, br, Ebuf, IMap(br), IMap(1), W, IMap(v.Dr * np),
         IMap(nbr, np, 1), T1, IMap(v.Dr * nbr), IMap(1), false, false);
     __syncthreads();
     // Z[(a,l),(k,c)] = sum_{in,r} T1[(a,in),(r,c)] A[l,r,in,k]: one product
     // with rows (a,c), columns (l,k) and contracted (in,r)
-    mgemm_map<T, false, false, M == MODE_BF16>(
+    mgemm_map<T, false, false, M == MODE_BF16, IsCplx<T>::value>(
         bl * nbr, v.Dl * v.Dout, v.Din * v.Dr, T1, IMap(nbr, v.Din * v.Dr * nbr, 1), IMap(nbr),
         Abuf, IMap(v.Dr, v.s_in, v.s_r), IMap(v.Dout, v.s_l, v.s_out), Z,
         IMap(nbr, v.Dl * np, 1), IMap(v.Dout, np, nbr), false, false);
@@ -732,9 +732,9 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
     if (y > 0) {
       const T* Gy = Gs + (size_t)y * np2;
       // Y = G_y Z, rho = Z^H Y (Hermitian)
-      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(Pl, zc, Pl, Gy, 1, np, Z, np, 1, X, np, false, false);
+      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16, IsCplx<T>::value>(Pl, zc, Pl, Gy, 1, np, Z, np, 1, X, np, false, false);
       __syncthreads();
-      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16>(zc, zc, Pl, Z, 1, np, X, np, 1, Pk, np, true, false);
+      mgemm<T, IsCplx<T>::value, false, M == MODE_BF16, IsCplx<T>::value>(zc, zc, Pl, Z, 1, np, X, np, 1, Pk, np, true, false);
       __syncthreads();
       // unit scale (eigenvectors only)
       R mx = 0;
@@ -799,7 +799,7 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
           if (i % rnew >= rkeep) Xe[i] = T(0);
       __syncthreads();
       // W_y = Z [v_0 .. v_{rnew-1}]
-      mgemm<T, false, false, M == MODE_BF16>(Pl, rnew, zc, Z, np, 1, Xe, rnew, 1, W, np, false, false);
+      mgemm<T, false, false, M == MODE_BF16, IsCplx<T>::value>(Pl, rnew, zc, Z, np, 1, Xe, rnew, 1, W, np, false, false);
       // the new tensor B[j, e] = conj(v_j[e]) / max |v|
       R bm = 0;
       for (int i = tid; i < zc * rnew; i += NT) {

@@ -79,9 +79,14 @@ struct IMap {
 // rows, columns and k read as zero. The caller synchronises before reading
 // C. BF (real FP32 operands only): the operands are rounded to bfloat16 and
 // multiplied by v_mfma_f32_16x16x32_bf16 (lane l holds A[l % 16][8 (l / 16)
-// + t] and B[8 (l / 16) + t][l % 16], t < 8) with FP32 accumulation.
+// + t] and B[8 (l / 16) + t][l % 16], t < 8) with FP32 accumulation. G3
+// (complex operands): three real products per complex one, P1 = Re A Re B,
+// P2 = Im A Im B, P3 = (Re A + Im A)(Re B + Im B), Re C = P1 - P2, Im C =
+// P3 - P1 - P2 (a quarter fewer matrix-core cycles; the imaginary part's
+// error bound grows from u (|Re A||Im B| + |Im A||Re B|) to about
+// u (|Re A| + |Im A|)(|Re B| + |Im B|)).
 // ---------------------------------------------------------------------------
-template <typename T, bool CA, bool CB, bool BF = false>
+template <typename T, bool CA, bool CB, bool BF = false, bool G3 = false>
 __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai, IMap ak,
                           const T* __restrict__ B, IMap bk, IMap bj, T* __restrict__ C, IMap ci,
                           IMap cj, bool herm, bool acc) {
@@ -105,7 +110,9 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
       bjb = job - bi * nbj;
     }
     const int i0 = bi * 32, j0 = bjb * 32;
-    V cr[2][2], ci_[2][2];
+    // complex: cr / ci_ the real and imaginary sums, or P1 / P2 with P3 in
+    // cp (G3)
+    V cr[2][2], ci_[2][2], cp[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -114,6 +121,7 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
         for (int v = 0; v < 4; ++v) {
           cr[a][b][v] = 0;
           ci_[a][b][v] = 0;
+          cp[a][b][v] = 0;
         }
     if (acc) {
 #pragma unroll
@@ -127,7 +135,10 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
               R re, im;
               split(C[ci(i) + cj(j)], re, im);
               cr[a][b][v] = re;
-              ci_[a][b][v] = im;
+              if constexpr (CX && G3)
+                cp[a][b][v] = re + im;
+              else
+                ci_[a][b][v] = im;
             }
           }
     }
@@ -184,7 +195,11 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
             cr[a][b] = F::mac(ar[s][a], br[s][b], cr[a][b]);
-            if constexpr (CX) {
+            if constexpr (CX && G3) {
+              const R ai2 = sa * aim[s][a], bi2 = sb * bim[s][b];
+              ci_[a][b] = F::mac(ai2, bi2, ci_[a][b]);
+              cp[a][b] = F::mac(ar[s][a] + ai2, br[s][b] + bi2, cp[a][b]);
+            } else if constexpr (CX) {
               // (ar + i sa ai)(br + i sb bi)
               const R ai2 = sa * aim[s][a], bi2 = sb * bim[s][b];
               cr[a][b] = F::mac(-ai2, bi2, cr[a][b]);
@@ -203,7 +218,13 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
         for (int v = 0; v < 4; ++v) {
           const int i = i0 + 16 * a + F::row(lane, v), j = j0 + 16 * b + li;
           if (i < m && j < n) {
-            const T val = join<T>(cr[a][b][v], ci_[a][b][v]);
+            T val;
+            if constexpr (CX && G3) {
+              const R p1 = cr[a][b][v], p2 = ci_[a][b][v];
+              val = join<T>(p1 - p2, cp[a][b][v] - p1 - p2);
+            } else {
+              val = join<T>(cr[a][b][v], ci_[a][b][v]);
+            }
             C[ci(i) + cj(j)] = val;
             if (herm && bi != bjb) C[ci(j) + cj(i)] = conjx(val);
           }
@@ -212,11 +233,11 @@ __device__ void mgemm_map(int m, int n, int k, const T* __restrict__ A, IMap ai,
 }
 
 // Strided form: A[i*sai + kk*sak], B[kk*sbk + j*sbj], C[i*ldc + j].
-template <typename T, bool CA, bool CB, bool BF = false>
+template <typename T, bool CA, bool CB, bool BF = false, bool G3 = false>
 __device__ __forceinline__ void mgemm(int m, int n, int k, const T* __restrict__ A, int sai,
                                       int sak, const T* __restrict__ B, int sbk, int sbj,
                                       T* __restrict__ C, int ldc, bool herm, bool acc) {
-  mgemm_map<T, CA, CB, BF>(m, n, k, A, IMap(sai), IMap(sak), B, IMap(sbk), IMap(sbj), C, IMap(ldc),
+  mgemm_map<T, CA, CB, BF, G3>(m, n, k, A, IMap(sai), IMap(sak), B, IMap(sbk), IMap(sbj), C, IMap(ldc),
                        IMap(1), herm, acc);
 }
 
