@@ -473,16 +473,16 @@ __device__ __forceinline__ void s1_step_left_mm(const T* Lp, const T* U, int ua,
                                 int Dr, int Du, int Dd, const T* Bt, int ba, int bb, T* X1, T* X2,
                                 T* Lout) {
   // X1[(m,c),(u,b)] = sum_a L[a,(m,c)] U[a,(u,b)]
-  mgemm_map<T, false, false, BF>(Dl * ba, Du * ub, ua, Lp, IMap(1), IMap(Dl * ba), U, IMap(Du * ub),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(Dl * ba, Du * ub, ua, Lp, IMap(1), IMap(Dl * ba), U, IMap(Du * ub),
                              IMap(1), X1, IMap(Du * ub), IMap(1), false, false);
   __syncthreads();
   // X2[(c,b),(r,d)] = sum_{(m,u)} X1[(m,c),(u,b)] A[m,r,u,d]
-  mgemm_map<T, false, false, BF>(ba * ub, Dr * Dd, Dl * Du, X1, IMap(ub, Du * ub, 1),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ba * ub, Dr * Dd, Dl * Du, X1, IMap(ub, Du * ub, 1),
                              IMap(Du, ba * Du * ub, ub), A, IMap(Du, Dr * Du * Dd, Dd),
                              IMap(Dd, Du * Dd, 1), X2, IMap(Dr * Dd), IMap(1), false, false);
   __syncthreads();
   // L'[(b,r),e] = sum_{(c,d)} X2[(c,b),(r,d)] B[(c,d),e]
-  mgemm_map<T, false, false, BF>(ub * Dr, bb, ba * Dd, X2, IMap(Dr, Dr * Dd, Dd),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ub * Dr, bb, ba * Dd, X2, IMap(Dr, Dr * Dd, Dd),
                              IMap(Dd, ub * Dr * Dd, 1), Bt, IMap(bb), IMap(1), Lout, IMap(bb),
                              IMap(1), false, false);
   __syncthreads();
@@ -493,16 +493,16 @@ __device__ void s1_step_right_mm(const T* Rp, const T* U, int ua, int ub, const 
                                  int Dr, int Du, int Dd, const T* Bt, int ba, int bb, T* X1,
                                  T* X2, T* Rout) {
   // X1[(a,u),(r,e)] = sum_b U[(a,u),b] R[b,(r,e)]
-  mgemm_map<T, false, false, BF>(ua * Du, Dr * bb, ub, U, IMap(ub), IMap(1), Rp, IMap(Dr * bb),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * Du, Dr * bb, ub, U, IMap(ub), IMap(1), Rp, IMap(Dr * bb),
                              IMap(1), X1, IMap(Dr * bb), IMap(1), false, false);
   __syncthreads();
   // X2[(a,e),(m,d)] = sum_{(u,r)} X1[(a,u),(r,e)] A[m,r,u,d]
-  mgemm_map<T, false, false, BF>(ua * bb, Dl * Dd, Du * Dr, X1, IMap(bb, Du * Dr * bb, 1), IMap(bb),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * bb, Dl * Dd, Du * Dr, X1, IMap(bb, Du * Dr * bb, 1), IMap(bb),
                              A, IMap(Dr, Dd, Du * Dd), IMap(Dd, Dr * Du * Dd, 1), X2,
                              IMap(Dl * Dd), IMap(1), false, false);
   __syncthreads();
   // R'[(a,m),c] = sum_{(d,e)} X2[(a,e),(m,d)] B[c,(d,e)]
-  mgemm_map<T, false, false, BF>(ua * Dl, ba, Dd * bb, X2, IMap(Dl, bb * Dl * Dd, Dd),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * Dl, ba, Dd * bb, X2, IMap(Dl, bb * Dl * Dd, Dd),
                              IMap(bb, 1, Dl * Dd), Bt, IMap(1), IMap(Dd * bb), Rout, IMap(ba),
                              IMap(1), false, false);
   __syncthreads();
@@ -515,12 +515,12 @@ template <typename T, bool BF = false>
 __device__ void s1_hole_mm(const T* Lp, const T* U, int ua, int ub, int Dl, int Dr, int Du,
                            int Dd, const T* Rn, const T* Bt, int ba, int bb, T* X1, T* X2,
                            T* Env) {
-  mgemm_map<T, false, false, BF>(Dl * ba, Du * ub, ua, Lp, IMap(1), IMap(Dl * ba), U, IMap(Du * ub),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(Dl * ba, Du * ub, ua, Lp, IMap(1), IMap(Dl * ba), U, IMap(Du * ub),
                              IMap(1), X1, IMap(Du * ub), IMap(1), false, false);
-  mgemm_map<T, false, false, BF>(ub * Dr, ba * Dd, bb, Rn, IMap(bb), IMap(1), Bt, IMap(1), IMap(bb),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ub * Dr, ba * Dd, bb, Rn, IMap(bb), IMap(1), Bt, IMap(1), IMap(bb),
                              X2, IMap(ba * Dd), IMap(1), false, false);
   __syncthreads();
-  mgemm_map<T, false, false, BF>(Dl * Du, Dr * Dd, ba * ub, X1, IMap(Du, ba * Du * ub, ub),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(Dl * Du, Dr * Dd, ba * ub, X1, IMap(Du, ba * Du * ub, ub),
                              IMap(ub, Du * ub, 1), X2, IMap(ub, Dd, Dr * ba * Dd),
                              IMap(Dd, ba * Dd, 1), Env, IMap(Du, Dr * Du * Dd, Dd),
                              IMap(Dd, Du * Dd, 1), false, false);
@@ -539,22 +539,22 @@ __device__ __forceinline__ void s2_step_left_mm(const T* Lp, const T* U, int ua,
                                 int Dd2, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout) {
   const int inner = Dl1 * Dl2 * ba;
   // X1[(m1,m2,c),(u,b)] = sum_a L[a,(m1,m2,c)] U[a,(u,b)]
-  mgemm_map<T, false, false, BF>(inner, uk * ub, ua, Lp, IMap(1), IMap(inner), U, IMap(uk * ub),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(inner, uk * ub, ua, Lp, IMap(1), IMap(inner), U, IMap(uk * ub),
                              IMap(1), X1, IMap(uk * ub), IMap(1), false, false);
   __syncthreads();
   // X2[(m2,c,b),(r1,t)] = sum_{(m1,u)} X1[(m1,m2,c),(u,b)] A1[m1,r1,u,t]
-  mgemm_map<T, false, false, BF>(Dl2 * ba * ub, Dr1 * Dd1, Dl1 * uk, X1, IMap(ub, uk * ub, 1),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(Dl2 * ba * ub, Dr1 * Dd1, Dl1 * uk, X1, IMap(ub, uk * ub, 1),
                              IMap(uk, Dl2 * ba * uk * ub, ub), A1, IMap(uk, Dr1 * uk * Dd1, Dd1),
                              IMap(Dd1, uk * Dd1, 1), X2, IMap(Dr1 * Dd1), IMap(1), false, false);
   __syncthreads();
   // X3[(c,b,r1),(s,d)] = sum_{(m2,t)} X2[(m2,c,b),(r1,t)] A2[m2,s,t,d]  (into X1)
   T* X3 = X1;
-  mgemm_map<T, false, false, BF>(ba * ub * Dr1, Dr2 * Dd2, Dl2 * Dd1, X2, IMap(Dd1),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ba * ub * Dr1, Dr2 * Dd2, Dl2 * Dd1, X2, IMap(Dd1),
                              IMap(Dd1, ba * ub * Dr1 * Dd1, 1), A2, IMap(Dd1, Dr2 * Dd1 * Dd2, Dd2),
                              IMap(Dd2, Dd1 * Dd2, 1), X3, IMap(Dr2 * Dd2), IMap(1), false, false);
   __syncthreads();
   // L'[(b,r1,s),e] = sum_{(c,d)} X3[(c,b,r1),(s,d)] B[(c,d),e]
-  mgemm_map<T, false, false, BF>(ub * Dr1 * Dr2, bb, ba * Dd2, X3, IMap(Dd2),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ub * Dr1 * Dr2, bb, ba * Dd2, X3, IMap(Dd2),
                              IMap(Dd2, ub * Dr1 * Dr2 * Dd2, 1), Bt, IMap(bb), IMap(1), Lout,
                              IMap(bb), IMap(1), false, false);
   __syncthreads();
@@ -566,25 +566,25 @@ __device__ void s2_step_right_mm(const T* Rp, const T* U, int ua, int uk, int ub
                                  int Dd2, const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Rout) {
   const int rw = Dr1 * Dr2 * bb;
   // Y1[(a,u),(r1,s,e)] = sum_b U[(a,u),b] R[b,(r1,s,e)]
-  mgemm_map<T, false, false, BF>(ua * uk, rw, ub, U, IMap(ub), IMap(1), Rp, IMap(rw), IMap(1), Y1,
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * uk, rw, ub, U, IMap(ub), IMap(1), Rp, IMap(rw), IMap(1), Y1,
                              IMap(rw), IMap(1), false, false);
   __syncthreads();
   // Y2[(a,s,e),(m1,t)] = sum_{(u,r1)} Y1[(a,u),(r1,s,e)] A1[m1,r1,u,t]
-  mgemm_map<T, false, false, BF>(ua * Dr2 * bb, Dl1 * Dd1, uk * Dr1, Y1, IMap(Dr2 * bb, uk * rw, 1),
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * Dr2 * bb, Dl1 * Dd1, uk * Dr1, Y1, IMap(Dr2 * bb, uk * rw, 1),
                              IMap(Dr1, rw, Dr2 * bb), A1, IMap(Dr1, Dd1, uk * Dd1),
                              IMap(Dd1, Dr1 * uk * Dd1, 1), Y2, IMap(Dl1 * Dd1), IMap(1), false,
                              false);
   __syncthreads();
   // Y3[(a,e,m1),(m2,d)] = sum_{(s,t)} Y2[(a,s,e),(m1,t)] A2[m2,s,t,d]  (into Y1)
   T* Y3 = Y1;
-  mgemm_map<T, false, false, BF>(ua * bb * Dl1, Dl2 * Dd2, Dr2 * Dd1, Y2,
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * bb * Dl1, Dl2 * Dd2, Dr2 * Dd1, Y2,
                              IMap(bb * Dl1, Dr2 * bb * Dl1 * Dd1, Dd1),
                              IMap(Dd1, bb * Dl1 * Dd1, 1), A2, IMap(Dd2),
                              IMap(Dd2, Dr2 * Dd1 * Dd2, 1), Y3, IMap(Dl2 * Dd2), IMap(1), false,
                              false);
   __syncthreads();
   // R'[(a,m1,m2),c] = sum_{(d,e)} Y3[(a,e,m1),(m2,d)] B[c,(d,e)]
-  mgemm_map<T, false, false, BF>(ua * Dl1 * Dl2, ba, Dd2 * bb, Y3,
+  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * Dl1 * Dl2, ba, Dd2 * bb, Y3,
                              IMap(Dl1 * Dl2, bb * Dl1 * Dl2 * Dd2, Dd2),
                              IMap(bb, 1, Dl1 * Dl2 * Dd2), Bt, IMap(1), IMap(Dd2 * bb), Rout,
                              IMap(ba), IMap(1), false, false);
