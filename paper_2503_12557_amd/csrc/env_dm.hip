@@ -90,8 +90,8 @@ __host__ __device__ inline size_t dm_big_elems(int bmax, int D, int chi, size_t 
   const size_t rho = np * (np + 1) / 2;
   if (rho > big) big = rho;
   if (np * rm > big) big = np * rm;
-  // U bands (3 np rm, R) under Xe (np rm, T), then Y (np rm, R)
-  const size_t xe_b = np * rm * tsize, u_b = 3 * np * rm * rsize;
+  // U bands and multipliers (4 np rm, R) under Xe (np rm, T), then Y (np rm, R)
+  const size_t xe_b = np * rm * tsize, u_b = 4 * np * rm * rsize;
   const size_t eig = ((xe_b > u_b ? xe_b : u_b) + np * rm * rsize + tsize - 1) / tsize;
   const size_t with = (eig > big ? eig : big);
   // FP32 modes run two workgroups per CU: each keeps below half the LDS
@@ -392,56 +392,88 @@ __device__ void top_eigenvalues(const R* dd, const R* ee, R* e2, R* lam, int nz,
   __syncthreads();
 }
 
+// The row-swap flag of an LU step kept in the lowest mantissa bit of its
+// multiplier (which moves the multiplier by at most one ulp).
+__device__ __forceinline__ float with_flag(float v, bool f) {
+  return __uint_as_float((__float_as_uint(v) & ~1u) | (f ? 1u : 0u));
+}
+__device__ __forceinline__ double with_flag(double v, bool f) {
+  return __longlong_as_double((__double_as_longlong(v) & ~1ll) | (f ? 1ll : 0ll));
+}
+__device__ __forceinline__ bool flag_of(float v) { return __float_as_uint(v) & 1u; }
+__device__ __forceinline__ bool flag_of(double v) { return __double_as_longlong(v) & 1ll; }
+
 // Eigenvector of the tridiagonal for eigenvalue x by inverse iteration:
-// three solves of (T - x I) y = b from b = ones, each forming the
-// partial-pivoting LU of T - x I row by row with b eliminated alongside (the
-// three bands of U kept for the back substitution), y scaled by its largest
-// entry after each solve. Serial in the calling lane; the bands u (3 n) and
-// y (n) are interleaved across lanes with stride ld (element i of this lane
-// at [i * ld]), so the lanes' accesses of one step are consecutive.
+// three solves of (T - x I) y = b from b = ones. The first forms the
+// partial-pivoting LU of T - x I row by row with b eliminated alongside,
+// keeping the three bands of U and each step's multiplier (its row swap in
+// the multiplier's last bit); the next two apply the stored steps to their
+// right-hand sides. y is scaled by its largest entry after each solve.
+// Serial in the calling lane; the bands u (4 n) and y (n) are interleaved
+// across lanes with stride ld (element i of this lane at [i * ld]), so the
+// lanes' accesses of one step are consecutive.
 template <typename R>
 __device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* u, R* y,
                               int ld) {
   R* u0 = u;
   R* u1 = u + (size_t)n * ld;
   R* u2 = u + (size_t)2 * n * ld;
+  R* um = u + (size_t)3 * n * ld;
   const R tiny = Eps<R>::v * (tnorm > R(0) ? tnorm : R(1));
   for (int i = 0; i < n; ++i) y[(size_t)i * ld] = R(1);
   for (int it = 0; it < 3; ++it) {
-    // rows i, i+1 with pivoting on the sub-diagonal; (c0, c1) the current
-    // row's entries at columns i, i+1 and r0 its right-hand side
-    R c0 = dd[0] - x, c1 = n > 1 ? ee[0] : R(0), r0 = y[0];
-    for (int i = 0; i + 1 < n; ++i) {
-      const R s0 = ee[i], s1 = dd[i + 1] - x, s2 = i + 2 < n ? ee[i + 1] : R(0);
-      const R rn = y[(size_t)(i + 1) * ld];
-      const size_t o = (size_t)i * ld;
-      if (fabs(s0) > fabs(c0)) {
-        const R mm = quot(c0, s0);
-        u0[o] = s0;
-        u1[o] = s1;
-        u2[o] = s2;
-        y[o] = rn;
-        c0 = c1 - mm * s1;
-        c1 = -(mm * s2);
-        r0 = r0 - mm * rn;
-      } else {
-        if (c0 == R(0)) c0 = tiny;
-        const R mm = quot(s0, c0);
-        u0[o] = c0;
-        u1[o] = c1;
-        u2[o] = R(0);
-        y[o] = r0;
-        c0 = s1 - mm * c1;
-        c1 = s2;
-        r0 = rn - mm * r0;
+    if (it == 0) {
+      // rows i, i+1 with pivoting on the sub-diagonal; (c0, c1) the current
+      // row's entries at columns i, i+1 and r0 its right-hand side
+      R c0 = dd[0] - x, c1 = n > 1 ? ee[0] : R(0), r0 = y[0];
+      for (int i = 0; i + 1 < n; ++i) {
+        const R s0 = ee[i], s1 = dd[i + 1] - x, s2 = i + 2 < n ? ee[i + 1] : R(0);
+        const R rn = y[(size_t)(i + 1) * ld];
+        const size_t o = (size_t)i * ld;
+        if (fabs(s0) > fabs(c0)) {
+          const R mm = quot(c0, s0);
+          u0[o] = s0;
+          u1[o] = s1;
+          u2[o] = s2;
+          um[o] = with_flag(mm, true);
+          y[o] = rn;
+          c0 = c1 - mm * s1;
+          c1 = -(mm * s2);
+          r0 = r0 - mm * rn;
+        } else {
+          if (c0 == R(0)) c0 = tiny;
+          const R mm = quot(s0, c0);
+          u0[o] = c0;
+          u1[o] = c1;
+          u2[o] = R(0);
+          um[o] = with_flag(mm, false);
+          y[o] = r0;
+          c0 = s1 - mm * c1;
+          c1 = s2;
+          r0 = rn - mm * r0;
+        }
       }
+      if (c0 == R(0)) c0 = tiny;
+      const size_t ol = (size_t)(n - 1) * ld;
+      u0[ol] = c0;
+      u1[ol] = R(0);
+      u2[ol] = R(0);
+      y[ol] = r0;
+    } else {
+      R r0 = y[0];
+      for (int i = 0; i + 1 < n; ++i) {
+        const size_t o = (size_t)i * ld;
+        const R rn = y[o + ld], m = um[o];
+        if (flag_of(m)) {
+          y[o] = rn;
+          r0 = r0 - m * rn;
+        } else {
+          y[o] = r0;
+          r0 = rn - m * r0;
+        }
+      }
+      y[(size_t)(n - 1) * ld] = r0;
     }
-    if (c0 == R(0)) c0 = tiny;
-    const size_t ol = (size_t)(n - 1) * ld;
-    u0[ol] = c0;
-    u1[ol] = R(0);
-    u2[ol] = R(0);
-    y[ol] = r0;
     R nrm = 0, y1 = 0, y2 = 0;
     for (int i = n - 1; i >= 0; --i) {
       const size_t o = (size_t)i * ld;
@@ -491,7 +523,7 @@ __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, type
   R* U = lu;
   R* Y = Yt;
   if (sh.eig_lds) {
-    const size_t xe_b = (size_t)nz * r * sizeof(T), u_b = (size_t)3 * nz * r * sizeof(R);
+    const size_t xe_b = (size_t)nz * r * sizeof(T), u_b = (size_t)4 * nz * r * sizeof(R);
     U = reinterpret_cast<R*>(sh.big);
     Y = reinterpret_cast<R*>(reinterpret_cast<char*>(sh.big) + (xe_b > u_b ? xe_b : u_b));
   }
