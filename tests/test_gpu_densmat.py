@@ -229,14 +229,14 @@ def test_truncated_weight_matches_oracle(dev):
 
 
 def test_full_size_chiral_10x10(dev):
-    # 10x10, D=5, chi=25, complex tensors, chiral spin liquid: complex128 at
-    # the 1e-10 bar against the oracle's density-matrix path on two sampled
-    # configurations; complex64 on the same configurations within 2e-2
-    # (random sign-indefinite tensors: cancellation-limited, as the
-    # canonical path's complex64)
+    # 10x10, D=5, chi=25, complex tensors, chiral spin liquid (the headline
+    # workload): complex128 at the 1e-10 bar against the oracle's
+    # density-matrix path on eight configurations; complex64 on the same
+    # configurations within 2e-2 (random sign-indefinite tensors:
+    # cancellation-limited, as the canonical path's complex64)
     Lx, Ly, D, chi = 10, 10, 5, 25
     theta = synth.theta(Lx, Ly, 2, D, seed=11, cplx=True)
-    cf = configs_for(CHIRAL, Lx * Ly, 2, seed=12)
+    cf = configs_for(CHIRAL, Lx * Ly, 8, seed=12)
     olp, oel, oO = oracle_eval(theta, Lx, Ly, D, chi, cf, model=CHIRAL, want_O=True,
                                method="densmat")
     for dtype in ("c128", "c64"):

@@ -36,7 +36,7 @@ HEIS = ("j1j2", dict(J1=1.0, J2=0.0))
 
 # name: (Lx, Ly, D, chi, complex, model, n samples, reference dtype, reduced dtypes)
 CASES = {
-    "10x10_D5_chi25_chiral": (10, 10, 5, 25, True, CHIRAL, 2, "c128", ["c64"]),
+    "10x10_D5_chi25_chiral": (10, 10, 5, 25, True, CHIRAL, 4, "c128", ["c64"]),
     "12x12_D4_chi16_rydberg": (12, 12, 4, 16, False, RYD, 2, "f64", ["f32", "bf16"]),
     "16x16_D6_chi36_heisenberg": (16, 16, 6, 36, False, HEIS, 1, "f64", ["f32"]),
     "12x12_D4_chi16_rydberg_mu0.5": (12, 12, 4, 16, False, RYD, 2, "f64", ["f32"]),
