@@ -173,17 +173,22 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
   typedef typename RealOf<T>::type R;
   const int tid = threadIdx.x, NT = PEPS_NT;
   // symv: TPR lanes per row of the trailing block (full rows through the
-  // symmetric storage, balanced); update: groups of 8 lanes per pair of rows
-  // (one from the top, one from the bottom of the trailing triangle), so
-  // every group has about the same number of elements
-  const int TPR = nz <= 128 ? 4 : 2;
-  const int rpp = NT / TPR;
-  const int ri = tid / TPR, q = tid - ri * TPR;
-  const int G8 = 8, ng = NT / G8, grp = tid / G8, q8 = tid - grp * G8;
+  // symmetric storage, balanced); update: groups of G8 lanes per pair of
+  // rows (one from the top, one from the bottom of the trailing triangle),
+  // so every group has about the same number of elements. Both widths grow
+  // as the trailing block shrinks (powers of two up to a wave), so every
+  // step spreads its rows over the whole workgroup.
   R s2 = 0;
   for (int i = 2 + tid; i < nz; i += NT) s2 += abs2x(rho[pk(i, 0)]);
   s2 = blk_sum2(s2, reinterpret_cast<R*>(sh.red), slot);
   for (int j = 0; j + 1 < nz; ++j) {
+    const int n1 = nz - j - 1, npair = (n1 + 1) / 2;
+    int lt = 0, lg = 3;
+    while (lt < 6 && (NT >> (lt + 1)) >= n1) ++lt;
+    while (lg < 6 && (NT >> (lg + 1)) >= npair) ++lg;
+    const int TPR = 1 << lt, rpp = NT >> lt;
+    const int ri = tid >> lt, q = tid & (TPR - 1);
+    const int G8 = 1 << lg, ng = NT >> lg, grp = tid >> lg, q8 = tid & (G8 - 1);
     const T alpha = rho[pk(j + 1, j)];
     R ar, aim;
     split(alpha, ar, aim);
@@ -247,7 +252,6 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
     // B -= v w^H + w v^H on the lower triangle, rows paired top / bottom;
     // column j+1's new squares below row j+2 feed the next reflector
     R t = 0;
-    const int n1 = nz - j - 1, npair = (n1 + 1) / 2;
     for (int g = grp; g < npair; g += ng) {
       for (int h = 0; h < 2; ++h) {
         const int i = h == 0 ? j + 1 + g : nz - 1 - g;
