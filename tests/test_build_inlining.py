@@ -8,7 +8,6 @@ raised, the strip steps marked inline) keep every kernel of these files
 free of calls; the canonical path's Jacobi helpers (env.hip and the files
 that include it) are called on purpose and are not checked here."""
 import os
-import shutil
 import subprocess
 
 import pytest
