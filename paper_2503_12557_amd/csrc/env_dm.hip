@@ -128,6 +128,39 @@ struct DmSh {
   }
 };
 
+// a / b on the serial chains of the eigensolver (the reflectors of the
+// tridiagonalisation, Sturm counts, inverse iteration): FP32 takes the hardware reciprocal (1 ulp) times a,
+// FP64 the hardware reciprocal refined by one Newton step, r (2 - b r),
+// which squares its relative error, times a (a few ulp). Both recurrences
+// only need the quotient to a few ulp: a Sturm count changes only for
+// shifts within rounding of an eigenvalue, and inverse iteration converges
+// from any nearby solve.
+template <typename R>
+__device__ __forceinline__ R quot(R a, R b);
+template <>
+__device__ __forceinline__ float quot<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+template <>
+__device__ __forceinline__ double quot<double>(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return a * r;
+}
+
+// 1 / x on the same chains (complex: Smith's scaling, no overflow of |x|^2)
+template <typename R>
+__device__ __forceinline__ R rcpq(R x) { return quot(R(1), x); }
+template <typename R>
+__device__ __forceinline__ cplx<R> rcpq(cplx<R> x) {
+  if (fabs(x.re) >= fabs(x.im)) {
+    const R r = quot(x.im, x.re), d = quot(R(1), x.re + x.im * r);
+    return cplx<R>(d, -r * d);
+  }
+  const R r = quot(x.re, x.im), d = quot(R(1), x.re * r + x.im);
+  return cplx<R>(r * d, -d);
+}
+
 // Multiply-adds as fused FMAs (four per complex product): u + a b,
 // u + conj(a) b and u - a conj(b).
 __device__ __forceinline__ float fmac(float u, float a, float b) { return fmaf(a, b, u); }
@@ -190,6 +223,10 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
     const int ri = tid >> lt, q = tid & (TPR - 1);
     const int G8 = 1 << lg, ng = NT >> lg, grp = tid >> lg, q8 = tid & (G8 - 1);
     const T alpha = rho[pk(j + 1, j)];
+    // this thread's entry of column j below the diagonal, loaded while the
+    // reflector's scalars form (n1 <= NT: one entry per thread)
+    const int iv = j + 1 + tid;
+    const T rv = iv < nz ? rho[pk(iv, j)] : T(0);
     R ar, aim;
     split(alpha, ar, aim);
     T tau = T(0), sc = T(0);
@@ -197,8 +234,9 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
     if (!(s2 == R(0) && aim == R(0))) {
       const R nrm = sqrt(ar * ar + aim * aim + s2);
       beta = ar >= R(0) ? -nrm : nrm;
-      tau = join<T>((beta - ar) / beta, -aim / beta);
-      sc = recipx(alpha - T(beta));
+      const R rb = rcpq(beta);
+      tau = join<T>((beta - ar) * rb, -aim * rb);
+      sc = rcpq(alpha - T(beta));
     }
     if (tid == 0) {
       sh.dd[j] = realx(rho[pk(j, j)]);
@@ -206,8 +244,13 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
       sh.tau[j] = tau;
     }
     // v_i = 1 (i = j+1), rho[i][j] sc below, once into LDS and Hv row j
-    for (int i = j + 1 + tid; i < nz; i += NT) {
-      const T v = i == j + 1 ? T(1) : rho[pk(i, j)] * sc;
+    if (iv < nz) {
+      const T v = iv == j + 1 ? T(1) : rv * sc;
+      sh.vb[iv] = v;
+      Hv[(size_t)j * ldh + iv] = v;
+    }
+    for (int i = iv + NT; i < nz; i += NT) {
+      const T v = rho[pk(i, j)] * sc;
       sh.vb[i] = v;
       Hv[(size_t)j * ldh + i] = v;
     }
@@ -272,26 +315,6 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
     sh.ee[nz - 1] = 0;
   }
   __syncthreads();
-}
-
-// a / b on the serial chains of the eigenvector phase (Sturm counts,
-// inverse iteration): FP32 takes the hardware reciprocal (1 ulp) times a,
-// FP64 the hardware reciprocal refined by one Newton step, r (2 - b r),
-// which squares its relative error, times a (a few ulp). Both recurrences
-// only need the quotient to a few ulp: a Sturm count changes only for
-// shifts within rounding of an eigenvalue, and inverse iteration converges
-// from any nearby solve.
-template <typename R>
-__device__ __forceinline__ R quot(R a, R b);
-template <>
-__device__ __forceinline__ float quot<float>(float a, float b) {
-  return a * __builtin_amdgcn_rcpf(b);
-}
-template <>
-__device__ __forceinline__ double quot<double>(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
-  return a * r;
 }
 
 // Eigenvalues below x of the symmetric tridiagonal (d, e^2): Sturm count.
