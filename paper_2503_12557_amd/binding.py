@@ -277,9 +277,10 @@ class Context:
         _check(load().peps_set_truncation(self._h, float(max_weight)))
 
     def set_compression(self, method):
-        """Truncation algorithm of the environment kernel: "canonical" (QR
-        then SVD) or "densmat" (the density-matrix algorithm on the matrix
-        cores)."""
+        """Truncation algorithm of the environment kernels (evaluation and
+        the Metropolis sampler): "canonical" (QR then SVD; the faster one at
+        chi*D <= 64) or "densmat" (the density-matrix algorithm on the matrix
+        cores; the faster one above, about 16x at 10x10 D=5 chi=25)."""
         _check(load().peps_set_compression(self._h, COMPRESS[method]))
         self.compression = method
 
