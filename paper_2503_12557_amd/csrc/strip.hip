@@ -267,7 +267,8 @@ __global__ void __launch_bounds__(PEPS_BLOCK_MAX, STRIP2_WAVES(M, GM))
 k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __restrict__ theta,
          const uint8_t* __restrict__ samples, const typename ModeT<M>::T* __restrict__ env,
          HamDev H, typename ModeT<M>::T* __restrict__ rtscr, double* __restrict__ epart,
-         int* __restrict__ flags, int n, typename ModeT<M>::T* __restrict__ gws, size_t slab) {
+         int* __restrict__ flags, int n, typename ModeT<M>::T* __restrict__ gws, size_t slab,
+         int xcap) {
   typedef typename ModeT<M>::T T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -293,6 +294,9 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
   T* A1s = Bs + box;
   T* A2s = A1s + D * D * D * D;
   T* red = GM ? lds : A2s + D * D * D * D;
+  // with the global slab, the last intermediate of each step (xcap elements
+  // of LDS after the reduction scratch) is formed and consumed on chip
+  T* xl = GM ? lds + 16 : nullptr;
   __shared__ T one[1];
   __shared__ int fl;
   if (tid == 0) {
@@ -363,7 +367,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     stage(y, pbit(s[n1]), pbit(s[n2]));
     if constexpr (MMP)
       s2_step_right_mm<T, BFP>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2,
-                          Dd2, Bs, ba_(y), bb_(y), X1, X2, rnxt);
+                          Dd2, Bs, ba_(y), bb_(y), X1, X2, rnxt, xl, xcap);
     else
       s2_step_right<M>(rcur, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
                        Bs, ba_(y), bb_(y), X1, X2, X1, rnxt);
@@ -413,7 +417,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
           stage(yy, p1, p2);
           if constexpr (MMP)
             s2_step_left_mm<T, BFP>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
-                               Dr2, Dd2, Bs, ba_(yy), bb_(yy), X1, X2, nxt);
+                               Dr2, Dd2, Bs, ba_(yy), bb_(yy), X1, X2, nxt, xl, xcap);
           else
             s2_step_left<M>(cur, Us, ua_(yy), uk_(yy), ub_(yy), A1s, Dl1, Dr1, Dd1, A2s, Dl2,
                             Dr2, Dd2, Bs, ba_(yy), bb_(yy), X1, X2, X1, nxt);
@@ -442,7 +446,7 @@ k_strip2(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
     stage(y, pbit(s[n1]), pbit(s[n2]));
     if constexpr (MMP)
       s2_step_left_mm<T, BFP>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2,
-                         Bs, ba_(y), bb_(y), X1, X2, Lt);
+                         Bs, ba_(y), bb_(y), X1, X2, Lt, xl, xcap);
     else
       s2_step_left<M>(Lf, Us, ua_(y), uk_(y), ub_(y), A1s, Dl1, Dr1, Dd1, A2s, Dl2, Dr2, Dd2, Bs,
                       ba_(y), bb_(y), X1, X2, X1, Lt);
@@ -643,8 +647,22 @@ hipError_t launch_strict_combine(int n, const int* off, const double* coef, cons
 size_t strip1_lds_bytes(int mode, const Lattice& L, bool gm) {
   return (gm ? strip1_small(L.D) : strip1_lds_elems(L.bmax, L.D)) * mode_elem_bytes(mode);
 }
+// LDS for the on-chip chunks of the steps' last intermediate (global slab,
+// FP32 modes, two workgroups to a CU): whole multiples of one carried-bond
+// slice (bmax D^3 elements) within half of a CU's 160 KiB, zero when not
+// even one slice fits. The FP64 modes keep the intermediate in the slab:
+// their slices are twice as large, and chunks of one to three slices leave
+// most waves of the last product idle (complex128 at 10x10 D=5 chi=25: 425
+// against 407 ms per launch, where complex64 gains 222 -> 212 ms).
+static int strip2_xcap(int mode, const Lattice& L) {
+  if (mode != MODE_F32 && mode != MODE_BF16 && mode != MODE_C64) return 0;
+  const size_t budget = 76 * 1024 / mode_elem_bytes(mode);
+  const size_t per = (size_t)L.bmax * L.D * L.D * L.D;
+  return (int)(budget / per * per);
+}
 size_t strip2_lds_bytes(int mode, const Lattice& L, bool gm) {
-  return (gm ? 16 : strip2_lds_elems(L.bmax, L.D)) * mode_elem_bytes(mode);
+  return (gm ? 16 + (size_t)strip2_xcap(mode, L) : strip2_lds_elems(L.bmax, L.D)) *
+         mode_elem_bytes(mode);
 }
 size_t strip1_slab_elems(const Lattice& L) { return (strip1_big(L.bmax, L.D) + 15) / 16 * 16; }
 size_t strip2_slab_elems(const Lattice& L, int mode) {
@@ -685,11 +703,11 @@ hipError_t launch_strip2(const Lattice& L, const int* tab, const void* theta,
   if (gm)
     hipLaunchKernelGGL((k_strip2<M, true>), dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
                        (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n,
-                       (T*)gws, strip2_slab_elems(L, M));
+                       (T*)gws, strip2_slab_elems(L, M), strip2_xcap(M, L));
   else
     hipLaunchKernelGGL((k_strip2<M, false>), dim3(n, L.Lx - 1), dim3(512), lds, st, L, tab,
                        (const T*)theta, samples, (const T*)env, H, (T*)rt, epart, flags, n,
-                       (T*)nullptr, (size_t)0);
+                       (T*)nullptr, (size_t)0, 0);
   return hipGetLastError();
 }
 

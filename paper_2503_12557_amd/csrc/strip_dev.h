@@ -536,17 +536,60 @@ __device__ void s1_hole_mm(const T* Lp, const T* U, int ua, int ub, int Dl, int 
 template <typename T, bool BF = false>
 __device__ __forceinline__ void s2_step_left_mm(const T* Lp, const T* U, int ua, int uk, int ub, const T* A1,
                                 int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2,
-                                int Dd2, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout) {
+                                int Dd2, const T* Bt, int ba, int bb, T* X1, T* X2, T* Lout,
+                                T* xl = nullptr, int xcap = 0) {
   const int inner = Dl1 * Dl2 * ba;
-  // X1[(m1,m2,c),(u,b)] = sum_a L[a,(m1,m2,c)] U[a,(u,b)]
-  mgemm_map<T, false, false, BF, IsCplx<T>::value>(inner, uk * ub, ua, Lp, IMap(1), IMap(inner), U, IMap(uk * ub),
-                             IMap(1), X1, IMap(uk * ub), IMap(1), false, false);
-  __syncthreads();
-  // X2[(m2,c,b),(r1,t)] = sum_{(m1,u)} X1[(m1,m2,c),(u,b)] A1[m1,r1,u,t]
-  mgemm_map<T, false, false, BF, IsCplx<T>::value>(Dl2 * ba * ub, Dr1 * Dd1, Dl1 * uk, X1, IMap(ub, uk * ub, 1),
-                             IMap(uk, Dl2 * ba * uk * ub, ub), A1, IMap(uk, Dr1 * uk * Dd1, Dd1),
-                             IMap(Dd1, uk * Dd1, 1), X2, IMap(Dr1 * Dd1), IMap(1), false, false);
-  __syncthreads();
+  const int q1 = Dl1 * uk * ub;
+  if (xl != nullptr && xcap >= q1) {
+    // with an LDS buffer, X1 goes chunk by chunk over q = (m2,c) and stays on
+    // chip: xl[(m1,qq),(u,b)] for q = q0 + qq, then the chunk's rows of X2
+    const int gq = xcap / q1, nq = Dl2 * ba;
+    for (int q0 = 0; q0 < nq; q0 += gq) {
+      const int g = nq - q0 < gq ? nq - q0 : gq;
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          Dl1 * g, uk * ub, ua, Lp + q0, IMap(g, Dl2 * ba, 1), IMap(inner), U, IMap(uk * ub),
+          IMap(1), xl, IMap(uk * ub), IMap(1), false, false);
+      __syncthreads();
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          g * ub, Dr1 * Dd1, Dl1 * uk, xl, IMap(ub, uk * ub, 1), IMap(uk, g * uk * ub, ub), A1,
+          IMap(uk, Dr1 * uk * Dd1, Dd1), IMap(Dd1, uk * Dd1, 1),
+          X2 + (size_t)q0 * ub * Dr1 * Dd1, IMap(Dr1 * Dd1), IMap(1), false, false);
+      __syncthreads();
+    }
+  } else {
+    // X1[(m1,m2,c),(u,b)] = sum_a L[a,(m1,m2,c)] U[a,(u,b)]
+    mgemm_map<T, false, false, BF, IsCplx<T>::value>(inner, uk * ub, ua, Lp, IMap(1), IMap(inner), U,
+                                                     IMap(uk * ub), IMap(1), X1, IMap(uk * ub),
+                                                     IMap(1), false, false);
+    __syncthreads();
+    // X2[(m2,c,b),(r1,t)] = sum_{(m1,u)} X1[(m1,m2,c),(u,b)] A1[m1,r1,u,t]
+    mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+        Dl2 * ba * ub, Dr1 * Dd1, Dl1 * uk, X1, IMap(ub, uk * ub, 1),
+        IMap(uk, Dl2 * ba * uk * ub, ub), A1, IMap(uk, Dr1 * uk * Dd1, Dd1),
+        IMap(Dd1, uk * Dd1, 1), X2, IMap(Dr1 * Dd1), IMap(1), false, false);
+    __syncthreads();
+  }
+  // with an LDS buffer xl (xcap elements), X3 and L' go chunk by chunk over
+  // the carried bond b, X3 of a chunk staying in LDS: X3[(c,bb,r1),(s,d)]
+  // for b = b0 + bb, then the chunk's rows of L'
+  const int per = ba * Dr1 * Dr2 * Dd2;
+  if (xl != nullptr && xcap >= per) {
+    const int gb = xcap / per;
+    for (int b0 = 0; b0 < ub; b0 += gb) {
+      const int g = ub - b0 < gb ? ub - b0 : gb;
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          ba * g * Dr1, Dr2 * Dd2, Dl2 * Dd1, X2 + (size_t)b0 * Dr1 * Dd1,
+          IMap(g * Dr1, ub * Dr1 * Dd1, Dd1), IMap(Dd1, ba * ub * Dr1 * Dd1, 1), A2,
+          IMap(Dd1, Dr2 * Dd1 * Dd2, Dd2), IMap(Dd2, Dd1 * Dd2, 1), xl, IMap(Dr2 * Dd2), IMap(1),
+          false, false);
+      __syncthreads();
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          g * Dr1 * Dr2, bb, ba * Dd2, xl, IMap(Dd2), IMap(Dd2, g * Dr1 * Dr2 * Dd2, 1), Bt,
+          IMap(bb), IMap(1), Lout + (size_t)b0 * Dr1 * Dr2 * bb, IMap(bb), IMap(1), false, false);
+      __syncthreads();
+    }
+    return;
+  }
   // X3[(c,b,r1),(s,d)] = sum_{(m2,t)} X2[(m2,c,b),(r1,t)] A2[m2,s,t,d]  (into X1)
   T* X3 = X1;
   mgemm_map<T, false, false, BF, IsCplx<T>::value>(ba * ub * Dr1, Dr2 * Dd2, Dl2 * Dd1, X2, IMap(Dd1),
@@ -563,18 +606,58 @@ __device__ __forceinline__ void s2_step_left_mm(const T* Lp, const T* U, int ua,
 template <typename T, bool BF = false>
 __device__ void s2_step_right_mm(const T* Rp, const T* U, int ua, int uk, int ub, const T* A1,
                                  int Dl1, int Dr1, int Dd1, const T* A2, int Dl2, int Dr2,
-                                 int Dd2, const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Rout) {
+                                 int Dd2, const T* Bt, int ba, int bb, T* Y1, T* Y2, T* Rout,
+                                 T* xl = nullptr, int xcap = 0) {
   const int rw = Dr1 * Dr2 * bb;
-  // Y1[(a,u),(r1,s,e)] = sum_b U[(a,u),b] R[b,(r1,s,e)]
-  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * uk, rw, ub, U, IMap(ub), IMap(1), Rp, IMap(rw), IMap(1), Y1,
-                             IMap(rw), IMap(1), false, false);
-  __syncthreads();
-  // Y2[(a,s,e),(m1,t)] = sum_{(u,r1)} Y1[(a,u),(r1,s,e)] A1[m1,r1,u,t]
-  mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * Dr2 * bb, Dl1 * Dd1, uk * Dr1, Y1, IMap(Dr2 * bb, uk * rw, 1),
-                             IMap(Dr1, rw, Dr2 * bb), A1, IMap(Dr1, Dd1, uk * Dd1),
-                             IMap(Dd1, Dr1 * uk * Dd1, 1), Y2, IMap(Dl1 * Dd1), IMap(1), false,
-                             false);
-  __syncthreads();
+  if (xl != nullptr && xcap >= uk * rw) {
+    // with an LDS buffer, Y1 goes chunk by chunk over a and stays on chip,
+    // then the chunk's rows of Y2
+    const int ga = xcap / (uk * rw);
+    for (int a0 = 0; a0 < ua; a0 += ga) {
+      const int g = ua - a0 < ga ? ua - a0 : ga;
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          g * uk, rw, ub, U + (size_t)a0 * uk * ub, IMap(ub), IMap(1), Rp, IMap(rw), IMap(1), xl,
+          IMap(rw), IMap(1), false, false);
+      __syncthreads();
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          g * Dr2 * bb, Dl1 * Dd1, uk * Dr1, xl, IMap(Dr2 * bb, uk * rw, 1),
+          IMap(Dr1, rw, Dr2 * bb), A1, IMap(Dr1, Dd1, uk * Dd1), IMap(Dd1, Dr1 * uk * Dd1, 1),
+          Y2 + (size_t)a0 * Dr2 * bb * Dl1 * Dd1, IMap(Dl1 * Dd1), IMap(1), false, false);
+      __syncthreads();
+    }
+  } else {
+    // Y1[(a,u),(r1,s,e)] = sum_b U[(a,u),b] R[b,(r1,s,e)]
+    mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * uk, rw, ub, U, IMap(ub), IMap(1), Rp,
+                                                     IMap(rw), IMap(1), Y1, IMap(rw), IMap(1),
+                                                     false, false);
+    __syncthreads();
+    // Y2[(a,s,e),(m1,t)] = sum_{(u,r1)} Y1[(a,u),(r1,s,e)] A1[m1,r1,u,t]
+    mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+        ua * Dr2 * bb, Dl1 * Dd1, uk * Dr1, Y1, IMap(Dr2 * bb, uk * rw, 1),
+        IMap(Dr1, rw, Dr2 * bb), A1, IMap(Dr1, Dd1, uk * Dd1), IMap(Dd1, Dr1 * uk * Dd1, 1), Y2,
+        IMap(Dl1 * Dd1), IMap(1), false, false);
+    __syncthreads();
+  }
+  // with an LDS buffer xl (xcap elements), Y3 and R' go chunk by chunk over
+  // the carried bond a, Y3 of a chunk staying in LDS
+  const int per = bb * Dl1 * Dl2 * Dd2;
+  if (xl != nullptr && xcap >= per) {
+    const int ga = xcap / per;
+    for (int a0 = 0; a0 < ua; a0 += ga) {
+      const int g = ua - a0 < ga ? ua - a0 : ga;
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          g * bb * Dl1, Dl2 * Dd2, Dr2 * Dd1, Y2 + (size_t)a0 * Dr2 * bb * Dl1 * Dd1,
+          IMap(bb * Dl1, Dr2 * bb * Dl1 * Dd1, Dd1), IMap(Dd1, bb * Dl1 * Dd1, 1), A2, IMap(Dd2),
+          IMap(Dd2, Dr2 * Dd1 * Dd2, 1), xl, IMap(Dl2 * Dd2), IMap(1), false, false);
+      __syncthreads();
+      mgemm_map<T, false, false, BF, IsCplx<T>::value>(
+          g * Dl1 * Dl2, ba, Dd2 * bb, xl, IMap(Dl1 * Dl2, bb * Dl1 * Dl2 * Dd2, Dd2),
+          IMap(bb, 1, Dl1 * Dl2 * Dd2), Bt, IMap(1), IMap(Dd2 * bb),
+          Rout + (size_t)a0 * Dl1 * Dl2 * ba, IMap(ba), IMap(1), false, false);
+      __syncthreads();
+    }
+    return;
+  }
   // Y3[(a,e,m1),(m2,d)] = sum_{(s,t)} Y2[(a,s,e),(m1,t)] A2[m2,s,t,d]  (into Y1)
   T* Y3 = Y1;
   mgemm_map<T, false, false, BF, IsCplx<T>::value>(ua * bb * Dl1, Dl2 * Dd2, Dr2 * Dd1, Y2,
