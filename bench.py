@@ -613,9 +613,9 @@ def main():
     if "strip2" in per_kernel:
         s2 = per_kernel["strip2"]
         rooflines["strip2"] = {
-            "kernel": "k_strip2", "bound": "alu",
+            "kernel": "k_strip2", "bound": "mfma",
             "achieved": s2_flops_total / s2["launches"] / (s2["ms_avg"] * 1e-3) / 1e12,
-            "peak": PEAK["fp32_vector_tflops"], "unit": "TFLOP/s",
+            "peak": PEAK["fp32_matrix_tflops"], "unit": "TFLOP/s",
             "algorithmic_flops_per_launch": s2_flops_total / s2["launches"],
             "samples_per_launch": B * steps_done / s2["launches"],
             "avg_launch_ms": s2["ms_avg"]}
