@@ -317,6 +317,167 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
   __syncthreads();
 }
 
+// The same reduction with the matrix in registers (FP32 modes, nz <= 128,
+// 512 threads). Thread (r, c) = (tid / 16, tid % 16) holds the full
+// Hermitian matrix's elements (r + 32 a, c + 16 b), a < 4, b < 8: u = B v is
+// a per-thread partial over its columns summed over the 16 lanes that share
+// its rows, and the rank-2 update touches registers only. LDS carries the
+// vectors: the column that makes the next reflector, written by its owners
+// during the update with its partial squared norms (two buffers, the
+// current column still being read), and u. Two barriers per reflector
+// instead of four, and O(nz) LDS traffic per reflector instead of O(nz^2).
+// rhoG: the full matrix (lower triangle read, row stride ldg).
+template <typename T>
+__device__ void tridiag_reg(const T* rhoG, int ldg, int nz, T* Hv, int ldh, const DmSh<T>& sh) {
+  typedef typename RealOf<T>::type R;
+  const int tid = threadIdx.x;
+  const int c = tid & 15, r = tid >> 4, w = tid >> 6;
+  // u and v of the current reflector (zero outside rows j+1 .. nz-1)
+  T* ub = sh.big;
+  T* vv = ub + 128;
+  R* nrm = reinterpret_cast<R*>(vv + 128);
+  R* vhp = nrm + 8;
+  if (tid < 128) {
+    ub[tid] = T(0);
+    vv[tid] = T(0);
+  }
+  T B[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = r + 32 * a, k = c + 16 * b;
+      T x = T(0);
+      if (i < nz && k < nz) x = k <= i ? rhoG[(size_t)i * ldg + k] : conjx(rhoG[(size_t)k * ldg + i]);
+      B[a][b] = x;
+    }
+  // column jc from rows jc.. into cb, its squares below row jc + 1 summed per wave
+  auto put_col = [&](int jc, T* cb) {
+    R s = 0;
+    if (c == (jc & 15)) {
+      const int bj = jc >> 4;
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (b == bj) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int i = r + 32 * a;
+            if (i >= jc && i < nz) cb[i] = B[a][b];
+            if (i >= jc + 2 && i < nz) s += abs2x(B[a][b]);
+          }
+        }
+    }
+    // nonzero on the owners only: lanes jc % 16 + 16 m of each wave
+    s += shfl_xor_x(s, 16);
+    s += shfl_xor_x(s, 32);
+    if ((tid & 63) == (jc & 15)) nrm[w] = s;
+  };
+  put_col(0, sh.vb);
+  __syncthreads();
+  for (int j = 0; j + 1 < nz; ++j) {
+    const T* cb = (j & 1) ? sh.wb : sh.vb;
+    T* cbn = (j & 1) ? sh.vb : sh.wb;
+    R s2 = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s2 += nrm[q];
+    const T alpha = cb[j + 1];
+    R ar, aim;
+    split(alpha, ar, aim);
+    T tau = T(0), sc = T(0);
+    R beta = ar;
+    if (!(s2 == R(0) && aim == R(0))) {
+      const R nv = sqrt(ar * ar + aim * aim + s2);
+      beta = ar >= R(0) ? -nv : nv;
+      const R rb = rcpq(beta);
+      tau = join<T>((beta - ar) * rb, -aim * rb);
+      sc = rcpq(alpha - T(beta));
+    }
+    if (tid == 0) {
+      sh.dd[j] = realx(cb[j]);
+      sh.ee[j] = beta;
+      sh.tau[j] = tau;
+    }
+    // v_i = 1 (i = j+1), column j's entry times sc below, 0 elsewhere
+    auto vval = [&](int i) -> T {
+      return i == j + 1 ? T(1) : ((i > j + 1 && i < nz) ? cb[i] * sc : T(0));
+    };
+    // row slots a < a0 and column slots b < b0 hold finished rows / columns
+    // (index <= j) only: the same for every thread, skipped
+    const int a0 = (j + 1) >> 5, b0 = (j + 1) >> 4;
+    // u = B v for the rows of the trailing block (zero for the others)
+    T acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b < b0) continue;
+      const T vk = vval(c + 16 * b);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a >= a0) acc[a] = fmac(acc[a], B[a][b], vk);
+    }
+    R vh = 0;
+    // u and v of row j (finished now) read as zero from here on
+    if (tid == 0) {
+      ub[j] = T(0);
+      vv[j] = T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a < a0) continue;
+      const int i = r + 32 * a;
+      const T u = group_sum(acc[a], 16);
+      if (c == 0 && i < nz) {
+        // each row's sum is held by its 16 lanes: one of them stores and counts it
+        const T vi = vval(i);
+        const T ui = i > j ? u : T(0);
+        ub[i] = ui;
+        vv[i] = vi;
+        if (i > j) Hv[(size_t)j * ldh + i] = vi;
+        vh += realx(conjx(vi) * ui);
+      }
+    }
+    // nonzero on lanes 0, 16, 32, 48 of each wave only
+    vh += shfl_xor_x(vh, 16);
+    vh += shfl_xor_x(vh, 32);
+    if ((tid & 63) == 0) vhp[w] = vh;
+    __syncthreads();
+    R vhu_r = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vhu_r += vhp[q];
+    // w = tau u - (|tau|^2 / 2) (v^H u) v; B -= v w^H + w v^H
+    const R t2 = abs2x(tau) * R(0.5) * vhu_r;
+    T vr[4], wr[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = r + 32 * a;
+      vr[a] = T(0);
+      wr[a] = T(0);
+      if (a < a0) continue;
+      vr[a] = vv[i];
+      wr[a] = tau * ub[i] - vr[a] * t2;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b < b0) continue;
+      const int k = c + 16 * b;
+      const T vk = vv[k];
+      const T wk = tau * ub[k] - vk * t2;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a >= a0) B[a][b] = fnmac_cb(fnmac_cb(B[a][b], vr[a], wk), wr[a], vk);
+    }
+    put_col(j + 1, cbn);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const T* cb = ((nz - 1) & 1) ? sh.wb : sh.vb;
+    sh.dd[nz - 1] = realx(cb[nz - 1]);
+    sh.ee[nz - 1] = 0;
+  }
+  __syncthreads();
+}
+
 // Eigenvalues below x of the symmetric tridiagonal (d, e^2): Sturm count.
 template <typename R>
 __device__ __forceinline__ int sturm(const R* d, const R* e2, int n, R x, R pivmin) {
@@ -522,27 +683,32 @@ __device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* 
 // The r leading eigenvectors of the Hermitian nz x nz matrix rho (full, in
 // the slab, row stride NP): on exit Xe (LDS, nz x r, row stride r) holds
 // them as columns, lam[0..rr) the rr = min(r + 1, nz) largest eigenvalues.
-// rho is copied to LDS as a packed lower triangle (sh.big) first; Xe
-// overlays it after the reduction.
+// REG (FP32 and complex64, up to 128 x 128, 512 threads): the reduction to
+// tridiagonal form holds rho in registers; otherwise rho is copied to LDS
+// as a packed lower triangle (sh.big) first. Xe overlays sh.big after it.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool REG>
 __device__ void dm_eig(const T* rhoG, int np, int nz, int r, int rr, T* Hv, typename RealOf<T>::type* Yt,
                        typename RealOf<T>::type* lu, const DmSh<T>& sh, int& slot,
                        typename RealOf<T>::type& tnorm) {
   typedef typename RealOf<T>::type R;
   const int tid = threadIdx.x, NT = PEPS_NT;
-  T* rho = sh.big;
-  const int tot = nz * (nz + 1) / 2;
-  for (int idx = tid; idx < tot; idx += NT) {
-    // invert idx = i (i + 1) / 2 + j
-    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while (pk(i + 1, 0) <= idx) ++i;
-    while (pk(i, 0) > idx) --i;
-    const int j = idx - pk(i, 0);
-    rho[idx] = rhoG[(size_t)i * np + j];
+  if (REG && NT == 512 && nz <= 128) {
+    tridiag_reg(rhoG, np, nz, Hv, np, sh);
+  } else {
+    T* rho = sh.big;
+    const int tot = nz * (nz + 1) / 2;
+    for (int idx = tid; idx < tot; idx += NT) {
+      // invert idx = i (i + 1) / 2 + j
+      int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (pk(i + 1, 0) <= idx) ++i;
+      while (pk(i, 0) > idx) --i;
+      const int j = idx - pk(i, 0);
+      rho[idx] = rhoG[(size_t)i * np + j];
+    }
+    __syncthreads();
+    tridiag(rho, nz, Hv, np, sh, slot);
   }
-  __syncthreads();
-  tridiag(rho, nz, Hv, np, sh, slot);
   top_eigenvalues(sh.dd, sh.ee, sh.e2, sh.lam, nz, rr, reinterpret_cast<R*>(sh.red), slot, tnorm);
   // eigenvectors of the tridiagonal, one lane each, vector c's element e at
   // Y[e * r + c]; in LDS when they fit (the packed matrix is dead now): the
@@ -667,7 +833,7 @@ __device__ __forceinline__ void load_block(T* dst, const T* src, int bl, int din
 // Every contraction runs over the kept bonds only; the tensors are stored
 // in the chi-wide layout with zeros beyond them.
 template <int M>
-__device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename ModeT<M>::T* theta,
+__device__ __forceinline__ void dm_absorb_row(const Lattice& L, const int* tab, const typename ModeT<M>::T* theta,
                               const uint8_t* s, bool bottom, int t, typename ModeT<M>::T* envs,
                               double* lg, typename ModeT<M>::T* slab, const DmSh<typename ModeT<M>::T>& sh,
                               int* flp, int& slot, const int* kprev, int* knew) {
@@ -814,7 +980,8 @@ __device__ void dm_absorb_row(const Lattice& L, const int* tab, const typename M
       rnew = rs < zc ? rs : zc;
       const int rr = rnew + 1 < zc ? rnew + 1 : zc;
       R tnorm;
-      dm_eig<T>(Pk, np, zc, rnew, rr, Hv, Yt, lu, sh, slot, tnorm);
+      dm_eig<T, M == MODE_F32 || M == MODE_C64>(Pk, np, zc, rnew, rr, Hv, Yt, lu, sh, slot,
+                                                 tnorm);
       // kept count and cut flags from the eigenvalues (lam = sigma^2)
       __shared__ int s_keep;
       if (tid == 0) {
