@@ -210,6 +210,33 @@ def test_bf16_matrix_cores_bounded(dev, shape, model, mu, bound, sanity):
         assert all(e.max() < b for e, b in zip(errs, sanity))
 
 
+# The FP32-mode eigensolver reduces rho to tridiagonal form with the matrix
+# in registers up to 128 x 128 and with the packed LDS form above: at 6x6
+# D=4 the middle bonds reach chi, so chi = 32 gives density matrices of
+# exactly 128 (the register form's largest) and chi = 40 gives 160 (the LDS
+# form in the same mode). Against the FP64 oracle on 8 configurations, within
+# the 6x6 FP32 bound of 1e-3 (measured: complex64 2.3e-5 and 2.6e-5, FP32
+# 1.2e-4).
+@pytest.mark.parametrize("dtype,chi", [("c64", 32), ("f32", 32), ("c64", 40)])
+def test_fp32_eigensolver_forms_match_oracle(dev, dtype, chi):
+    cplx = dtype == "c64"
+    Lx, Ly, D = 6, 6, 4
+    model = CHIRAL if cplx else J1J2
+    theta = synth.theta(Lx, Ly, 2, D, seed=61 + chi, cplx=cplx)
+    cf = configs_for(model, Lx * Ly, 8, seed=62)
+    olp, oel, oO = oracle_eval(theta, Lx, Ly, D, chi, cf, model=model, want_O=True,
+                               method="densmat")
+    lp, el, O, fl = _eval(dev, _ctx(Lx, Ly, D, chi, dtype, model), theta, cf)
+    ok = (fl & 8) == 0
+    assert ok.any()
+    e_psi = rel_amp_err(lp, olp)
+    e_el = np.abs(el - oel) / np.maximum(1.0, np.abs(oel))
+    e_O = _o_err(theta, cf, O, oO, Lx, Ly, D)
+    print(f"6x6 D=4 chi={chi} {dtype}: psi {e_psi.max():.2e} eloc {e_el.max():.2e} "
+          f"O {e_O.max():.2e}")
+    assert max(e_psi[ok].max(), e_el[ok].max(), e_O[ok].max()) <= 1e-3
+
+
 def test_truncated_weight_matches_oracle(dev):
     Lx, Ly, D, chi = 5, 6, 3, 7
     theta = synth.theta(Lx, Ly, 2, D, seed=61, mu=0.5)
