@@ -317,8 +317,8 @@ __device__ void tridiag(T* rho, int nz, T* Hv, int ldh, const DmSh<T>& sh, int& 
   __syncthreads();
 }
 
-// The same reduction with the matrix in registers (FP32 modes, nz <= 128,
-// 512 threads). Thread (r, c) = (tid / 16, tid % 16) holds the full
+// The same reduction with the matrix in registers (nz <= 128, 512 threads;
+// every mode but BF16, whose kernel spills in it). Thread (r, c) = (tid / 16, tid % 16) holds the full
 // Hermitian matrix's elements (r + 32 a, c + 16 b), a < 4, b < 8: u = B v is
 // a per-thread partial over its columns summed over the 16 lanes that share
 // its rows, and the rank-2 update touches registers only. LDS carries the
@@ -683,8 +683,8 @@ __device__ void inv_iter_lane(const R* dd, const R* ee, int n, R x, R tnorm, R* 
 // The r leading eigenvectors of the Hermitian nz x nz matrix rho (full, in
 // the slab, row stride NP): on exit Xe (LDS, nz x r, row stride r) holds
 // them as columns, lam[0..rr) the rr = min(r + 1, nz) largest eigenvalues.
-// REG (FP32 and complex64, up to 128 x 128, 512 threads): the reduction to
-// tridiagonal form holds rho in registers; otherwise rho is copied to LDS
+// REG (every mode but BF16; up to 128 x 128, 512 threads): the reduction
+// to tridiagonal form holds rho in registers; otherwise rho is copied to LDS
 // as a packed lower triangle (sh.big) first. Xe overlays sh.big after it.
 // ---------------------------------------------------------------------------
 template <typename T, bool REG>
@@ -980,8 +980,7 @@ __device__ __forceinline__ void dm_absorb_row(const Lattice& L, const int* tab, 
       rnew = rs < zc ? rs : zc;
       const int rr = rnew + 1 < zc ? rnew + 1 : zc;
       R tnorm;
-      dm_eig<T, M == MODE_F32 || M == MODE_C64>(Pk, np, zc, rnew, rr, Hv, Yt, lu, sh, slot,
-                                                 tnorm);
+      dm_eig<T, M != MODE_BF16>(Pk, np, zc, rnew, rr, Hv, Yt, lu, sh, slot, tnorm);
       // kept count and cut flags from the eigenvalues (lam = sigma^2)
       __shared__ int s_keep;
       if (tid == 0) {

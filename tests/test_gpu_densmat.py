@@ -77,7 +77,7 @@ def _o_err(theta, cf, O, oO, Lx, Ly, D):
 
 # (Lx, Ly, D, chi, complex, model, n): exact regime, truncating, ragged
 # (Lx != Ly, chi not a power of two), complex chiral, Rydberg flips, the
-# 8x8 D=4 chi=16 shape
+# 8x8 D=4 chi=16 shape, and 6x6 D=4 chi=40 (the eigensolver's LDS form)
 CASES = [
     (2, 3, 2, 2, False, J1J2, 8),
     (4, 4, 2, 4, False, J1J2, 8),
@@ -86,6 +86,8 @@ CASES = [
     (4, 5, 3, 5, True, CHIRAL, 6),
     (5, 6, 3, 7, True, CHIRAL, 4),
     (8, 8, 4, 16, False, J1J2, 4),
+    # density matrices of 160 (chi D > 128): the packed LDS eigensolver form
+    (6, 6, 4, 40, False, J1J2, 4),
 ]
 
 
@@ -210,8 +212,8 @@ def test_bf16_matrix_cores_bounded(dev, shape, model, mu, bound, sanity):
         assert all(e.max() < b for e, b in zip(errs, sanity))
 
 
-# The FP32-mode eigensolver reduces rho to tridiagonal form with the matrix
-# in registers up to 128 x 128 and with the packed LDS form above: at 6x6
+# The eigensolver reduces rho to tridiagonal form with the matrix in
+# registers up to 128 x 128 and with the packed LDS form above: at 6x6
 # D=4 the middle bonds reach chi, so chi = 32 gives density matrices of
 # exactly 128 (the register form's largest) and chi = 40 gives 160 (the LDS
 # form in the same mode). Against the FP64 oracle on 8 configurations, within
