@@ -34,7 +34,8 @@ struct HamDev {
 // they fit ("_lds_bytes" with gm = false); otherwise the host passes a
 // global working-set buffer gws of one slab ("_slab_elems" elements of the
 // compute type) per workgroup of the grid, and only the small vectors stay
-// in LDS (gm = true).
+// in LDS (gm = true; the two-row strips in the FP32 modes also keep chunks
+// of their steps' first and last intermediates there).
 size_t env_lds_elems(int bmax, int D, int mode);
 size_t strip1_lds_elems(int bmax, int D);
 size_t strip2_lds_elems(int bmax, int D);

@@ -250,7 +250,8 @@ k_strip1(Lattice L, const int* __restrict__ tab, const typename ModeT<M>::T* __r
 // staged on chip, so its contractions read LDS only
 // With the matrix-core steps (global working set, every mode; bfloat16
 // products in BF16 mode) the intermediates hold the whole outer bond:
-// B^2 D^3 each.
+// B^2 D^3 each; in the FP32 modes the first and last of them are formed
+// and consumed in LDS chunks instead (strip2_xcap), the slab keeping X2.
 __host__ __device__ inline bool strip2_mm(int mode, bool gm) { return gm; }
 __host__ __device__ inline size_t strip2_xsz(int bmax, int D, bool mm) {
   return mm ? (size_t)bmax * bmax * D * D * D : (size_t)S2G * bmax * D * D * D;
