@@ -201,8 +201,8 @@ peps_status peps_set_truncation(peps_ctx* ctx, double max_weight);
  * an unknown method; PEPS_ERR_UNSUPPORTED for DENSMAT when chi*D rounded
  * up to 32 exceeds 256, chi exceeds 255 or the packed density matrix
  * (n(n+1)/2 elements, n = that padded size) does not fit in LDS (e.g.
- * complex128 or FP64 at chi*D > 128). Host-side setting, takes effect at
- * the next call. */
+ * complex128 at chi*D > 128, FP64 at chi*D > 160). Host-side setting,
+ * takes effect at the next call. */
 #define PEPS_COMPRESS_CANONICAL 0
 #define PEPS_COMPRESS_DENSMAT 1
 peps_status peps_set_compression(peps_ctx* ctx, int method);
