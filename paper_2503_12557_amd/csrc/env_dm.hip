@@ -377,9 +377,7 @@ __device__ void tridiag_reg(const T* rhoG, int ldg, int nz, T* Hv, int ldh, cons
   for (int j = 0; j + 1 < nz; ++j) {
     const T* cb = (j & 1) ? sh.wb : sh.vb;
     T* cbn = (j & 1) ? sh.vb : sh.wb;
-    R s2 = 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s2 += nrm[q];
+    const R s2 = ((nrm[0] + nrm[1]) + (nrm[2] + nrm[3])) + ((nrm[4] + nrm[5]) + (nrm[6] + nrm[7]));
     const T alpha = cb[j + 1];
     R ar, aim;
     split(alpha, ar, aim);
@@ -404,18 +402,32 @@ __device__ void tridiag_reg(const T* rhoG, int ldg, int nz, T* Hv, int ldh, cons
     // row slots a < a0 and column slots b < b0 hold finished rows / columns
     // (index <= j) only: the same for every thread, skipped
     const int a0 = (j + 1) >> 5, b0 = (j + 1) >> 4;
-    // u = B v for the rows of the trailing block (zero for the others)
-    T acc[4];
+    // u = B v for the rows of the trailing block (zero for the others),
+    // from the unscaled column: u = sc (B x) + B[:, j+1] with x the column
+    // below row j+1 (v = sc x there, v_{j+1} = 1)
+    T acc[4], e1[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) acc[a] = T(0);
+    for (int a = 0; a < 4; ++a) {
+      acc[a] = T(0);
+      e1[a] = T(0);
+    }
+    const int b1 = (j + 1) >> 4;
+    const bool own1 = c == ((j + 1) & 15);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       if (b < b0) continue;
-      const T vk = vval(c + 16 * b);
+      const int k = c + 16 * b;
+      const T xk = (k > j + 1 && k < nz) ? cb[k] : T(0);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        if (a >= a0) acc[a] = fmac(acc[a], B[a][b], vk);
+        if (a >= a0) acc[a] = fmac(acc[a], B[a][b], xk);
+      if (b == b1) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) e1[a] = own1 ? B[a][b] : T(0);
+      }
     }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a] = acc[a] * sc + e1[a];
     R vh = 0;
     // u and v of row j (finished now) read as zero from here on
     if (tid == 0) {
@@ -442,9 +454,7 @@ __device__ void tridiag_reg(const T* rhoG, int ldg, int nz, T* Hv, int ldh, cons
     vh += shfl_xor_x(vh, 32);
     if ((tid & 63) == 0) vhp[w] = vh;
     __syncthreads();
-    R vhu_r = 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) vhu_r += vhp[q];
+    const R vhu_r = ((vhp[0] + vhp[1]) + (vhp[2] + vhp[3])) + ((vhp[4] + vhp[5]) + (vhp[6] + vhp[7]));
     // w = tau u - (|tau|^2 / 2) (v^H u) v; B -= v w^H + w v^H
     const R t2 = abs2x(tau) * R(0.5) * vhu_r;
     T vr[4], wr[4];
